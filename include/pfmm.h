@@ -1,0 +1,158 @@
+/*
+ * pfmm — polarizable fast multipole method on AMD MI355X (gfx950).
+ *
+ * C interface of the library libpfmm.so.  It evaluates the electrostatics of point charges and
+ * self-consistent induced point dipoles of Coles & Masella, "The Fast Multipole Method and Point
+ * Dipole Moment Polarizable Force Fields" (arXiv:1408.6527):
+ *
+ *   U      = U^{qq'} + U^pol                                   (Sec. II.A, energy decomposition)
+ *   U^{qq'} = 1/2 sum_i q_i sum_{j != i} q_j / r_ij             (Sec. II.A, Coulomb energy)
+ *   mu_i   = alpha_i (E^q_i + E^mu_i)                          (Sec. II.A, dipole-moment equation)
+ *   U^pol  = 1/2 sum |mu_i|^2/alpha_i - sum mu_i.E^q_i - 1/2 sum mu_i.E^mu_i
+ *                                                              (Sec. II.A, A(mu) and U^pol)
+ * with the fields evaluated by a Cartesian Taylor FMM (Sec. II.B-II.C) on a Morton-sorted,
+ * uniform-depth octree, the dipoles found by conjugate gradients on the symmetric scaled system,
+ * and forces and parameter gradients taken at fixed converged dipoles (stationarity, Sec. II.A).
+ *
+ * Conventions used by every entry point
+ *   - Units: positions in Angstrom, charges in e, polarisabilities as volumes in Angstrom^3,
+ *     dipoles in e*Angstrom.  Energies, forces and potentials returned by pfmm_solve and
+ *     pfmm_backward are multiplied by cfg.coulomb_k (default 332.06371 kcal*Angstrom/(mol*e^2)).
+ *   - Every pointer to particle data is a DEVICE pointer to float64 data on the current HIP
+ *     device, owned by the caller.  pos, mu, forces are n x 3 row-major (x, y, z per particle);
+ *     n-vectors are contiguous.  Inputs are read only; outputs are fully overwritten.
+ *   - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream).  The calls that return
+ *     host scalars (pfmm_solve, pfmm_field) synchronise that stream before returning; device
+ *     outputs are then complete.  pfmm_backward returns after enqueueing its kernels.
+ *   - A handle owns its device workspace (grown on demand and reused across calls), its constant
+ *     tables and the state saved for pfmm_backward.  A handle is not thread safe; separate handles
+ *     are independent.  No caller pointer is retained after a call returns.
+ *   - Errors: every call returns a pfmm_status; pfmm_last_error(h) gives a message for the last
+ *     failure on h.  On error the contents of the output buffers are unspecified, except for
+ *     PFMM_ERR_NOT_CONVERGED, where all outputs hold the last iterate and *res is filled.
+ */
+#ifndef PFMM_H
+#define PFMM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum pfmm_status {
+  PFMM_OK = 0,
+  PFMM_ERR_INVALID_ARG = 1,   /* bad config, negative n or alpha, NULL where data is required    */
+  PFMM_ERR_NONFINITE = 2,     /* a position, charge, polarisability or warm-start dipole is NaN/Inf */
+  PFMM_ERR_COINCIDENT = 3,    /* two particles at the same position                               */
+  PFMM_ERR_NOT_CONVERGED = 4, /* the dipole solve did not reach scf_tol within scf_max_iter        */
+  PFMM_ERR_NOT_SPD = 5,       /* conjugate gradients met p.Ap <= 0: the dipole system is not
+                                 positive definite (polarisation catastrophe)                      */
+  PFMM_ERR_OOM = 6,           /* device allocation failed                                          */
+  PFMM_ERR_HIP = 7,           /* a HIP runtime call failed; the message carries hipGetErrorString */
+  PFMM_ERR_NO_STATE = 8       /* pfmm_backward without a preceding successful pfmm_solve          */
+} pfmm_status;
+
+typedef enum pfmm_precision {
+  PFMM_FP64 = 0,   /* every kernel in float64                                                  */
+  PFMM_MIXED = 1   /* M2L and P2P in float32 with float32 accumulation; tree, P2M/M2M/L2L/L2P,
+                      levels <= 3 of M2L, the dipole-solve vectors, dot products, residual norms
+                      and the energy reduction stay in float64                                   */
+} pfmm_precision;
+
+enum pfmm_flags {
+  PFMM_WANT_FORCES = 1u << 0,        /* compute forces (else `forces` may be NULL)                */
+  PFMM_WANT_POTENTIALS = 1u << 1,    /* compute potentials (else `phi` may be NULL)               */
+  PFMM_SAVE_FOR_BACKWARD = 1u << 2,  /* keep what pfmm_backward needs inside the handle          */
+  PFMM_WARM_START = 1u << 3,         /* `mu` holds an initial guess on entry                      */
+  PFMM_TIMING = 1u << 4              /* fill pfmm_result.t_phase_ms with HIP-event phase times    */
+};
+
+typedef struct pfmm_config {
+  int order_p;         /* expansion order p, 1..10 (Sec. II.B truncation |n| + |m| <= p)          */
+  int ws;              /* well-separation parameter, 1 or 2: near field = leaves within Chebyshev
+                          distance ws; M2L between children of near parents that are farther     */
+  double leaf_width;   /* leaf cell edge in Angstrom; 0 = choose from the mean density            */
+  int precision;       /* pfmm_precision                                                           */
+  double scf_tol;      /* stop when ||alpha E(mu) - mu||_2 / ||alpha E^q||_2 <= scf_tol            */
+  int scf_max_iter;    /* maximum conjugate-gradient iterations                                    */
+  int graph_iters;     /* iterations captured per HIP graph launch (0 = plain launches)           */
+  double thole_a;      /* Thole linear-damping constant a: s_ij = a (alpha_i alpha_j)^(1/6);
+                          0 disables damping.  Applied to dipole-dipole pairs only.               */
+  double coulomb_k;    /* energy scale k_e                                                         */
+  unsigned flags;      /* pfmm_flags                                                               */
+} pfmm_config;
+
+typedef struct pfmm_result {
+  double U_total, U_qq, U_pol;  /* k_e-scaled energies; U_pol in the full (variational) form      */
+  int iters;                    /* conjugate-gradient iterations taken                             */
+  double residual;              /* final ||alpha E(mu) - mu||_2 / ||alpha E^q||_2, recomputed from
+                                   the final dipoles                                               */
+  double residual_max_debye;    /* max_i |alpha_i E_i(mu) - mu_i| in Debye                         */
+  int levels;                   /* leaf level L of the octree (root = level 0)                     */
+  double leaf_width;            /* leaf edge actually used                                         */
+  int64_t n_leaves, n_cells;    /* non-empty leaves, non-empty cells on all levels                 */
+  int64_t n_m2l;                /* source-target M2L cell pairs per evaluation                     */
+  int64_t n_p2p;                /* ordered near-field particle pairs per evaluation (i != j)       */
+  int n_evals;                  /* FMM field evaluations performed                                 */
+  double t_phase_ms[8];         /* with PFMM_TIMING: tree, charge field, dipole solve, final pass,
+                                   assembly, total, -, -                                           */
+} pfmm_result;
+
+typedef struct pfmm_handle pfmm_handle;
+
+/* Fill *cfg with the defaults: p = 6, ws = 2, leaf_width = 0, FP64, scf_tol = 1e-6,
+   scf_max_iter = 200, graph_iters = 4, thole_a = 2.0, coulomb_k = 332.06371,
+   flags = WANT_FORCES | WANT_POTENTIALS | SAVE_FOR_BACKWARD. */
+void pfmm_config_default(pfmm_config* cfg);
+
+/* Create a handle for a configuration.  Validates cfg, builds the constant operator tables of
+   Sec. II.B for (p, ws) and uploads them to the current device.  *out is NULL on failure. */
+pfmm_status pfmm_create(const pfmm_config* cfg, pfmm_handle** out);
+
+/* Release the handle, its workspace and its tables.  NULL is accepted. */
+void pfmm_destroy(pfmm_handle* h);
+
+/* Full polarizable evaluation (Sec. III, three stages): charge field, dipole solve, energy and
+   forces.  n >= 0; pos (n x 3), q (n), alpha (n, every entry >= 0; 0 = not polarisable) are
+   read; mu (n x 3) receives the converged dipoles (and holds the initial guess with
+   PFMM_WARM_START); forces (n x 3, or NULL without WANT_FORCES) receive F_i = -dU/dx_i; phi
+   (n, or NULL without WANT_POTENTIALS) receives the total electrostatic potential
+   k_e sum_j (q_j/r + mu_j.r/r^3) = dU/dq_i.  *res (host) receives energies and statistics.
+   n = 0 and n = 1 return PFMM_OK with zero outputs. */
+pfmm_status pfmm_solve(pfmm_handle* h, int64_t n, const double* pos, const double* q,
+                       const double* alpha, double* mu, double* forces, double* phi,
+                       pfmm_result* res, void* stream);
+
+/* Gradients of g * U at the state saved by the last successful pfmm_solve on h (needs
+   PFMM_SAVE_FOR_BACKWARD).  By stationarity of U^pol in mu (Sec. II.A), no derivative of the
+   dipole solve is needed: grad_pos = -g F, grad_q = g phi, grad_alpha = g dU/dalpha with
+   dU/dalpha_i = k_e (-|mu_i|^2/(2 alpha_i^2) - sum_j mu_i.(dT~_ij/ds_ij) mu_j s_ij/(6 alpha_i))
+   (-|E_i|^2/2 for alpha_i = 0).  Each output is n-sized (n x 3 for positions) or NULL to skip. */
+pfmm_status pfmm_backward(pfmm_handle* h, double g, double* grad_pos, double* grad_q,
+                          double* grad_alpha, void* stream);
+
+/* One FMM field evaluation of fixed sources (Sec. II.B-II.C and the direct part of Sec. III),
+   without any scaling by k_e.  Sources: charges q (n, or NULL) and point dipoles mu (n x 3, or
+   NULL); alpha (n) sets the Thole radius of dipole-dipole pairs.  Outputs at every particle
+   (each may be NULL): phi (n) total potential; E (n x 3) field with undamped dipole part;
+   E_damped (n x 3) field with the Thole-damped dipole part; grad_E (n x 9, row-major 3 x 3,
+   grad_E[a][b] = d_a E_b) gradient of E_damped. */
+pfmm_status pfmm_field(pfmm_handle* h, int64_t n, const double* pos, const double* q,
+                       const double* mu, const double* alpha, double* phi, double* E,
+                       double* E_damped, double* grad_E, void* stream);
+
+/* Static description of a status code. */
+const char* pfmm_status_string(pfmm_status s);
+
+/* Message for the last failure on h ("" if none); valid until the next call on h. */
+const char* pfmm_last_error(const pfmm_handle* h);
+
+/* Library version string. */
+const char* pfmm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PFMM_H */

@@ -325,3 +325,32 @@ def energy_only(X, q, alpha, thole_a=2.0, k_e=COULOMB_K):
     phi_q, _, _ = charge_fields(X, q, want_grad=False)
     mu = solve_dipoles_dense(X, q, alpha, thole_a, E_q=E_q)
     return k_e * (0.5 * np.sum(np.asarray(q) * phi_q) - 0.5 * np.sum(mu * E_q))
+
+
+def fields_at(idx, X, q=None, mu=None, alpha=None, thole_a=2.0):
+    """Exact fields at the particles listed in idx from every other particle (sampled targets).
+
+    Returns phi (undamped), E_u (undamped dipole part), E_d (damped dipole part) and G_d = d_a (E_d)_b,
+    each restricted to the targets in idx.  Used to check large systems on a sample of outputs.
+    """
+    X = np.asarray(X, np.float64)
+    n = X.shape[0]
+    q = np.zeros(n) if q is None else np.asarray(q, np.float64)
+    mu = np.zeros((n, 3)) if mu is None else np.asarray(mu, np.float64)
+    alpha = np.zeros(n) if alpha is None else np.asarray(alpha, np.float64)
+    idx = np.asarray(idx)
+    m = idx.size
+    phi = np.zeros(m); Eu = np.zeros((m, 3)); Ed = np.zeros((m, 3)); Gd = np.zeros((m, 3, 3))
+    for k, i in enumerate(idx):
+        mask = np.arange(n) != i
+        rv = X[i] - X[mask]
+        g, grad, H, T3 = hessian_and_third(rv)
+        s = thole_radius(alpha[i], alpha[mask], thole_a)
+        _, _, Hd, T3d = hessian_and_third(rv, s)
+        qs = q[mask]; ms = mu[mask]
+        phi[k] = np.sum(qs * g) - np.sum(ms * grad)
+        Eq = -np.sum(qs[:, None] * grad, axis=0)
+        Eu[k] = Eq + np.einsum("jab,jb->a", H, ms)
+        Ed[k] = Eq + np.einsum("jab,jb->a", Hd, ms)
+        Gd[k] = -np.sum(qs[:, None, None] * H, axis=0) + np.einsum("jabc,jc->ab", T3d, ms)
+    return phi, Eu, Ed, Gd

@@ -1,0 +1,217 @@
+"""Python interface of the pfmm library: argument marshalling only.
+
+Every step of the computation runs in the HIP kernels of libpfmm.so; this module checks tensor
+types, hands device pointers and PyTorch's current stream to the C interface and wraps the
+results.  Tensors must be float64, contiguous and on the current HIP device.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass, field
+
+import torch
+
+from . import _lib
+from ._lib import lib
+
+__all__ = ["PFMMError", "Solver", "SolveResult", "solve", "field_eval", "PolarizableEnergy", "config"]
+
+
+class PFMMError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        self.status = status
+        self.code = _lib.STATUS.get(status, str(status))
+        super().__init__(f"{self.code}: {message}")
+
+
+def config(**kw) -> _lib.Config:
+    """A pfmm_config with the library defaults, overridden by keyword arguments.
+
+    Keywords: order_p, ws, leaf_width, precision ("fp64" | "mixed"), scf_tol, scf_max_iter,
+    graph_iters, thole_a, coulomb_k, forces (bool), potentials (bool), save_for_backward (bool),
+    warm_start (bool), timing (bool).
+    """
+    c = _lib.Config()
+    lib.pfmm_config_default(ctypes.byref(c))
+    prec = kw.pop("precision", None)
+    if prec is not None:
+        c.precision = {"fp64": _lib.PFMM_FP64, "mixed": _lib.PFMM_MIXED}[prec] if isinstance(prec, str) else int(prec)
+    flagmap = {"forces": _lib.PFMM_WANT_FORCES, "potentials": _lib.PFMM_WANT_POTENTIALS,
+               "save_for_backward": _lib.PFMM_SAVE_FOR_BACKWARD, "warm_start": _lib.PFMM_WARM_START,
+               "timing": _lib.PFMM_TIMING}
+    for k, bit in flagmap.items():
+        if k in kw:
+            if kw.pop(k):
+                c.flags |= bit
+            else:
+                c.flags &= ~bit
+    for k, v in kw.items():
+        if not hasattr(c, k):
+            raise TypeError(f"unknown pfmm option {k!r}")
+        setattr(c, k, type(getattr(c, k))(v))
+    return c
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _check_tensor(name, t, shape):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.dtype != torch.float64:
+        raise TypeError(f"{name} must be float64, got {t.dtype}")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be on the GPU")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+@dataclass
+class SolveResult:
+    U: float
+    U_qq: float
+    U_pol: float
+    mu: torch.Tensor
+    forces: torch.Tensor | None
+    phi: torch.Tensor | None
+    iters: int
+    residual: float
+    residual_max_debye: float
+    stats: dict = field(default_factory=dict)
+
+
+class Solver:
+    """Owns one pfmm handle (device tables and workspace) for a fixed configuration."""
+
+    def __init__(self, **kw):
+        if not torch.cuda.is_available():
+            raise RuntimeError("pfmm needs a GPU (HIP device); none is available")
+        self.cfg = config(**kw)
+        h = ctypes.c_void_p()
+        st = lib.pfmm_create(ctypes.byref(self.cfg), ctypes.byref(h))
+        if st != 0:
+            raise PFMMError(st, "pfmm_create failed: " + lib.pfmm_status_string(st).decode())
+        self._h = h
+        self.last_result = None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.pfmm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _raise(self, st):
+        raise PFMMError(st, lib.pfmm_last_error(self._h).decode())
+
+    def solve(self, pos, q, alpha, mu_init=None, allow_unconverged=False) -> SolveResult:
+        n = pos.shape[0]
+        _check_tensor("pos", pos, (n, 3))
+        _check_tensor("q", q, (n,))
+        _check_tensor("alpha", alpha, (n,))
+        want_f = bool(self.cfg.flags & _lib.PFMM_WANT_FORCES)
+        want_p = bool(self.cfg.flags & _lib.PFMM_WANT_POTENTIALS)
+        mu = torch.empty((n, 3), dtype=torch.float64, device=pos.device)
+        if self.cfg.flags & _lib.PFMM_WARM_START:
+            if mu_init is None:
+                raise ValueError("warm_start needs mu_init")
+            _check_tensor("mu_init", mu_init, (n, 3))
+            mu.copy_(mu_init)
+        F = torch.empty((n, 3), dtype=torch.float64, device=pos.device) if want_f else None
+        phi = torch.empty((n,), dtype=torch.float64, device=pos.device) if want_p else None
+        res = _lib.Result()
+        st = lib.pfmm_solve(self._h, n, _ptr(pos), _ptr(q), _ptr(alpha), _ptr(mu), _ptr(F), _ptr(phi),
+                            ctypes.byref(res), _stream())
+        if st != 0 and not (allow_unconverged and st == 4):
+            self._raise(st)
+        self.last_result = res
+        self._n_last = n
+        stats = dict(levels=res.levels, leaf_width=res.leaf_width, n_leaves=res.n_leaves,
+                     n_cells=res.n_cells, n_m2l=res.n_m2l, n_p2p=res.n_p2p, n_evals=res.n_evals,
+                     t_phase_ms=list(res.t_phase_ms), status=_lib.STATUS[st])
+        return SolveResult(res.U_total, res.U_qq, res.U_pol, mu, F, phi, res.iters, res.residual,
+                           res.residual_max_debye, stats)
+
+    def backward(self, g=1.0, want_pos=True, want_q=True, want_alpha=True, n=None):
+        n = n if n is not None else self._n_last
+        dev = torch.device("cuda", torch.cuda.current_device())
+        gp = torch.empty((n, 3), dtype=torch.float64, device=dev) if want_pos else None
+        gq = torch.empty((n,), dtype=torch.float64, device=dev) if want_q else None
+        ga = torch.empty((n,), dtype=torch.float64, device=dev) if want_alpha else None
+        st = lib.pfmm_backward(self._h, float(g), _ptr(gp), _ptr(gq), _ptr(ga), _stream())
+        if st != 0:
+            self._raise(st)
+        return gp, gq, ga
+
+    def field(self, pos, q=None, mu=None, alpha=None):
+        """phi, E (undamped dipole part), E_damped and grad E_damped (n x 3 x 3) of the sources."""
+        n = pos.shape[0]
+        _check_tensor("pos", pos, (n, 3))
+        if q is not None:
+            _check_tensor("q", q, (n,))
+        if mu is not None:
+            _check_tensor("mu", mu, (n, 3))
+        if alpha is None:
+            alpha = torch.zeros(n, dtype=torch.float64, device=pos.device)
+        _check_tensor("alpha", alpha, (n,))
+        phi = torch.empty(n, dtype=torch.float64, device=pos.device)
+        E = torch.empty((n, 3), dtype=torch.float64, device=pos.device)
+        Ed = torch.empty((n, 3), dtype=torch.float64, device=pos.device)
+        G = torch.empty((n, 3, 3), dtype=torch.float64, device=pos.device)
+        st = lib.pfmm_field(self._h, n, _ptr(pos), _ptr(q), _ptr(mu), _ptr(alpha), _ptr(phi), _ptr(E),
+                            _ptr(Ed), _ptr(G), _stream())
+        if st != 0:
+            self._raise(st)
+        return phi, E, Ed, G
+
+
+def solve(pos, q, alpha, **kw) -> SolveResult:
+    """One-shot polarizable solve: dipoles, energies, forces and potentials."""
+    s = Solver(**kw)
+    try:
+        return s.solve(pos, q, alpha)
+    finally:
+        s.close()
+
+
+def field_eval(pos, q=None, mu=None, alpha=None, **kw):
+    s = Solver(**kw)
+    try:
+        return s.field(pos, q, mu, alpha)
+    finally:
+        s.close()
+
+
+class PolarizableEnergy(torch.autograd.Function):
+    """U(pos, q, alpha) = U^{qq'} + U^pol at the converged dipoles, differentiable in all three inputs.
+
+    The backward uses the stationarity of U^pol in the dipoles, so the dipole solve itself is not
+    differentiated; gradients of mu or of the forces are not available through this function.
+    """
+
+    @staticmethod
+    def forward(ctx, pos, q, alpha, solver: Solver):
+        pos_c, q_c, a_c = pos.detach().contiguous(), q.detach().contiguous(), alpha.detach().contiguous()
+        res = solver.solve(pos_c, q_c, a_c)
+        ctx.solver = solver
+        ctx.n = pos.shape[0]
+        ctx.mark_non_differentiable()
+        return torch.tensor(res.U, dtype=torch.float64, device=pos.device)
+
+    @staticmethod
+    def backward(ctx, gU):
+        g = float(gU.item())
+        gp, gq, ga = ctx.solver.backward(g, ctx.needs_input_grad[0], ctx.needs_input_grad[1],
+                                         ctx.needs_input_grad[2], n=ctx.n)
+        return gp, gq, ga, None

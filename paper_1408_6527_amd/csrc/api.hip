@@ -1,0 +1,660 @@
+// C interface and host orchestration of the pfmm library (declarations in include/pfmm.h).
+//
+// A solve runs the three stages of Sec. III on one device stream:
+//   tree      bounding box, Morton sort, cells, colleagues, M2L tiles          (tree.hip, m2l.hip)
+//   stage 1   field of the charges: phi^q, E^q, grad E^q                       (one FMM pass)
+//   stage 2   conjugate gradients on (I - S T~ S) y = S E^q, one FMM pass of the
+//             dipoles per iteration                                             (solver.hip)
+//   stage 3   field of the converged dipoles, energy, forces, un-permutation
+// An FMM pass is P2M -> M2M (up) -> M2L -> L2L (down) -> L2P, plus P2P over colleague leaves.
+#include <algorithm>
+#include <chrono>
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "kernels.hpp"
+#include "tables.hpp"
+
+using namespace pfmm;
+
+namespace {
+
+constexpr int NRED = 7;  // bbox partial width (tree.hip)
+constexpr double EANG_TO_DEBYE = 4.80320;
+
+struct HostPinned {
+  void* p = nullptr;
+  size_t bytes = 0;
+  ~HostPinned() { if (p) (void)hipHostFree(p); }
+  void* get(size_t b) {
+    if (b > bytes) {
+      if (p) (void)hipHostFree(p);
+      p = nullptr;
+      PFMM_HIP(hipHostMalloc(&p, b, hipHostMallocDefault));
+      bytes = b;
+    }
+    return p;
+  }
+};
+
+}  // namespace
+
+struct pfmm_handle {
+  pfmm_config cfg{};
+  HostTables tab;
+  OpTables op;
+  int device = 0;
+  // constant tables
+  DevBuf t_mi, t_p2m, t_ifact, t_l2p, t_m2m_ptr, t_m2m_col, t_m2m_val, t_l2l_ptr, t_l2l_col, t_l2l_val, t_code,
+      t_kpack, t_kpack32;
+  // tree workspace
+  DevBuf w_partial, w_flags, w_bbox, w_keys_in, w_keys, w_vals_in, w_perm, w_sort_tmp, w_scan_tmp,
+      w_lvl_flags, w_cid, w_counts, w_ckey, w_cfirst, w_ccount, w_cparent, w_child8, w_coll, w_okeys,
+      w_ovals, w_okeys2, w_tgt, w_octcnt, w_list, w_stats;
+  // particles
+  DevBuf w_P, w_al, w_sqa, w_tau, w_itau, w_mu4;
+  // expansions
+  DevBuf w_M, w_F;
+  // fields (sorted order)
+  DevBuf f_phiq, f_Eq, f_Eq2, f_Gq, f_phim, f_Eum, f_Edm, f_Gm, f_E;
+  // solver
+  DevBuf cg_y, cg_r, cg_p, cg_Ap, w_red, w_state, w_ep, w_dal;
+  // saved for backward
+  DevBuf s_F, s_phi, s_Etot;
+  bool saved = false;
+  int saved_n = 0;
+  HostPinned pinned;
+  std::string err;
+  TreeView tv;
+  Particles pa;
+  int ntgt = 0, ntiles = 0;
+  int64_t n_m2l = 0, n_p2p = 0;
+  int n_evals = 0;
+};
+
+namespace {
+
+template <class T>
+T* dev(DevBuf& b, int64_t count) {
+  return static_cast<T*>(b.reserve((size_t)std::max<int64_t>(count, 1) * sizeof(T)));
+}
+
+template <class T>
+void upload(DevBuf& b, const std::vector<T>& v) {
+  T* p = dev<T>(b, (int64_t)v.size());
+  if (!v.empty()) PFMM_HIP(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+}
+
+void sync_read(pfmm_handle* h, const void* dsrc, void* hdst, size_t bytes, hipStream_t s) {
+  void* pin = h->pinned.get(bytes);
+  PFMM_HIP(hipMemcpyAsync(pin, dsrc, bytes, hipMemcpyDeviceToHost, s));
+  PFMM_HIP(hipStreamSynchronize(s));
+  std::memcpy(hdst, pin, bytes);
+}
+
+void validate_config(const pfmm_config* c) {
+  if (!c) throw Error(PFMM_ERR_INVALID_ARG, "config is NULL");
+  if (c->order_p < 1 || c->order_p > MAX_P) throw Error(PFMM_ERR_INVALID_ARG, "order_p must be in 1..10");
+  if (c->ws < 1 || c->ws > 2) throw Error(PFMM_ERR_INVALID_ARG, "ws must be 1 or 2");
+  if (!(c->leaf_width >= 0.0) || !std::isfinite(c->leaf_width))
+    throw Error(PFMM_ERR_INVALID_ARG, "leaf_width must be >= 0");
+  if (c->precision != PFMM_FP64 && c->precision != PFMM_MIXED)
+    throw Error(PFMM_ERR_INVALID_ARG, "precision must be PFMM_FP64 or PFMM_MIXED");
+  if (!(c->scf_tol > 0.0)) throw Error(PFMM_ERR_INVALID_ARG, "scf_tol must be > 0");
+  if (c->scf_max_iter < 1) throw Error(PFMM_ERR_INVALID_ARG, "scf_max_iter must be >= 1");
+  if (c->graph_iters < 0) throw Error(PFMM_ERR_INVALID_ARG, "graph_iters must be >= 0");
+  if (!(c->thole_a >= 0.0) || !std::isfinite(c->thole_a))
+    throw Error(PFMM_ERR_INVALID_ARG, "thole_a must be >= 0");
+  if (!std::isfinite(c->coulomb_k)) throw Error(PFMM_ERR_INVALID_ARG, "coulomb_k must be finite");
+}
+
+// ------------------------------------------------------------------------------------------------
+// Tree build.  Leaves h->tv / h->pa describing the sorted particles and the octree.
+// ------------------------------------------------------------------------------------------------
+void build_tree(pfmm_handle* h, int n, const double* pos, const double* q, const double* alpha,
+                hipStream_t s) {
+  const pfmm_config& c = h->cfg;
+  const int nblk = std::min(1024, std::max(1, (n + 255) / 256));
+  double* partial = dev<double>(h->w_partial, (int64_t)nblk * NRED);
+  int* flags = dev<int>(h->w_flags, 4);
+  double* bbox = dev<double>(h->w_bbox, NRED);
+  launch_fill_int(flags, 4, 0, s);
+  launch_scan_inputs(pos, q, alpha, n, partial, nblk, flags, s);
+  launch_bbox_final(partial, nblk, bbox, s);
+  struct { double bb[NRED]; int fl[4]; } hb;
+  // two small readbacks share one synchronisation
+  void* pin = h->pinned.get(sizeof(hb));
+  PFMM_HIP(hipMemcpyAsync(pin, bbox, NRED * sizeof(double), hipMemcpyDeviceToHost, s));
+  PFMM_HIP(hipMemcpyAsync((char*)pin + offsetof(decltype(hb), fl), flags, 4 * sizeof(int),
+                          hipMemcpyDeviceToHost, s));
+  PFMM_HIP(hipStreamSynchronize(s));
+  std::memcpy(&hb, pin, sizeof(hb));
+  if (hb.fl[0] & 1) throw Error(PFMM_ERR_NONFINITE, "non-finite position, charge or polarizability");
+  if (hb.fl[0] & 2) throw Error(PFMM_ERR_INVALID_ARG, "negative polarizability");
+
+  double lo[3], hi[3], cen[3], extent = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = hb.bb[a];
+    hi[a] = hb.bb[3 + a];
+    cen[a] = (lo[a] + hi[a]) * 0.5;
+    extent = std::max(extent, hi[a] - lo[a]);
+  }
+  const double alpha_max = hb.bb[6];
+  const double s_max = c.thole_a * std::cbrt(alpha_max);  // a (alpha_max^2)^(1/6)
+  double w = c.leaf_width;
+  if (w == 0.0) {
+    double vol = 1.0;
+    for (int a = 0; a < 3; ++a) vol *= std::max(hi[a] - lo[a], 1.0);
+    const double occ = c.ws == 1 ? 24.0 : 12.0;
+    w = std::cbrt(occ * vol / std::max(n, 1));
+    w = std::max(w, 1.0001 * s_max / c.ws);
+    w = std::max(w, 1e-3);
+  }
+  if (s_max > c.ws * w)
+    throw Error(PFMM_ERR_INVALID_ARG,
+                "Thole damping radius " + std::to_string(s_max) + " exceeds the near-field range ws * leaf_width = " +
+                    std::to_string(c.ws * w) + "; increase leaf_width or ws");
+  int L = 0;
+  while (w * std::ldexp(1.0, L) < extent * (1.0 + std::ldexp(1.0, -20))) {
+    ++L;
+    if (L > MAX_LEVELS) throw Error(PFMM_ERR_INVALID_ARG, "leaf_width too small for the extent (more than 21 levels)");
+  }
+  const double side = w * std::ldexp(1.0, L);
+  double origin[3];
+  for (int a = 0; a < 3; ++a) origin[a] = cen[a] - side * 0.5;
+
+  // Morton keys and sort
+  uint64_t* keys_in = dev<uint64_t>(h->w_keys_in, n);
+  uint64_t* keys = dev<uint64_t>(h->w_keys, n);
+  int* vals_in = dev<int>(h->w_vals_in, n);
+  int* perm = dev<int>(h->w_perm, n);
+  launch_morton(pos, n, origin, w, L, keys_in, vals_in, s);
+  if (L > 0) {
+    size_t tb = sort_temp_bytes(n, 3 * L);
+    void* tmp = h->w_sort_tmp.reserve(tb);
+    launch_sort(tmp, tb, keys_in, keys, vals_in, perm, n, 3 * L, s);
+  } else {
+    PFMM_HIP(hipMemcpyAsync(keys, keys_in, (size_t)n * 8, hipMemcpyDeviceToDevice, s));
+    PFMM_HIP(hipMemcpyAsync(perm, vals_in, (size_t)n * 4, hipMemcpyDeviceToDevice, s));
+  }
+  double4* P = dev<double4>(h->w_P, n);
+  double* al = dev<double>(h->w_al, n);
+  double* sqa = dev<double>(h->w_sqa, n);
+  double* tau = dev<double>(h->w_tau, n);
+  double* itau = dev<double>(h->w_itau, n);
+  launch_gather(perm, pos, q, alpha, n, std::sqrt(c.thole_a), P, al, sqa, tau, itau, s);
+
+  // level cells
+  int* lflags = dev<int>(h->w_lvl_flags, n);
+  int* cid = dev<int>(h->w_cid, (int64_t)n * (L + 1));
+  int* counts = dev<int>(h->w_counts, L + 2);
+  size_t sb = scan_temp_bytes(n);
+  void* stmp = h->w_scan_tmp.reserve(sb);
+  for (int l = 0; l <= L; ++l)
+    launch_level_scan(keys, n, 3 * (L - l), lflags, cid + (int64_t)l * n, counts + l, stmp, sb, s);
+  std::vector<int> cnt(L + 1);
+  sync_read(h, counts, cnt.data(), sizeof(int) * (L + 1), s);
+
+  TreeView& t = h->tv;
+  t = TreeView();
+  t.L = L;
+  t.off[0] = 0;
+  for (int l = 0; l <= L; ++l) t.off[l + 1] = t.off[l] + cnt[l];
+  t.ncell = t.off[L + 1];
+  for (int a = 0; a < 3; ++a) t.origin[a] = origin[a];
+  t.w = w;
+  t.ws = c.ws;
+  t.nnear = h->tab.nnear;
+  const int ncell = t.ncell;
+  uint64_t* ckey = dev<uint64_t>(h->w_ckey, ncell);
+  int* cfirst = dev<int>(h->w_cfirst, ncell);
+  int* ccount = dev<int>(h->w_ccount, ncell);
+  int* cparent = dev<int>(h->w_cparent, ncell);
+  int* child8 = dev<int>(h->w_child8, (int64_t)ncell * 8);
+  int* coll = dev<int>(h->w_coll, (int64_t)ncell * t.nnear);
+  launch_fill_int(child8, (int64_t)ncell * 8, -1, s);
+  for (int l = 0; l <= L; ++l) {
+    launch_cells(keys, n, L, l, cid + (int64_t)l * n, l > 0 ? cid + (int64_t)(l - 1) * n : nullptr,
+                 t.off[l], l > 0 ? t.off[l - 1] : 0, ckey, cfirst, cparent, child8, s);
+    launch_cell_counts(cfirst, t.off[l], cnt[l], n, ccount, s);
+    launch_colleagues(ckey, t.off[l], cnt[l], l, c.ws, coll, s);
+  }
+  t.key = ckey; t.first = cfirst; t.count = ccount; t.parent = cparent; t.child8 = child8; t.coll = coll;
+
+  Particles& pa = h->pa;
+  pa.n = n; pa.P = P; pa.alpha = al; pa.sqa = sqa; pa.tau = tau; pa.itau = itau;
+
+  // M2L targets grouped by octant, and the per-tile source lists
+  h->ntgt = L >= 2 ? ncell - t.off[2] : 0;
+  h->ntiles = 0;
+  unsigned long long* stats = dev<unsigned long long>(h->w_stats, 2);
+  PFMM_HIP(hipMemsetAsync(stats, 0, 2 * sizeof(unsigned long long), s));
+  int* octcnt = dev<int>(h->w_octcnt, 8);
+  launch_fill_int(octcnt, 8, 0, s);
+  if (h->ntgt > 0) {
+    int* okeys = dev<int>(h->w_okeys, h->ntgt);
+    int* ovals = dev<int>(h->w_ovals, h->ntgt);
+    int* okeys2 = dev<int>(h->w_okeys2, h->ntgt);
+    int* tgt = dev<int>(h->w_tgt, h->ntgt);
+    launch_octant_keys(t, okeys, ovals, octcnt, s);
+    size_t ob = octsort_temp_bytes(h->ntgt);
+    void* otmp = h->w_sort_tmp.reserve(std::max(ob, h->w_sort_tmp.bytes));
+    launch_octant_sort(otmp, ob, okeys, okeys2, ovals, tgt, h->ntgt, s);
+    h->ntiles = m2l_max_tiles(h->ntgt);
+    int* list = dev<int>(h->w_list, (int64_t)h->ntiles * h->op.noff * 16);
+    launch_m2l_list(t, h->op, tgt, octcnt, h->ntiles, list, s);
+    launch_tree_stats(t, h->op.m2l_code, h->op.noff, stats, s);
+  } else {
+    launch_tree_stats(t, h->op.m2l_code, h->op.noff, stats, s);
+  }
+  // expansions (one extra zero row serves empty M2L sources)
+  const int64_t rows = (int64_t)ncell + 1;
+  double* M = dev<double>(h->w_M, rows * h->op.stride);
+  dev<double>(h->w_F, rows * h->op.stride);
+  launch_fill_double(M + (int64_t)ncell * h->op.stride, h->op.stride, 0.0, s);
+  unsigned long long st[2];
+  sync_read(h, stats, st, sizeof(st), s);
+  h->n_m2l = (int64_t)st[0];
+  h->n_p2p = (int64_t)st[1];
+  h->n_evals = 0;
+}
+
+// One FMM evaluation: sources 1 = charges, 2 = dipoles (mu4), 3 = both.
+// mode 0: Ed only; mode 1: phi, Eu, Ed, G.
+void fmm_pass(pfmm_handle* h, int sources, int mode, FieldOut out, int* err, const int* done,
+              hipStream_t s) {
+  const TreeView& t = h->tv;
+  const OpTables& op = h->op;
+  const bool fp32 = h->cfg.precision == PFMM_MIXED;
+  const int n = h->pa.n;
+  double* M = h->w_M.as<double>();
+  double* F = h->w_F.as<double>();
+  const double4* mu4 = h->w_mu4.as<double4>();
+  if (t.L >= 2) {
+    launch_p2m(t, op, h->pa, mu4, sources, M, done, s);
+    for (int lp = t.L - 1; lp >= 2; --lp) launch_m2m(t, op, lp, M, done, s);
+    launch_m2l(t, op, h->w_tgt.as<int>(), h->w_octcnt.as<int>(), h->ntgt, h->w_list.as<int>(), M, F,
+               fp32, 3, done, s);
+    for (int lc = 3; lc <= t.L; ++lc) launch_l2l(t, op, lc, F, done, s);
+    launch_l2p(t, op, h->pa, F, mode, out, done, s);
+  } else {
+    launch_fill_double(out.Ed, 3 * (int64_t)n, 0.0, s);
+    if (mode == 1) {
+      launch_fill_double(out.phi, n, 0.0, s);
+      launch_fill_double(out.Eu, 3 * (int64_t)n, 0.0, s);
+      launch_fill_double(out.G, 6 * (int64_t)n, 0.0, s);
+    }
+  }
+  launch_p2p(t, h->pa, mu4, mode == 0 ? 0 : 1, sources, fp32, out, nullptr, err, done, s);
+  h->n_evals += 1;
+}
+
+struct Timer {
+  bool on;
+  hipStream_t s;
+  hipEvent_t ev[8];
+  int k = 0;
+  Timer(bool on_, hipStream_t s_) : on(on_), s(s_) {
+    if (on)
+      for (auto& e : ev) PFMM_HIP(hipEventCreate(&e));
+  }
+  ~Timer() {
+    if (on)
+      for (auto& e : ev) (void)hipEventDestroy(e);
+  }
+  void mark() {
+    if (on && k < 8) PFMM_HIP(hipEventRecord(ev[k++], s));
+  }
+  void fill(double* out) {
+    if (!on) return;
+    PFMM_HIP(hipEventSynchronize(ev[k - 1]));
+    for (int i = 0; i + 1 < k && i < 5; ++i) {
+      float ms = 0;
+      PFMM_HIP(hipEventElapsedTime(&ms, ev[i], ev[i + 1]));
+      out[i] = ms;
+    }
+    float tot = 0;
+    PFMM_HIP(hipEventElapsedTime(&tot, ev[0], ev[k - 1]));
+    out[5] = tot;
+  }
+};
+
+pfmm_status fail(pfmm_handle* h, const Error& e) {
+  if (h) h->err = e.what();
+  return e.status;
+}
+
+void check_flag(pfmm_handle* h, int* dflag, hipStream_t s) {
+  int f = 0;
+  sync_read(h, dflag, &f, sizeof(int), s);
+  if (f) throw Error(PFMM_ERR_COINCIDENT, "two particles share the same position");
+}
+
+pfmm_status solve_impl(pfmm_handle* h, int64_t n64, const double* pos, const double* q,
+                       const double* alpha, double* mu, double* forces, double* phi, pfmm_result* res,
+                       hipStream_t s) {
+  const pfmm_config& c = h->cfg;
+  if (n64 < 0 || n64 > INT_MAX / 8) throw Error(PFMM_ERR_INVALID_ARG, "n out of range");
+  if (!res) throw Error(PFMM_ERR_INVALID_ARG, "res is NULL");
+  std::memset(res, 0, sizeof(*res));
+  h->saved = false;
+  const int n = (int)n64;
+  const bool want_f = (c.flags & PFMM_WANT_FORCES) != 0;
+  const bool want_phi = (c.flags & PFMM_WANT_POTENTIALS) != 0;
+  if (n > 0 && (!pos || !q || !alpha || !mu)) throw Error(PFMM_ERR_INVALID_ARG, "NULL input or mu");
+  if (n > 0 && want_f && !forces) throw Error(PFMM_ERR_INVALID_ARG, "forces is NULL with PFMM_WANT_FORCES");
+  if (n > 0 && want_phi && !phi) throw Error(PFMM_ERR_INVALID_ARG, "phi is NULL with PFMM_WANT_POTENTIALS");
+  if (n == 0) return PFMM_OK;
+  PFMM_HIP(hipGetDevice(&h->device));
+
+  Timer tm((c.flags & PFMM_TIMING) != 0, s);
+  tm.mark();
+  if ((c.flags & PFMM_WARM_START) != 0) {
+    int* fl = dev<int>(h->w_flags, 4);
+    launch_fill_int(fl, 1, 0, s);
+    launch_check_finite(mu, 3 * n64, fl, s);
+    int f = 0;
+    sync_read(h, fl, &f, sizeof(int), s);
+    if (f) throw Error(PFMM_ERR_NONFINITE, "non-finite warm-start dipole");
+  }
+  build_tree(h, n, pos, q, alpha, s);
+  tm.mark();
+  const Particles& pa = h->pa;
+  double4* mu4 = dev<double4>(h->w_mu4, n);
+  int* err = dev<int>(h->w_flags, 4);
+  launch_fill_int(err, 4, 0, s);
+
+  // stage 1: field of the charges
+  double* phiq = dev<double>(h->f_phiq, n);
+  double* Eq = dev<double>(h->f_Eq, 3 * (int64_t)n);
+  double* Eq2 = dev<double>(h->f_Eq2, 3 * (int64_t)n);
+  double* Gq = dev<double>(h->f_Gq, 6 * (int64_t)n);
+  fmm_pass(h, 1, 1, FieldOut{phiq, Eq, Eq2, Gq}, err, nullptr, s);
+  check_flag(h, err, s);
+  tm.mark();
+
+  // stage 2: conjugate gradients
+  double* y = dev<double>(h->cg_y, 3 * (int64_t)n);
+  double* r = dev<double>(h->cg_r, 3 * (int64_t)n);
+  double* pv = dev<double>(h->cg_p, 3 * (int64_t)n);
+  double* Ap = dev<double>(h->cg_Ap, 3 * (int64_t)n);
+  double* E = dev<double>(h->f_E, 3 * (int64_t)n);
+  double* part = dev<double>(h->w_red, RED_BLOCKS * 8);
+  CGState* st = static_cast<CGState*>(h->w_state.reserve(sizeof(CGState)));
+  const bool warm = (c.flags & PFMM_WARM_START) != 0;
+  if (warm) launch_permute_dipoles(h->w_perm.as<int>(), n, mu, pa.tau, mu4, s);
+  launch_cg_init(pa, Eq, mu4, warm, y, pv, mu4, part, st, s);
+  FieldOut fo{nullptr, nullptr, E, nullptr};
+  fmm_pass(h, 2, 0, fo, err, nullptr, s);
+  launch_cg_residual0(pa, Eq, E, y, r, pv, part, st, c.scf_tol, s);
+  const int* done = &st->done;
+  const int chunk = c.graph_iters > 0 ? c.graph_iters : 4;
+  CGState hs{};
+  sync_read(h, st, &hs, sizeof(hs), s);
+  int launched = 0;
+  while (!hs.done && launched < c.scf_max_iter) {
+    for (int k = 0; k < chunk && launched < c.scf_max_iter; ++k, ++launched) {
+      launch_make_dipoles(pa, pv, mu4, done, s);
+      fmm_pass(h, 2, 0, fo, err, done, s);
+      launch_cg_ap(pa, pv, E, Ap, part, st, s);
+      launch_cg_update(pa, y, r, pv, Ap, part, st, c.scf_tol, c.scf_max_iter, s);
+      launch_cg_direction(3 * n, r, pv, st, s);
+    }
+    sync_read(h, st, &hs, sizeof(hs), s);
+  }
+  tm.mark();
+
+  // stage 3: field of the converged dipoles, energy and forces
+  launch_make_dipoles(pa, y, mu4, nullptr, s);
+  double* phim = dev<double>(h->f_phim, n);
+  double* Eum = dev<double>(h->f_Eum, 3 * (int64_t)n);
+  double* Edm = dev<double>(h->f_Edm, 3 * (int64_t)n);
+  double* Gm = dev<double>(h->f_Gm, 6 * (int64_t)n);
+  fmm_pass(h, 2, 1, FieldOut{phim, Eum, Edm, Gm}, err, nullptr, s);
+  tm.mark();
+  double* Fs = dev<double>(h->s_F, 3 * (int64_t)n);
+  double* phs = dev<double>(h->s_phi, n);
+  double* Ets = dev<double>(h->s_Etot, 3 * (int64_t)n);
+  EnergyParts* ep = static_cast<EnergyParts*>(h->w_ep.reserve(sizeof(EnergyParts)));
+  launch_assemble(pa, h->w_perm.as<int>(), mu4, phiq, Eq, Gq, phim, Eum, Edm, Gm, c.coulomb_k, mu,
+                  want_f ? forces : nullptr, want_phi ? phi : nullptr, Fs, phs, Ets, part, ep, s);
+  tm.mark();
+  EnergyParts he{};
+  sync_read(h, ep, &he, sizeof(he), s);
+  tm.fill(res->t_phase_ms);
+
+  const double ke = c.coulomb_k;
+  res->U_qq = ke * he.Uqq;
+  res->U_pol = ke * (he.Amu - he.muEq - 0.5 * he.muEd);
+  res->U_total = res->U_qq + res->U_pol;
+  res->iters = hs.iters;
+  res->residual = he.bn2 > 0.0 ? std::sqrt(he.res2 / he.bn2) : 0.0;
+  res->residual_max_debye = he.resmax * EANG_TO_DEBYE;
+  res->levels = h->tv.L;
+  res->leaf_width = h->tv.w;
+  res->n_leaves = h->tv.off[h->tv.L + 1] - h->tv.off[h->tv.L];
+  res->n_cells = h->tv.ncell;
+  res->n_m2l = h->n_m2l;
+  res->n_p2p = h->n_p2p;
+  res->n_evals = h->n_evals;
+  h->saved = true;
+  h->saved_n = n;
+  if (hs.notspd) throw Error(PFMM_ERR_NOT_SPD, "conjugate gradients met p.Ap <= 0: the dipole system is not positive definite");
+  if (!hs.done || (hs.maxed && hs.res > c.scf_tol))
+    throw Error(PFMM_ERR_NOT_CONVERGED, "dipole solve did not converge: residual " + std::to_string(hs.res) +
+                                            " after " + std::to_string(hs.iters) + " iterations");
+  return PFMM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void pfmm_config_default(pfmm_config* c) {
+  if (!c) return;
+  c->order_p = 6;
+  c->ws = 2;
+  c->leaf_width = 0.0;
+  c->precision = PFMM_FP64;
+  c->scf_tol = 1e-6;
+  c->scf_max_iter = 200;
+  c->graph_iters = 4;
+  c->thole_a = 2.0;
+  c->coulomb_k = 332.06371;
+  c->flags = PFMM_WANT_FORCES | PFMM_WANT_POTENTIALS | PFMM_SAVE_FOR_BACKWARD;
+}
+
+pfmm_status pfmm_create(const pfmm_config* cfg, pfmm_handle** out) {
+  if (!out) return PFMM_ERR_INVALID_ARG;
+  *out = nullptr;
+  pfmm_handle* h = nullptr;
+  try {
+    validate_config(cfg);
+    h = new pfmm_handle();
+    h->cfg = *cfg;
+    h->tab.build(cfg->order_p, cfg->ws);
+    const HostTables& T = h->tab;
+    upload(h->t_mi, T.mi);
+    upload(h->t_p2m, T.p2m_coef);
+    upload(h->t_ifact, T.inv_fact);
+    upload(h->t_l2p, T.l2p_tab);
+    upload(h->t_m2m_ptr, T.m2m_ptr); upload(h->t_m2m_col, T.m2m_col); upload(h->t_m2m_val, T.m2m_val);
+    upload(h->t_l2l_ptr, T.l2l_ptr); upload(h->t_l2l_col, T.l2l_col); upload(h->t_l2l_val, T.l2l_val);
+    upload(h->t_code, T.m2l_code);
+    upload(h->t_kpack, T.kpack);
+    if (cfg->precision == PFMM_MIXED) {
+      std::vector<float> k32(T.kpack.begin(), T.kpack.end());
+      upload(h->t_kpack32, k32);
+    }
+    OpTables& op = h->op;
+    op.p = T.p; op.nc = T.nc; op.stride = T.stride;
+    op.mi = h->t_mi.as<int>();
+    op.p2m_coef = h->t_p2m.as<double>();
+    op.inv_fact = h->t_ifact.as<double>();
+    op.l2p_tab = h->t_l2p.as<int>();
+    op.m2m_ptr = h->t_m2m_ptr.as<int>(); op.m2m_col = h->t_m2m_col.as<int>(); op.m2m_val = h->t_m2m_val.as<double>();
+    op.l2l_ptr = h->t_l2l_ptr.as<int>(); op.l2l_col = h->t_l2l_col.as<int>(); op.l2l_val = h->t_l2l_val.as<double>();
+    op.m2l_code = h->t_code.as<int>();
+    op.noff = T.noff;
+    op.kpack = h->t_kpack.as<double>();
+    op.kpack32 = cfg->precision == PFMM_MIXED ? h->t_kpack32.as<float>() : nullptr;
+    op.nblocks = T.nblocks;
+    PFMM_HIP(hipGetDevice(&h->device));
+    *out = h;
+    return PFMM_OK;
+  } catch (const Error& e) {
+    delete h;
+    return e.status;
+  } catch (const std::bad_alloc&) {
+    delete h;
+    return PFMM_ERR_OOM;
+  }
+}
+
+void pfmm_destroy(pfmm_handle* h) { delete h; }
+
+pfmm_status pfmm_solve(pfmm_handle* h, int64_t n, const double* pos, const double* q, const double* alpha,
+                       double* mu, double* forces, double* phi, pfmm_result* res, void* stream) {
+  if (!h) return PFMM_ERR_INVALID_ARG;
+  h->err.clear();
+  try {
+    return solve_impl(h, n, pos, q, alpha, mu, forces, phi, res, (hipStream_t)stream);
+  } catch (const Error& e) {
+    return fail(h, e);
+  } catch (const std::bad_alloc&) {
+    h->err = "host allocation failed";
+    return PFMM_ERR_OOM;
+  }
+}
+
+pfmm_status pfmm_backward(pfmm_handle* h, double g, double* grad_pos, double* grad_q, double* grad_alpha,
+                          void* stream) {
+  if (!h) return PFMM_ERR_INVALID_ARG;
+  h->err.clear();
+  try {
+    if (!h->saved || !(h->cfg.flags & PFMM_SAVE_FOR_BACKWARD))
+      throw Error(PFMM_ERR_NO_STATE, "pfmm_backward needs a preceding successful pfmm_solve with PFMM_SAVE_FOR_BACKWARD");
+    if (!std::isfinite(g)) throw Error(PFMM_ERR_NONFINITE, "non-finite upstream gradient");
+    hipStream_t s = (hipStream_t)stream;
+    const int n = h->saved_n;
+    if (n == 0) return PFMM_OK;
+    double* dal = nullptr;
+    if (grad_alpha && h->cfg.thole_a > 0.0) {
+      dal = dev<double>(h->w_dal, n);
+      launch_p2p(h->tv, h->pa, h->w_mu4.as<double4>(), 2, 2, false, FieldOut{}, dal, nullptr, nullptr, s);
+    }
+    launch_backward(h->pa, h->w_perm.as<int>(), h->w_mu4.as<double4>(), h->s_F.as<double>(),
+                    h->s_phi.as<double>(), h->s_Etot.as<double>(), dal, h->cfg.coulomb_k, g, grad_pos,
+                    grad_q, grad_alpha, s);
+    return PFMM_OK;
+  } catch (const Error& e) {
+    return fail(h, e);
+  }
+}
+
+pfmm_status pfmm_field(pfmm_handle* h, int64_t n64, const double* pos, const double* q, const double* mu,
+                       const double* alpha, double* phi, double* E, double* E_damped, double* grad_E,
+                       void* stream) {
+  if (!h) return PFMM_ERR_INVALID_ARG;
+  h->err.clear();
+  try {
+    hipStream_t s = (hipStream_t)stream;
+    if (n64 < 0 || n64 > INT_MAX / 8) throw Error(PFMM_ERR_INVALID_ARG, "n out of range");
+    h->saved = false;
+    const int n = (int)n64;
+    if (n == 0) return PFMM_OK;
+    if (!pos || !alpha) throw Error(PFMM_ERR_INVALID_ARG, "NULL positions or polarizabilities");
+    build_tree(h, n, pos, q, alpha, s);
+    double4* mu4 = dev<double4>(h->w_mu4, n);
+    int* err = dev<int>(h->w_flags, 4);
+    launch_fill_int(err, 4, 0, s);
+    if (mu) {
+      launch_check_finite(mu, 3 * n64, err + 1, s);
+      launch_permute_dipoles(h->w_perm.as<int>(), n, mu, h->pa.tau, mu4, s);
+    }
+    const int sources = (q ? 1 : 0) | (mu ? 2 : 0);
+    double* ph = dev<double>(h->f_phim, n);
+    double* Eu = dev<double>(h->f_Eum, 3 * (int64_t)n);
+    double* Ed = dev<double>(h->f_Edm, 3 * (int64_t)n);
+    double* G = dev<double>(h->f_Gm, 6 * (int64_t)n);
+    FieldOut fo{ph, Eu, Ed, G};
+    if (sources == 0) {
+      launch_fill_double(ph, n, 0.0, s);
+      launch_fill_double(Eu, 3 * n64, 0.0, s);
+      launch_fill_double(Ed, 3 * n64, 0.0, s);
+      launch_fill_double(G, 6 * n64, 0.0, s);
+    } else {
+      fmm_pass(h, sources, 1, fo, err, nullptr, s);
+    }
+    int flags[2];
+    sync_read(h, err, flags, sizeof(flags), s);
+    if (flags[1]) throw Error(PFMM_ERR_NONFINITE, "non-finite dipole");
+    if (flags[0]) throw Error(PFMM_ERR_COINCIDENT, "two particles share the same position");
+    launch_unpermute_field(h->w_perm.as<int>(), n, fo, phi, E, E_damped, grad_E, s);
+    PFMM_HIP(hipStreamSynchronize(s));
+    return PFMM_OK;
+  } catch (const Error& e) {
+    return fail(h, e);
+  }
+}
+
+const char* pfmm_status_string(pfmm_status s) {
+  switch (s) {
+    case PFMM_OK: return "ok";
+    case PFMM_ERR_INVALID_ARG: return "invalid argument";
+    case PFMM_ERR_NONFINITE: return "non-finite input";
+    case PFMM_ERR_COINCIDENT: return "coincident particles";
+    case PFMM_ERR_NOT_CONVERGED: return "dipole solve did not converge";
+    case PFMM_ERR_NOT_SPD: return "dipole system not positive definite";
+    case PFMM_ERR_OOM: return "out of memory";
+    case PFMM_ERR_HIP: return "HIP runtime error";
+    case PFMM_ERR_NO_STATE: return "no saved state for backward";
+  }
+  return "unknown status";
+}
+
+const char* pfmm_last_error(const pfmm_handle* h) { return h ? h->err.c_str() : ""; }
+
+const char* pfmm_version(void) { return "pfmm 0.1.0 (gfx950)"; }
+
+}  // extern "C"
+
+// ------------------------------------------------------------------------------------------------
+// Internal inspection hook for tests and debugging (not part of the public interface): device
+// pointer and size of a named workspace buffer of the last tree build / evaluation.
+// ------------------------------------------------------------------------------------------------
+extern "C" int pfmm_internal_buffer(pfmm_handle* h, const char* name, void** ptr, int64_t* bytes) {
+  if (!h || !name || !ptr || !bytes) return PFMM_ERR_INVALID_ARG;
+  const std::string s(name);
+  const TreeView& t = h->tv;
+  const int64_t rows = (int64_t)t.ncell + 1;
+  struct Item { const char* n; const DevBuf* b; int64_t size; };
+  const Item items[] = {
+      {"M", &h->w_M, rows * h->op.stride * 8}, {"F", &h->w_F, rows * h->op.stride * 8},
+      {"ckey", &h->w_ckey, (int64_t)t.ncell * 8}, {"cfirst", &h->w_cfirst, (int64_t)t.ncell * 4},
+      {"ccount", &h->w_ccount, (int64_t)t.ncell * 4}, {"cparent", &h->w_cparent, (int64_t)t.ncell * 4},
+      {"child8", &h->w_child8, (int64_t)t.ncell * 32}, {"coll", &h->w_coll, (int64_t)t.ncell * t.nnear * 4},
+      {"tgt", &h->w_tgt, (int64_t)h->ntgt * 4}, {"octcnt", &h->w_octcnt, 32},
+      {"list", &h->w_list, (int64_t)h->ntiles * h->op.noff * 16 * 4}, {"perm", &h->w_perm, (int64_t)h->pa.n * 4},
+      {"P", &h->w_P, (int64_t)h->pa.n * 32}};
+  for (const auto& it : items)
+    if (s == it.n) {
+      *ptr = it.b->ptr;
+      *bytes = it.size;
+      return PFMM_OK;
+    }
+  if (s == "tree") {  // host copy of the level offsets and geometry: int L, int ncell, int off[23], double origin[3], double w
+    static thread_local char buf[4 + 4 + 4 * (MAX_LEVELS + 2) + 8 * 4];
+    std::memcpy(buf, &t.L, 4);
+    std::memcpy(buf + 4, &t.ncell, 4);
+    std::memcpy(buf + 8, t.off, 4 * (MAX_LEVELS + 2));
+    std::memcpy(buf + 8 + 4 * (MAX_LEVELS + 2), t.origin, 24);
+    std::memcpy(buf + 8 + 4 * (MAX_LEVELS + 2) + 24, &t.w, 8);
+    *ptr = buf;
+    *bytes = sizeof(buf);
+    return PFMM_OK;
+  }
+  return PFMM_ERR_INVALID_ARG;
+}

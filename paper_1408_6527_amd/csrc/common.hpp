@@ -1,0 +1,66 @@
+// Shared host/device helpers of the pfmm library: error handling, device buffers, small math.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+
+#include "../../include/pfmm.h"
+
+namespace pfmm {
+
+// Internal exception carrying a status code; converted to a return value at the C boundary.
+struct Error : public std::runtime_error {
+  pfmm_status status;
+  Error(pfmm_status s, const std::string& m) : std::runtime_error(m), status(s) {}
+};
+
+#define PFMM_HIP(call)                                                                      \
+  do {                                                                                      \
+    hipError_t e_ = (call);                                                                 \
+    if (e_ != hipSuccess)                                                                   \
+      throw ::pfmm::Error(e_ == hipErrorOutOfMemory ? PFMM_ERR_OOM : PFMM_ERR_HIP,          \
+                          std::string(#call) + ": " + hipGetErrorString(e_));               \
+  } while (0)
+
+#define PFMM_LAUNCH_CHECK() PFMM_HIP(hipGetLastError())
+
+// A device allocation that only grows.  Contents are not preserved across growth.
+struct DevBuf {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (ptr) (void)hipFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+  }
+  void* reserve(size_t want) {
+    if (want == 0) want = 256;
+    if (want > bytes) {
+      release();
+      size_t b = want + want / 4;
+      hipError_t e = hipMalloc(&ptr, b);
+      if (e != hipSuccess) {
+        ptr = nullptr;
+        throw Error(PFMM_ERR_OOM, "device allocation of " + std::to_string(b) + " bytes failed");
+      }
+      bytes = b;
+    }
+    return ptr;
+  }
+  template <class T>
+  T* as() const { return static_cast<T*>(ptr); }
+};
+
+inline int ncoef(int p) { return (p + 1) * (p + 2) * (p + 3) / 6; }
+inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
+inline int64_t div_up(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+}  // namespace pfmm

@@ -1,0 +1,157 @@
+// Launchers of the HIP kernels of the pfmm library (one translation unit per group).
+// Every launcher enqueues on the given stream and checks the launch; none synchronises.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "common.hpp"
+
+namespace pfmm {
+
+constexpr int MAX_LEVELS = 21;  // 63-bit Morton keys
+constexpr int MAX_P = 10;
+
+// Device view of the octree.  Cells of all levels live in one array, level by level; inside a
+// level they are in Morton order, so each cell's particles are a contiguous range of the sorted
+// particle arrays and each cell's children are contiguous in the next level.
+struct TreeView {
+  int L = 0;                       // leaf level
+  int ncell = 0;                   // cells on all levels
+  int off[MAX_LEVELS + 2] = {0};   // first cell of each level; off[L + 1] = ncell
+  double origin[3] = {0, 0, 0};
+  double w = 1.0;                  // leaf edge
+  int ws = 1, nnear = 1;
+  const uint64_t* key = nullptr;   // cell key at its own level (3 bits per level)
+  const int* first = nullptr;      // first sorted particle
+  const int* count = nullptr;      // particles in the cell
+  const int* parent = nullptr;     // global index of the parent, -1 at the root
+  const int* child8 = nullptr;     // 8 global child indices per cell (octant order), -1 if empty
+  const int* coll = nullptr;       // nnear colleagues per cell (offset order), -1 if empty
+};
+
+// Particle arrays in sorted (Morton) order.
+struct Particles {
+  int n = 0;
+  const double4* P = nullptr;      // x, y, z, q
+  const double* alpha = nullptr;   // polarisability
+  const double* sqa = nullptr;     // sqrt(alpha)
+  const double* tau = nullptr;     // sqrt(thole_a) * alpha^(1/6): s_ij = tau_i tau_j
+  const double* itau = nullptr;    // 1 / tau, 0 where tau = 0 (no damping)
+};
+
+// Field outputs in sorted order (any may be null when not requested by the mode).
+struct FieldOut {
+  double* phi = nullptr;  // n
+  double* Eu = nullptr;   // 3n, field with undamped dipole part
+  double* Ed = nullptr;   // 3n, field with damped dipole part
+  double* G = nullptr;    // 6n, d_a (Ed)_b as xx, yy, zz, xy, xz, yz
+};
+
+// ---------------------------------------------------------------- tree.hip
+void launch_scan_inputs(const double* pos, const double* q, const double* alpha, int n,
+                        double* partial, int nblk, int* flags, hipStream_t s);
+void launch_bbox_final(const double* partial, int nblk, double* bbox, hipStream_t s);
+void launch_morton(const double* pos, int n, const double origin[3], double w, int L,
+                   uint64_t* keys, int* vals, hipStream_t s);
+size_t sort_temp_bytes(int n, int end_bit);
+void launch_sort(void* tmp, size_t tmp_bytes, const uint64_t* kin, uint64_t* kout, const int* vin,
+                 int* vout, int n, int end_bit, hipStream_t s);
+void launch_gather(const int* perm, const double* pos, const double* q, const double* alpha, int n,
+                   double sqrt_a, double4* P, double* al, double* sqa, double* tau, double* itau,
+                   hipStream_t s);
+size_t scan_temp_bytes(int n);
+// cid[i] = 1 + index (within the level) of the cell holding sorted particle i (inclusive scan of
+// the cell-head flags); *count_out = cells on the level.
+void launch_level_scan(const uint64_t* keys, int n, int shift, int* flags, int* cid, int* count_out,
+                       void* tmp, size_t tmp_bytes, hipStream_t s);
+void launch_fill_int(int* p, int64_t count, int value, hipStream_t s);
+void launch_fill_double(double* p, int64_t count, double value, hipStream_t s);
+void launch_cells(const uint64_t* keys, int n, int L, int l, const int* cid_l, const int* cid_parent,
+                  int off_l, int off_parent, uint64_t* ckey, int* cfirst, int* cparent, int* child8,
+                  hipStream_t s);
+void launch_cell_counts(const int* cfirst, int off_l, int ncell_l, int n, int* ccount, hipStream_t s);
+void launch_colleagues(const uint64_t* ckey, int off_l, int ncell_l, int l, int ws, int* coll,
+                       hipStream_t s);
+void launch_tree_stats(const TreeView& t, const int* m2l_code, int noff, unsigned long long* stats,
+                       hipStream_t s);
+
+// ---------------------------------------------------------------- expansions.hip
+struct OpTables {
+  int p = 0, nc = 0, stride = 0;
+  const int* mi = nullptr;
+  const double* p2m_coef = nullptr;
+  const double* inv_fact = nullptr;
+  const int* l2p_tab = nullptr;  // 16 ints per coefficient: nx ny nz |n|, n+e_c (3), n+e_a+e_b (6), pad
+  const int* m2m_ptr = nullptr; const int* m2m_col = nullptr; const double* m2m_val = nullptr;
+  const int* l2l_ptr = nullptr; const int* l2l_col = nullptr; const double* l2l_val = nullptr;
+  const int* m2l_code = nullptr; int noff = 0;
+  const double* kpack = nullptr; const float* kpack32 = nullptr; int nblocks = 0;
+};
+// sources: 1 = charges (P.w), 2 = dipoles (mu4), 3 = both
+void launch_p2m(const TreeView& t, const OpTables& op, const Particles& pa, const double4* mu4,
+                int sources, double* M, const int* done, hipStream_t s);
+void launch_m2m(const TreeView& t, const OpTables& op, int parent_level, double* M, const int* done,
+                hipStream_t s);
+void launch_l2l(const TreeView& t, const OpTables& op, int child_level, double* F, const int* done,
+                hipStream_t s);
+// mode 0: Ed only (written, not added); mode 1: phi, Eu, Ed, G written
+void launch_l2p(const TreeView& t, const OpTables& op, const Particles& pa, const double* F, int mode,
+                FieldOut out, const int* done, hipStream_t s);
+
+// ---------------------------------------------------------------- m2l.hip
+// Targets: every cell of level >= 2, grouped by octant (tgt_list), oct_count[8] targets per octant,
+// cut into wave tiles of 16; list holds the source cell of every (tile, offset, column).
+int m2l_max_tiles(int ntgt);
+void launch_m2l_list(const TreeView& t, const OpTables& op, const int* tgt_list, const int* oct_count,
+                     int ntiles, int* list, hipStream_t s);
+void launch_m2l(const TreeView& t, const OpTables& op, const int* tgt_list, const int* oct_count,
+                int ntgt, const int* list, const double* M, double* F, bool fp32, int fp64_max_level,
+                const int* done, hipStream_t s);
+void launch_octant_keys(const TreeView& t, int* keys, int* vals, int* oct_count, hipStream_t s);
+size_t octsort_temp_bytes(int n);
+void launch_octant_sort(void* tmp, size_t bytes, const int* kin, int* kout, const int* vin, int* vout,
+                        int n, hipStream_t s);
+
+// ---------------------------------------------------------------- p2p.hip
+// mode 0: dipole sources, Ed only (added); mode 1: full outputs (added) from charges and/or dipoles
+// (sources bit 1 = charges, bit 2 = dipoles); mode 2: Thole term of dU/dalpha (written to dal).
+void launch_p2p(const TreeView& t, const Particles& pa, const double4* mu4, int mode, int sources,
+                bool fp32, FieldOut out, double* dal, int* err, const int* done, hipStream_t s);
+
+// ---------------------------------------------------------------- solver.hip
+struct CGState {
+  double rr, pAp, a, b, bnorm2, res, res_true, res_max;
+  int done, iters, notspd, maxed;
+};
+constexpr int RED_BLOCKS = 512;   // partial sums per reduction
+void launch_cg_init(const Particles& pa, const double* Eq, const double4* mu_warm, bool warm,
+                    double* y, double* pvec, double4* mu4, double* part, CGState* st, hipStream_t s);
+void launch_cg_residual0(const Particles& pa, const double* Eq, const double* E, double* y,
+                         double* r, double* pvec, double* part, CGState* st, double tol,
+                         hipStream_t s);
+void launch_make_dipoles(const Particles& pa, const double* v, double4* mu4, const int* done,
+                         hipStream_t s);
+void launch_cg_ap(const Particles& pa, const double* pvec, const double* E, double* Ap, double* part,
+                  CGState* st, hipStream_t s);
+void launch_cg_update(const Particles& pa, double* y, double* r, const double* pvec, const double* Ap,
+                      double* part, CGState* st, double tol, int max_iter, hipStream_t s);
+void launch_cg_direction(int n3, const double* r, double* pvec, const CGState* st, hipStream_t s);
+
+struct EnergyParts { double Uqq, Amu, muEq, muEd, res2, bn2, resmax; };
+void launch_assemble(const Particles& pa, const int* perm, const double4* mu4, const double* phiq,
+                     const double* Eq, const double* Gq, const double* phim, const double* Eum,
+                     const double* Edm, const double* Gm, double k_e, double* mu_out,
+                     double* F_out, double* phi_out, double* F_s, double* phi_s, double* Etot_s,
+                     double* part, EnergyParts* ep, hipStream_t s);
+void launch_backward(const Particles& pa, const int* perm, const double4* mu4, const double* F_s,
+                     const double* phi_s, const double* Etot_s, const double* dal_thole, double k_e,
+                     double g, double* gpos, double* gq, double* galpha, hipStream_t s);
+void launch_unpermute_field(const int* perm, int n, const FieldOut& src, double* phi, double* E,
+                            double* Ed, double* G9, hipStream_t s);
+void launch_permute_dipoles(const int* perm, int n, const double* mu_in, const double* tau,
+                            double4* mu4, hipStream_t s);
+void launch_check_finite(const double* v, int64_t count, int* flags, hipStream_t s);
+
+}  // namespace pfmm

@@ -1,0 +1,202 @@
+// Near field by direct summation over neighbouring leaves (the direct component of Sec. III),
+// with true point dipoles and Thole damping of dipole-dipole pairs.
+//
+// One wavefront per target leaf.  The wave walks the leaf's colleagues (Chebyshev distance <= ws);
+// each colleague's particles are staged in LDS 64 at a time and every lane (one target particle)
+// sweeps the staged sources, reading them as LDS broadcasts.  Results are added to the far-field
+// values already written by L2P.
+//
+// Pair kernels, with r = x_i - x_j, u = r/|r|:
+//   charge  q_j:  phi += q/r,  E += q r/r^3,  d_a E_b += q (delta_ab/r^3 - 3 r_a r_b/r^5)
+//   dipole mu_j:  phi += mu.r/r^3 (undamped),  E_u += (3 u (u.mu) - mu)/r^3 (undamped),
+//                 E_d += (3 f_t u (u.mu) - f_e mu)/r^3,
+//                 d_a (E_d)_b += A u_a u_b (u.mu)/r^4 + B (delta_ab (u.mu) + u_a mu_b + u_b mu_a)/r^4
+// where, for the Thole linear model with v = min(r/s, 1), s = a (alpha_i alpha_j)^(1/6):
+//   f_t = v^4, f_e = 4 v^3 - 3 v^4, A = -3 v^4 (v < 1) or -15 (v >= 1), B = 3 v^4.
+// Float32 variant (mixed path): offsets relative to the target leaf centre, float32 arithmetic
+// and accumulation, results added to the float64 fields.
+#include <type_traits>
+
+#include "kernels.hpp"
+#include "morton.hpp"
+
+namespace pfmm {
+
+namespace {
+
+constexpr int TPB = 64;
+
+__device__ inline double rsqrt_t(double x) { return rsqrt(x); }
+__device__ inline float rsqrt_t(float x) { return rsqrtf(x); }
+
+template <typename T, int MODE, int SRC>
+__global__ __launch_bounds__(TPB) void k_p2p(TreeView t, Particles pa, const double4* __restrict__ mu4,
+                                             FieldOut out, double* __restrict__ dal,
+                                             int* __restrict__ err, const int* done) {
+  if (done && *done) return;
+  constexpr bool HQ = (SRC & 1) != 0;
+  constexpr bool HM = (SRC & 2) != 0;
+  __shared__ T sx[TPB], sy[TPB], sz[TPB], sq[TPB], smx[TPB], smy[TPB], smz[TPB], sit[TPB];
+  __shared__ int sidx[TPB];
+  const int g = t.off[t.L] + blockIdx.x;
+  const int first = t.first[g], cnt = t.count[g];
+  const int lane = threadIdx.x;
+  double cen[3];
+  {
+    const uint64_t k = t.key[g];
+    cen[0] = t.origin[0] + ((double)compact3(k >> 2) + 0.5) * t.w;
+    cen[1] = t.origin[1] + ((double)compact3(k >> 1) + 0.5) * t.w;
+    cen[2] = t.origin[2] + ((double)compact3(k) + 0.5) * t.w;
+  }
+  for (int t0 = 0; t0 < cnt; t0 += TPB) {
+    const int li = t0 + lane;
+    const bool active = li < cnt;
+    const int i = first + (active ? li : 0);
+    const double4 Pi = pa.P[i];
+    const T xi = (T)(Pi.x - cen[0]), yi = (T)(Pi.y - cen[1]), zi = (T)(Pi.z - cen[2]);
+    const T iti = (T)pa.itau[i];
+    double4 mui = make_double4(0, 0, 0, 0);
+    if (MODE == 2) mui = mu4[i];
+    T phi = 0, eux = 0, euy = 0, euz = 0, edx = 0, edy = 0, edz = 0;
+    T gxx = 0, gyy = 0, gzz = 0, gxy = 0, gxz = 0, gyz = 0;
+    double dsum = 0.0;
+    int bad = 0;
+    for (int k = 0; k < t.nnear; ++k) {
+      const int A = t.coll[(int64_t)g * t.nnear + k];
+      if (A < 0) continue;
+      const int sf = t.first[A], sc = t.count[A];
+      for (int s0 = 0; s0 < sc; s0 += TPB) {
+        const int m = min(TPB, sc - s0);
+        __syncthreads();
+        if (lane < m) {
+          const int j = sf + s0 + lane;
+          const double4 Pj = pa.P[j];
+          sx[lane] = (T)(Pj.x - cen[0]);
+          sy[lane] = (T)(Pj.y - cen[1]);
+          sz[lane] = (T)(Pj.z - cen[2]);
+          sq[lane] = (T)Pj.w;
+          if (HM || MODE == 2) {
+            const double4 u = mu4[j];
+            smx[lane] = (T)u.x; smy[lane] = (T)u.y; smz[lane] = (T)u.z;
+          }
+          sit[lane] = (T)pa.itau[j];
+          sidx[lane] = j;
+        }
+        __syncthreads();
+        if (!active) continue;
+        for (int jj = 0; jj < m; ++jj) {
+          const T rx = xi - sx[jj], ry = yi - sy[jj], rz = zi - sz[jj];
+          const T r2 = rx * rx + ry * ry + rz * rz;
+          const bool valid = r2 > T(0);
+          if (MODE == 1 && !valid && sidx[jj] != i) bad = 1;
+          const T rinv = valid ? rsqrt_t(valid ? r2 : T(1)) : T(0);
+          const T rinv2 = rinv * rinv;
+          const T rinv3 = rinv * rinv2;
+          if (MODE == 1 && HQ) {
+            const T qj = sq[jj];
+            const T qr3 = qj * rinv3;
+            phi += qj * rinv;
+            const T ex = qr3 * rx, ey = qr3 * ry, ez = qr3 * rz;
+            eux += ex; euy += ey; euz += ez;
+            edx += ex; edy += ey; edz += ez;
+            const T c5 = T(3) * qr3 * rinv2;
+            gxx += qr3 - c5 * rx * rx; gyy += qr3 - c5 * ry * ry; gzz += qr3 - c5 * rz * rz;
+            gxy -= c5 * rx * ry; gxz -= c5 * rx * rz; gyz -= c5 * ry * rz;
+          }
+          if (MODE == 2) {
+            // Thole term of dU/dalpha_i: (2 v^4 (mu_i.u)(mu_j.u) - 2 (v^3 - v^4) mu_i.mu_j) / (alpha_i r^3)
+            const T ii = iti * sit[jj];
+            const T rr = r2 * rinv;
+            const T v = ii > T(0) ? fmin(rr * ii, T(1)) : T(1);
+            if (valid && v < T(1)) {
+              const T v3 = v * v * v, v4 = v3 * v;
+              const T miu = (T(mui.x) * rx + T(mui.y) * ry + T(mui.z) * rz) * rinv;
+              const T mju = (smx[jj] * rx + smy[jj] * ry + smz[jj] * rz) * rinv;
+              const T mm = T(mui.x) * smx[jj] + T(mui.y) * smy[jj] + T(mui.z) * smz[jj];
+              dsum += (double)((T(2) * v4 * miu * mju - T(2) * (v3 - v4) * mm) * rinv3);
+            }
+          }
+          if ((MODE == 0 || MODE == 1) && HM) {
+            const T mx = smx[jj], my = smy[jj], mz = smz[jj];
+            const T rmu = rx * mx + ry * my + rz * mz;
+            const T ii = iti * sit[jj];
+            const T rr = r2 * rinv;
+            const T v = ii > T(0) ? fmin(rr * ii, T(1)) : T(1);
+            const T v3 = v * v * v, v4 = v3 * v;
+            const T ft = v4, fe = v3 * (T(4) - T(3) * v);
+            const T c3 = T(3) * ft * rmu * rinv2;
+            edx += (c3 * rx - fe * mx) * rinv3;
+            edy += (c3 * ry - fe * my) * rinv3;
+            edz += (c3 * rz - fe * mz) * rinv3;
+            if (MODE == 1) {
+              phi += rmu * rinv3;
+              const T cu = T(3) * rmu * rinv2;
+              eux += (cu * rx - mx) * rinv3;
+              euy += (cu * ry - my) * rinv3;
+              euz += (cu * rz - mz) * rinv3;
+              const T Ac = (v < T(1)) ? T(-3) * v4 : T(-15);
+              const T Bc = T(3) * v4;
+              const T rinv5 = rinv3 * rinv2;
+              const T a7 = Ac * rmu * rinv5 * rinv2;  // A (u.mu) u_a u_b / r^4 = A rmu r_a r_b / r^7
+              const T b5 = Bc * rinv5;
+              gxx += a7 * rx * rx + b5 * (rmu + T(2) * rx * mx);
+              gyy += a7 * ry * ry + b5 * (rmu + T(2) * ry * my);
+              gzz += a7 * rz * rz + b5 * (rmu + T(2) * rz * mz);
+              gxy += a7 * rx * ry + b5 * (rx * my + ry * mx);
+              gxz += a7 * rx * rz + b5 * (rx * mz + rz * mx);
+              gyz += a7 * ry * rz + b5 * (ry * mz + rz * my);
+            }
+          }
+        }
+      }
+    }
+    if (!active) continue;
+    if (bad) atomicOr(err, 1);
+    if (MODE == 0) {
+      out.Ed[3 * i] += (double)edx; out.Ed[3 * i + 1] += (double)edy; out.Ed[3 * i + 2] += (double)edz;
+    } else if (MODE == 1) {
+      out.phi[i] += (double)phi;
+      out.Eu[3 * i] += (double)eux; out.Eu[3 * i + 1] += (double)euy; out.Eu[3 * i + 2] += (double)euz;
+      out.Ed[3 * i] += (double)edx; out.Ed[3 * i + 1] += (double)edy; out.Ed[3 * i + 2] += (double)edz;
+      double* G = out.G + 6 * (int64_t)i;
+      G[0] += (double)gxx; G[1] += (double)gyy; G[2] += (double)gzz;
+      G[3] += (double)gxy; G[4] += (double)gxz; G[5] += (double)gyz;
+    } else {
+      const double ai = pa.alpha[i];
+      dal[i] = ai > 0.0 ? dsum / ai : 0.0;
+    }
+  }
+}
+
+template <typename T>
+void p2p_dispatch(const TreeView& t, const Particles& pa, const double4* mu4, int mode, int sources,
+                  FieldOut out, double* dal, int* err, const int* done, hipStream_t s, int nleaf) {
+  if (mode == 0)
+    hipLaunchKernelGGL((k_p2p<T, 0, 2>), dim3(nleaf), dim3(TPB), 0, s, t, pa, mu4, out, dal, err, done);
+  else if (mode == 1 && sources == 1)
+    hipLaunchKernelGGL((k_p2p<T, 1, 1>), dim3(nleaf), dim3(TPB), 0, s, t, pa, mu4, out, dal, err, done);
+  else if (mode == 1 && sources == 2)
+    hipLaunchKernelGGL((k_p2p<T, 1, 2>), dim3(nleaf), dim3(TPB), 0, s, t, pa, mu4, out, dal, err, done);
+  else if (mode == 1 && sources == 3)
+    hipLaunchKernelGGL((k_p2p<T, 1, 3>), dim3(nleaf), dim3(TPB), 0, s, t, pa, mu4, out, dal, err, done);
+  else if (mode == 2)
+    hipLaunchKernelGGL((k_p2p<double, 2, 2>), dim3(nleaf), dim3(TPB), 0, s, t, pa, mu4, out, dal, err,
+                       done);
+  else
+    throw Error(PFMM_ERR_INVALID_ARG, "internal: bad P2P mode");
+}
+
+}  // namespace
+
+void launch_p2p(const TreeView& t, const Particles& pa, const double4* mu4, int mode, int sources,
+                bool fp32, FieldOut out, double* dal, int* err, const int* done, hipStream_t s) {
+  const int nleaf = t.off[t.L + 1] - t.off[t.L];
+  if (nleaf <= 0) return;
+  if (fp32 && mode != 2)
+    p2p_dispatch<float>(t, pa, mu4, mode, sources, out, dal, err, done, s, nleaf);
+  else
+    p2p_dispatch<double>(t, pa, mu4, mode, sources, out, dal, err, done, s, nleaf);
+  PFMM_LAUNCH_CHECK();
+}
+
+}  // namespace pfmm

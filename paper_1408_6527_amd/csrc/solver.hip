@@ -1,0 +1,440 @@
+// Induced-dipole solve, energy/force assembly and the adjoint backward (Sec. II.A and Sec. III).
+//
+// The dipole equation mu = alpha (E^q + T~ mu) is solved in the symmetric scaled form
+//   (I - S T~ S) y = S E^q,   mu = S y,   S = diag(sqrt(alpha)),
+// by conjugate gradients (the paper iterates the dipoles but gives the scheme elsewhere; plain
+// fixed-point iteration diverges at protein densities).  Vectors are float64 in Morton order; dot
+// products are two-stage block reductions in a fixed order, so results are deterministic.  All
+// scalars live on the device (CGState); every kernel of an iteration returns at once when the
+// `done` flag is set, so iterations can be enqueued ahead of the convergence test.
+#include "kernels.hpp"
+
+namespace pfmm {
+
+namespace {
+
+constexpr int TPB = 256;
+
+template <int K>
+__device__ inline void block_sum(double (&v)[K], double* part) {
+  __shared__ double red[K][TPB];
+  for (int k = 0; k < K; ++k) red[k][threadIdx.x] = v[k];
+  __syncthreads();
+  for (int h = TPB / 2; h > 0; h >>= 1) {
+    if (threadIdx.x < h)
+      for (int k = 0; k < K; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x < K) part[blockIdx.x * K + threadIdx.x] = red[threadIdx.x][0];
+}
+
+template <int K>
+__device__ inline void finish_sum(const double* part, int nblk, double (&out)[K]) {
+  __shared__ double red[K][TPB];
+  double v[K];
+  for (int k = 0; k < K; ++k) v[k] = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += TPB)
+    for (int k = 0; k < K; ++k) v[k] += part[b * K + k];
+  for (int k = 0; k < K; ++k) red[k][threadIdx.x] = v[k];
+  __syncthreads();
+  for (int h = TPB / 2; h > 0; h >>= 1) {
+    if (threadIdx.x < h)
+      for (int k = 0; k < K; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + h];
+    __syncthreads();
+  }
+  for (int k = 0; k < K; ++k) out[k] = red[k][0];
+}
+
+#define GRID_STRIDE(i, n) \
+  for (int i = blockIdx.x * TPB + threadIdx.x; i < (n); i += gridDim.x * TPB)
+
+// y0 = S E^q (or the warm start mu0 / S), dipoles for the first matvec, ||alpha E^q||^2.
+// mu_warm may alias mu4 (each thread reads its own entry before writing it).
+__global__ __launch_bounds__(TPB) void k_cg_init(Particles pa, const double* __restrict__ Eq,
+                                                 const double4* mu_warm, int warm,
+                                                 double* __restrict__ y, double* __restrict__ pv,
+                                                 double4* mu4, double* __restrict__ part) {
+  double v[1] = {0.0};
+  GRID_STRIDE(i, pa.n) {
+    const double s = pa.sqa[i], a = pa.alpha[i];
+    double yi[3];
+    for (int c = 0; c < 3; ++c) {
+      const double e = Eq[3 * i + c];
+      v[0] += a * a * e * e;
+      if (warm) {
+        const double m = c == 0 ? mu_warm[i].x : (c == 1 ? mu_warm[i].y : mu_warm[i].z);
+        yi[c] = s > 0.0 ? m / s : 0.0;
+      } else {
+        yi[c] = s * e;
+      }
+      y[3 * i + c] = yi[c];
+      pv[3 * i + c] = yi[c];
+    }
+    mu4[i] = make_double4(s * yi[0], s * yi[1], s * yi[2], pa.tau[i]);
+  }
+  block_sum<1>(v, part);
+}
+
+__global__ __launch_bounds__(TPB) void k_cg_init_finish(const double* part, int nblk, CGState* st) {
+  double o[1];
+  finish_sum<1>(part, nblk, o);
+  if (threadIdx.x == 0) {
+    st->bnorm2 = o[0];
+    st->done = 0; st->iters = 0; st->notspd = 0; st->maxed = 0;
+    st->rr = st->pAp = st->a = st->b = 0.0;
+    st->res = 0.0;
+  }
+}
+
+// r0 = S E^q - (y0 - S E(S y0)); p0 = r0; rr = r.r; residual in dipole units.
+__global__ __launch_bounds__(TPB) void k_cg_res0(Particles pa, const double* __restrict__ Eq,
+                                                 const double* __restrict__ E, double* __restrict__ y,
+                                                 double* __restrict__ r, double* __restrict__ pv,
+                                                 double* __restrict__ part) {
+  double v[2] = {0.0, 0.0};
+  GRID_STRIDE(i, pa.n) {
+    const double s = pa.sqa[i], a = pa.alpha[i];
+    for (int c = 0; c < 3; ++c) {
+      const int k = 3 * i + c;
+      const double rk = s * Eq[k] - (y[k] - s * E[k]);
+      r[k] = rk;
+      pv[k] = rk;
+      v[0] += rk * rk;
+      v[1] += a * rk * rk;
+    }
+  }
+  block_sum<2>(v, part);
+}
+
+__global__ __launch_bounds__(TPB) void k_cg_res0_finish(const double* part, int nblk, CGState* st,
+                                                        double tol) {
+  double o[2];
+  finish_sum<2>(part, nblk, o);
+  if (threadIdx.x == 0) {
+    st->rr = o[0];
+    st->res = st->bnorm2 > 0.0 ? sqrt(o[1] / st->bnorm2) : 0.0;
+    if (st->bnorm2 == 0.0 || st->res <= tol) st->done = 1;
+  }
+}
+
+__global__ __launch_bounds__(TPB) void k_make_dipoles(Particles pa, const double* __restrict__ v,
+                                                      double4* __restrict__ mu4, const int* done) {
+  if (done && *done) return;
+  GRID_STRIDE(i, pa.n) {
+    const double s = pa.sqa[i];
+    mu4[i] = make_double4(s * v[3 * i], s * v[3 * i + 1], s * v[3 * i + 2], pa.tau[i]);
+  }
+}
+
+// Ap = p - S E(S p); partial p.Ap
+__global__ __launch_bounds__(TPB) void k_cg_ap(Particles pa, const double* __restrict__ pv,
+                                               const double* __restrict__ E, double* __restrict__ Ap,
+                                               double* __restrict__ part, const CGState* st) {
+  if (st->done) return;
+  double v[1] = {0.0};
+  GRID_STRIDE(i, pa.n) {
+    const double s = pa.sqa[i];
+    for (int c = 0; c < 3; ++c) {
+      const int k = 3 * i + c;
+      const double a = pv[k] - s * E[k];
+      Ap[k] = a;
+      v[0] += pv[k] * a;
+    }
+  }
+  block_sum<1>(v, part);
+}
+
+__global__ __launch_bounds__(TPB) void k_cg_ap_finish(const double* part, int nblk, CGState* st) {
+  if (st->done) return;
+  double o[1];
+  finish_sum<1>(part, nblk, o);
+  if (threadIdx.x == 0) {
+    st->pAp = o[0];
+    if (!(o[0] > 0.0)) {
+      st->notspd = 1;
+      st->done = 1;
+    } else {
+      st->a = st->rr / o[0];
+    }
+  }
+}
+
+// y += a p; r -= a Ap; partial r.r and sum alpha |r|^2
+__global__ __launch_bounds__(TPB) void k_cg_update(Particles pa, double* __restrict__ y,
+                                                   double* __restrict__ r,
+                                                   const double* __restrict__ pv,
+                                                   const double* __restrict__ Ap,
+                                                   double* __restrict__ part, const CGState* st) {
+  if (st->done) return;
+  const double a = st->a;
+  double v[2] = {0.0, 0.0};
+  GRID_STRIDE(i, pa.n) {
+    const double al = pa.alpha[i];
+    for (int c = 0; c < 3; ++c) {
+      const int k = 3 * i + c;
+      y[k] += a * pv[k];
+      const double rk = r[k] - a * Ap[k];
+      r[k] = rk;
+      v[0] += rk * rk;
+      v[1] += al * rk * rk;
+    }
+  }
+  block_sum<2>(v, part);
+}
+
+__global__ __launch_bounds__(TPB) void k_cg_update_finish(const double* part, int nblk, CGState* st,
+                                                          double tol, int max_iter) {
+  if (st->done) return;
+  double o[2];
+  finish_sum<2>(part, nblk, o);
+  if (threadIdx.x == 0) {
+    st->b = o[0] / st->rr;
+    st->rr = o[0];
+    st->iters += 1;
+    st->res = st->bnorm2 > 0.0 ? sqrt(o[1] / st->bnorm2) : 0.0;
+    if (st->res <= tol) st->done = 1;
+    else if (st->iters >= max_iter) { st->maxed = 1; st->done = 1; }
+  }
+}
+
+__global__ __launch_bounds__(TPB) void k_cg_dir(int n3, const double* __restrict__ r,
+                                                double* __restrict__ pv, const CGState* st) {
+  if (st->done) return;
+  const double b = st->b;
+  GRID_STRIDE(k, n3) pv[k] = r[k] + b * pv[k];
+}
+
+__device__ inline double m3(const double4& u, int c) { return c == 0 ? u.x : (c == 1 ? u.y : u.z); }
+
+// Energies, forces, potentials; outputs un-permuted to the caller's order.
+__global__ __launch_bounds__(TPB) void k_assemble(
+    Particles pa, const int* __restrict__ perm, const double4* __restrict__ mu4,
+    const double* __restrict__ phiq, const double* __restrict__ Eq, const double* __restrict__ Gq,
+    const double* __restrict__ phim, const double* __restrict__ Eum, const double* __restrict__ Edm,
+    const double* __restrict__ Gm, double k_e, double* __restrict__ mu_out, double* __restrict__ F_out,
+    double* __restrict__ phi_out, double* __restrict__ F_s, double* __restrict__ phi_s,
+    double* __restrict__ Etot_s, double* __restrict__ part) {
+  double v[6] = {0, 0, 0, 0, 0, 0};
+  double vmax = 0.0;
+  GRID_STRIDE(i, pa.n) {
+    const int o = perm[i];
+    const double q = pa.P[i].w, a = pa.alpha[i];
+    const double4 u = mu4[i];
+    const double mu[3] = {u.x, u.y, u.z};
+    v[0] += 0.5 * q * phiq[i];
+    double mm = mu[0] * mu[0] + mu[1] * mu[1] + mu[2] * mu[2];
+    if (a > 0.0) v[1] += 0.5 * mm / a;
+    double G[6];
+    for (int k = 0; k < 6; ++k) G[k] = Gq[6 * i + k] + Gm[6 * i + k];
+    // G as xx, yy, zz, xy, xz, yz; (mu.grad) E_b = sum_a mu_a d_a E_b
+    const double gm[3] = {mu[0] * G[0] + mu[1] * G[3] + mu[2] * G[4],
+                          mu[0] * G[3] + mu[1] * G[1] + mu[2] * G[5],
+                          mu[0] * G[4] + mu[1] * G[5] + mu[2] * G[2]};
+    double rl2 = 0.0;
+    for (int c = 0; c < 3; ++c) {
+      const double eq = Eq[3 * i + c], ed = Edm[3 * i + c], eu = Eum[3 * i + c];
+      v[2] += mu[c] * eq;
+      v[3] += mu[c] * ed;
+      const double et = eq + ed;
+      const double rc = a * et - mu[c];
+      rl2 += rc * rc;
+      v[5] += a * a * eq * eq;
+      const double f = k_e * (q * (eq + eu) + gm[c]);
+      if (F_out) F_out[3 * o + c] = f;
+      F_s[3 * i + c] = f;
+      Etot_s[3 * i + c] = et;
+      mu_out[3 * o + c] = mu[c];
+    }
+    v[4] += rl2;
+    vmax = fmax(vmax, sqrt(rl2));
+    const double ph = k_e * (phiq[i] + phim[i]);
+    phi_s[i] = ph;
+    if (phi_out) phi_out[o] = ph;
+  }
+  block_sum<6>(v, part);
+  __shared__ double mx[TPB];
+  mx[threadIdx.x] = vmax;
+  __syncthreads();
+  for (int h = TPB / 2; h > 0; h >>= 1) {
+    if (threadIdx.x < h) mx[threadIdx.x] = fmax(mx[threadIdx.x], mx[threadIdx.x + h]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[gridDim.x * 6 + blockIdx.x] = mx[0];
+}
+
+__global__ __launch_bounds__(TPB) void k_assemble_finish(const double* part, int nblk, EnergyParts* ep) {
+  double o[6];
+  finish_sum<6>(part, nblk, o);
+  __shared__ double mx[TPB];
+  double m = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += TPB) m = fmax(m, part[nblk * 6 + b]);
+  mx[threadIdx.x] = m;
+  __syncthreads();
+  for (int h = TPB / 2; h > 0; h >>= 1) {
+    if (threadIdx.x < h) mx[threadIdx.x] = fmax(mx[threadIdx.x], mx[threadIdx.x + h]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    ep->Uqq = o[0]; ep->Amu = o[1]; ep->muEq = o[2]; ep->muEd = o[3]; ep->res2 = o[4];
+    ep->bn2 = o[5]; ep->resmax = mx[0];
+  }
+}
+
+__global__ __launch_bounds__(TPB) void k_backward(Particles pa, const int* __restrict__ perm,
+                                                  const double4* __restrict__ mu4,
+                                                  const double* __restrict__ F_s,
+                                                  const double* __restrict__ phi_s,
+                                                  const double* __restrict__ Etot_s,
+                                                  const double* __restrict__ dal, double k_e, double g,
+                                                  double* __restrict__ gpos, double* __restrict__ gq,
+                                                  double* __restrict__ ga) {
+  GRID_STRIDE(i, pa.n) {
+    const int o = perm[i];
+    if (gpos)
+      for (int c = 0; c < 3; ++c) gpos[3 * o + c] = -g * F_s[3 * i + c];
+    if (gq) gq[o] = g * phi_s[i];
+    if (ga) {
+      const double a = pa.alpha[i];
+      const double4 u = mu4[i];
+      double d;
+      if (a > 0.0) {
+        d = -(u.x * u.x + u.y * u.y + u.z * u.z) / (2.0 * a * a) + (dal ? dal[i] : 0.0);
+      } else {
+        const double ex = Etot_s[3 * i], ey = Etot_s[3 * i + 1], ez = Etot_s[3 * i + 2];
+        d = -0.5 * (ex * ex + ey * ey + ez * ez);
+      }
+      ga[o] = g * k_e * d;
+    }
+  }
+}
+
+__global__ __launch_bounds__(TPB) void k_unpermute_field(const int* __restrict__ perm, int n,
+                                                         FieldOut src, double* __restrict__ phi,
+                                                         double* __restrict__ E,
+                                                         double* __restrict__ Ed,
+                                                         double* __restrict__ G9) {
+  GRID_STRIDE(i, n) {
+    const int o = perm[i];
+    if (phi) phi[o] = src.phi[i];
+    for (int c = 0; c < 3; ++c) {
+      if (E) E[3 * o + c] = src.Eu[3 * i + c];
+      if (Ed) Ed[3 * o + c] = src.Ed[3 * i + c];
+    }
+    if (G9) {
+      const double* g = src.G + 6 * (int64_t)i;
+      const double full[9] = {g[0], g[3], g[4], g[3], g[1], g[5], g[4], g[5], g[2]};
+      for (int k = 0; k < 9; ++k) G9[9 * (int64_t)o + k] = full[k];
+    }
+  }
+}
+
+__global__ __launch_bounds__(TPB) void k_permute_dipoles(const int* __restrict__ perm, int n,
+                                                         const double* __restrict__ mu,
+                                                         const double* __restrict__ tau,
+                                                         double4* __restrict__ mu4) {
+  GRID_STRIDE(i, n) {
+    const int o = perm[i];
+    mu4[i] = make_double4(mu[3 * o], mu[3 * o + 1], mu[3 * o + 2], tau[i]);
+  }
+}
+
+__global__ __launch_bounds__(TPB) void k_check_finite(const double* __restrict__ v, int64_t count,
+                                                      int* flags) {
+  int f = 0;
+  for (int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x; i < count; i += (int64_t)gridDim.x * TPB)
+    if (!isfinite(v[i])) f = 1;
+  if (f) atomicOr(flags, 1);
+}
+
+inline int grid(int64_t n) {
+  int64_t g = (n + TPB - 1) / TPB;
+  if (g < 1) g = 1;
+  if (g > RED_BLOCKS) g = RED_BLOCKS;
+  return (int)g;
+}
+
+}  // namespace
+
+void launch_cg_init(const Particles& pa, const double* Eq, const double4* mu_warm, bool warm,
+                    double* y, double* pvec, double4* mu4, double* part, CGState* st, hipStream_t s) {
+  const int g = grid(pa.n);
+  hipLaunchKernelGGL(k_cg_init, dim3(g), dim3(TPB), 0, s, pa, Eq, mu_warm, warm ? 1 : 0, y, pvec, mu4,
+                     part);
+  hipLaunchKernelGGL(k_cg_init_finish, dim3(1), dim3(TPB), 0, s, part, g, st);
+  PFMM_LAUNCH_CHECK();
+}
+
+void launch_cg_residual0(const Particles& pa, const double* Eq, const double* E, double* y, double* r,
+                         double* pvec, double* part, CGState* st, double tol, hipStream_t s) {
+  const int g = grid(pa.n);
+  hipLaunchKernelGGL(k_cg_res0, dim3(g), dim3(TPB), 0, s, pa, Eq, E, y, r, pvec, part);
+  hipLaunchKernelGGL(k_cg_res0_finish, dim3(1), dim3(TPB), 0, s, part, g, st, tol);
+  PFMM_LAUNCH_CHECK();
+}
+
+void launch_make_dipoles(const Particles& pa, const double* v, double4* mu4, const int* done,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_make_dipoles, dim3(grid(pa.n)), dim3(TPB), 0, s, pa, v, mu4, done);
+  PFMM_LAUNCH_CHECK();
+}
+
+void launch_cg_ap(const Particles& pa, const double* pvec, const double* E, double* Ap, double* part,
+                  CGState* st, hipStream_t s) {
+  const int g = grid(pa.n);
+  hipLaunchKernelGGL(k_cg_ap, dim3(g), dim3(TPB), 0, s, pa, pvec, E, Ap, part, st);
+  hipLaunchKernelGGL(k_cg_ap_finish, dim3(1), dim3(TPB), 0, s, part, g, st);
+  PFMM_LAUNCH_CHECK();
+}
+
+void launch_cg_update(const Particles& pa, double* y, double* r, const double* pvec, const double* Ap,
+                      double* part, CGState* st, double tol, int max_iter, hipStream_t s) {
+  const int g = grid(pa.n);
+  hipLaunchKernelGGL(k_cg_update, dim3(g), dim3(TPB), 0, s, pa, y, r, pvec, Ap, part, st);
+  hipLaunchKernelGGL(k_cg_update_finish, dim3(1), dim3(TPB), 0, s, part, g, st, tol, max_iter);
+  PFMM_LAUNCH_CHECK();
+}
+
+void launch_cg_direction(int n3, const double* r, double* pvec, const CGState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_dir, dim3(grid(n3)), dim3(TPB), 0, s, n3, r, pvec, st);
+  PFMM_LAUNCH_CHECK();
+}
+
+void launch_assemble(const Particles& pa, const int* perm, const double4* mu4, const double* phiq,
+                     const double* Eq, const double* Gq, const double* phim, const double* Eum,
+                     const double* Edm, const double* Gm, double k_e, double* mu_out, double* F_out,
+                     double* phi_out, double* F_s, double* phi_s, double* Etot_s, double* part,
+                     EnergyParts* ep, hipStream_t s) {
+  const int g = grid(pa.n);
+  hipLaunchKernelGGL(k_assemble, dim3(g), dim3(TPB), 0, s, pa, perm, mu4, phiq, Eq, Gq, phim, Eum, Edm,
+                     Gm, k_e, mu_out, F_out, phi_out, F_s, phi_s, Etot_s, part);
+  hipLaunchKernelGGL(k_assemble_finish, dim3(1), dim3(TPB), 0, s, part, g, ep);
+  PFMM_LAUNCH_CHECK();
+}
+
+void launch_backward(const Particles& pa, const int* perm, const double4* mu4, const double* F_s,
+                     const double* phi_s, const double* Etot_s, const double* dal_thole, double k_e,
+                     double g, double* gpos, double* gq, double* galpha, hipStream_t s) {
+  hipLaunchKernelGGL(k_backward, dim3(grid(pa.n)), dim3(TPB), 0, s, pa, perm, mu4, F_s, phi_s, Etot_s,
+                     dal_thole, k_e, g, gpos, gq, galpha);
+  PFMM_LAUNCH_CHECK();
+}
+
+void launch_unpermute_field(const int* perm, int n, const FieldOut& src, double* phi, double* E,
+                            double* Ed, double* G9, hipStream_t s) {
+  hipLaunchKernelGGL(k_unpermute_field, dim3(grid(n)), dim3(TPB), 0, s, perm, n, src, phi, E, Ed, G9);
+  PFMM_LAUNCH_CHECK();
+}
+
+void launch_permute_dipoles(const int* perm, int n, const double* mu_in, const double* tau,
+                            double4* mu4, hipStream_t s) {
+  hipLaunchKernelGGL(k_permute_dipoles, dim3(grid(n)), dim3(TPB), 0, s, perm, n, mu_in, tau, mu4);
+  PFMM_LAUNCH_CHECK();
+}
+
+void launch_check_finite(const double* v, int64_t count, int* flags, hipStream_t s) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_check_finite, dim3(grid(count)), dim3(TPB), 0, s, v, count, flags);
+  PFMM_LAUNCH_CHECK();
+}
+
+}  // namespace pfmm

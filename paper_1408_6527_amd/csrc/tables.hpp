@@ -1,0 +1,45 @@
+// Constant operator tables of the Cartesian FMM (Sec. II.B), built on the host once per (p, ws)
+// and uploaded to the device.  Every expansion on the device is stored in level-scaled form:
+//   M~_n = M_n / w^|n|,   F~_n = F_n * w^(|n|+1),
+// where w is the edge of the cell's level.  With this scaling the M2L kernel for an offset of
+// d cells is D_{n+m}(d) at unit cell width on every level (homogeneity of 1/r), and the M2M/L2L
+// shifts between a parent and its child in octant o are one of eight constant matrices.
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+#include "common.hpp"
+
+namespace pfmm {
+
+struct HostTables {
+  int p = 0, ws = 0, nc = 0, stride = 0;
+  int nnear = 0;        // (2 ws + 1)^3 colleagues per cell
+  int noff = 0;         // M2L offsets per target octant: (4 ws + 2)^3 - (2 ws + 1)^3
+  int R = 0;            // offsets span [-R, R]^3 with R = 2 ws + 1
+  int nslot = 0;        // (2R + 1)^3 offset slots
+  int nblocks = 0;      // MFMA blocks per offset (schedule.hpp)
+
+  std::vector<int> mi;          // nc x 3 exponents
+  std::vector<double> inv_fact; // nc
+  std::vector<double> p2m_coef; // nc: (-1)^|n| / n!
+  std::vector<int> idx_e;       // nc x 3: index of n + e_c, or -1 (needs |n| <= p - 1)
+  std::vector<int> idx_ee;      // nc x 6: index of n + e_a + e_b for (xx, yy, zz, xy, xz, yz), or -1
+  std::vector<int> l2p_tab;     // nc x 16: nx, ny, nz, |n|, idx_e (3), idx_ee (6), 0 0 0
+  // shift operators in CSR form, one matrix per child octant: out[row] = sum coef * in[col]
+  std::vector<int> m2m_ptr, m2m_col;  std::vector<double> m2m_val;   // 8 x (nc + 1)
+  std::vector<int> l2l_ptr, l2l_col;  std::vector<double> l2l_val;
+  // M2L: for each target octant, noff entries packed as
+  //   slot | (colleague index of the source's parent) << 12 | (source octant) << 20
+  std::vector<int> m2l_code;    // 8 x noff
+  std::vector<double> kpack;    // nslot x nblocks x 64, MFMA operand order (schedule.hpp)
+
+  void build(int p, int ws);
+};
+
+// D_n(d) = d^n (1/|d|) for |n| <= p at an integer offset d, by the Taylor-coefficient recurrence
+// |n| r^2 a_n = -(2|n| - 1) sum_i d_i a_{n - e_i} - (|n| - 1) sum_i a_{n - 2 e_i},  D_n = n! a_n.
+void derivative_tensor_unit(int p, const int* mi, int nc, const int d[3], double* out);
+
+}  // namespace pfmm

@@ -1,0 +1,66 @@
+"""The C interface: every function declared in include/pfmm.h is exported by libpfmm.so, and the
+host-only entry points behave as documented.  No GPU call is made here."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pfmm.h")
+LIB = os.path.join(ROOT, "paper_1408_6527_amd", "libpfmm.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pfmm_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch  # noqa: F401  (same load order as the product path)
+    assert os.path.exists(LIB), "libpfmm.so is not built"
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for f in ["pfmm_config_default", "pfmm_create", "pfmm_destroy", "pfmm_solve", "pfmm_backward",
+              "pfmm_field", "pfmm_status_string", "pfmm_last_error", "pfmm_version"]:
+        assert f in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    missing = [f for f in declared_functions() if not hasattr(lib, f)]
+    assert not missing, missing
+
+
+def test_status_strings_and_defaults(lib):
+    from paper_1408_6527_amd import _lib
+    lib.pfmm_status_string.restype = ctypes.c_char_p
+    for code in range(9):
+        assert lib.pfmm_status_string(code)
+    c = _lib.Config()
+    lib.pfmm_config_default(ctypes.byref(c))
+    assert (c.order_p, c.ws, c.precision, c.scf_max_iter) == (6, 2, 0, 200)
+    assert c.scf_tol == 1e-6 and c.thole_a == 2.0 and c.coulomb_k == 332.06371
+
+
+@pytest.mark.parametrize("field,value", [("order_p", 0), ("order_p", 11), ("ws", 3), ("precision", 5),
+                                         ("scf_tol", 0.0), ("scf_max_iter", 0), ("thole_a", -1.0),
+                                         ("leaf_width", -2.0)])
+def test_create_rejects_bad_config(lib, field, value):
+    from paper_1408_6527_amd import _lib
+    c = _lib.Config()
+    lib.pfmm_config_default(ctypes.byref(c))
+    setattr(c, field, value)
+    h = ctypes.c_void_p()
+    assert lib.pfmm_create(ctypes.byref(c), ctypes.byref(h)) == 1
+    assert not h.value
+
+
+def test_null_handle_is_rejected(lib):
+    lib.pfmm_solve.restype = ctypes.c_int
+    assert lib.pfmm_solve(None, 0, None, None, None, None, None, None, None, None) == 1
+    lib.pfmm_destroy(None)

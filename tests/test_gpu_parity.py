@@ -1,0 +1,331 @@
+"""Parity of the HIP path (through the C interface) with the CPU oracle.
+
+Tolerances (float64 path):
+* one-leaf (direct) mode reproduces the direct sums to rounding: 1e-12 relative to the largest entry;
+* FMM fields reproduce the oracle's FMM (same octree, same operators) to 1e-11 relative to the largest
+  entry: both evaluate the same truncated expansions, only the summation order differs;
+* solves are compared at a tight dipole tolerance, so the SCF error is far below the gate.
+Mixed path: 1e-4 relative force error against the float64 oracle.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import direct as D
+from oracle import fmm as FM
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def api():
+    import torch
+    from paper_1408_6527_amd import api as A
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return A
+
+
+def T(x):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+
+
+def N(t):
+    return t.detach().cpu().numpy()
+
+
+def relmax(a, b):
+    a = np.asarray(a); b = np.asarray(b)
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def relnorm(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def cube(n, side, seed, r_min=1.0):
+    rng = np.random.default_rng(seed)
+    pts = np.empty((0, 3))
+    while pts.shape[0] < n:
+        x = rng.uniform(0, side, (4 * n, 3))
+        for p in x:
+            if pts.shape[0] == 0 or np.min(np.sum((pts - p) ** 2, axis=1)) >= r_min**2:
+                pts = np.vstack([pts, p])
+                if pts.shape[0] == n:
+                    break
+    q = rng.normal(0, 0.5, n)
+    q -= q.mean()
+    a = rng.uniform(0.5, 2.0, n)
+    mu = rng.normal(0, 0.2, (n, 3))
+    return pts, q, a, mu
+
+
+def print_case(name):
+    print(f"[case] {name}", flush=True)
+
+
+# ------------------------------------------------------------------ single evaluation of the field
+
+def test_field_one_leaf_equals_direct_sums(api):
+    print_case("field one leaf n=200")
+    X, q, a, mu = cube(200, 9.0, 1)
+    s = api.Solver(order_p=4, ws=1, leaf_width=50.0, thole_a=2.0)
+    phi, E, Ed, G = s.field(T(X), T(q), T(mu), T(a))
+    pq, Eq, Gq = D.charge_fields(X, q)
+    pm, Eu, Edm, Gd = D.dipole_fields(X, mu, a, 2.0)
+    assert relmax(N(phi), pq + pm) < 1e-12
+    assert relmax(N(E), Eq + Eu) < 1e-12
+    assert relmax(N(Ed), Eq + Edm) < 1e-12
+    assert relmax(N(G), Gq + Gd) < 1e-12
+
+
+@pytest.mark.parametrize("p,ws,lw", [(4, 1, 1.8), (6, 2, 1.8), (8, 2, 1.8), (3, 1, 1.2)])
+def test_field_fmm_matches_oracle_fmm(api, p, ws, lw):
+    print_case(f"field fmm p={p} ws={ws}")
+    X, q, a, mu = cube(600, 13.0, 2)
+    s = api.Solver(order_p=p, ws=ws, leaf_width=lw, thole_a=2.0 if lw * ws > 2.6 else 0.0)
+    thole = 2.0 if lw * ws > 2.6 else 0.0
+    phi, E, Ed, G = s.field(T(X), T(q), T(mu), T(a))
+    ref = FM.fmm_fields(X, q, mu, a, thole, p, lw, ws)
+    assert ref["tree"].L >= 3
+    assert relmax(N(phi), ref["phi"]) < 1e-11
+    assert relmax(N(E), ref["E_u"]) < 1e-11
+    assert relmax(N(Ed), ref["E_d"]) < 1e-11
+    assert relmax(N(G), ref["G_d"]) < 1e-11
+
+
+def test_field_charges_only_and_dipoles_only(api):
+    print_case("field sources split")
+    X, q, a, mu = cube(400, 11.0, 3)
+    s = api.Solver(order_p=5, ws=1, leaf_width=2.7, thole_a=2.0)
+    f_q = s.field(T(X), T(q), None, T(a))
+    f_m = s.field(T(X), None, T(mu), T(a))
+    f_b = s.field(T(X), T(q), T(mu), T(a))
+    for a1, a2, ab in zip(f_q, f_m, f_b):
+        assert relmax(N(a1) + N(a2), N(ab)) < 1e-13
+    ref = FM.fmm_fields(X, q, None, a, 2.0, 5, 2.7, 1)
+    assert relmax(N(f_q[1]), ref["E_u"]) < 1e-11
+
+
+def test_field_crowded_leaves(api):
+    """Leaves holding more than one wavefront of particles (ragged target and source chunks)."""
+    print_case("field crowded leaves")
+    rng = np.random.default_rng(4)
+    # a dense block of 150 particles on a 0.6 A lattice plus a sparse cloud
+    g = np.stack(np.meshgrid(np.arange(6), np.arange(5), np.arange(5), indexing="ij"), -1).reshape(-1, 3) * 0.6
+    X = np.vstack([g + 5.0, rng.uniform(0, 20, (250, 3))])
+    X = X[np.r_[np.ones(150, bool), np.min(np.linalg.norm(X[150:, None] - g[None] - 5.0, axis=2), axis=1) > 0.5]]
+    n = X.shape[0]
+    q = rng.normal(0, 0.5, n); a = np.zeros(n); mu = rng.normal(0, 0.1, (n, 3))
+    s = api.Solver(order_p=4, ws=1, leaf_width=2.6, thole_a=0.0)
+    phi, E, Ed, G = s.field(T(X), T(q), T(mu), T(a))
+    ref = FM.fmm_fields(X, q, mu, a, 0.0, 4, 2.6, 1)
+    counts = [len(v) for v in ref["tree"].leaves.values()]
+    assert max(counts) > 64
+    assert relmax(N(phi), ref["phi"]) < 1e-11
+    assert relmax(N(G), ref["G_d"]) < 1e-11
+
+
+# ------------------------------------------------------------------ full solve
+
+def test_solve_one_leaf_equals_dense_oracle(api):
+    print_case("solve one leaf n=150")
+    X, q, a, _ = cube(150, 8.0, 5)
+    ref = D.solve(X, q, a, thole_a=2.0)
+    s = api.Solver(order_p=4, ws=1, leaf_width=50.0, scf_tol=1e-13, scf_max_iter=300)
+    r = s.solve(T(X), T(q), T(a))
+    assert r.stats["levels"] == 0
+    assert relmax(N(r.mu), ref["mu"]) < 1e-10
+    assert abs(r.U - ref["U"]) < 1e-10 * abs(ref["U"])
+    assert abs(r.U_qq - ref["U_qq"]) < 1e-11 * abs(ref["U_qq"])
+    assert relmax(N(r.forces), ref["F"]) < 1e-10
+    assert relmax(N(r.phi), ref["phi"]) < 1e-10
+    assert r.residual < 1e-12
+
+
+def test_solve_uniform_cube_1k_matches_oracle_fmm(api):
+    """1,000 particles in a 20 A cube, +/-1 charges, p = 4.  The oracle's FMM (same tree, same
+    operators), applied to the library's converged dipoles, gives the same residual, energy, forces
+    and potentials; against the direct oracle the error is the FMM truncation error."""
+    print_case("solve uniform cube 1k p=4")
+    from paper_1408_6527_amd import inputs
+    ps = inputs.uniform_cube(1000)
+    lw = 2.6
+    s = api.Solver(order_p=4, ws=1, leaf_width=lw, scf_tol=1e-10)
+    r = s.solve(T(ps.pos), T(ps.q), T(ps.alpha))
+    mu = N(r.mu)
+    st1 = FM.fmm_fields(ps.pos, ps.q, None, ps.alpha, 2.0, 4, lw, 1)
+    st3 = FM.fmm_fields(ps.pos, None, mu, ps.alpha, 2.0, 4, lw, 1)
+    res = np.linalg.norm(ps.alpha[:, None] * (st1["E_d"] + st3["E_d"]) - mu) / np.linalg.norm(ps.alpha[:, None] * st1["E_d"])
+    assert res < 2e-10
+    assert abs(res - r.residual) < 1e-11
+    ev = D.evaluate(ps.pos, ps.q, ps.alpha, mu, 2.0, D.COULOMB_K,
+                    charge=(st1["phi"], st1["E_d"], st1["G_d"]),
+                    dip=(st3["phi"], st3["E_u"], st3["E_d"], st3["G_d"]))
+    assert abs(r.U - ev["U"]) < 1e-11 * abs(ev["U"])
+    assert relmax(N(r.forces), ev["F"]) < 1e-10
+    assert relmax(N(r.phi), ev["phi"]) < 1e-10
+    ref = D.solve(ps.pos, ps.q, ps.alpha, thole_a=2.0)
+    err_f = relnorm(N(r.forces), ref["F"])
+    err_mu = relnorm(mu, ref["mu"])
+    print(f"uniform cube 1k p=4 ws=1: force err {err_f:.3e}, dipole err {err_mu:.3e},"
+          f" energy err {abs(r.U - ref['U']) / abs(ref['U']):.3e}, iters {r.iters}", flush=True)
+    assert err_f < 3e-2 and err_mu < 3e-2
+
+
+def test_solve_error_falls_with_order(api):
+    print_case("solve error vs p")
+    X, q, a, _ = cube(500, 16.0, 6)
+    ref = D.solve(X, q, a, thole_a=2.0)
+    errs = []
+    for p in (2, 4, 6, 8):
+        r = api.Solver(order_p=p, ws=2, leaf_width=1.5, scf_tol=1e-11).solve(T(X), T(q), T(a))
+        assert r.stats["levels"] >= 3
+        errs.append(relnorm(N(r.forces), ref["F"]))
+    print("force error vs p (ws=2):", errs, flush=True)
+    assert all(errs[i + 1] < errs[i] for i in range(3))
+    assert errs[-1] < 1e-4
+
+
+def test_backward_gradients_match_oracle(api):
+    print_case("backward one leaf")
+    X, q, a, _ = cube(120, 7.5, 7)
+    a[5] = 0.0
+    ref = D.solve(X, q, a, thole_a=2.0)
+    s = api.Solver(order_p=4, ws=1, leaf_width=50.0, scf_tol=1e-13, scf_max_iter=300)
+    s.solve(T(X), T(q), T(a))
+    gp, gq, ga = s.backward(2.0)
+    assert relmax(N(gp), -2.0 * ref["F"]) < 1e-10
+    assert relmax(N(gq), 2.0 * ref["phi"]) < 1e-10
+    assert relmax(N(ga), 2.0 * ref["grad_alpha"]) < 1e-9
+
+
+def test_autograd_function_against_finite_differences(api):
+    import torch
+    print_case("autograd fd")
+    X, q, a, _ = cube(60, 6.0, 8)
+    s = api.Solver(order_p=4, ws=1, leaf_width=50.0, scf_tol=1e-13, scf_max_iter=300)
+    pos = T(X).requires_grad_(True); qq = T(q).requires_grad_(True); al = T(a).requires_grad_(True)
+    U = api.PolarizableEnergy.apply(pos, qq, al, s)
+    U.backward()
+    rng = np.random.default_rng(0)
+    h = 1e-5
+
+    def energy(X_, q_, a_):
+        return s.solve(T(X_), T(q_), T(a_)).U
+
+    for _ in range(4):
+        i, c = rng.integers(60), rng.integers(3)
+        Xp = X.copy(); Xp[i, c] += h; Xm = X.copy(); Xm[i, c] -= h
+        fd = (energy(Xp, q, a) - energy(Xm, q, a)) / (2 * h)
+        assert abs(fd - pos.grad[i, c].item()) < 1e-6 * max(1.0, abs(fd))
+        qp = q.copy(); qp[i] += h; qm = q.copy(); qm[i] -= h
+        fd = (energy(X, qp, a) - energy(X, qm, a)) / (2 * h)
+        assert abs(fd - qq.grad[i].item()) < 1e-6 * max(1.0, abs(fd))
+        ap = a.copy(); ap[i] += h; am = a.copy(); am[i] -= h
+        fd = (energy(X, q, ap) - energy(X, q, am)) / (2 * h)
+        assert abs(fd - al.grad[i].item()) < 1e-6 * max(1.0, abs(fd))
+
+
+def test_mixed_precision_error(api):
+    print_case("mixed precision")
+    X, q, a, _ = cube(800, 18.0, 9)
+    ref = D.solve(X, q, a, thole_a=2.0)
+    r64 = api.Solver(order_p=8, ws=2, leaf_width=1.6, scf_tol=1e-10).solve(T(X), T(q), T(a))
+    r32 = api.Solver(order_p=8, ws=2, leaf_width=1.6, scf_tol=1e-10, precision="mixed").solve(T(X), T(q), T(a))
+    e64 = relnorm(N(r64.forces), ref["F"]); e32 = relnorm(N(r32.forces), ref["F"])
+    print(f"mixed: fp64 force err {e64:.2e}, mixed force err {e32:.2e}, mixed vs fp64 {relnorm(N(r32.forces), N(r64.forces)):.2e}",
+          flush=True)
+    assert e32 < 1e-4
+    assert relnorm(N(r32.mu), ref["mu"]) < 1e-4
+    assert abs(r32.U - ref["U"]) < 1e-4 * abs(ref["U"])
+
+
+def test_deterministic(api):
+    print_case("determinism")
+    X, q, a, _ = cube(700, 15.0, 10)
+    s = api.Solver(order_p=6, ws=2, leaf_width=1.6, scf_tol=1e-8)
+    r1 = s.solve(T(X), T(q), T(a))
+    r2 = s.solve(T(X), T(q), T(a))
+    assert np.array_equal(N(r1.mu), N(r2.mu))
+    assert np.array_equal(N(r1.forces), N(r2.forces))
+    assert r1.U == r2.U
+
+
+# ------------------------------------------------------------------ edge cases and failure modes
+
+def test_edge_sizes(api):
+    import torch
+    print_case("edge sizes")
+    s = api.Solver(order_p=4, ws=1)
+    z = torch.zeros((0, 3), dtype=torch.float64, device="cuda")
+    r = s.solve(z, torch.zeros(0, dtype=torch.float64, device="cuda"), torch.zeros(0, dtype=torch.float64, device="cuda"))
+    assert r.U == 0.0 and r.mu.shape == (0, 3)
+    r = s.solve(T([[1.0, 2.0, 3.0]]), T([0.7]), T([1.2]))
+    assert r.U == 0.0 and np.all(N(r.mu) == 0) and np.all(N(r.forces) == 0)
+    X = np.array([[0.0, 0.0, 0.0], [0.0, 0.0, 3.1]])
+    r = api.Solver(order_p=4, ws=1, scf_tol=1e-14, thole_a=0.0).solve(T(X), T([0.7, -0.4]), T([1.3, 0.9]))
+    ref = D.solve(X, np.array([0.7, -0.4]), np.array([1.3, 0.9]), thole_a=0.0)
+    assert relmax(N(r.mu), ref["mu"]) < 1e-13
+
+
+def test_errors(api):
+    print_case("error codes")
+    X, q, a, _ = cube(50, 6.0, 11)
+    s = api.Solver(order_p=4, ws=1)
+    Xc = X.copy(); Xc[7] = Xc[3]
+    with pytest.raises(api.PFMMError, match="COINCIDENT"):
+        s.solve(T(Xc), T(q), T(a))
+    Xn = X.copy(); Xn[2, 1] = np.nan
+    with pytest.raises(api.PFMMError, match="NONFINITE"):
+        s.solve(T(Xn), T(q), T(a))
+    an = a.copy(); an[4] = -1.0
+    with pytest.raises(api.PFMMError, match="INVALID_ARG"):
+        s.solve(T(X), T(q), T(an))
+    with pytest.raises(api.PFMMError, match="NOT_CONVERGED"):
+        api.Solver(order_p=4, ws=1, scf_max_iter=1, scf_tol=1e-14).solve(T(X), T(q), T(a))
+    r = api.Solver(order_p=4, ws=1, scf_max_iter=1, scf_tol=1e-14).solve(T(X), T(q), T(a), allow_unconverged=True)
+    assert r.iters == 1 and np.all(np.isfinite(N(r.mu)))
+    Xs = np.array([[0.0, 0.0, 0.0], [0.0, 0.0, 0.5], [3.0, 0.0, 0.0]])
+    with pytest.raises(api.PFMMError, match="NOT_SPD"):
+        api.Solver(order_p=4, ws=1, thole_a=0.0).solve(T(Xs), T([1.0, -1.0, 0.5]), T([2.0, 2.0, 1.0]))
+    with pytest.raises(api.PFMMError, match="INVALID_ARG"):
+        api.Solver(order_p=4, ws=1, leaf_width=1.0, thole_a=2.0).solve(T(X), T(q), T(a))
+    with pytest.raises(api.PFMMError, match="NO_STATE"):
+        api.Solver(order_p=4, ws=1).backward(1.0, n=5)
+    with pytest.raises(api.PFMMError):
+        api.Solver(order_p=11)
+
+
+def test_zero_polarizability_is_coulomb(api):
+    print_case("alpha = 0")
+    X, q, a, _ = cube(300, 12.0, 12)
+    r = api.Solver(order_p=6, ws=2, leaf_width=1.6).solve(T(X), T(q), T(np.zeros(300)))
+    ref = D.solve(X, q, np.zeros(300))
+    assert r.U_pol == 0.0 and np.all(N(r.mu) == 0.0)
+    assert abs(r.U - ref["U"]) < 1e-5 * abs(ref["U"])
+
+
+# ------------------------------------------------------------------ large systems on sampled outputs
+
+@pytest.mark.parametrize("p,gate", [(6, 1e-4), (8, 1e-5)])
+def test_globular_50k_sampled(api, p, gate):
+    """50,000-particle globular system: at 64 sampled particles the exact forces and dipole
+    residual computed by the oracle from the library's own dipoles agree with the library."""
+    print_case(f"globular 50k p={p}")
+    from paper_1408_6527_amd import inputs
+    ps = inputs.globular(50_000)
+    s = api.Solver(order_p=p, ws=2, leaf_width=4.0, scf_tol=1e-6)
+    r = s.solve(T(ps.pos), T(ps.q), T(ps.alpha))
+    mu = N(r.mu)
+    idx = np.random.default_rng(5).choice(ps.n, 64, replace=False)
+    phi, Eu, Ed, G = D.fields_at(idx, ps.pos, ps.q, mu, ps.alpha, 2.0)
+    F = D.COULOMB_K * (ps.q[idx, None] * Eu + np.einsum("ia,iab->ib", mu[idx], G))
+    ferr = relnorm(N(r.forces)[idx], F)
+    res = np.linalg.norm(ps.alpha[idx, None] * Ed - mu[idx]) / np.linalg.norm(ps.alpha[idx, None] * Ed)
+    print(f"globular 50k p={p}: sampled force err {ferr:.2e}, sampled dipole residual {res:.2e}, iters {r.iters},"
+          f" levels {r.stats['levels']}, m2l {r.stats['n_m2l']}, p2p {r.stats['n_p2p']}", flush=True)
+    assert ferr < gate
+    assert res < 5e-6
+    assert r.residual <= 1e-6
