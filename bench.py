@@ -1,0 +1,196 @@
+"""Benchmark: particles/s of one polarizable FMM step (tree, charge field, dipole solve to the
+stated tolerance, energy, forces, and the adjoint backward) on one MI355X, float64 path and mixed
+path, with the error of each against the CPU oracle stated.
+
+    python bench.py [--steps K] [--warmup W] [--workload globular_50k] [--gpus 1]
+
+Prints ONE JSON line.  Inputs are synthetic (seeded), resident on the GPU before timing starts.
+The dominant kernel's roofline fraction is measured live with HIP events on the library's stream;
+the CPU oracle is timed on a bounded sample of the same workload on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Workload presets: geometry generator, expansion order, separation, leaf edge, dipole tolerance.
+WORKLOADS = {
+    "globular_50k": dict(gen="globular_50k", p=6, ws=2, leaf=4.0, tol=1e-6),
+    "uniform_cube_1k": dict(gen="uniform_cube_1k", p=4, ws=1, leaf=5.0, tol=1e-8),
+    "hexamer_shell_160k": dict(gen="hexamer_shell_160k", p=8, ws=2, leaf=4.0, tol=1e-6),
+    "scaling_1m": dict(gen="scaling_1m", p=8, ws=2, leaf=4.0, tol=1e-6),
+}
+
+PEAK = {"fp64_vector": 78.6, "fp64_mfma": 78.6, "fp32_mfma": 157.3, "fp32_vector": 157.3, "hbm": 8000.0}
+P2P_SCF_FLOPS_PER_PAIR = 44  # damped dipole field of one source at one target (p2p.hip)
+
+
+def m2l_flops_per_pair(p: int) -> int:
+    return 2 * math.comb(p + 6, 6)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="globular_50k", choices=sorted(WORKLOADS))
+    ap.add_argument("--p", type=int, default=None)
+    ap.add_argument("--ws", type=int, default=None)
+    ap.add_argument("--leaf", type=float, default=None)
+    ap.add_argument("--tol", type=float, default=None)
+    ap.add_argument("--oracle-sample", type=int, default=192)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precision", default="both", choices=["fp64", "mixed", "both"])
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (see DESIGN.md for how "
+              "the method would shard); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_1408_6527_amd import api, inputs
+
+    wl = dict(WORKLOADS[args.workload])
+    for k in ("p", "ws", "leaf", "tol"):
+        if getattr(args, k) is not None:
+            wl[k] = getattr(args, k)
+    ps = inputs.make(wl["gen"])
+    n = ps.n
+    dev = torch.device("cuda", 0)
+    pos = torch.as_tensor(ps.pos, dtype=torch.float64, device=dev)
+    q = torch.as_tensor(ps.q, dtype=torch.float64, device=dev)
+    al = torch.as_tensor(ps.alpha, dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+
+    def make(prec, timing=False):
+        return api.Solver(order_p=wl["p"], ws=wl["ws"], leaf_width=wl["leaf"], scf_tol=wl["tol"],
+                          precision=prec, timing=timing)
+
+    def step(s):
+        r = s.solve(pos, q, al)
+        s.backward(1.0)
+        return r
+
+    def timed(prec):
+        s = make(prec)
+        for _ in range(args.warmup):
+            step(s)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            r = step(s)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        return s, r, dt
+
+    precs = ["fp64", "mixed"] if args.precision == "both" else [args.precision]
+    results = {}
+    for prec in precs:
+        s, r, dt = timed(prec)
+        results[prec] = dict(solver=s, res=r, dt=dt)
+
+    # accuracy on sampled particles: exact forces from the library's own dipoles (oracle), and the
+    # exact dipole residual there
+    from oracle import direct as D
+    rng = np.random.default_rng(7)
+    idx = np.sort(rng.choice(n, min(64, n), replace=False))
+    errs = {}
+    for prec in precs:
+        r = results[prec]["res"]
+        mu = r.mu.cpu().numpy()
+        phi, Eu, Ed, G = D.fields_at(idx, ps.pos, ps.q, mu, ps.alpha, 2.0)
+        F = D.COULOMB_K * (ps.q[idx, None] * Eu + np.einsum("ia,iab->ib", mu[idx], G))
+        Fg = r.forces.cpu().numpy()[idx]
+        errs[prec] = dict(
+            force_rel_l2=float(np.linalg.norm(Fg - F) / np.linalg.norm(F)),
+            dipole_residual_exact=float(np.linalg.norm(ps.alpha[idx, None] * Ed - mu[idx])
+                                        / np.linalg.norm(ps.alpha[idx, None] * Ed)),
+            scf_residual=float(r.residual), iters=int(r.iters))
+    if "mixed" in results and "fp64" in results:
+        a = results["mixed"]["res"]; b = results["fp64"]["res"]
+        errs["mixed"]["vs_fp64_force"] = float(torch.linalg.norm(a.forces - b.forces) / torch.linalg.norm(b.forces))
+        errs["mixed"]["vs_fp64_energy"] = float(abs(a.U - b.U) / abs(b.U))
+        errs["mixed"]["vs_fp64_dipole"] = float(torch.linalg.norm(a.mu - b.mu) / torch.linalg.norm(b.mu))
+
+    # per-kernel device time of one step of the primary path, HIP events on the library's stream
+    prim = precs[0]
+    st = make(prim, timing=True)
+    rt = st.solve(pos, q, al)
+    kms = rt.stats["t_kernel_ms"]; kl = rt.stats["kernel_launches"]
+    dominant = max(kms, key=lambda k: kms[k])
+    avg_ms = {k: (kms[k] / kl[k] if kl[k] else 0.0) for k in kms}
+    p = wl["p"]
+    if dominant == "m2l":
+        work = rt.stats["n_m2l"] * m2l_flops_per_pair(p)
+        peak = PEAK["fp32_mfma"] if prim == "mixed" else PEAK["fp64_mfma"]
+        bound = "mfma"
+    else:
+        # P2P of the dipole solve (the launch repeated every iteration) and any other kernel are
+        # priced as plain vector arithmetic
+        work = rt.stats["n_p2p"] * P2P_SCF_FLOPS_PER_PAIR
+        peak = PEAK["fp64_vector"] if prim == "fp64" else PEAK["fp32_vector"]
+        bound = "alu"
+    achieved = work / (avg_ms[dominant] * 1e-3) / 1e12
+    roofline = {"bound": bound, "kernel": dominant, "achieved": round(achieved, 3), "peak": peak,
+                "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                "avg_launch_ms": round(avg_ms[dominant], 4),
+                "work_per_launch": work,
+                "kernel_ms_per_step": {k: round(v, 3) for k, v in kms.items()},
+                "launches_per_step": dict(kl)}
+
+    # CPU oracle on a bounded sample: exact fields of all sources at S targets, extrapolated to
+    # the evaluations of one step (charge field, initial residual, iterations, final pass)
+    cpu = None
+    if not args.no_cpu_baseline:
+        S = min(args.oracle_sample, n)
+        sidx = np.sort(rng.choice(n, S, replace=False))
+        mu = results[prim]["res"].mu.cpu().numpy()
+        t0 = time.perf_counter()
+        D.fields_at(sidx, ps.pos, ps.q, mu, ps.alpha, 2.0)
+        tS = time.perf_counter() - t0
+        evals = results[prim]["res"].iters + 3
+        t_step = tS * (n / S) * evals
+        cpu = {"value": round(n / t_step, 3), "unit": "particles/s", "cores": 1, "kind": "oracle",
+               "sample": f"direct-sum fields (phi, E, damped E, grad E) at {S} of {n} particles from all "
+                         f"{n} sources in {tS:.1f} s, scaled by n/{S} and by the {evals} field "
+                         f"evaluations of one step"}
+
+    r0 = results[prim]
+    value = n / r0["dt"]
+    out = {
+        "metric": "particles/s per polarizable FMM step (SCF+forces), mixed vs FP64 at stated err",
+        "value": round(value, 2), "unit": "particles/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(r0["dt"] * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if prim == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n": n, "order_p": p, "ws": wl["ws"],
+                   "leaf_width": wl["leaf"], "scf_tol": wl["tol"], "levels": r0["res"].stats["levels"],
+                   "step": "solve (tree, charge field, dipole CG, energy, forces) + backward",
+                   "parallelism": "single GPU"},
+        "errors": errs,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    if "mixed" in results and "fp64" in results:
+        out["mixed"] = {"value": round(n / results["mixed"]["dt"], 2),
+                        "ms_per_step": round(results["mixed"]["dt"] * 1e3, 3),
+                        "speedup_vs_fp64": round(results["fp64"]["dt"] / results["mixed"]["dt"], 3)}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -97,6 +97,11 @@ typedef struct pfmm_result {
   int n_evals;                  /* FMM field evaluations performed                                 */
   double t_phase_ms[8];         /* with PFMM_TIMING: tree, charge field, dipole solve, final pass,
                                    assembly, total, -, -                                           */
+  double t_kernel_ms[8];        /* with PFMM_TIMING: summed device time per kernel class, measured
+                                   with HIP events on the call's stream: P2M, M2M, M2L, L2L, L2P,
+                                   P2P of the dipole solve (damped field only), P2P of the charge and
+                                   final passes (all outputs), dipole-solve vector kernels          */
+  int kernel_launches[8];       /* launches per kernel class counted in t_kernel_ms               */
 } pfmm_result;
 
 typedef struct pfmm_handle pfmm_handle;

@@ -66,7 +66,11 @@ class Result(ctypes.Structure):
         ("n_p2p", ctypes.c_int64),
         ("n_evals", ctypes.c_int),
         ("t_phase_ms", ctypes.c_double * 8),
+        ("t_kernel_ms", ctypes.c_double * 8),
+        ("kernel_launches", ctypes.c_int * 8),
     ]
+
+KERNEL_CLASSES = ["p2m", "m2m", "m2l", "l2l", "l2p", "p2p_scf", "p2p_full", "solver"]
 
 
 def _load():

@@ -139,7 +139,9 @@ class Solver:
         self._n_last = n
         stats = dict(levels=res.levels, leaf_width=res.leaf_width, n_leaves=res.n_leaves,
                      n_cells=res.n_cells, n_m2l=res.n_m2l, n_p2p=res.n_p2p, n_evals=res.n_evals,
-                     t_phase_ms=list(res.t_phase_ms), status=_lib.STATUS[st])
+                     t_phase_ms=list(res.t_phase_ms), status=_lib.STATUS[st],
+                     t_kernel_ms=dict(zip(_lib.KERNEL_CLASSES, res.t_kernel_ms)),
+                     kernel_launches=dict(zip(_lib.KERNEL_CLASSES, res.kernel_launches)))
         return SolveResult(res.U_total, res.U_qq, res.U_pol, mu, F, phi, res.iters, res.residual,
                            res.residual_max_debye, stats)
 

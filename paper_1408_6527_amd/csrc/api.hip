@@ -13,6 +13,8 @@
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <utility>
+#include <vector>
 
 #include "kernels.hpp"
 #include "tables.hpp"
@@ -41,7 +43,55 @@ struct HostPinned {
 
 }  // namespace
 
+// Per-launch HIP events on the call's stream, grouped by kernel class (PFMM_TIMING only).
+struct KernelTimer {
+  bool on = false;
+  hipStream_t s = nullptr;
+  std::vector<hipEvent_t> pool;
+  std::vector<std::pair<int, int>> marks;  // (class, index of the start event; end = start + 1)
+  size_t used = 0;
+  ~KernelTimer() {
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+  void reset(bool on_, hipStream_t s_) {
+    on = on_;
+    s = s_;
+    marks.clear();
+    used = 0;
+  }
+  int begin() {
+    if (!on) return -1;
+    if (used + 2 > pool.size()) {
+      for (int k = 0; k < 64; ++k) {
+        hipEvent_t e;
+        PFMM_HIP(hipEventCreate(&e));
+        pool.push_back(e);
+      }
+    }
+    PFMM_HIP(hipEventRecord(pool[used], s));
+    used += 2;
+    return (int)used - 2;
+  }
+  void end(int cls, int start) {
+    if (!on || start < 0) return;
+    PFMM_HIP(hipEventRecord(pool[start + 1], s));
+    marks.emplace_back(cls, start);
+  }
+  void collect(double* ms, int* count) {
+    if (!on) return;
+    PFMM_HIP(hipStreamSynchronize(s));
+    for (auto& m : marks) {
+      float t = 0.f;
+      PFMM_HIP(hipEventElapsedTime(&t, pool[m.second], pool[m.second + 1]));
+      ms[m.first] += t;
+      count[m.first] += 1;
+    }
+  }
+};
+enum { KC_P2M = 0, KC_M2M, KC_M2L, KC_L2L, KC_L2P, KC_P2P_SCF, KC_P2P_FULL, KC_SOLVER };
+
 struct pfmm_handle {
+  KernelTimer kt;
   pfmm_config cfg{};
   HostTables tab;
   OpTables op;
@@ -272,13 +322,24 @@ void fmm_pass(pfmm_handle* h, int sources, int mode, FieldOut out, int* err, con
   double* M = h->w_M.as<double>();
   double* F = h->w_F.as<double>();
   const double4* mu4 = h->w_mu4.as<double4>();
+  KernelTimer& kt = h->kt;
   if (t.L >= 2) {
+    int e = kt.begin();
     launch_p2m(t, op, h->pa, mu4, sources, M, done, s);
+    kt.end(KC_P2M, e);
+    e = kt.begin();
     for (int lp = t.L - 1; lp >= 2; --lp) launch_m2m(t, op, lp, M, done, s);
+    kt.end(KC_M2M, e);
+    e = kt.begin();
     launch_m2l(t, op, h->w_tgt.as<int>(), h->w_octcnt.as<int>(), h->ntgt, h->w_list.as<int>(), M, F,
                fp32, 3, done, s);
+    kt.end(KC_M2L, e);
+    e = kt.begin();
     for (int lc = 3; lc <= t.L; ++lc) launch_l2l(t, op, lc, F, done, s);
+    kt.end(KC_L2L, e);
+    e = kt.begin();
     launch_l2p(t, op, h->pa, F, mode, out, done, s);
+    kt.end(KC_L2P, e);
   } else {
     launch_fill_double(out.Ed, 3 * (int64_t)n, 0.0, s);
     if (mode == 1) {
@@ -287,7 +348,9 @@ void fmm_pass(pfmm_handle* h, int sources, int mode, FieldOut out, int* err, con
       launch_fill_double(out.G, 6 * (int64_t)n, 0.0, s);
     }
   }
+  int e = kt.begin();
   launch_p2p(t, h->pa, mu4, mode == 0 ? 0 : 1, sources, fp32, out, nullptr, err, done, s);
+  kt.end(mode == 0 ? KC_P2P_SCF : KC_P2P_FULL, e);
   h->n_evals += 1;
 }
 
@@ -350,6 +413,7 @@ pfmm_status solve_impl(pfmm_handle* h, int64_t n64, const double* pos, const dou
   PFMM_HIP(hipGetDevice(&h->device));
 
   Timer tm((c.flags & PFMM_TIMING) != 0, s);
+  h->kt.reset((c.flags & PFMM_TIMING) != 0, s);
   tm.mark();
   if ((c.flags & PFMM_WARM_START) != 0) {
     int* fl = dev<int>(h->w_flags, 4);
@@ -390,17 +454,22 @@ pfmm_status solve_impl(pfmm_handle* h, int64_t n64, const double* pos, const dou
   fmm_pass(h, 2, 0, fo, err, nullptr, s);
   launch_cg_residual0(pa, Eq, E, y, r, pv, part, st, c.scf_tol, s);
   const int* done = &st->done;
-  const int chunk = c.graph_iters > 0 ? c.graph_iters : 4;
+  // with timing, test convergence after every iteration so that no launch runs past it
+  const int chunk = (c.flags & PFMM_TIMING) ? 1 : (c.graph_iters > 0 ? c.graph_iters : 4);
   CGState hs{};
   sync_read(h, st, &hs, sizeof(hs), s);
   int launched = 0;
   while (!hs.done && launched < c.scf_max_iter) {
     for (int k = 0; k < chunk && launched < c.scf_max_iter; ++k, ++launched) {
+      int ev = h->kt.begin();
       launch_make_dipoles(pa, pv, mu4, done, s);
+      h->kt.end(KC_SOLVER, ev);
       fmm_pass(h, 2, 0, fo, err, done, s);
+      ev = h->kt.begin();
       launch_cg_ap(pa, pv, E, Ap, part, st, s);
       launch_cg_update(pa, y, r, pv, Ap, part, st, c.scf_tol, c.scf_max_iter, s);
       launch_cg_direction(3 * n, r, pv, st, s);
+      h->kt.end(KC_SOLVER, ev);
     }
     sync_read(h, st, &hs, sizeof(hs), s);
   }
@@ -424,6 +493,7 @@ pfmm_status solve_impl(pfmm_handle* h, int64_t n64, const double* pos, const dou
   EnergyParts he{};
   sync_read(h, ep, &he, sizeof(he), s);
   tm.fill(res->t_phase_ms);
+  h->kt.collect(res->t_kernel_ms, res->kernel_launches);
 
   const double ke = c.coulomb_k;
   res->U_qq = ke * he.Uqq;
