@@ -88,10 +88,61 @@ struct KernelTimer {
     }
   }
 };
+// A captured sequence of launches, re-instantiated only when its topology changes
+// (hipGraphExecUpdate otherwise refreshes the kernel arguments of the existing executable graph).
+// Capture happens on a private stream (the caller's stream may be the null stream, which cannot
+// be captured); the executable graph is then launched on the caller's stream.
+struct GraphCache {
+  hipGraphExec_t exec = nullptr;
+  hipStream_t cap = nullptr;
+  ~GraphCache() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (cap) (void)hipStreamDestroy(cap);
+  }
+  template <class F>
+  void capture(F&& body) {
+    if (!cap) PFMM_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    hipStream_t s = cap;
+    hipGraph_t g = nullptr;
+    PFMM_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    try {
+      body();
+    } catch (...) {
+      hipGraph_t junk = nullptr;
+      (void)hipStreamEndCapture(s, &junk);
+      if (junk) (void)hipGraphDestroy(junk);
+      throw;
+    }
+    PFMM_HIP(hipStreamEndCapture(s, &g));
+    bool updated = false;
+    if (exec) {
+      hipGraphNode_t err_node = nullptr;
+      hipGraphExecUpdateResult why;
+      updated = hipGraphExecUpdate(exec, g, &err_node, &why) == hipSuccess && why == hipGraphExecUpdateSuccess;
+      if (!updated) {
+        (void)hipGetLastError();
+        (void)hipGraphExecDestroy(exec);
+        exec = nullptr;
+      }
+    }
+    if (!updated) {
+      hipError_t e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+      if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        exec = nullptr;
+        PFMM_HIP(e);
+      }
+    }
+    PFMM_HIP(hipGraphDestroy(g));
+  }
+  void launch(hipStream_t s) { PFMM_HIP(hipGraphLaunch(exec, s)); }
+};
+
 enum { KC_P2M = 0, KC_M2M, KC_M2L, KC_L2L, KC_L2P, KC_P2P_SCF, KC_P2P_FULL, KC_SOLVER };
 
 struct pfmm_handle {
   KernelTimer kt;
+  GraphCache graph;
   pfmm_config cfg{};
   HostTables tab;
   OpTables op;
@@ -119,7 +170,8 @@ struct pfmm_handle {
   std::string err;
   TreeView tv;
   Particles pa;
-  int ntgt = 0, ntiles = 0;
+  int ntgt = 0, ntiles = 0, m2l_wg = 0, nsplit = 1;
+  int64_t split_stride = 0;
   int64_t n_m2l = 0, n_p2p = 0;
   int n_evals = 0;
 };
@@ -299,15 +351,33 @@ void build_tree(pfmm_handle* h, int n, const double* pos, const double* q, const
   } else {
     launch_tree_stats(t, h->op.m2l_code, h->op.noff, stats, s);
   }
-  // expansions (one extra zero row serves empty M2L sources)
-  const int64_t rows = (int64_t)ncell + 1;
-  double* M = dev<double>(h->w_M, rows * h->op.stride);
-  dev<double>(h->w_F, rows * h->op.stride);
-  launch_fill_double(M + (int64_t)ncell * h->op.stride, h->op.stride, 0.0, s);
+  // per-octant target counts decide the M2L launch shape; the two readbacks share one sync
   unsigned long long st[2];
-  sync_read(h, stats, st, sizeof(st), s);
+  int octh[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  {
+    void* pin = h->pinned.get(sizeof(st) + sizeof(octh));
+    PFMM_HIP(hipMemcpyAsync(pin, stats, sizeof(st), hipMemcpyDeviceToHost, s));
+    PFMM_HIP(hipMemcpyAsync((char*)pin + sizeof(st), octcnt, sizeof(octh), hipMemcpyDeviceToHost, s));
+    PFMM_HIP(hipStreamSynchronize(s));
+    std::memcpy(st, pin, sizeof(st));
+    std::memcpy(octh, (char*)pin + sizeof(st), sizeof(octh));
+  }
   h->n_m2l = (int64_t)st[0];
   h->n_p2p = (int64_t)st[1];
+  // enough workgroups to fill the device: split each target tile's offset list when tiles are few
+  h->m2l_wg = h->ntgt > 0 ? m2l_workgroups(h->op.p, octh) : 0;
+  h->nsplit = 1;
+  if (h->m2l_wg > 0) {
+    const int want_wg = 1024;  // 4 workgroups of 4 waves per CU
+    h->nsplit = std::max(1, std::min(8, (want_wg + h->m2l_wg - 1) / h->m2l_wg));
+    h->nsplit = std::min(h->nsplit, std::max(1, h->op.noff / 8));
+  }
+  // expansions (one extra zero row serves empty M2L sources); F holds nsplit partial copies
+  const int64_t rows = (int64_t)ncell + 1;
+  h->split_stride = rows * h->op.stride;
+  double* M = dev<double>(h->w_M, rows * h->op.stride);
+  dev<double>(h->w_F, rows * h->op.stride * h->nsplit);
+  launch_fill_double(M + (int64_t)ncell * h->op.stride, h->op.stride, 0.0, s);
   h->n_evals = 0;
 }
 
@@ -331,11 +401,11 @@ void fmm_pass(pfmm_handle* h, int sources, int mode, FieldOut out, int* err, con
     for (int lp = t.L - 1; lp >= 2; --lp) launch_m2m(t, op, lp, M, done, s);
     kt.end(KC_M2M, e);
     e = kt.begin();
-    launch_m2l(t, op, h->w_tgt.as<int>(), h->w_octcnt.as<int>(), h->ntgt, h->w_list.as<int>(), M, F,
-               fp32, 3, done, s);
+    launch_m2l(t, op, h->w_tgt.as<int>(), h->w_octcnt.as<int>(), h->m2l_wg, h->nsplit,
+               h->w_list.as<int>(), M, F, h->split_stride, fp32, 3, done, s);
     kt.end(KC_M2L, e);
     e = kt.begin();
-    for (int lc = 3; lc <= t.L; ++lc) launch_l2l(t, op, lc, F, done, s);
+    for (int lc = 2; lc <= t.L; ++lc) launch_l2l(t, op, lc, F, h->nsplit, h->split_stride, done, s);
     kt.end(KC_L2L, e);
     e = kt.begin();
     launch_l2p(t, op, h->pa, F, mode, out, done, s);
@@ -454,24 +524,40 @@ pfmm_status solve_impl(pfmm_handle* h, int64_t n64, const double* pos, const dou
   fmm_pass(h, 2, 0, fo, err, nullptr, s);
   launch_cg_residual0(pa, Eq, E, y, r, pv, part, st, c.scf_tol, s);
   const int* done = &st->done;
+  auto iteration = [&](hipStream_t q) {
+    int ev = h->kt.begin();
+    launch_make_dipoles(pa, pv, mu4, done, q);
+    h->kt.end(KC_SOLVER, ev);
+    fmm_pass(h, 2, 0, fo, err, done, q);
+    ev = h->kt.begin();
+    launch_cg_ap(pa, pv, E, Ap, part, st, q);
+    launch_cg_update(pa, y, r, pv, Ap, part, st, c.scf_tol, c.scf_max_iter, q);
+    launch_cg_direction(3 * n, r, pv, st, q);
+    h->kt.end(KC_SOLVER, ev);
+  };
+  const bool timing = (c.flags & PFMM_TIMING) != 0;
   // with timing, test convergence after every iteration so that no launch runs past it
-  const int chunk = (c.flags & PFMM_TIMING) ? 1 : (c.graph_iters > 0 ? c.graph_iters : 4);
+  const int chunk = timing ? 1 : (c.graph_iters > 0 ? c.graph_iters : 4);
+  const bool use_graph = c.graph_iters > 0 && !timing;
   CGState hs{};
   sync_read(h, st, &hs, sizeof(hs), s);
   int launched = 0;
-  while (!hs.done && launched < c.scf_max_iter) {
-    for (int k = 0; k < chunk && launched < c.scf_max_iter; ++k, ++launched) {
-      int ev = h->kt.begin();
-      launch_make_dipoles(pa, pv, mu4, done, s);
-      h->kt.end(KC_SOLVER, ev);
-      fmm_pass(h, 2, 0, fo, err, done, s);
-      ev = h->kt.begin();
-      launch_cg_ap(pa, pv, E, Ap, part, st, s);
-      launch_cg_update(pa, y, r, pv, Ap, part, st, c.scf_tol, c.scf_max_iter, s);
-      launch_cg_direction(3 * n, r, pv, st, s);
-      h->kt.end(KC_SOLVER, ev);
+  if (use_graph && !hs.done) {
+    // chunk iterations captured once per solve as one HIP graph; every kernel in it returns at
+    // once when the device-side `done` flag is set, so replays past convergence are no-ops
+    h->graph.capture([&]() {
+      for (int k = 0; k < chunk; ++k) iteration(h->graph.cap);
+    });
+    while (!hs.done && launched < c.scf_max_iter) {
+      h->graph.launch(s);
+      launched += chunk;
+      sync_read(h, st, &hs, sizeof(hs), s);
     }
-    sync_read(h, st, &hs, sizeof(hs), s);
+  } else {
+    while (!hs.done && launched < c.scf_max_iter) {
+      for (int k = 0; k < chunk && launched < c.scf_max_iter; ++k, ++launched) iteration(s);
+      sync_read(h, st, &hs, sizeof(hs), s);
+    }
   }
   tm.mark();
 
@@ -508,7 +594,7 @@ pfmm_status solve_impl(pfmm_handle* h, int64_t n64, const double* pos, const dou
   res->n_cells = h->tv.ncell;
   res->n_m2l = h->n_m2l;
   res->n_p2p = h->n_p2p;
-  res->n_evals = h->n_evals;
+  res->n_evals = 3 + hs.iters;  // charge field, initial residual, iterations, final pass
   h->saved = true;
   h->saved_n = n;
   if (hs.notspd) throw Error(PFMM_ERR_NOT_SPD, "conjugate gradients met p.Ap <= 0: the dipole system is not positive definite");

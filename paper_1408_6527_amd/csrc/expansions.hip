@@ -115,9 +115,10 @@ __global__ __launch_bounds__(SH_TPB) void k_m2m(TreeView t, OpTables op, int lp,
   }
 }
 
-// One block per child cell: F~(child) += shift of F~(parent).
-__global__ __launch_bounds__(SH_TPB) void k_l2l(TreeView t, OpTables op, int lc,
-                                                double* __restrict__ F, const int* done) {
+// One block per child cell: F~(child) += partial M2L sums of the other offset splits, then the
+// shift of F~(parent) (levels >= 3; the parent row is complete because levels run top-down).
+__global__ __launch_bounds__(SH_TPB) void k_l2l(TreeView t, OpTables op, int lc, double* F,
+                                                int nsplit, int64_t split_stride, const int* done) {
   if (done && *done) return;
   const int g = t.off[lc] + blockIdx.x;
   const int par = t.parent[g];
@@ -125,8 +126,11 @@ __global__ __launch_bounds__(SH_TPB) void k_l2l(TreeView t, OpTables op, int lc,
   const double* Fp = F + (int64_t)par * op.stride;
   for (int k = threadIdx.x; k < op.nc; k += SH_TPB) {
     double acc = 0.0;
-    const int b = op.l2l_ptr[o * (op.nc + 1) + k], e = op.l2l_ptr[o * (op.nc + 1) + k + 1];
-    for (int j = b; j < e; ++j) acc += op.l2l_val[j] * Fp[op.l2l_col[j]];
+    for (int sp = 1; sp < nsplit; ++sp) acc += F[sp * split_stride + (int64_t)g * op.stride + k];
+    if (lc >= 3) {
+      const int b = op.l2l_ptr[o * (op.nc + 1) + k], e = op.l2l_ptr[o * (op.nc + 1) + k + 1];
+      for (int j = b; j < e; ++j) acc += op.l2l_val[j] * Fp[op.l2l_col[j]];
+    }
     F[(int64_t)g * op.stride + k] += acc;
   }
 }
@@ -216,11 +220,12 @@ void launch_m2m(const TreeView& t, const OpTables& op, int parent_level, double*
   PFMM_LAUNCH_CHECK();
 }
 
-void launch_l2l(const TreeView& t, const OpTables& op, int child_level, double* F, const int* done,
-                hipStream_t s) {
+void launch_l2l(const TreeView& t, const OpTables& op, int child_level, double* F, int nsplit,
+                int64_t split_stride, const int* done, hipStream_t s) {
   const int nc = t.off[child_level + 1] - t.off[child_level];
-  if (nc <= 0) return;
-  hipLaunchKernelGGL(k_l2l, dim3(nc), dim3(SH_TPB), 0, s, t, op, child_level, F, done);
+  if (nc <= 0 || (child_level < 3 && nsplit <= 1)) return;
+  hipLaunchKernelGGL(k_l2l, dim3(nc), dim3(SH_TPB), 0, s, t, op, child_level, F, nsplit, split_stride,
+                     done);
   PFMM_LAUNCH_CHECK();
 }
 

@@ -94,8 +94,10 @@ void launch_p2m(const TreeView& t, const OpTables& op, const Particles& pa, cons
                 int sources, double* M, const int* done, hipStream_t s);
 void launch_m2m(const TreeView& t, const OpTables& op, int parent_level, double* M, const int* done,
                 hipStream_t s);
-void launch_l2l(const TreeView& t, const OpTables& op, int child_level, double* F, const int* done,
-                hipStream_t s);
+// F~(child) += partial M2L sums of splits 1..nsplit-1 (at F + s * split_stride) and, from level 3
+// on, the shift of F~(parent).
+void launch_l2l(const TreeView& t, const OpTables& op, int child_level, double* F, int nsplit,
+                int64_t split_stride, const int* done, hipStream_t s);
 // mode 0: Ed only (written, not added); mode 1: phi, Eu, Ed, G written
 void launch_l2p(const TreeView& t, const OpTables& op, const Particles& pa, const double* F, int mode,
                 FieldOut out, const int* done, hipStream_t s);
@@ -106,9 +108,13 @@ void launch_l2p(const TreeView& t, const OpTables& op, const Particles& pa, cons
 int m2l_max_tiles(int ntgt);
 void launch_m2l_list(const TreeView& t, const OpTables& op, const int* tgt_list, const int* oct_count,
                      int ntiles, int* list, hipStream_t s);
+// Workgroups of the M2L launch for the per-octant target counts (host copy), before splitting.
+int m2l_workgroups(int p, const int* oct_count_host);
+// Split s of the offset list writes its partial F~ at F + s * split_stride (s = 0: F itself); the
+// downward pass (launch_l2l) adds the partials of splits 1.. to F.
 void launch_m2l(const TreeView& t, const OpTables& op, const int* tgt_list, const int* oct_count,
-                int ntgt, const int* list, const double* M, double* F, bool fp32, int fp64_max_level,
-                const int* done, hipStream_t s);
+                int nwg, int nsplit, const int* list, const double* M, double* F, int64_t split_stride,
+                bool fp32, int fp64_max_level, const int* done, hipStream_t s);
 void launch_octant_keys(const TreeView& t, int* keys, int* vals, int* oct_count, hipStream_t s);
 size_t octsort_temp_bytes(int n);
 void launch_octant_sort(void* tmp, size_t bytes, const int* kin, int* kout, const int* vin, int* vout,

@@ -93,102 +93,173 @@ __global__ __launch_bounds__(TPB) void k_m2l_list(TreeView t, const int* __restr
   }
 }
 
-template <int P, bool F32>
+// Work split: a workgroup of 4 waves owns 4 * NCB consecutive 16-target tiles of one octant and
+// one slice of that octant's offset list (the slices of a target are summed by the downward
+// pass).  For every offset in its slice the workgroup stages K_d in LDS once; each wave then runs
+// the degree-blocked MFMA schedule on NCB target tiles, reusing every K_d block from LDS NCB times.
+// The next offset's K_d is fetched into registers while the current one is being used.
+template <int P, bool F32, int NCB>
 __global__ __launch_bounds__(TPB) void k_m2l(TreeView t, OpTables op, const int* __restrict__ tgt_list,
                                              const int* __restrict__ oct_count,
                                              const int* __restrict__ list,
                                              const double* __restrict__ M, double* __restrict__ F,
-                                             int fp64_max_level, const int* done) {
+                                             int64_t split_stride, int nsplit, int fp64_max_level,
+                                             const int* done) {
   if (done && *done) return;
+  using kt = typename std::conditional<F32, float, double>::type;
+  using acc_t = typename std::conditional<F32, f4, d4>::type;
   constexpr int NRB = sched_nrb(P);
   constexpr int MAXS = sched_maxsteps(P);
   constexpr int NB = sched_nblocks(P);
   constexpr int NC = mi_count(P);
   constexpr int STRIDE = sched_stride(P);
-  const int lane = threadIdx.x & 63;
-  const int wtile = blockIdx.x * WAVES + (threadIdx.x >> 6);
-  int o, seg, in_oct;
-  if (!locate_tile(oct_count, wtile, o, seg, in_oct)) return;
-  const int col = lane & 15;
-  const int tl = in_oct * 16 + col;
-  int B = tl < oct_count[o] ? tgt_list[seg + tl] : -1;
-  if (B >= 0) {
-    const int lev = level_of(t, B);
-    const bool mine = F32 ? (lev > fp64_max_level) : (lev <= fp64_max_level);
-    if (!mine) B = -1;
-  }
-  if (__ballot(B >= 0) == 0) return;
-  const int zero_row = t.ncell;
-  const int kq = lane >> 4;
+  constexpr int KSZ = NB * 64;                 // K_d values per offset
+  constexpr int KPT = (KSZ + TPB - 1) / TPB;   // K_d values staged per thread
+  constexpr int TPW = WAVES * NCB;             // 16-target tiles per workgroup
+  __shared__ kt sK[KSZ];
 
-  using acc_t = typename std::conditional<F32, f4, d4>::type;
-  acc_t acc[NRB];
-#pragma unroll
-  for (int rb = 0; rb < NRB; ++rb) acc[rb] = acc_t{0, 0, 0, 0};
-
-  const int* lst = list + (int64_t)wtile * op.noff * 16 + col;
-  int A_next = lst[0];
-  for (int j = 0; j < op.noff; ++j) {
-    const int A = A_next;
-    if (j + 1 < op.noff) A_next = lst[(j + 1) * 16];
-    const int code = op.m2l_code[o * op.noff + j];
-    if (__ballot(A >= 0 && B >= 0) == 0) continue;
-    const int src = (A >= 0 && B >= 0) ? A : zero_row;
-    const double* Mrow = M + (int64_t)src * STRIDE + kq;
-    const int slot = code & 0xfff;
-    if constexpr (F32) {
-      const float* K = op.kpack32 + (int64_t)slot * NB * 64 + lane;
-      int blk = 0;
-#pragma unroll
-      for (int s = 0; s < MAXS; ++s) {
-        const float b = (float)Mrow[4 * s];
-#pragma unroll
-        for (int rb = 0; rb < NRB; ++rb) {
-          if (sched_nsteps(P, rb) > s) {
-            acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(K[blk * 64], b, acc[rb], 0, 0, 0);
-            ++blk;
-          }
-        }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int split = blockIdx.x % nsplit;
+  const int wg = blockIdx.x / nsplit;
+  // locate the workgroup's octant and its first 16-target tile
+  int o = -1, seg = 0, t16_0 = 0, tiles_before = 0, nt_o = 0;
+  {
+    int wstart = 0, start = 0, tb = 0;
+    for (int oc = 0; oc < 8; ++oc) {
+      const int cnt = oct_count[oc];
+      const int nt = (cnt + 15) >> 4;
+      const int nw = (nt + TPW - 1) / TPW;
+      if (o < 0 && wg < wstart + nw) {
+        o = oc; seg = start; t16_0 = (wg - wstart) * TPW; tiles_before = tb; nt_o = nt;
       }
-    } else {
-      const double* K = op.kpack + (int64_t)slot * NB * 64 + lane;
-      int blk = 0;
+      wstart += nw; start += cnt; tb += nt;
+    }
+  }
+  if (o < 0) return;  // whole workgroup: no barrier has been reached yet
+  const int noff = op.noff;
+  const int j0 = (int)((int64_t)noff * split / nsplit), j1 = (int)((int64_t)noff * (split + 1) / nsplit);
+  const int col = lane & 15, kq = lane >> 4;
+  const int cnt_o = oct_count[o];
+  int B[NCB];
+  const int* lst[NCB];
 #pragma unroll
-      for (int s = 0; s < MAXS; ++s) {
-        const double b = Mrow[4 * s];
+  for (int cb = 0; cb < NCB; ++cb) {
+    const int t16 = t16_0 + wave * NCB + cb;
+    const int tl = t16 * 16 + col;
+    int b = (t16 < nt_o && tl < cnt_o) ? tgt_list[seg + tl] : -1;
+    if (b >= 0) {
+      const int lev = level_of(t, b);
+      if (F32 ? (lev <= fp64_max_level) : (lev > fp64_max_level)) b = -1;
+    }
+    B[cb] = b;
+    lst[cb] = list + ((int64_t)(tiles_before + (t16 < nt_o ? t16 : 0)) * noff) * 16 + col;
+  }
+  {
+    // workgroups whose targets all belong to the other precision's kernel leave together
+    int mine = 0;
 #pragma unroll
-        for (int rb = 0; rb < NRB; ++rb) {
-          if (sched_nsteps(P, rb) > s) {
-            acc[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(K[blk * 64], b, acc[rb], 0, 0, 0);
-            ++blk;
+    for (int cb = 0; cb < NCB; ++cb) mine |= B[cb] >= 0;
+    if (!__syncthreads_or(mine)) return;
+  }
+  const int zero_row = t.ncell;
+  acc_t acc[NCB][NRB];
+#pragma unroll
+  for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+    for (int rb = 0; rb < NRB; ++rb) acc[cb][rb] = acc_t{0, 0, 0, 0};
+
+  const kt* kbase = F32 ? (const kt*)op.kpack32 : (const kt*)op.kpack;
+  kt kreg[KPT];
+  auto fetch_k = [&](int j) {
+    const int slot = op.m2l_code[o * noff + j] & 0xfff;
+    const kt* src = kbase + (int64_t)slot * KSZ;
+#pragma unroll
+    for (int i = 0; i < KPT; ++i) {
+      const int e = threadIdx.x + i * TPB;
+      kreg[i] = e < KSZ ? src[e] : kt(0);
+    }
+  };
+  if (j0 < j1) fetch_k(j0);
+  for (int j = j0; j < j1; ++j) {
+    __syncthreads();  // every wave is done with the previous K_d
+#pragma unroll
+    for (int i = 0; i < KPT; ++i) {
+      const int e = threadIdx.x + i * TPB;
+      if (e < KSZ) sK[e] = kreg[i];
+    }
+    __syncthreads();
+    if (j + 1 < j1) fetch_k(j + 1);
+    int src[NCB];
+    bool any = false;
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) {
+      const int A = B[cb] >= 0 ? lst[cb][j * 16] : -1;
+      src[cb] = A >= 0 ? A : zero_row;
+      any |= A >= 0;
+    }
+    if (__ballot(any) == 0) continue;
+    const kt* K = sK + lane;
+    int blk = 0;
+#pragma unroll
+    for (int s = 0; s < MAXS; ++s) {
+      kt b[NCB];
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) b[cb] = (kt)M[(int64_t)src[cb] * STRIDE + 4 * s + kq];
+#pragma unroll
+      for (int rb = 0; rb < NRB; ++rb) {
+        if (sched_nsteps(P, rb) > s) {
+          const kt a = K[blk * 64];
+#pragma unroll
+          for (int cb = 0; cb < NCB; ++cb) {
+            if constexpr (F32)
+              acc[cb][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b[cb], acc[cb][rb], 0, 0, 0);
+            else
+              acc[cb][rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[cb], acc[cb][rb], 0, 0, 0);
           }
+          ++blk;
         }
       }
     }
   }
-  if (B < 0) return;
-  double* Fr = F + (int64_t)B * STRIDE;
+  double* Fs = F + (int64_t)split * split_stride;
 #pragma unroll
-  for (int rb = 0; rb < NRB; ++rb) {
+  for (int cb = 0; cb < NCB; ++cb) {
+    if (B[cb] < 0) continue;
+    double* Fr = Fs + (int64_t)B[cb] * STRIDE;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      // f64 16x16x4: lane l, register r holds row 4 r + l/16; f32 16x16x4: row 4 (l/16) + r
-      const int row = 16 * rb + (F32 ? (4 * kq + r) : (4 * r + kq));
-      if (row < NC) Fr[row] = (double)acc[rb][r];
+    for (int rb = 0; rb < NRB; ++rb) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        // f64 16x16x4: lane l, register r holds row 4 r + l/16; f32 16x16x4: row 4 (l/16) + r
+        const int row = 16 * rb + (F32 ? (4 * kq + r) : (4 * r + kq));
+        if (row < NC) Fr[row] = (double)acc[cb][rb][r];
+      }
     }
   }
 }
 
 template <int P>
-void m2l_dispatch(const TreeView& t, const OpTables& op, const int* tgt, const int* oc,
-                  const int* list, int nblk, const double* M, double* F, bool fp32, int fp64_max,
-                  const int* done, hipStream_t s) {
+constexpr int ncb_for() { return P <= 6 ? 4 : (P <= 8 ? 2 : 1); }
+
+template <int P>
+int m2l_wgs(const int* oc_host) {
+  int n = 0;
+  for (int o = 0; o < 8; ++o) n += (((oc_host[o] + 15) >> 4) + WAVES * ncb_for<P>() - 1) / (WAVES * ncb_for<P>());
+  return n;
+}
+
+template <int P>
+void m2l_dispatch(const TreeView& t, const OpTables& op, const int* tgt, const int* oc, const int* list,
+                  int nwg, int nsplit, const double* M, double* F, int64_t split_stride, bool fp32,
+                  int fp64_max, const int* done, hipStream_t s) {
+  constexpr int NCB = ncb_for<P>();
+  const int grid = nwg * nsplit;
   if (!fp32 || fp64_max >= 2)
-    hipLaunchKernelGGL((k_m2l<P, false>), dim3(nblk), dim3(TPB), 0, s, t, op, tgt, oc, list, M, F,
-                       fp32 ? fp64_max : t.L, done);
+    hipLaunchKernelGGL((k_m2l<P, false, NCB>), dim3(grid), dim3(TPB), 0, s, t, op, tgt, oc, list, M, F,
+                       split_stride, nsplit, fp32 ? fp64_max : t.L, done);
   if (fp32)
-    hipLaunchKernelGGL((k_m2l<P, true>), dim3(nblk), dim3(TPB), 0, s, t, op, tgt, oc, list, M, F,
-                       fp64_max, done);
+    hipLaunchKernelGGL((k_m2l<P, true, NCB>), dim3(grid), dim3(TPB), 0, s, t, op, tgt, oc, list, M, F,
+                       split_stride, nsplit, fp64_max, done);
 }
 
 }  // namespace
@@ -227,23 +298,35 @@ void launch_m2l_list(const TreeView& t, const OpTables& op, const int* tgt_list,
   PFMM_LAUNCH_CHECK();
 }
 
+int m2l_workgroups(int p, const int* oct_count_host) {
+  switch (p) {
+    case 1: return m2l_wgs<1>(oct_count_host);
+    case 2: return m2l_wgs<2>(oct_count_host);
+    case 3: return m2l_wgs<3>(oct_count_host);
+    case 4: return m2l_wgs<4>(oct_count_host);
+    case 5: return m2l_wgs<5>(oct_count_host);
+    case 6: return m2l_wgs<6>(oct_count_host);
+    case 7: return m2l_wgs<7>(oct_count_host);
+    case 8: return m2l_wgs<8>(oct_count_host);
+    case 9: return m2l_wgs<9>(oct_count_host);
+    case 10: return m2l_wgs<10>(oct_count_host);
+  }
+  throw Error(PFMM_ERR_INVALID_ARG, "order_p out of range");
+}
+
 void launch_m2l(const TreeView& t, const OpTables& op, const int* tgt_list, const int* oct_count,
-                int ntgt, const int* list, const double* M, double* F, bool fp32, int fp64_max_level,
-                const int* done, hipStream_t s) {
-  if (ntgt <= 0) return;
-  const int ntiles = m2l_max_tiles(ntgt);
-  const int nblk = (ntiles + WAVES - 1) / WAVES;
+                int nwg, int nsplit, const int* list, const double* M, double* F, int64_t split_stride,
+                bool fp32, int fp64_max_level, const int* done, hipStream_t s) {
+  if (nwg <= 0) return;
   switch (op.p) {
-    case 1: m2l_dispatch<1>(t, op, tgt_list, oct_count, list, nblk, M, F, fp32, fp64_max_level, done, s); break;
-    case 2: m2l_dispatch<2>(t, op, tgt_list, oct_count, list, nblk, M, F, fp32, fp64_max_level, done, s); break;
-    case 3: m2l_dispatch<3>(t, op, tgt_list, oct_count, list, nblk, M, F, fp32, fp64_max_level, done, s); break;
-    case 4: m2l_dispatch<4>(t, op, tgt_list, oct_count, list, nblk, M, F, fp32, fp64_max_level, done, s); break;
-    case 5: m2l_dispatch<5>(t, op, tgt_list, oct_count, list, nblk, M, F, fp32, fp64_max_level, done, s); break;
-    case 6: m2l_dispatch<6>(t, op, tgt_list, oct_count, list, nblk, M, F, fp32, fp64_max_level, done, s); break;
-    case 7: m2l_dispatch<7>(t, op, tgt_list, oct_count, list, nblk, M, F, fp32, fp64_max_level, done, s); break;
-    case 8: m2l_dispatch<8>(t, op, tgt_list, oct_count, list, nblk, M, F, fp32, fp64_max_level, done, s); break;
-    case 9: m2l_dispatch<9>(t, op, tgt_list, oct_count, list, nblk, M, F, fp32, fp64_max_level, done, s); break;
-    case 10: m2l_dispatch<10>(t, op, tgt_list, oct_count, list, nblk, M, F, fp32, fp64_max_level, done, s); break;
+#define PFMM_M2L_CASE(PP)                                                                            \
+  case PP:                                                                                           \
+    m2l_dispatch<PP>(t, op, tgt_list, oct_count, list, nwg, nsplit, M, F, split_stride, fp32,        \
+                     fp64_max_level, done, s);                                                       \
+    break;
+    PFMM_M2L_CASE(1) PFMM_M2L_CASE(2) PFMM_M2L_CASE(3) PFMM_M2L_CASE(4) PFMM_M2L_CASE(5)
+    PFMM_M2L_CASE(6) PFMM_M2L_CASE(7) PFMM_M2L_CASE(8) PFMM_M2L_CASE(9) PFMM_M2L_CASE(10)
+#undef PFMM_M2L_CASE
     default: throw Error(PFMM_ERR_INVALID_ARG, "order_p out of range");
   }
   PFMM_LAUNCH_CHECK();

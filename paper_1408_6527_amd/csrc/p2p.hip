@@ -1,10 +1,13 @@
 // Near field by direct summation over neighbouring leaves (the direct component of Sec. III),
 // with true point dipoles and Thole damping of dipole-dipole pairs.
 //
-// One wavefront per target leaf.  The wave walks the leaf's colleagues (Chebyshev distance <= ws);
-// each colleague's particles are staged in LDS 64 at a time and every lane (one target particle)
-// sweeps the staged sources, reading them as LDS broadcasts.  Results are added to the far-field
-// values already written by L2P.
+// One wavefront per target leaf.  The sources of all colleague leaves (Chebyshev distance <= ws)
+// are walked as one concatenated sequence and staged in LDS 64 at a time, densely, whatever the
+// leaf occupancy.  A leaf holds only a few particles at protein density, so each target is served
+// by G = 64 / T lanes (T = its occupancy rounded up to a power of two); every lane sweeps a
+// 1/G slice of each staged chunk, and the G partial sums of a target are combined at the end by a
+// butterfly of cross-lane exchanges (fixed order, deterministic).  Results are added to the
+// far-field values already written by L2P.
 //
 // Pair kernels, with r = x_i - x_j, u = r/|r|:
 //   charge  q_j:  phi += q/r,  E += q r/r^3,  d_a E_b += q (delta_ab/r^3 - 3 r_a r_b/r^5)
@@ -25,6 +28,7 @@ namespace pfmm {
 namespace {
 
 constexpr int TPB = 64;
+constexpr int MAXNN = 125;  // colleagues per leaf at ws = 2
 
 __device__ inline double rsqrt_t(double x) { return rsqrt(x); }
 __device__ inline float rsqrt_t(float x) { return rsqrtf(x); }
@@ -36,11 +40,40 @@ __global__ __launch_bounds__(TPB) void k_p2p(TreeView t, Particles pa, const dou
   if (done && *done) return;
   constexpr bool HQ = (SRC & 1) != 0;
   constexpr bool HM = (SRC & 2) != 0;
+  constexpr bool STAGE_MU = HM || MODE == 2;
+  __shared__ int s_pref[MAXNN + 1], s_first[MAXNN];
   __shared__ T sx[TPB], sy[TPB], sz[TPB], sq[TPB], smx[TPB], smy[TPB], smz[TPB], sit[TPB];
   __shared__ int sidx[TPB];
   const int g = t.off[t.L] + blockIdx.x;
   const int first = t.first[g], cnt = t.count[g];
   const int lane = threadIdx.x;
+  const int nn = t.nnear;
+
+  // exclusive prefix of the colleague occupancies (up to 125 entries, two per lane)
+  {
+    int c0 = 0, c1 = 0, f0 = 0, f1 = 0;
+    if (lane < nn) {
+      const int A = t.coll[(int64_t)g * nn + lane];
+      if (A >= 0) { c0 = t.count[A]; f0 = t.first[A]; }
+    }
+    if (lane + TPB < nn) {
+      const int A = t.coll[(int64_t)g * nn + lane + TPB];
+      if (A >= 0) { c1 = t.count[A]; f1 = t.first[A]; }
+    }
+    int i0 = c0, i1 = c1;
+    for (int d = 1; d < TPB; d <<= 1) {
+      const int u0 = __shfl_up(i0, d), u1 = __shfl_up(i1, d);
+      if (lane >= d) { i0 += u0; i1 += u1; }
+    }
+    const int tot0 = __shfl(i0, TPB - 1);
+    if (lane < nn) { s_pref[lane] = i0 - c0; s_first[lane] = f0; }
+    if (lane + TPB < nn) { s_pref[lane + TPB] = tot0 + i1 - c1; s_first[lane + TPB] = f1; }
+    const int tot = tot0 + __shfl(i1, TPB - 1);
+    if (lane == 0) s_pref[nn] = tot;
+  }
+  __syncthreads();
+  const int total = s_pref[nn];
+
   double cen[3];
   {
     const uint64_t k = t.key[g];
@@ -48,8 +81,13 @@ __global__ __launch_bounds__(TPB) void k_p2p(TreeView t, Particles pa, const dou
     cen[1] = t.origin[1] + ((double)compact3(k >> 1) + 0.5) * t.w;
     cen[2] = t.origin[2] + ((double)compact3(k) + 0.5) * t.w;
   }
+  // lanes per target: T targets per pass (a power of two), G = 64 / T lanes each
+  const int T_ = cnt >= TPB ? TPB : (cnt <= 1 ? 1 : (1 << (32 - __clz(cnt - 1))));
+  const int G = TPB / T_;
+  const int slot = lane & (T_ - 1), slice = lane / T_;
+
   for (int t0 = 0; t0 < cnt; t0 += TPB) {
-    const int li = t0 + lane;
+    const int li = t0 + slot;
     const bool active = li < cnt;
     const int i = first + (active ? li : 0);
     const double4 Pi = pa.P[i];
@@ -61,96 +99,112 @@ __global__ __launch_bounds__(TPB) void k_p2p(TreeView t, Particles pa, const dou
     T gxx = 0, gyy = 0, gzz = 0, gxy = 0, gxz = 0, gyz = 0;
     double dsum = 0.0;
     int bad = 0;
-    for (int k = 0; k < t.nnear; ++k) {
-      const int A = t.coll[(int64_t)g * t.nnear + k];
-      if (A < 0) continue;
-      const int sf = t.first[A], sc = t.count[A];
-      for (int s0 = 0; s0 < sc; s0 += TPB) {
-        const int m = min(TPB, sc - s0);
-        __syncthreads();
-        if (lane < m) {
-          const int j = sf + s0 + lane;
-          const double4 Pj = pa.P[j];
-          sx[lane] = (T)(Pj.x - cen[0]);
-          sy[lane] = (T)(Pj.y - cen[1]);
-          sz[lane] = (T)(Pj.z - cen[2]);
-          sq[lane] = (T)Pj.w;
-          if (HM || MODE == 2) {
-            const double4 u = mu4[j];
-            smx[lane] = (T)u.x; smy[lane] = (T)u.y; smz[lane] = (T)u.z;
-          }
-          sit[lane] = (T)pa.itau[j];
-          sidx[lane] = j;
+    for (int S0 = 0; S0 < total; S0 += TPB) {
+      const int m = min(TPB, total - S0);
+      __syncthreads();
+      if (lane < m) {
+        const int idx = S0 + lane;
+        int lo = 0, hi = nn - 1;  // last colleague k with s_pref[k] <= idx
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (s_pref[mid] <= idx) lo = mid; else hi = mid - 1;
         }
-        __syncthreads();
-        if (!active) continue;
-        for (int jj = 0; jj < m; ++jj) {
-          const T rx = xi - sx[jj], ry = yi - sy[jj], rz = zi - sz[jj];
-          const T r2 = rx * rx + ry * ry + rz * rz;
-          const bool valid = r2 > T(0);
-          if (MODE == 1 && !valid && sidx[jj] != i) bad = 1;
-          const T rinv = valid ? rsqrt_t(valid ? r2 : T(1)) : T(0);
-          const T rinv2 = rinv * rinv;
-          const T rinv3 = rinv * rinv2;
-          if (MODE == 1 && HQ) {
-            const T qj = sq[jj];
-            const T qr3 = qj * rinv3;
-            phi += qj * rinv;
-            const T ex = qr3 * rx, ey = qr3 * ry, ez = qr3 * rz;
-            eux += ex; euy += ey; euz += ez;
-            edx += ex; edy += ey; edz += ez;
-            const T c5 = T(3) * qr3 * rinv2;
-            gxx += qr3 - c5 * rx * rx; gyy += qr3 - c5 * ry * ry; gzz += qr3 - c5 * rz * rz;
-            gxy -= c5 * rx * ry; gxz -= c5 * rx * rz; gyz -= c5 * ry * rz;
-          }
-          if (MODE == 2) {
-            // Thole term of dU/dalpha_i: (2 v^4 (mu_i.u)(mu_j.u) - 2 (v^3 - v^4) mu_i.mu_j) / (alpha_i r^3)
-            const T ii = iti * sit[jj];
-            const T rr = r2 * rinv;
-            const T v = ii > T(0) ? fmin(rr * ii, T(1)) : T(1);
-            if (valid && v < T(1)) {
-              const T v3 = v * v * v, v4 = v3 * v;
-              const T miu = (T(mui.x) * rx + T(mui.y) * ry + T(mui.z) * rz) * rinv;
-              const T mju = (smx[jj] * rx + smy[jj] * ry + smz[jj] * rz) * rinv;
-              const T mm = T(mui.x) * smx[jj] + T(mui.y) * smy[jj] + T(mui.z) * smz[jj];
-              dsum += (double)((T(2) * v4 * miu * mju - T(2) * (v3 - v4) * mm) * rinv3);
-            }
-          }
-          if ((MODE == 0 || MODE == 1) && HM) {
-            const T mx = smx[jj], my = smy[jj], mz = smz[jj];
-            const T rmu = rx * mx + ry * my + rz * mz;
-            const T ii = iti * sit[jj];
-            const T rr = r2 * rinv;
-            const T v = ii > T(0) ? fmin(rr * ii, T(1)) : T(1);
+        const int j = s_first[lo] + idx - s_pref[lo];
+        const double4 Pj = pa.P[j];
+        sx[lane] = (T)(Pj.x - cen[0]);
+        sy[lane] = (T)(Pj.y - cen[1]);
+        sz[lane] = (T)(Pj.z - cen[2]);
+        sq[lane] = (T)Pj.w;
+        if (STAGE_MU) {
+          const double4 u = mu4[j];
+          smx[lane] = (T)u.x; smy[lane] = (T)u.y; smz[lane] = (T)u.z;
+        }
+        sit[lane] = (T)pa.itau[j];
+        sidx[lane] = j;
+      }
+      __syncthreads();
+      if (!active) continue;
+      for (int jj = slice; jj < m; jj += G) {
+        const T rx = xi - sx[jj], ry = yi - sy[jj], rz = zi - sz[jj];
+        const T r2 = rx * rx + ry * ry + rz * rz;
+        const bool valid = r2 > T(0);
+        if (MODE == 1 && !valid && sidx[jj] != i) bad = 1;
+        const T rinv = valid ? rsqrt_t(valid ? r2 : T(1)) : T(0);
+        const T rinv2 = rinv * rinv;
+        const T rinv3 = rinv * rinv2;
+        if (MODE == 1 && HQ) {
+          const T qj = sq[jj];
+          const T qr3 = qj * rinv3;
+          phi += qj * rinv;
+          const T ex = qr3 * rx, ey = qr3 * ry, ez = qr3 * rz;
+          eux += ex; euy += ey; euz += ez;
+          edx += ex; edy += ey; edz += ez;
+          const T c5 = T(3) * qr3 * rinv2;
+          gxx += qr3 - c5 * rx * rx; gyy += qr3 - c5 * ry * ry; gzz += qr3 - c5 * rz * rz;
+          gxy -= c5 * rx * ry; gxz -= c5 * rx * rz; gyz -= c5 * ry * rz;
+        }
+        if (MODE == 2) {
+          // Thole term of dU/dalpha_i: (2 v^4 (mu_i.u)(mu_j.u) - 2 (v^3 - v^4) mu_i.mu_j) / (alpha_i r^3)
+          const T ii = iti * sit[jj];
+          const T rr = r2 * rinv;
+          const T v = ii > T(0) ? fmin(rr * ii, T(1)) : T(1);
+          if (valid && v < T(1)) {
             const T v3 = v * v * v, v4 = v3 * v;
-            const T ft = v4, fe = v3 * (T(4) - T(3) * v);
-            const T c3 = T(3) * ft * rmu * rinv2;
-            edx += (c3 * rx - fe * mx) * rinv3;
-            edy += (c3 * ry - fe * my) * rinv3;
-            edz += (c3 * rz - fe * mz) * rinv3;
-            if (MODE == 1) {
-              phi += rmu * rinv3;
-              const T cu = T(3) * rmu * rinv2;
-              eux += (cu * rx - mx) * rinv3;
-              euy += (cu * ry - my) * rinv3;
-              euz += (cu * rz - mz) * rinv3;
-              const T Ac = (v < T(1)) ? T(-3) * v4 : T(-15);
-              const T Bc = T(3) * v4;
-              const T rinv5 = rinv3 * rinv2;
-              const T a7 = Ac * rmu * rinv5 * rinv2;  // A (u.mu) u_a u_b / r^4 = A rmu r_a r_b / r^7
-              const T b5 = Bc * rinv5;
-              gxx += a7 * rx * rx + b5 * (rmu + T(2) * rx * mx);
-              gyy += a7 * ry * ry + b5 * (rmu + T(2) * ry * my);
-              gzz += a7 * rz * rz + b5 * (rmu + T(2) * rz * mz);
-              gxy += a7 * rx * ry + b5 * (rx * my + ry * mx);
-              gxz += a7 * rx * rz + b5 * (rx * mz + rz * mx);
-              gyz += a7 * ry * rz + b5 * (ry * mz + rz * my);
-            }
+            const T miu = (T(mui.x) * rx + T(mui.y) * ry + T(mui.z) * rz) * rinv;
+            const T mju = (smx[jj] * rx + smy[jj] * ry + smz[jj] * rz) * rinv;
+            const T mm = T(mui.x) * smx[jj] + T(mui.y) * smy[jj] + T(mui.z) * smz[jj];
+            dsum += (double)((T(2) * v4 * miu * mju - T(2) * (v3 - v4) * mm) * rinv3);
+          }
+        }
+        if ((MODE == 0 || MODE == 1) && HM) {
+          const T mx = smx[jj], my = smy[jj], mz = smz[jj];
+          const T rmu = rx * mx + ry * my + rz * mz;
+          const T ii = iti * sit[jj];
+          const T rr = r2 * rinv;
+          const T v = ii > T(0) ? fmin(rr * ii, T(1)) : T(1);
+          const T v3 = v * v * v, v4 = v3 * v;
+          const T ft = v4, fe = v3 * (T(4) - T(3) * v);
+          const T c3 = T(3) * ft * rmu * rinv2;
+          edx += (c3 * rx - fe * mx) * rinv3;
+          edy += (c3 * ry - fe * my) * rinv3;
+          edz += (c3 * rz - fe * mz) * rinv3;
+          if (MODE == 1) {
+            phi += rmu * rinv3;
+            const T cu = T(3) * rmu * rinv2;
+            eux += (cu * rx - mx) * rinv3;
+            euy += (cu * ry - my) * rinv3;
+            euz += (cu * rz - mz) * rinv3;
+            const T Ac = (v < T(1)) ? T(-3) * v4 : T(-15);
+            const T Bc = T(3) * v4;
+            const T rinv5 = rinv3 * rinv2;
+            const T a7 = Ac * rmu * rinv5 * rinv2;  // A (u.mu) u_a u_b / r^4 = A rmu r_a r_b / r^7
+            const T b5 = Bc * rinv5;
+            gxx += a7 * rx * rx + b5 * (rmu + T(2) * rx * mx);
+            gyy += a7 * ry * ry + b5 * (rmu + T(2) * ry * my);
+            gzz += a7 * rz * rz + b5 * (rmu + T(2) * rz * mz);
+            gxy += a7 * rx * ry + b5 * (rx * my + ry * mx);
+            gxz += a7 * rx * rz + b5 * (rx * mz + rz * mx);
+            gyz += a7 * ry * rz + b5 * (ry * mz + rz * my);
           }
         }
       }
     }
-    if (!active) continue;
+    // combine the G slices of every target (lanes slot, slot + T, slot + 2T, ...)
+    for (int msk = T_; msk < TPB; msk <<= 1) {
+      if (MODE == 0) {
+        edx += __shfl_xor(edx, msk); edy += __shfl_xor(edy, msk); edz += __shfl_xor(edz, msk);
+      } else if (MODE == 1) {
+        phi += __shfl_xor(phi, msk);
+        eux += __shfl_xor(eux, msk); euy += __shfl_xor(euy, msk); euz += __shfl_xor(euz, msk);
+        edx += __shfl_xor(edx, msk); edy += __shfl_xor(edy, msk); edz += __shfl_xor(edz, msk);
+        gxx += __shfl_xor(gxx, msk); gyy += __shfl_xor(gyy, msk); gzz += __shfl_xor(gzz, msk);
+        gxy += __shfl_xor(gxy, msk); gxz += __shfl_xor(gxz, msk); gyz += __shfl_xor(gyz, msk);
+        bad |= __shfl_xor(bad, msk);
+      } else {
+        dsum += __shfl_xor(dsum, msk);
+      }
+    }
+    if (!active || slice != 0) continue;
     if (bad) atomicOr(err, 1);
     if (MODE == 0) {
       out.Ed[3 * i] += (double)edx; out.Ed[3 * i + 1] += (double)edy; out.Ed[3 * i + 2] += (double)edz;
@@ -158,9 +212,9 @@ __global__ __launch_bounds__(TPB) void k_p2p(TreeView t, Particles pa, const dou
       out.phi[i] += (double)phi;
       out.Eu[3 * i] += (double)eux; out.Eu[3 * i + 1] += (double)euy; out.Eu[3 * i + 2] += (double)euz;
       out.Ed[3 * i] += (double)edx; out.Ed[3 * i + 1] += (double)edy; out.Ed[3 * i + 2] += (double)edz;
-      double* G = out.G + 6 * (int64_t)i;
-      G[0] += (double)gxx; G[1] += (double)gyy; G[2] += (double)gzz;
-      G[3] += (double)gxy; G[4] += (double)gxz; G[5] += (double)gyz;
+      double* G6 = out.G + 6 * (int64_t)i;
+      G6[0] += (double)gxx; G6[1] += (double)gyy; G6[2] += (double)gzz;
+      G6[3] += (double)gxy; G6[4] += (double)gxz; G6[5] += (double)gyz;
     } else {
       const double ai = pa.alpha[i];
       dal[i] = ai > 0.0 ? dsum / ai : 0.0;
