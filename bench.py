@@ -49,6 +49,9 @@ def parse():
     ap.add_argument("--oracle-sample", type=int, default=192)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", default="both", choices=["fp64", "mixed", "both"])
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="run one device-to-device copy of this many MiB before the benchmark, so that a "
+                         "profiler's memory counters can be calibrated against a kernel of known traffic")
     return ap.parse_args()
 
 
@@ -74,6 +77,12 @@ def main():
     q = torch.as_tensor(ps.q, dtype=torch.float64, device=dev)
     al = torch.as_tensor(ps.alpha, dtype=torch.float64, device=dev)
     torch.cuda.synchronize()
+    if args.copy_probe_mib > 0:
+        src = torch.ones(args.copy_probe_mib * (1 << 20) // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     def make(prec, timing=False):
         return api.Solver(order_p=wl["p"], ws=wl["ws"], leaf_width=wl["leaf"], scf_tol=wl["tol"],
