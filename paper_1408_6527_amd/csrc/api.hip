@@ -368,9 +368,9 @@ void build_tree(pfmm_handle* h, int n, const double* pos, const double* q, const
   h->m2l_wg = h->ntgt > 0 ? m2l_workgroups(h->op.p, octh) : 0;
   h->nsplit = 1;
   if (h->m2l_wg > 0) {
-    const int want_wg = 1024;  // 4 workgroups of 4 waves per CU
-    h->nsplit = std::max(1, std::min(8, (want_wg + h->m2l_wg - 1) / h->m2l_wg));
-    h->nsplit = std::min(h->nsplit, std::max(1, h->op.noff / 8));
+    const int want_wg = 2048;  // 8 workgroups of 4 waves per CU
+    h->nsplit = std::max(1, std::min(32, (want_wg + h->m2l_wg - 1) / h->m2l_wg));
+    h->nsplit = std::min(h->nsplit, std::max(1, h->op.noff / 16));
   }
   // expansions (one extra zero row serves empty M2L sources); F holds nsplit partial copies
   const int64_t rows = (int64_t)ncell + 1;

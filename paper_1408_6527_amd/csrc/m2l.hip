@@ -99,7 +99,7 @@ __global__ __launch_bounds__(TPB) void k_m2l_list(TreeView t, const int* __restr
 // the degree-blocked MFMA schedule on NCB target tiles, reusing every K_d block from LDS NCB times.
 // The next offset's K_d is fetched into registers while the current one is being used.
 template <int P, bool F32, int NCB>
-__global__ __launch_bounds__(TPB) void k_m2l(TreeView t, OpTables op, const int* __restrict__ tgt_list,
+__global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2))) void k_m2l(TreeView t, OpTables op, const int* __restrict__ tgt_list,
                                              const int* __restrict__ oct_count,
                                              const int* __restrict__ list,
                                              const double* __restrict__ M, double* __restrict__ F,
@@ -201,22 +201,30 @@ __global__ __launch_bounds__(TPB) void k_m2l(TreeView t, OpTables op, const int*
     const kt* K = sK + lane;
     int blk = 0;
 #pragma unroll
-    for (int s = 0; s < MAXS; ++s) {
-      kt b[NCB];
+    for (int s2 = 0; s2 < MAXS; s2 += 2) {
+      // one 16-byte load per lane serves steps s2 and s2 + 1 (coefficients m(s2, q), m(s2, q) + 1)
+      double2 bb[NCB];
 #pragma unroll
-      for (int cb = 0; cb < NCB; ++cb) b[cb] = (kt)M[(int64_t)src[cb] * STRIDE + 4 * s + kq];
+      for (int cb = 0; cb < NCB; ++cb)
+        bb[cb] = *reinterpret_cast<const double2*>(M + (int64_t)src[cb] * STRIDE + sched_coef(s2, kq));
 #pragma unroll
-      for (int rb = 0; rb < NRB; ++rb) {
-        if (sched_nsteps(P, rb) > s) {
-          const kt a = K[blk * 64];
+      for (int h = 0; h < 2; ++h) {
+        const int s = s2 + h;
+        if (s >= MAXS) break;
 #pragma unroll
-          for (int cb = 0; cb < NCB; ++cb) {
-            if constexpr (F32)
-              acc[cb][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b[cb], acc[cb][rb], 0, 0, 0);
-            else
-              acc[cb][rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[cb], acc[cb][rb], 0, 0, 0);
+        for (int rb = 0; rb < NRB; ++rb) {
+          if (sched_nsteps(P, rb) > s) {
+            const kt a = K[blk * 64];
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) {
+              const kt b = (kt)(h == 0 ? bb[cb].x : bb[cb].y);
+              if constexpr (F32)
+                acc[cb][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[cb][rb], 0, 0, 0);
+              else
+                acc[cb][rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[cb][rb], 0, 0, 0);
+            }
+            ++blk;
           }
-          ++blk;
         }
       }
     }
@@ -239,7 +247,7 @@ __global__ __launch_bounds__(TPB) void k_m2l(TreeView t, OpTables op, const int*
 }
 
 template <int P>
-constexpr int ncb_for() { return P <= 6 ? 4 : (P <= 8 ? 2 : 1); }
+constexpr int ncb_for() { return P <= 4 ? 4 : (P <= 6 ? 3 : (P <= 8 ? 2 : 1)); }
 
 template <int P>
 int m2l_wgs(const int* oc_host) {

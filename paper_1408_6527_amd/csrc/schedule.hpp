@@ -4,11 +4,14 @@
 // Multi-indices n with |n| <= p are ordered by degree.  The M2L of Sec. II.B,
 //   F_n = sum_{|m| <= p - |n|} M_m D_{n+m},
 // is a matrix product F = K M with K[n][m] = D_{n+m} where |n| + |m| <= p and 0 elsewhere.
-// Rows are cut into blocks of 16 (the MFMA tile height) and columns into steps of 4 (the MFMA
-// reduction depth).  Row block rb starts at degree dmin(rb), so only its first
-// count(p - dmin(rb)) columns can be non-zero: the staircase of the truncation is skipped at
-// 16 x 4 granularity.  Blocks are visited step-major: for each step s, every row block that
-// still has columns at s.
+// Rows are cut into blocks of 16 (the MFMA tile height).  The reduction runs in steps of 4
+// coefficients, one per lane quarter q = 0..3; step s reads coefficient
+//   m(s, q) = 8 (s / 2) + 2 q + (s % 2),
+// so that each lane's two consecutive steps are two adjacent coefficients (one 16-byte load) and
+// the four quarters of a 16-target tile cover 8 adjacent coefficients of each source row.
+// Row block rb starts at degree dmin(rb), so only its first count(p - dmin(rb)) coefficients can be
+// non-zero: the blocks of the truncation staircase that are all zero are skipped.  Blocks are
+// visited step-major: for each step s, every row block that still has coefficients at s.
 #pragma once
 
 namespace pfmm {
@@ -16,15 +19,20 @@ namespace pfmm {
 // number of multi-indices of degree <= d in 3D: C(d + 3, 3)
 __host__ __device__ constexpr int mi_count(int d) { return d < 0 ? 0 : (d + 1) * (d + 2) * (d + 3) / 6; }
 __host__ __device__ constexpr int sched_nc(int p) { return mi_count(p); }
-__host__ __device__ constexpr int sched_stride(int p) { return (mi_count(p) + 3) / 4 * 4; }
+__host__ __device__ constexpr int sched_stride(int p) { return (mi_count(p) + 7) / 8 * 8; }
+// coefficient read by lane quarter q at step s
+__host__ __device__ constexpr int sched_coef(int s, int q) { return 8 * (s / 2) + 2 * q + (s % 2); }
 __host__ __device__ constexpr int sched_nrb(int p) { return (mi_count(p) + 15) / 16; }
 __host__ __device__ constexpr int sched_deg_of(int row) {
   int d = 0;
   while (mi_count(d) <= row) ++d;
   return d;
 }
+// steps s whose quarter-0 coefficient is still inside row block rb's non-zero columns
 __host__ __device__ constexpr int sched_nsteps(int p, int rb) {
-  return (mi_count(p - sched_deg_of(16 * rb)) + 3) / 4;
+  int s = 0;
+  while (sched_coef(s, 0) < mi_count(p - sched_deg_of(16 * rb))) ++s;
+  return s;
 }
 __host__ __device__ constexpr int sched_maxsteps(int p) { return sched_nsteps(p, 0); }
 __host__ __device__ constexpr int sched_nblocks(int p) {

@@ -192,7 +192,7 @@ void HostTables::build(int p_, int ws_) {
   }
 
   // K tables for every offset slot in MFMA operand order: block (rb, s) holds 64 values, lane l
-  // carrying K[16 rb + (l & 15)][4 s + (l >> 4)].
+  // carrying K[16 rb + (l & 15)][m(s, l >> 4)] (schedule.hpp).
   kpack.assign((size_t)nslot * nblocks * 64, 0.0);
   std::vector<double> Dn(nc);
   std::vector<int> degv(nc);
@@ -211,7 +211,7 @@ void HostTables::build(int p_, int ws_) {
           for (int rb = 0; rb < nrb; ++rb) {
             if (sched_nsteps(p, rb) <= s) continue;
             for (int l = 0; l < 64; ++l) {
-              const int row = 16 * rb + (l & 15), col = 4 * s + (l >> 4);
+              const int row = 16 * rb + (l & 15), col = sched_coef(s, l >> 4);
               double v = 0.0;
               if (row < nc && col < nc && degv[row] + degv[col] <= p)
                 v = Dn[ix.at(mi[3 * row] + mi[3 * col], mi[3 * row + 1] + mi[3 * col + 1],
