@@ -93,43 +93,104 @@ __global__ __launch_bounds__(P2M_TPB) void k_p2m(TreeView t, OpTables op, Partic
 }
 
 constexpr int SH_TPB = 128;
+constexpr int MAX_STRIDE = 288;  // row stride of an expansion at p = 10
 
-// One block per parent cell: M~(parent) = sum over children of the octant's shift matrix.
+__host__ __device__ constexpr int mi_index(int nx, int ny, int nz) {
+  // position of n = (nx, ny, nz) in the degree-major order (descending nx, then descending ny)
+  return mi_count(nx + ny + nz - 1) + (ny + nz) * (ny + nz + 1) / 2 + nz;
+}
+
+// (+-1/4)^e / e! for e = 0..MAX_P: the per-axis factors of the shift coefficients x^k / k! with
+// |x_a| = 1/4 of the cell edge of the parent (child centre offset from the parent centre)
+__device__ inline void quarter_powers(double* plus, double* minus, int p) {
+  double v = 1.0;
+  for (int e = 0; e <= p; ++e) {
+    plus[e] = v;
+    minus[e] = (e & 1) ? -v : v;
+    v *= 0.25 / (double)(e + 1);
+  }
+}
+
+// One block per parent cell.  M~_n(parent) = sum_children sum_{k <= n} xt^k/k! 2^-(|n|-|k|) M~_{n-k}(child)
+// with xt = 1/4 - o/2 per axis for the child in octant o (+1/4 for bit 0, -1/4 for bit 1).  The
+// children's rows are staged in LDS and the coefficients are formed on the fly from per-axis
+// factors, so the kernel reads each child row once and no table.
 __global__ __launch_bounds__(SH_TPB) void k_m2m(TreeView t, OpTables op, int lp,
                                                 double* __restrict__ M, const int* done) {
   if (done && *done) return;
+  __shared__ double sM[8][MAX_STRIDE];
+  __shared__ double qp[2][MAX_P + 1];
+  __shared__ int ch[8];
   const int g = t.off[lp] + blockIdx.x;
-  int ch[8];
-  for (int o = 0; o < 8; ++o) ch[o] = t.child8[8 * g + o];
+  const int nc = op.nc, p = op.p;
+  if (threadIdx.x < 8) ch[threadIdx.x] = t.child8[8 * g + threadIdx.x];
+  if (threadIdx.x == 0) quarter_powers(qp[0], qp[1], p);
+  __syncthreads();
+  for (int o = 0; o < 8; ++o) {
+    const int c = ch[o];
+    for (int k = threadIdx.x; k < nc; k += SH_TPB) sM[o][k] = c >= 0 ? M[(int64_t)c * op.stride + k] : 0.0;
+  }
+  __syncthreads();
   for (int k = threadIdx.x; k < op.stride; k += SH_TPB) {
     double acc = 0.0;
-    if (k < op.nc) {
+    if (k < nc) {
+      const int nx = op.mi[3 * k], ny = op.mi[3 * k + 1], nz = op.mi[3 * k + 2];
+      const int dn = nx + ny + nz;
       for (int o = 0; o < 8; ++o) {
         if (ch[o] < 0) continue;
-        const double* Mc = M + (int64_t)ch[o] * op.stride;
-        const int b = op.m2m_ptr[o * (op.nc + 1) + k], e = op.m2m_ptr[o * (op.nc + 1) + k + 1];
-        for (int j = b; j < e; ++j) acc += op.m2m_val[j] * Mc[op.m2m_col[j]];
+        const double* fx = qp[(o >> 2) & 1];
+        const double* fy = qp[(o >> 1) & 1];
+        const double* fz = qp[o & 1];
+        for (int kx = 0; kx <= nx; ++kx)
+          for (int ky = 0; ky <= ny; ++ky) {
+            const double cxy = fx[kx] * fy[ky];
+            for (int kz = 0; kz <= nz; ++kz) {
+              const int dm = dn - kx - ky - kz;  // |n - k|
+              acc += ldexp(cxy * fz[kz], -dm) * sM[o][mi_index(nx - kx, ny - ky, nz - kz)];
+            }
+          }
       }
     }
     M[(int64_t)g * op.stride + k] = acc;
   }
 }
 
-// One block per child cell: F~(child) += partial M2L sums of the other offset splits, then the
-// shift of F~(parent) (levels >= 3; the parent row is complete because levels run top-down).
+// One block per child cell: F~(child) += partial M2L sums of the other offset splits, then, from
+// level 3 on, F~_n(child) += 2^-(|n|+1) sum_{|k| <= p-|n|} xl^k/k! F~_{n+k}(parent) with
+// xl = o/2 - 1/4 per axis (the parent row is complete because levels run top-down).
 __global__ __launch_bounds__(SH_TPB) void k_l2l(TreeView t, OpTables op, int lc, double* F,
                                                 int nsplit, int64_t split_stride, const int* done) {
   if (done && *done) return;
+  __shared__ double sF[MAX_STRIDE];
+  __shared__ double qp[2][MAX_P + 1];
   const int g = t.off[lc] + blockIdx.x;
-  const int par = t.parent[g];
+  const int nc = op.nc, p = op.p;
   const int o = (int)(t.key[g] & 7);
-  const double* Fp = F + (int64_t)par * op.stride;
-  for (int k = threadIdx.x; k < op.nc; k += SH_TPB) {
+  if (lc >= 3) {
+    const int par = t.parent[g];
+    for (int k = threadIdx.x; k < nc; k += SH_TPB) sF[k] = F[(int64_t)par * op.stride + k];
+    if (threadIdx.x == 0) quarter_powers(qp[0], qp[1], p);
+  }
+  __syncthreads();
+  // xl = +1/4 for bit 1, -1/4 for bit 0
+  const double* fx = qp[((o >> 2) & 1) ^ 1];
+  const double* fy = qp[((o >> 1) & 1) ^ 1];
+  const double* fz = qp[(o & 1) ^ 1];
+  for (int k = threadIdx.x; k < nc; k += SH_TPB) {
     double acc = 0.0;
     for (int sp = 1; sp < nsplit; ++sp) acc += F[sp * split_stride + (int64_t)g * op.stride + k];
     if (lc >= 3) {
-      const int b = op.l2l_ptr[o * (op.nc + 1) + k], e = op.l2l_ptr[o * (op.nc + 1) + k + 1];
-      for (int j = b; j < e; ++j) acc += op.l2l_val[j] * Fp[op.l2l_col[j]];
+      const int nx = op.mi[3 * k], ny = op.mi[3 * k + 1], nz = op.mi[3 * k + 2];
+      const int dn = nx + ny + nz;
+      const int rem = p - dn;
+      double sh = 0.0;
+      for (int kx = 0; kx <= rem; ++kx)
+        for (int ky = 0; ky <= rem - kx; ++ky) {
+          const double cxy = fx[kx] * fy[ky];
+          for (int kz = 0; kz <= rem - kx - ky; ++kz)
+            sh += cxy * fz[kz] * sF[mi_index(nx + kx, ny + ky, nz + kz)];
+        }
+      acc += ldexp(sh, -(dn + 1));
     }
     F[(int64_t)g * op.stride + k] += acc;
   }
@@ -138,10 +199,12 @@ __global__ __launch_bounds__(SH_TPB) void k_l2l(TreeView t, OpTables op, int lc,
 constexpr int L2P_TPB = 64;
 constexpr int MAX_NC = 286;  // multi-indices of degree <= 10
 
-// One wavefront per leaf; one particle per lane.  The leaf's F~ is staged in LDS, each lane keeps
-// the powers of its scaled offset in its own LDS column, and the coefficient loop walks a table
-// (exponents, degree, indices of n + e_c and n + e_a + e_b) whose entries are uniform across
-// the wave, so table reads are scalar and F~ reads are LDS broadcasts.
+// One wavefront per leaf.  A leaf holds few particles at protein density, so each particle is
+// served by G = 64 / T lanes (T = the leaf occupancy rounded up to a power of two), each lane taking
+// every G-th coefficient; the partial sums are combined by a fixed butterfly of cross-lane
+// exchanges.  The leaf's F~ is staged in LDS, each particle's powers of its scaled offset sit in its
+// own LDS column, and the coefficient table (exponents, degree, indices of n + e_c and n + e_a + e_b)
+// is read through the scalar cache.
 __global__ __launch_bounds__(L2P_TPB) void k_l2p(TreeView t, OpTables op, Particles pa,
                                                  const double* __restrict__ F, int mode, FieldOut out,
                                                  const int* done) {
@@ -152,28 +215,34 @@ __global__ __launch_bounds__(L2P_TPB) void k_l2p(TreeView t, OpTables op, Partic
   const int first = t.first[g], cnt = t.count[g];
   const int p = op.p, nc = op.nc;
   for (int k = threadIdx.x; k < nc; k += L2P_TPB) sF[k] = F[(int64_t)g * op.stride + k];
-  __syncthreads();
   double c[3], w;
   cell_centre(t, g, t.L, c, w);
   const double iw = 1.0 / w;
-  const int tid = threadIdx.x;
+  const int lane = threadIdx.x;
+  const int T_ = cnt >= L2P_TPB ? L2P_TPB : (cnt <= 1 ? 1 : (1 << (32 - __clz(cnt - 1))));
+  const int G = L2P_TPB / T_;
+  const int slot = lane & (T_ - 1), slice = lane / T_;
   for (int i0 = 0; i0 < cnt; i0 += L2P_TPB) {
-    const int li = i0 + tid;
-    if (li >= cnt) break;
-    const int i = first + li;
-    const double4 Pi = pa.P[i];
-    const double rho[3] = {(Pi.x - c[0]) * iw, (Pi.y - c[1]) * iw, (Pi.z - c[2]) * iw};
-    for (int a = 0; a < 3; ++a) {
-      double v = 1.0;
-      pw[a][0][tid] = 1.0;
-      for (int e = 1; e <= p; ++e) { v *= rho[a]; pw[a][e][tid] = v; }
+    const int li = i0 + slot;
+    const bool active = li < cnt;
+    const int i = first + (active ? li : 0);
+    __syncthreads();  // sF staged; previous chunk done with pw
+    if (slice == 0) {
+      const double4 Pi = pa.P[i];
+      const double rho[3] = {(Pi.x - c[0]) * iw, (Pi.y - c[1]) * iw, (Pi.z - c[2]) * iw};
+      for (int a = 0; a < 3; ++a) {
+        double v = 1.0;
+        pw[a][0][slot] = 1.0;
+        for (int e = 1; e <= p; ++e) { v *= rho[a]; pw[a][e][slot] = v; }
+      }
     }
+    __syncthreads();
     double phi = 0.0, ex = 0.0, ey = 0.0, ez = 0.0;
     double gxx = 0.0, gyy = 0.0, gzz = 0.0, gxy = 0.0, gxz = 0.0, gyz = 0.0;
-    for (int k = 0; k < nc; ++k) {
+    for (int k = slice; k < nc; k += G) {
       const int* tk = op.l2p_tab + 16 * k;
       const int deg = tk[3];
-      const double m = pw[0][tk[0]][tid] * pw[1][tk[1]][tid] * pw[2][tk[2]][tid] * op.inv_fact[k];
+      const double m = pw[0][tk[0]][slot] * pw[1][tk[1]][slot] * pw[2][tk[2]][slot] * op.inv_fact[k];
       phi += m * sF[k];
       if (deg <= p - 1) {
         ex -= m * sF[tk[4]];
@@ -189,15 +258,24 @@ __global__ __launch_bounds__(L2P_TPB) void k_l2p(TreeView t, OpTables op, Partic
         }
       }
     }
+    for (int msk = T_; msk < L2P_TPB; msk <<= 1) {
+      ex += __shfl_xor(ex, msk); ey += __shfl_xor(ey, msk); ez += __shfl_xor(ez, msk);
+      if (mode == 1) {
+        phi += __shfl_xor(phi, msk);
+        gxx += __shfl_xor(gxx, msk); gyy += __shfl_xor(gyy, msk); gzz += __shfl_xor(gzz, msk);
+        gxy += __shfl_xor(gxy, msk); gxz += __shfl_xor(gxz, msk); gyz += __shfl_xor(gyz, msk);
+      }
+    }
+    if (!active || slice != 0) continue;
     const double iw2 = iw * iw, iw3 = iw2 * iw;
     ex *= iw2; ey *= iw2; ez *= iw2;
     out.Ed[3 * i] = ex; out.Ed[3 * i + 1] = ey; out.Ed[3 * i + 2] = ez;
     if (mode == 1) {
       out.phi[i] = phi * iw;
       out.Eu[3 * i] = ex; out.Eu[3 * i + 1] = ey; out.Eu[3 * i + 2] = ez;
-      double* G = out.G + 6 * (int64_t)i;
-      G[0] = gxx * iw3; G[1] = gyy * iw3; G[2] = gzz * iw3;
-      G[3] = gxy * iw3; G[4] = gxz * iw3; G[5] = gyz * iw3;
+      double* G6 = out.G + 6 * (int64_t)i;
+      G6[0] = gxx * iw3; G6[1] = gyy * iw3; G6[2] = gzz * iw3;
+      G6[3] = gxy * iw3; G6[4] = gxz * iw3; G6[5] = gyz * iw3;
     }
   }
 }
