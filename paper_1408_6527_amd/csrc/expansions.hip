@@ -92,7 +92,7 @@ __global__ __launch_bounds__(P2M_TPB) void k_p2m(TreeView t, OpTables op, Partic
   }
 }
 
-constexpr int SH_TPB = 128;
+constexpr int SH_TPB = 256;
 constexpr int MAX_STRIDE = 288;  // row stride of an expansion at p = 10
 
 __host__ __device__ constexpr int mi_index(int nx, int ny, int nz) {
@@ -100,99 +100,132 @@ __host__ __device__ constexpr int mi_index(int nx, int ny, int nz) {
   return mi_count(nx + ny + nz - 1) + (ny + nz) * (ny + nz + 1) / 2 + nz;
 }
 
-// (+-1/4)^e / e! for e = 0..MAX_P: the per-axis factors of the shift coefficients x^k / k! with
-// |x_a| = 1/4 of the cell edge of the parent (child centre offset from the parent centre)
-__device__ inline void quarter_powers(double* plus, double* minus, int p) {
+// (h/4)^e / e! and (-h/4)^e / e! for e = 0..p: per-axis factors of the shift coefficients x^k / k!
+// for a child centre offset of a quarter of the parent edge, times 2^e when h = 2
+__device__ inline void shift_powers(double* plus, double* minus, int p, double h) {
   double v = 1.0;
   for (int e = 0; e <= p; ++e) {
     plus[e] = v;
     minus[e] = (e & 1) ? -v : v;
-    v *= 0.25 / (double)(e + 1);
+    v *= 0.25 * h / (double)(e + 1);
   }
 }
 
-// One block per parent cell.  M~_n(parent) = sum_children sum_{k <= n} xt^k/k! 2^-(|n|-|k|) M~_{n-k}(child)
-// with xt = 1/4 - o/2 per axis for the child in octant o (+1/4 for bit 0, -1/4 for bit 1).  The
-// children's rows are staged in LDS and the coefficients are formed on the fly from per-axis
-// factors, so the kernel reads each child row once and no table.
+// One block per parent cell:
+//   M~_n(parent) = 2^-|n| sum_children sum_{k <= n} prod_a (2 xt_a)^{k_a} / k_a! M~_{n-k}(child),
+// xt_a = +1/4 for octant bit 0 and -1/4 for bit 1 (parent centre minus child centre, in parent
+// edges).  The shift coefficient factorises over the axes, and children that differ only in their
+// z bit (then y, then x) share the x and y factors, so the sum runs as three passes over LDS rows:
+// z (8 rows -> 4), y (4 -> 2), x (2 -> 1), each term one multiply-add.
 __global__ __launch_bounds__(SH_TPB) void k_m2m(TreeView t, OpTables op, int lp,
                                                 double* __restrict__ M, const int* done) {
   if (done && *done) return;
-  __shared__ double sM[8][MAX_STRIDE];
-  __shared__ double qp[2][MAX_P + 1];
+  __shared__ double sA[8][MAX_STRIDE];
+  __shared__ double sB[4][MAX_STRIDE];
+  __shared__ double hp[2][MAX_P + 1];
   __shared__ int ch[8];
   const int g = t.off[lp] + blockIdx.x;
   const int nc = op.nc, p = op.p;
   if (threadIdx.x < 8) ch[threadIdx.x] = t.child8[8 * g + threadIdx.x];
-  if (threadIdx.x == 0) quarter_powers(qp[0], qp[1], p);
+  if (threadIdx.x == 8) shift_powers(hp[0], hp[1], p, 2.0);
   __syncthreads();
-  for (int o = 0; o < 8; ++o) {
+  for (int e = threadIdx.x; e < 8 * nc; e += SH_TPB) {
+    const int o = e / nc, k = e - o * nc;
     const int c = ch[o];
-    for (int k = threadIdx.x; k < nc; k += SH_TPB) sM[o][k] = c >= 0 ? M[(int64_t)c * op.stride + k] : 0.0;
+    sA[o][k] = c >= 0 ? M[(int64_t)c * op.stride + k] : 0.0;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 4 * nc; e += SH_TPB) {  // z: pair (bx, by) of children
+    const int pr = e / nc, k = e - pr * nc;
+    const int nx = op.mi[3 * k], ny = op.mi[3 * k + 1], nz = op.mi[3 * k + 2];
+    double v = 0.0;
+    for (int bz = 0; bz < 2; ++bz) {
+      if (ch[2 * pr + bz] < 0) continue;
+      const double* row = sA[2 * pr + bz];
+      for (int kz = 0; kz <= nz; ++kz) v += hp[bz][kz] * row[mi_index(nx, ny, nz - kz)];
+    }
+    sB[pr][k] = v;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 2 * nc; e += SH_TPB) {  // y: children rows are no longer needed
+    const int bx = e / nc, k = e - bx * nc;
+    const int nx = op.mi[3 * k], ny = op.mi[3 * k + 1], nz = op.mi[3 * k + 2];
+    double v = 0.0;
+    for (int by = 0; by < 2; ++by)
+      for (int ky = 0; ky <= ny; ++ky) v += hp[by][ky] * sB[2 * bx + by][mi_index(nx, ny - ky, nz)];
+    sA[bx][k] = v;
   }
   __syncthreads();
   for (int k = threadIdx.x; k < op.stride; k += SH_TPB) {
-    double acc = 0.0;
+    double v = 0.0;
     if (k < nc) {
       const int nx = op.mi[3 * k], ny = op.mi[3 * k + 1], nz = op.mi[3 * k + 2];
-      const int dn = nx + ny + nz;
-      for (int o = 0; o < 8; ++o) {
-        if (ch[o] < 0) continue;
-        const double* fx = qp[(o >> 2) & 1];
-        const double* fy = qp[(o >> 1) & 1];
-        const double* fz = qp[o & 1];
-        for (int kx = 0; kx <= nx; ++kx)
-          for (int ky = 0; ky <= ny; ++ky) {
-            const double cxy = fx[kx] * fy[ky];
-            for (int kz = 0; kz <= nz; ++kz) {
-              const int dm = dn - kx - ky - kz;  // |n - k|
-              acc += ldexp(cxy * fz[kz], -dm) * sM[o][mi_index(nx - kx, ny - ky, nz - kz)];
-            }
-          }
-      }
+      for (int bx = 0; bx < 2; ++bx)
+        for (int kx = 0; kx <= nx; ++kx) v += hp[bx][kx] * sA[bx][mi_index(nx - kx, ny, nz)];
+      v = ldexp(v, -(nx + ny + nz));
     }
-    M[(int64_t)g * op.stride + k] = acc;
+    M[(int64_t)g * op.stride + k] = v;
   }
 }
 
-// One block per child cell: F~(child) += partial M2L sums of the other offset splits, then, from
-// level 3 on, F~_n(child) += 2^-(|n|+1) sum_{|k| <= p-|n|} xl^k/k! F~_{n+k}(parent) with
-// xl = o/2 - 1/4 per axis (the parent row is complete because levels run top-down).
+// One block per parent cell, for its children at level lc: F~(child) += partial M2L sums of the
+// other offset splits, then, from level 3 on,
+//   F~_n(child) += 2^-(|n|+1) sum_{|k| <= p-|n|} prod_a xl_a^{k_a} / k_a! F~_{n+k}(parent),
+// xl_a = +1/4 for octant bit 1 and -1/4 for bit 0 (the parent row is complete because levels run
+// top-down).  As in M2M the sum factorises: z (1 row -> 2), y (2 -> 4), x (4 -> 8 children).
+// The truncation |k| <= p - |n| is kept exactly: each pass only reaches indices of degree <= p.
 __global__ __launch_bounds__(SH_TPB) void k_l2l(TreeView t, OpTables op, int lc, double* F,
                                                 int nsplit, int64_t split_stride, const int* done) {
   if (done && *done) return;
-  __shared__ double sF[MAX_STRIDE];
-  __shared__ double qp[2][MAX_P + 1];
-  const int g = t.off[lc] + blockIdx.x;
+  __shared__ double sP[MAX_STRIDE];
+  __shared__ double sU1[2][MAX_STRIDE];
+  __shared__ double sU2[4][MAX_STRIDE];
+  __shared__ double qp[2][MAX_P + 1];  // [bit]: bit 1 -> +1/4, bit 0 -> -1/4
+  __shared__ int ch[8];
+  const int g = t.off[lc - 1] + blockIdx.x;
   const int nc = op.nc, p = op.p;
-  const int o = (int)(t.key[g] & 7);
-  if (lc >= 3) {
-    const int par = t.parent[g];
-    for (int k = threadIdx.x; k < nc; k += SH_TPB) sF[k] = F[(int64_t)par * op.stride + k];
-    if (threadIdx.x == 0) quarter_powers(qp[0], qp[1], p);
+  const bool shift = lc >= 3;
+  if (threadIdx.x < 8) ch[threadIdx.x] = t.child8[8 * g + threadIdx.x];
+  if (shift) {
+    if (threadIdx.x == 8) shift_powers(qp[1], qp[0], p, 1.0);
+    for (int k = threadIdx.x; k < nc; k += SH_TPB) sP[k] = F[(int64_t)g * op.stride + k];
+    __syncthreads();
+    for (int e = threadIdx.x; e < 2 * nc; e += SH_TPB) {
+      const int bz = e / nc, k = e - bz * nc;
+      const int nx = op.mi[3 * k], ny = op.mi[3 * k + 1], nz = op.mi[3 * k + 2];
+      const int rem = p - nx - ny - nz;
+      double v = 0.0;
+      for (int kz = 0; kz <= rem; ++kz) v += qp[bz][kz] * sP[mi_index(nx, ny, nz + kz)];
+      sU1[bz][k] = v;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 4 * nc; e += SH_TPB) {
+      const int yz = e / nc, k = e - yz * nc;
+      const int by = yz >> 1, bz = yz & 1;
+      const int nx = op.mi[3 * k], ny = op.mi[3 * k + 1], nz = op.mi[3 * k + 2];
+      const int rem = p - nx - ny - nz;
+      double v = 0.0;
+      for (int ky = 0; ky <= rem; ++ky) v += qp[by][ky] * sU1[bz][mi_index(nx, ny + ky, nz)];
+      sU2[yz][k] = v;
+    }
   }
   __syncthreads();
-  // xl = +1/4 for bit 1, -1/4 for bit 0
-  const double* fx = qp[((o >> 2) & 1) ^ 1];
-  const double* fy = qp[((o >> 1) & 1) ^ 1];
-  const double* fz = qp[(o & 1) ^ 1];
-  for (int k = threadIdx.x; k < nc; k += SH_TPB) {
+  for (int e = threadIdx.x; e < 8 * nc; e += SH_TPB) {
+    const int o = e / nc, k = e - o * nc;
+    const int c = ch[o];
+    if (c < 0) continue;
     double acc = 0.0;
-    for (int sp = 1; sp < nsplit; ++sp) acc += F[sp * split_stride + (int64_t)g * op.stride + k];
-    if (lc >= 3) {
+    for (int sp = 1; sp < nsplit; ++sp) acc += F[sp * split_stride + (int64_t)c * op.stride + k];
+    if (shift) {
       const int nx = op.mi[3 * k], ny = op.mi[3 * k + 1], nz = op.mi[3 * k + 2];
       const int dn = nx + ny + nz;
-      const int rem = p - dn;
-      double sh = 0.0;
-      for (int kx = 0; kx <= rem; ++kx)
-        for (int ky = 0; ky <= rem - kx; ++ky) {
-          const double cxy = fx[kx] * fy[ky];
-          for (int kz = 0; kz <= rem - kx - ky; ++kz)
-            sh += cxy * fz[kz] * sF[mi_index(nx + kx, ny + ky, nz + kz)];
-        }
-      acc += ldexp(sh, -(dn + 1));
+      const int bx = (o >> 2) & 1;
+      const double* u = sU2[o & 3];
+      double v = 0.0;
+      for (int kx = 0; kx <= p - dn; ++kx) v += qp[bx][kx] * u[mi_index(nx + kx, ny, nz)];
+      acc += ldexp(v, -(dn + 1));
     }
-    F[(int64_t)g * op.stride + k] += acc;
+    F[(int64_t)c * op.stride + k] += acc;
   }
 }
 
@@ -300,9 +333,10 @@ void launch_m2m(const TreeView& t, const OpTables& op, int parent_level, double*
 
 void launch_l2l(const TreeView& t, const OpTables& op, int child_level, double* F, int nsplit,
                 int64_t split_stride, const int* done, hipStream_t s) {
-  const int nc = t.off[child_level + 1] - t.off[child_level];
-  if (nc <= 0 || (child_level < 3 && nsplit <= 1)) return;
-  hipLaunchKernelGGL(k_l2l, dim3(nc), dim3(SH_TPB), 0, s, t, op, child_level, F, nsplit, split_stride,
+  if (child_level < 2) return;
+  const int np = t.off[child_level] - t.off[child_level - 1];
+  if (np <= 0 || (child_level < 3 && nsplit <= 1)) return;
+  hipLaunchKernelGGL(k_l2l, dim3(np), dim3(SH_TPB), 0, s, t, op, child_level, F, nsplit, split_stride,
                      done);
   PFMM_LAUNCH_CHECK();
 }
