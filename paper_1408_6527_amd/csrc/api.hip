@@ -1,7 +1,7 @@
 // C interface and host orchestration of the pfmm library (declarations in include/pfmm.h).
 //
 // A solve runs the three stages of Sec. III on one device stream:
-//   tree      bounding box, Morton sort, cells, colleagues, M2L tiles          (tree.hip, m2l.hip)
+//   tree      bounding box, Morton sort, cells, colleagues, M2L launch shape    (tree.hip)
 //   stage 1   field of the charges: phi^q, E^q, grad E^q                       (one FMM pass)
 //   stage 2   conjugate gradients on (I - S T~ S) y = S E^q, one FMM pass of the
 //             dipoles per iteration                                             (solver.hip)
@@ -148,12 +148,10 @@ struct pfmm_handle {
   OpTables op;
   int device = 0;
   // constant tables
-  DevBuf t_mi, t_p2m, t_ifact, t_l2p, t_m2m_ptr, t_m2m_col, t_m2m_val, t_l2l_ptr, t_l2l_col, t_l2l_val, t_code,
-      t_kpack, t_kpack32;
+  DevBuf t_mi, t_p2m, t_ifact, t_l2p, t_code, t_dvec, t_dvec32, t_hidx;
   // tree workspace
   DevBuf w_partial, w_flags, w_bbox, w_keys_in, w_keys, w_vals_in, w_perm, w_sort_tmp, w_scan_tmp,
-      w_lvl_flags, w_cid, w_counts, w_ckey, w_cfirst, w_ccount, w_cparent, w_child8, w_coll, w_okeys,
-      w_ovals, w_okeys2, w_tgt, w_octcnt, w_list, w_stats;
+      w_lvl_flags, w_cid, w_counts, w_ckey, w_cfirst, w_ccount, w_cparent, w_child8, w_coll, w_stats;
   // particles
   DevBuf w_P, w_al, w_sqa, w_tau, w_itau, w_mu4;
   // expansions
@@ -170,7 +168,7 @@ struct pfmm_handle {
   std::string err;
   TreeView tv;
   Particles pa;
-  int ntgt = 0, ntiles = 0, m2l_wg = 0, nsplit = 1;
+  int m2l_tiles = 0, nsplit = 1;
   int64_t split_stride = 0;
   int64_t n_m2l = 0, n_p2p = 0;
   int n_evals = 0;
@@ -328,49 +326,26 @@ void build_tree(pfmm_handle* h, int n, const double* pos, const double* q, const
   Particles& pa = h->pa;
   pa.n = n; pa.P = P; pa.alpha = al; pa.sqa = sqa; pa.tau = tau; pa.itau = itau;
 
-  // M2L targets grouped by octant, and the per-tile source lists
-  h->ntgt = L >= 2 ? ncell - t.off[2] : 0;
-  h->ntiles = 0;
   unsigned long long* stats = dev<unsigned long long>(h->w_stats, 2);
   PFMM_HIP(hipMemsetAsync(stats, 0, 2 * sizeof(unsigned long long), s));
-  int* octcnt = dev<int>(h->w_octcnt, 8);
-  launch_fill_int(octcnt, 8, 0, s);
-  if (h->ntgt > 0) {
-    int* okeys = dev<int>(h->w_okeys, h->ntgt);
-    int* ovals = dev<int>(h->w_ovals, h->ntgt);
-    int* okeys2 = dev<int>(h->w_okeys2, h->ntgt);
-    int* tgt = dev<int>(h->w_tgt, h->ntgt);
-    launch_octant_keys(t, okeys, ovals, octcnt, s);
-    size_t ob = octsort_temp_bytes(h->ntgt);
-    void* otmp = h->w_sort_tmp.reserve(std::max(ob, h->w_sort_tmp.bytes));
-    launch_octant_sort(otmp, ob, okeys, okeys2, ovals, tgt, h->ntgt, s);
-    h->ntiles = m2l_max_tiles(h->ntgt);
-    int* list = dev<int>(h->w_list, (int64_t)h->ntiles * h->op.noff * 16);
-    launch_m2l_list(t, h->op, tgt, octcnt, h->ntiles, list, s);
-    launch_tree_stats(t, h->op.m2l_code, h->op.noff, stats, s);
-  } else {
-    launch_tree_stats(t, h->op.m2l_code, h->op.noff, stats, s);
-  }
-  // per-octant target counts decide the M2L launch shape; the two readbacks share one sync
+  launch_tree_stats(t, h->op.m2l_code, h->op.noff, stats, s);
   unsigned long long st[2];
-  int octh[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   {
-    void* pin = h->pinned.get(sizeof(st) + sizeof(octh));
+    void* pin = h->pinned.get(sizeof(st));
     PFMM_HIP(hipMemcpyAsync(pin, stats, sizeof(st), hipMemcpyDeviceToHost, s));
-    PFMM_HIP(hipMemcpyAsync((char*)pin + sizeof(st), octcnt, sizeof(octh), hipMemcpyDeviceToHost, s));
     PFMM_HIP(hipStreamSynchronize(s));
     std::memcpy(st, pin, sizeof(st));
-    std::memcpy(octh, (char*)pin + sizeof(st), sizeof(octh));
   }
   h->n_m2l = (int64_t)st[0];
   h->n_p2p = (int64_t)st[1];
-  // enough workgroups to fill the device: split each target tile's offset list when tiles are few
-  h->m2l_wg = h->ntgt > 0 ? m2l_workgroups(h->op.p, octh) : 0;
+  // enough workgroups to fill the device: split each parent tile's colleague offsets when tiles are
+  // few (at least 4 offsets per split, so that staging the index table stays a small share)
+  h->m2l_tiles = L >= 2 ? m2l_tiles(t, 1, L - 1, 2) : 0;  // workgroups of 32 parents
   h->nsplit = 1;
-  if (h->m2l_wg > 0) {
-    const int want_wg = 2048;  // 8 workgroups of 4 waves per CU
-    h->nsplit = std::max(1, std::min(32, (want_wg + h->m2l_wg - 1) / h->m2l_wg));
-    h->nsplit = std::min(h->nsplit, std::max(1, h->op.noff / 16));
+  if (h->m2l_tiles > 0) {
+    const int want_wg = 2048;
+    h->nsplit = std::max(1, std::min(32, (want_wg + h->m2l_tiles - 1) / h->m2l_tiles));
+    h->nsplit = std::min(h->nsplit, std::max(1, t.nnear / 4));
   }
   // expansions (one extra zero row serves empty M2L sources); F holds nsplit partial copies
   const int64_t rows = (int64_t)ncell + 1;
@@ -401,8 +376,7 @@ void fmm_pass(pfmm_handle* h, int sources, int mode, FieldOut out, int* err, con
     for (int lp = t.L - 1; lp >= 2; --lp) launch_m2m(t, op, lp, M, done, s);
     kt.end(KC_M2M, e);
     e = kt.begin();
-    launch_m2l(t, op, h->w_tgt.as<int>(), h->w_octcnt.as<int>(), h->m2l_wg, h->nsplit,
-               h->w_list.as<int>(), M, F, h->split_stride, fp32, 3, done, s);
+    launch_m2l(t, op, h->nsplit, M, F, h->split_stride, fp32, 3, done, s);
     kt.end(KC_M2L, e);
     e = kt.begin();
     for (int lc = 2; lc <= t.L; ++lc) launch_l2l(t, op, lc, F, h->nsplit, h->split_stride, done, s);
@@ -636,13 +610,12 @@ pfmm_status pfmm_create(const pfmm_config* cfg, pfmm_handle** out) {
     upload(h->t_p2m, T.p2m_coef);
     upload(h->t_ifact, T.inv_fact);
     upload(h->t_l2p, T.l2p_tab);
-    upload(h->t_m2m_ptr, T.m2m_ptr); upload(h->t_m2m_col, T.m2m_col); upload(h->t_m2m_val, T.m2m_val);
-    upload(h->t_l2l_ptr, T.l2l_ptr); upload(h->t_l2l_col, T.l2l_col); upload(h->t_l2l_val, T.l2l_val);
     upload(h->t_code, T.m2l_code);
-    upload(h->t_kpack, T.kpack);
+    upload(h->t_dvec, T.dvec);
+    upload(h->t_hidx, T.hidx);
     if (cfg->precision == PFMM_MIXED) {
-      std::vector<float> k32(T.kpack.begin(), T.kpack.end());
-      upload(h->t_kpack32, k32);
+      std::vector<float> d32(T.dvec.begin(), T.dvec.end());
+      upload(h->t_dvec32, d32);
     }
     OpTables& op = h->op;
     op.p = T.p; op.nc = T.nc; op.stride = T.stride;
@@ -650,12 +623,11 @@ pfmm_status pfmm_create(const pfmm_config* cfg, pfmm_handle** out) {
     op.p2m_coef = h->t_p2m.as<double>();
     op.inv_fact = h->t_ifact.as<double>();
     op.l2p_tab = h->t_l2p.as<int>();
-    op.m2m_ptr = h->t_m2m_ptr.as<int>(); op.m2m_col = h->t_m2m_col.as<int>(); op.m2m_val = h->t_m2m_val.as<double>();
-    op.l2l_ptr = h->t_l2l_ptr.as<int>(); op.l2l_col = h->t_l2l_col.as<int>(); op.l2l_val = h->t_l2l_val.as<double>();
     op.m2l_code = h->t_code.as<int>();
     op.noff = T.noff;
-    op.kpack = h->t_kpack.as<double>();
-    op.kpack32 = cfg->precision == PFMM_MIXED ? h->t_kpack32.as<float>() : nullptr;
+    op.dvec = h->t_dvec.as<double>();
+    op.dvec32 = cfg->precision == PFMM_MIXED ? h->t_dvec32.as<float>() : nullptr;
+    op.hidx = h->t_hidx.as<unsigned short>();
     op.nblocks = T.nblocks;
     PFMM_HIP(hipGetDevice(&h->device));
     *out = h;
@@ -792,8 +764,7 @@ extern "C" int pfmm_internal_buffer(pfmm_handle* h, const char* name, void** ptr
       {"ckey", &h->w_ckey, (int64_t)t.ncell * 8}, {"cfirst", &h->w_cfirst, (int64_t)t.ncell * 4},
       {"ccount", &h->w_ccount, (int64_t)t.ncell * 4}, {"cparent", &h->w_cparent, (int64_t)t.ncell * 4},
       {"child8", &h->w_child8, (int64_t)t.ncell * 32}, {"coll", &h->w_coll, (int64_t)t.ncell * t.nnear * 4},
-      {"tgt", &h->w_tgt, (int64_t)h->ntgt * 4}, {"octcnt", &h->w_octcnt, 32},
-      {"list", &h->w_list, (int64_t)h->ntiles * h->op.noff * 16 * 4}, {"perm", &h->w_perm, (int64_t)h->pa.n * 4},
+      {"perm", &h->w_perm, (int64_t)h->pa.n * 4},
       {"P", &h->w_P, (int64_t)h->pa.n * 32}};
   for (const auto& it : items)
     if (s == it.n) {

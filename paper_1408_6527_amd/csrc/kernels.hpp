@@ -84,10 +84,12 @@ struct OpTables {
   const double* p2m_coef = nullptr;
   const double* inv_fact = nullptr;
   const int* l2p_tab = nullptr;  // 16 ints per coefficient: nx ny nz |n|, n+e_c (3), n+e_a+e_b (6), pad
-  const int* m2m_ptr = nullptr; const int* m2m_col = nullptr; const double* m2m_val = nullptr;
-  const int* l2l_ptr = nullptr; const int* l2l_col = nullptr; const double* l2l_val = nullptr;
-  const int* m2l_code = nullptr; int noff = 0;
-  const double* kpack = nullptr; const float* kpack32 = nullptr; int nblocks = 0;
+  const int* m2l_code = nullptr; int noff = 0;  // M2L offsets per target octant (tree statistics)
+  // M2L operators: D_k(d) at unit cell width for every offset d in [-R, R]^3, R = 2 ws + 1, as
+  // rows of sched_dpitch(p) values (float copy only on the mixed path), and the K-entry index table
+  // (one index into such a row per MFMA block and lane, schedule.hpp)
+  const double* dvec = nullptr; const float* dvec32 = nullptr; const unsigned short* hidx = nullptr;
+  int nblocks = 0;
 };
 // sources: 1 = charges (P.w), 2 = dipoles (mu4), 3 = both
 void launch_p2m(const TreeView& t, const OpTables& op, const Particles& pa, const double4* mu4,
@@ -103,22 +105,14 @@ void launch_l2p(const TreeView& t, const OpTables& op, const Particles& pa, cons
                 FieldOut out, const int* done, hipStream_t s);
 
 // ---------------------------------------------------------------- m2l.hip
-// Targets: every cell of level >= 2, grouped by octant (tgt_list), oct_count[8] targets per octant,
-// cut into wave tiles of 16; list holds the source cell of every (tile, offset, column).
-int m2l_max_tiles(int ntgt);
-void launch_m2l_list(const TreeView& t, const OpTables& op, const int* tgt_list, const int* oct_count,
-                     int ntiles, int* list, hipStream_t s);
-// Workgroups of the M2L launch for the per-octant target counts (host copy), before splitting.
-int m2l_workgroups(int p, const int* oct_count_host);
-// Split s of the offset list writes its partial F~ at F + s * split_stride (s = 0: F itself); the
-// downward pass (launch_l2l) adds the partials of splits 1.. to F.
-void launch_m2l(const TreeView& t, const OpTables& op, const int* tgt_list, const int* oct_count,
-                int nwg, int nsplit, const int* list, const double* M, double* F, int64_t split_stride,
-                bool fp32, int fp64_max_level, const int* done, hipStream_t s);
-void launch_octant_keys(const TreeView& t, int* keys, int* vals, int* oct_count, hipStream_t s);
-size_t octsort_temp_bytes(int n);
-void launch_octant_sort(void* tmp, size_t bytes, const int* kin, int* kout, const int* vin, int* vout,
-                        int n, hipStream_t s);
+// Targets are the cells of levels >= 2, taken as the children of 16-parent tiles; a launch covers
+// the parents of levels [lp_lo, lp_hi].  Workgroup tiles of 16 ncb parents over those levels:
+int m2l_tiles(const TreeView& t, int lp_lo, int lp_hi, int ncb = 1);
+// Split s of the colleague-offset range writes its partial F~ at F + s * split_stride (s = 0: F
+// itself); the downward pass (launch_l2l) adds the partials of splits 1.. to F.  On the mixed path,
+// targets at levels <= fp64_max_level still run in float64.
+void launch_m2l(const TreeView& t, const OpTables& op, int nsplit, const double* M, double* F,
+                int64_t split_stride, bool fp32, int fp64_max_level, const int* done, hipStream_t s);
 
 // ---------------------------------------------------------------- p2p.hip
 // mode 0: dipole sources, Ed only (added); mode 1: full outputs (added) from charges and/or dipoles

@@ -3,7 +3,9 @@
 //
 // Multi-indices n with |n| <= p are ordered by degree.  The M2L of Sec. II.B,
 //   F_n = sum_{|m| <= p - |n|} M_m D_{n+m},
-// is a matrix product F = K M with K[n][m] = D_{n+m} where |n| + |m| <= p and 0 elsewhere.
+// is a matrix product F = K M with K[n][m] = D_{n+m} where |n| + |m| <= p and 0 elsewhere.  K is
+// a Hankel-type matrix: its entries are the C(p + 3, 3) values D_k, |k| <= p, so the kernels keep
+// only that vector per offset and address it through a fixed table of indices k = n + m.
 // Rows are cut into blocks of 16 (the MFMA tile height).  The reduction runs in steps of 4
 // coefficients, one per lane quarter q = 0..3; step s reads coefficient
 //   m(s, q) = 8 (s / 2) + 2 q + (s % 2),
@@ -20,6 +22,9 @@ namespace pfmm {
 __host__ __device__ constexpr int mi_count(int d) { return d < 0 ? 0 : (d + 1) * (d + 2) * (d + 3) / 6; }
 __host__ __device__ constexpr int sched_nc(int p) { return mi_count(p); }
 __host__ __device__ constexpr int sched_stride(int p) { return (mi_count(p) + 7) / 8 * 8; }
+// length of a stored derivative vector D_k(d): the C(p + 3, 3) values, then at least one zero (the
+// entry that the index table names for the zero entries of K), rounded up to an even count
+__host__ __device__ constexpr int sched_dpitch(int p) { return (mi_count(p) + 2) / 2 * 2; }
 // coefficient read by lane quarter q at step s
 __host__ __device__ constexpr int sched_coef(int s, int q) { return 8 * (s / 2) + 2 * q + (s % 2); }
 __host__ __device__ constexpr int sched_nrb(int p) { return (mi_count(p) + 15) / 16; }
@@ -40,5 +45,9 @@ __host__ __device__ constexpr int sched_nblocks(int p) {
   for (int rb = 0; rb < sched_nrb(p); ++rb) t += sched_nsteps(p, rb);
   return t;
 }
+// The K-entry index table is stored in groups of 8 consecutive blocks, each lane's 8 indices
+// adjacent (one 16-byte read per lane per group): position of (block, lane).
+__host__ __device__ constexpr int sched_hgroups(int p) { return (sched_nblocks(p) + 7) / 8; }
+__host__ __device__ constexpr int sched_hpos(int blk, int lane) { return ((blk >> 3) * 64 + lane) * 8 + (blk & 7); }
 
 }  // namespace pfmm

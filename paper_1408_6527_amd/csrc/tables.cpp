@@ -122,45 +122,6 @@ void HostTables::build(int p_, int ws_) {
     for (int a = 0; a < 6; ++a) l2p_tab[16 * k + 7 + a] = std::max(idx_ee[6 * k + a], 0);
   }
 
-  // M2M: M~_n(parent) = sum_{k <= n} xt^k / k! 2^-(|n| - |k|) M~_{n-k}(child), xt = 1/4 - o/2 per axis.
-  // L2L: F~_n(child) = sum_{|k| <= p - |n|} xt'^k / k! 2^-(|n| + 1) F~_{n+k}(parent), xt' = o/2 - 1/4.
-  m2m_ptr.assign(8 * (nc + 1), 0);
-  l2l_ptr.assign(8 * (nc + 1), 0);
-  m2m_col.clear(); m2m_val.clear(); l2l_col.clear(); l2l_val.clear();
-  for (int o = 0; o < 8; ++o) {
-    const int ob[3] = {(o >> 2) & 1, (o >> 1) & 1, o & 1};
-    long double xt[3], xl[3];
-    for (int a = 0; a < 3; ++a) {
-      xt[a] = 0.25L - 0.5L * ob[a];
-      xl[a] = 0.5L * ob[a] - 0.25L;
-    }
-    for (int row = 0; row < nc; ++row) {
-      m2m_ptr[o * (nc + 1) + row] = (int)m2m_col.size();
-      l2l_ptr[o * (nc + 1) + row] = (int)l2l_col.size();
-      const int n[3] = {mi[3 * row], mi[3 * row + 1], mi[3 * row + 2]};
-      const int dn = n[0] + n[1] + n[2];
-      for (int kk = 0; kk < nc; ++kk) {
-        const int k[3] = {mi[3 * kk], mi[3 * kk + 1], mi[3 * kk + 2]};
-        const int dk = k[0] + k[1] + k[2];
-        const long double kf = ix.fact(kk);
-        if (k[0] <= n[0] && k[1] <= n[1] && k[2] <= n[2]) {
-          long double c = ipow(xt[0], k[0]) * ipow(xt[1], k[1]) * ipow(xt[2], k[2]) / kf;
-          c = std::ldexp(c, -(dn - dk));
-          m2m_col.push_back(ix.at(n[0] - k[0], n[1] - k[1], n[2] - k[2]));
-          m2m_val.push_back((double)c);
-        }
-        if (dn + dk <= p) {
-          long double c = ipow(xl[0], k[0]) * ipow(xl[1], k[1]) * ipow(xl[2], k[2]) / kf;
-          c = std::ldexp(c, -(dn + 1));
-          l2l_col.push_back(ix.at(n[0] + k[0], n[1] + k[1], n[2] + k[2]));
-          l2l_val.push_back((double)c);
-        }
-      }
-    }
-    m2m_ptr[o * (nc + 1) + nc] = (int)m2m_col.size();
-    l2l_ptr[o * (nc + 1) + nc] = (int)l2l_col.size();
-  }
-
   // M2L offsets per target octant.  A target B in octant oB of its parent P sees, through the
   // children of P's colleagues, the cells A = 2 (P + e) + c, e in [-ws, ws]^3, c in {0,1}^3, and
   // interacts by M2L with those that are not its own colleagues: d = B - A = oB - c - 2 e with
@@ -191,13 +152,13 @@ void HostTables::build(int p_, int ws_) {
     if (cnt != noff) throw Error(PFMM_ERR_INVALID_ARG, "internal: M2L offset count mismatch");
   }
 
-  // K tables for every offset slot in MFMA operand order: block (rb, s) holds 64 values, lane l
-  // carrying K[16 rb + (l & 15)][m(s, l >> 4)] (schedule.hpp).
-  kpack.assign((size_t)nslot * nblocks * 64, 0.0);
+  // D_k(d) for every offset slot (zeros for the near slots, which no M2L reads), each row followed
+  // by zeros up to the pitch; and the index of K[n][m] = D_{n+m} for every MFMA block (rb, s) and
+  // lane l, n = 16 rb + (l & 15), m = m(s, l >> 4) (schedule.hpp), pointing at the zero entry nc
+  // where |n| + |m| > p or n, m fall in the padding.
+  dpitch = sched_dpitch(p);
+  dvec.assign((size_t)nslot * dpitch, 0.0);
   std::vector<double> Dn(nc);
-  std::vector<int> degv(nc);
-  for (int k = 0; k < nc; ++k) degv[k] = ix.deg(k);
-  const int nrb = sched_nrb(p);
   for (int dx = -R; dx <= R; ++dx)
     for (int dy = -R; dy <= R; ++dy)
       for (int dz = -R; dz <= R; ++dz) {
@@ -205,23 +166,25 @@ void HostTables::build(int p_, int ws_) {
         const int slot = ((dx + R) * cube + (dy + R)) * cube + (dz + R);
         const int d[3] = {dx, dy, dz};
         derivative_tensor_unit(p, mi.data(), nc, d, Dn.data());
-        double* dst = kpack.data() + (size_t)slot * nblocks * 64;
-        int blk = 0;
-        for (int s = 0; s < sched_maxsteps(p); ++s)
-          for (int rb = 0; rb < nrb; ++rb) {
-            if (sched_nsteps(p, rb) <= s) continue;
-            for (int l = 0; l < 64; ++l) {
-              const int row = 16 * rb + (l & 15), col = sched_coef(s, l >> 4);
-              double v = 0.0;
-              if (row < nc && col < nc && degv[row] + degv[col] <= p)
-                v = Dn[ix.at(mi[3 * row] + mi[3 * col], mi[3 * row + 1] + mi[3 * col + 1],
-                             mi[3 * row + 2] + mi[3 * col + 2])];
-              dst[blk * 64 + l] = v;
-            }
-            ++blk;
-          }
-        if (blk != nblocks) throw Error(PFMM_ERR_INVALID_ARG, "internal: M2L block count mismatch");
+        std::copy(Dn.begin(), Dn.end(), dvec.begin() + (size_t)slot * dpitch);
       }
+  std::vector<int> degv(nc);
+  for (int k = 0; k < nc; ++k) degv[k] = ix.deg(k);
+  const int nrb = sched_nrb(p);
+  hidx.assign((size_t)sched_hgroups(p) * 8 * 64, (unsigned short)nc);
+  int blk = 0;
+  for (int s = 0; s < sched_maxsteps(p); ++s)
+    for (int rb = 0; rb < nrb; ++rb) {
+      if (sched_nsteps(p, rb) <= s) continue;
+      for (int l = 0; l < 64; ++l) {
+        const int row = 16 * rb + (l & 15), col = sched_coef(s, l >> 4);
+        if (row < nc && col < nc && degv[row] + degv[col] <= p)
+          hidx[sched_hpos(blk, l)] = (unsigned short)ix.at(
+              mi[3 * row] + mi[3 * col], mi[3 * row + 1] + mi[3 * col + 1], mi[3 * row + 2] + mi[3 * col + 2]);
+      }
+      ++blk;
+    }
+  if (blk != nblocks) throw Error(PFMM_ERR_INVALID_ARG, "internal: M2L block count mismatch");
 }
 
 }  // namespace pfmm

@@ -2,8 +2,7 @@
 // and uploaded to the device.  Every expansion on the device is stored in level-scaled form:
 //   M~_n = M_n / w^|n|,   F~_n = F_n * w^(|n|+1),
 // where w is the edge of the cell's level.  With this scaling the M2L kernel for an offset of
-// d cells is D_{n+m}(d) at unit cell width on every level (homogeneity of 1/r), and the M2M/L2L
-// shifts between a parent and its child in octant o are one of eight constant matrices.
+// d cells is D_{n+m}(d) at unit cell width on every level (homogeneity of 1/r).
 #pragma once
 
 #include <cstdint>
@@ -27,13 +26,12 @@ struct HostTables {
   std::vector<int> idx_e;       // nc x 3: index of n + e_c, or -1 (needs |n| <= p - 1)
   std::vector<int> idx_ee;      // nc x 6: index of n + e_a + e_b for (xx, yy, zz, xy, xz, yz), or -1
   std::vector<int> l2p_tab;     // nc x 16: nx, ny, nz, |n|, idx_e (3), idx_ee (6), 0 0 0
-  // shift operators in CSR form, one matrix per child octant: out[row] = sum coef * in[col]
-  std::vector<int> m2m_ptr, m2m_col;  std::vector<double> m2m_val;   // 8 x (nc + 1)
-  std::vector<int> l2l_ptr, l2l_col;  std::vector<double> l2l_val;
   // M2L: for each target octant, noff entries packed as
   //   slot | (colleague index of the source's parent) << 12 | (source octant) << 20
   std::vector<int> m2l_code;    // 8 x noff
-  std::vector<double> kpack;    // nslot x nblocks x 64, MFMA operand order (schedule.hpp)
+  int dpitch = 0;                // sched_dpitch(p)
+  std::vector<double> dvec;      // nslot x dpitch: D_k(d) of every offset slot, zero-padded
+  std::vector<unsigned short> hidx;  // index of K[n][m] in a dvec row per block and lane (sched_hpos)
 
   void build(int p, int ws);
 };
