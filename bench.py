@@ -2,15 +2,17 @@
 stated tolerance, energy, forces, and the adjoint backward) on one MI355X, float64 path and mixed
 path, with the error of each against the CPU oracle stated.
 
-    python bench.py [--steps K] [--warmup W] [--workload globular_50k] [--gpus 1]
+    python bench.py [--steps K] [--warmup W] [--workload scaling_1m] [--gpus 1]
 
 Prints ONE JSON line.  Inputs are synthetic (seeded), resident on the GPU before timing starts.
 The dominant kernel's roofline fraction is measured live with HIP events on the library's stream;
-the CPU oracle is timed on a bounded sample of the same workload on the host cores.
+the CPU oracle is timed on a bounded sample of the same workload on the host cores, and the same
+oracle run gives the force error of both paths on that sample.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -21,12 +23,48 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # Workload presets: geometry generator, expansion order, separation, leaf edge, dipole tolerance.
+# The 1M-particle preset uses the smallest p / fastest leaf edge whose float64 force error on the
+# sampled oracle check stays below 1e-5 (p = 10, 6 A leaves).
 WORKLOADS = {
+    "scaling_1m": dict(gen="scaling_1m", p=10, ws=2, leaf=6.0, tol=1e-6),
+    "scaling_250k": dict(gen="scaling_250k", p=10, ws=2, leaf=6.0, tol=1e-6),
+    "scaling_4m": dict(gen="scaling_4m", p=10, ws=2, leaf=6.0, tol=1e-6),
     "globular_50k": dict(gen="globular_50k", p=6, ws=2, leaf=4.0, tol=1e-6),
     "uniform_cube_1k": dict(gen="uniform_cube_1k", p=4, ws=1, leaf=5.0, tol=1e-8),
     "hexamer_shell_160k": dict(gen="hexamer_shell_160k", p=8, ws=2, leaf=4.0, tol=1e-6),
-    "scaling_1m": dict(gen="scaling_1m", p=8, ws=2, leaf=4.0, tol=1e-6),
 }
+
+# HBM traffic of the dominant kernel from rocprofv3 counters (profiles/), valid only while the
+# kernel sources hash to the value recorded with the counters
+TRAFFIC_SOURCES = ["paper_1408_6527_amd/csrc/m2l.hip", "paper_1408_6527_amd/csrc/schedule.hpp"]
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for rel in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(workload: str, precision: str):
+    """Calibrated HBM bytes per launch of M2L recorded in profiles/<workload>_m2l_traffic.txt
+    ('key: value' lines), or None when absent or taken from other kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"{workload}_m2l_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith(" "):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("source_hash") != kernel_source_hash() or kv.get("precision") != precision:
+        return None
+    try:
+        return float(kv["bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 PEAK = {"fp64_vector": 78.6, "fp64_mfma": 78.6, "fp32_mfma": 157.3, "fp32_vector": 157.3, "hbm": 8000.0}
 P2P_SCF_FLOPS_PER_PAIR = 44  # damped dipole field of one source at one target (p2p.hip)
@@ -41,12 +79,13 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="globular_50k", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="scaling_1m", choices=sorted(WORKLOADS))
     ap.add_argument("--p", type=int, default=None)
     ap.add_argument("--ws", type=int, default=None)
     ap.add_argument("--leaf", type=float, default=None)
     ap.add_argument("--tol", type=float, default=None)
-    ap.add_argument("--oracle-sample", type=int, default=192)
+    ap.add_argument("--oracle-sample", type=int, default=0,
+                    help="targets of the sampled oracle check (0: about 2e7 / n, between 8 and 192)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", default="both", choices=["fp64", "mixed", "both"])
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -111,23 +150,31 @@ def main():
         s, r, dt = timed(prec)
         results[prec] = dict(solver=s, res=r, dt=dt)
 
-    # accuracy on sampled particles: exact forces from the library's own dipoles (oracle), and the
-    # exact dipole residual there
+    # One oracle run on a sample of S targets: exact fields there from all n sources with the
+    # dipoles of the primary path.  It gives the reference forces for the error of both paths
+    # (a path's error thus includes its dipoles' distance from the primary path's) and, timed, the
+    # CPU baseline.
     from oracle import direct as D
     rng = np.random.default_rng(7)
-    idx = np.sort(rng.choice(n, min(64, n), replace=False))
+    S = args.oracle_sample if args.oracle_sample > 0 else max(8, min(192, int(2e7 / n)))
+    S = min(S, n)
+    idx = np.sort(rng.choice(n, S, replace=False))
+    prim = precs[0]
+    mu_ref = results[prim]["res"].mu.cpu().numpy()
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):  # one host thread: the figure is per core
+        t0 = time.perf_counter()
+        phi_o, Eu_o, Ed_o, G_o = D.fields_at(idx, ps.pos, ps.q, mu_ref, ps.alpha, 2.0)
+        t_oracle = time.perf_counter() - t0
+    F_ref = D.COULOMB_K * (ps.q[idx, None] * Eu_o + np.einsum("ia,iab->ib", mu_ref[idx], G_o))
     errs = {}
     for prec in precs:
         r = results[prec]["res"]
-        mu = r.mu.cpu().numpy()
-        phi, Eu, Ed, G = D.fields_at(idx, ps.pos, ps.q, mu, ps.alpha, 2.0)
-        F = D.COULOMB_K * (ps.q[idx, None] * Eu + np.einsum("ia,iab->ib", mu[idx], G))
         Fg = r.forces.cpu().numpy()[idx]
-        errs[prec] = dict(
-            force_rel_l2=float(np.linalg.norm(Fg - F) / np.linalg.norm(F)),
-            dipole_residual_exact=float(np.linalg.norm(ps.alpha[idx, None] * Ed - mu[idx])
-                                        / np.linalg.norm(ps.alpha[idx, None] * Ed)),
-            scf_residual=float(r.residual), iters=int(r.iters))
+        errs[prec] = dict(force_rel_l2_vs_oracle=float(np.linalg.norm(Fg - F_ref) / np.linalg.norm(F_ref)),
+                          scf_residual=float(r.residual), iters=int(r.iters), oracle_sample=int(S))
+    errs[prim]["dipole_residual_exact"] = float(
+        np.linalg.norm(ps.alpha[idx, None] * Ed_o - mu_ref[idx]) / np.linalg.norm(ps.alpha[idx, None] * Ed_o))
     if "mixed" in results and "fp64" in results:
         a = results["mixed"]["res"]; b = results["fp64"]["res"]
         errs["mixed"]["vs_fp64_force"] = float(torch.linalg.norm(a.forces - b.forces) / torch.linalg.norm(b.forces))
@@ -135,7 +182,6 @@ def main():
         errs["mixed"]["vs_fp64_dipole"] = float(torch.linalg.norm(a.mu - b.mu) / torch.linalg.norm(b.mu))
 
     # per-kernel device time of one step of the primary path, HIP events on the library's stream
-    prim = precs[0]
     st = make(prim, timing=True)
     rt = st.solve(pos, q, al)
     kms = rt.stats["t_kernel_ms"]; kl = rt.stats["kernel_launches"]
@@ -153,29 +199,25 @@ def main():
         peak = PEAK["fp64_vector"] if prim == "fp64" else PEAK["fp32_vector"]
         bound = "alu"
     achieved = work / (avg_ms[dominant] * 1e-3) / 1e12
+    traffic = recorded_traffic(args.workload, prim) if dominant == "m2l" else None
     roofline = {"bound": bound, "kernel": dominant, "achieved": round(achieved, 3), "peak": peak,
-                "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": traffic,
                 "avg_launch_ms": round(avg_ms[dominant], 4),
                 "work_per_launch": work,
                 "kernel_ms_per_step": {k: round(v, 3) for k, v in kms.items()},
                 "launches_per_step": dict(kl)}
 
-    # CPU oracle on a bounded sample: exact fields of all sources at S targets, extrapolated to
-    # the evaluations of one step (charge field, initial residual, iterations, final pass)
+    # CPU oracle on the bounded sample above: exact fields of all n sources at S targets,
+    # extrapolated to the field evaluations of one step (charge field, initial residual, one per
+    # iteration, final pass)
     cpu = None
     if not args.no_cpu_baseline:
-        S = min(args.oracle_sample, n)
-        sidx = np.sort(rng.choice(n, S, replace=False))
-        mu = results[prim]["res"].mu.cpu().numpy()
-        t0 = time.perf_counter()
-        D.fields_at(sidx, ps.pos, ps.q, mu, ps.alpha, 2.0)
-        tS = time.perf_counter() - t0
         evals = results[prim]["res"].iters + 3
-        t_step = tS * (n / S) * evals
+        t_step = t_oracle * (n / S) * evals
         cpu = {"value": round(n / t_step, 3), "unit": "particles/s", "cores": 1, "kind": "oracle",
                "sample": f"direct-sum fields (phi, E, damped E, grad E) at {S} of {n} particles from all "
-                         f"{n} sources in {tS:.1f} s, scaled by n/{S} and by the {evals} field "
-                         f"evaluations of one step"}
+                         f"{n} sources in {t_oracle:.1f} s (numpy, one thread), scaled by n/{S} and by the "
+                         f"{evals} field evaluations of one step"}
 
     r0 = results[prim]
     value = n / r0["dt"]
