@@ -81,6 +81,11 @@ typedef struct pfmm_config {
                           0 disables damping.  Applied to dipole-dipole pairs only.               */
   double coulomb_k;    /* energy scale k_e                                                         */
   unsigned flags;      /* pfmm_flags                                                               */
+  int m2l_order_slack; /* -1: every M2L at order p (the plain method).  >= 0: the M2L at cell offset
+                          d is truncated at the smallest order q whose error bound (sqrt(3)/|d|)^(q+1)
+                          does not exceed that of the nearest offsets at order p,
+                          (sqrt(3)/(ws+1))^(p+1), plus this slack, at most p (an extension: it
+                          equalises the per-interaction error bound over the offsets of the list)  */
 } pfmm_config;
 
 typedef struct pfmm_result {
@@ -94,6 +99,7 @@ typedef struct pfmm_result {
   int64_t n_leaves, n_cells;    /* non-empty leaves, non-empty cells on all levels                 */
   int64_t n_m2l;                /* source-target M2L cell pairs per evaluation                     */
   int64_t n_p2p;                /* ordered near-field particle pairs per evaluation (i != j)       */
+  int64_t m2l_flops;            /* useful M2L flops per evaluation: 2 C(q+6, 6) per pair of order q */
   int n_evals;                  /* FMM field evaluations performed                                 */
   double t_phase_ms[8];         /* with PFMM_TIMING: tree, charge field, dipole solve, final pass,
                                    assembly, total, -, -                                           */
@@ -108,7 +114,7 @@ typedef struct pfmm_handle pfmm_handle;
 
 /* Fill *cfg with the defaults: p = 6, ws = 2, leaf_width = 0, FP64, scf_tol = 1e-6,
    scf_max_iter = 200, graph_iters = 4, thole_a = 2.0, coulomb_k = 332.06371,
-   flags = WANT_FORCES | WANT_POTENTIALS | SAVE_FOR_BACKWARD. */
+   flags = WANT_FORCES | WANT_POTENTIALS | SAVE_FOR_BACKWARD, m2l_order_slack = -1. */
 void pfmm_config_default(pfmm_config* cfg);
 
 /* Create a handle for a configuration.  Validates cfg, builds the constant operator tables of

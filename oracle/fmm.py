@@ -171,8 +171,9 @@ def m2l_matrix(p: int):
     return nm
 
 
-def m2l(p, M_src, R, nm=None):
-    """F_n(z_B) = sum_{|m| <= p - |n|} M_m(z_A) D_{n+m}(z_B - z_A) for a batch of pairs.
+def m2l(p, M_src, R, nm=None, orders=None):
+    """F_n(z_B) = sum_{|m| <= q - |n|} M_m(z_A) D_{n+m}(z_B - z_A) for a batch of pairs, with the
+    truncation order q = p, or q = orders[k] for pair k when given (q <= p; F_n = 0 for |n| > q).
 
     M_src: (k, ncoef) source multipoles; R: (k, 3) = z_B - z_A.  Returns (k, ncoef).
     """
@@ -183,7 +184,29 @@ def m2l(p, M_src, R, nm=None):
     idx = np.where(mask, nm, 0)
     # restrict the order-2p index to order p: indices of degree <= p coincide in both orderings
     K = np.where(mask[None], D[:, idx], 0.0)
+    if orders is not None:
+        deg = np.array([sum(t) for t in _mi(p).items])
+        keep = (deg[None, :, None] + deg[None, None, :]) <= np.asarray(orders)[:, None, None]
+        K = np.where(keep, K, 0.0)
     return np.einsum("knm,km->kn", K, M_src)
+
+
+def offset_order(d, p, ws, slack):
+    """Truncation order of the M2L at the integer cell offset d (an extension of the fixed-order
+    scheme, not in the paper): the smallest q whose bound on the relative truncation error at this
+    offset, (rho_d)^(q+1) with rho_d = sqrt(3) / |d| (two cells of unit edge, radius sqrt(3)/2 each,
+    centres |d| apart), does not exceed that of the nearest offsets at order p, (sqrt(3)/(ws+1))^(p+1);
+    then raised by slack and capped at p.  Compared exactly in integers:
+        3^(q+1) (ws+1)^(2(p+1)) <= 3^(p+1) |d|^(2(q+1)).
+    slack < 0 means the fixed order p."""
+    if slack < 0:
+        return p
+    r2 = int(d[0]) ** 2 + int(d[1]) ** 2 + int(d[2]) ** 2
+    lhs_base = (ws + 1) ** (2 * (p + 1))
+    q = 0
+    while q < p and 3 ** (q + 1) * lhs_base > 3 ** (p + 1) * r2 ** (q + 1):
+        q += 1
+    return min(p, q + slack)
 
 
 def l2l(p, F_parent, x):
@@ -282,7 +305,7 @@ class Octree:
 # Field evaluation.
 # ----------------------------------------------------------------------------------------------
 
-def fmm_fields(X, q, mu, alpha, thole_a, p, leaf_width, ws=1, want_grad=True):
+def fmm_fields(X, q, mu, alpha, thole_a, p, leaf_width, ws=1, want_grad=True, order_slack=-1):
     """FMM fields of charges q and point dipoles mu at every particle.
 
     Returns a dict with
@@ -321,7 +344,11 @@ def fmm_fields(X, q, mu, alpha, thole_a, p, leaf_width, ws=1, want_grad=True):
             chunk = pairs[s:s + 256]
             R = np.array([tree.centre(l, B) - tree.centre(l, A) for B, A in chunk])
             Ms = np.array([M[l][A] for B, A in chunk])
-            Fk = m2l(p, Ms, R, nm)
+            orders = None
+            if order_slack >= 0:
+                orders = [offset_order((B[0] - A[0], B[1] - A[1], B[2] - A[2]), p, ws, order_slack)
+                          for B, A in chunk]
+            Fk = m2l(p, Ms, R, nm, orders)
             for (B, A), f in zip(chunk, Fk):
                 F[l][B] = F[l].get(B, np.zeros(nc)) + f
 

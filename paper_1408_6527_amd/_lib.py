@@ -47,6 +47,7 @@ class Config(ctypes.Structure):
         ("thole_a", ctypes.c_double),
         ("coulomb_k", ctypes.c_double),
         ("flags", ctypes.c_uint),
+        ("m2l_order_slack", ctypes.c_int),
     ]
 
 
@@ -64,6 +65,7 @@ class Result(ctypes.Structure):
         ("n_cells", ctypes.c_int64),
         ("n_m2l", ctypes.c_int64),
         ("n_p2p", ctypes.c_int64),
+        ("m2l_flops", ctypes.c_int64),
         ("n_evals", ctypes.c_int),
         ("t_phase_ms", ctypes.c_double * 8),
         ("t_kernel_ms", ctypes.c_double * 8),

@@ -138,7 +138,7 @@ class Solver:
         self.last_result = res
         self._n_last = n
         stats = dict(levels=res.levels, leaf_width=res.leaf_width, n_leaves=res.n_leaves,
-                     n_cells=res.n_cells, n_m2l=res.n_m2l, n_p2p=res.n_p2p, n_evals=res.n_evals,
+                     n_cells=res.n_cells, n_m2l=res.n_m2l, n_p2p=res.n_p2p, m2l_flops=res.m2l_flops, n_evals=res.n_evals,
                      t_phase_ms=list(res.t_phase_ms), status=_lib.STATUS[st],
                      t_kernel_ms=dict(zip(_lib.KERNEL_CLASSES, res.t_kernel_ms)),
                      kernel_launches=dict(zip(_lib.KERNEL_CLASSES, res.kernel_launches)))

@@ -148,7 +148,7 @@ struct pfmm_handle {
   OpTables op;
   int device = 0;
   // constant tables
-  DevBuf t_mi, t_p2m, t_ifact, t_l2p, t_code, t_dvec, t_dvec32, t_hidx;
+  DevBuf t_mi, t_p2m, t_ifact, t_l2p, t_code, t_dvec, t_dvec32, t_hidx, t_dorder;
   // tree workspace
   DevBuf w_partial, w_flags, w_bbox, w_keys_in, w_keys, w_vals_in, w_perm, w_sort_tmp, w_scan_tmp,
       w_lvl_flags, w_cid, w_counts, w_ckey, w_cfirst, w_ccount, w_cparent, w_child8, w_coll, w_stats;
@@ -170,7 +170,7 @@ struct pfmm_handle {
   Particles pa;
   int m2l_tiles = 0, nsplit = 1;
   int64_t split_stride = 0;
-  int64_t n_m2l = 0, n_p2p = 0;
+  int64_t n_m2l = 0, n_p2p = 0, m2l_flops = 0;
   int n_evals = 0;
 };
 
@@ -208,6 +208,7 @@ void validate_config(const pfmm_config* c) {
   if (!(c->thole_a >= 0.0) || !std::isfinite(c->thole_a))
     throw Error(PFMM_ERR_INVALID_ARG, "thole_a must be >= 0");
   if (!std::isfinite(c->coulomb_k)) throw Error(PFMM_ERR_INVALID_ARG, "coulomb_k must be finite");
+  if (c->m2l_order_slack < -1) throw Error(PFMM_ERR_INVALID_ARG, "m2l_order_slack must be >= -1");
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -326,10 +327,10 @@ void build_tree(pfmm_handle* h, int n, const double* pos, const double* q, const
   Particles& pa = h->pa;
   pa.n = n; pa.P = P; pa.alpha = al; pa.sqa = sqa; pa.tau = tau; pa.itau = itau;
 
-  unsigned long long* stats = dev<unsigned long long>(h->w_stats, 2);
-  PFMM_HIP(hipMemsetAsync(stats, 0, 2 * sizeof(unsigned long long), s));
-  launch_tree_stats(t, h->op.m2l_code, h->op.noff, stats, s);
-  unsigned long long st[2];
+  unsigned long long* stats = dev<unsigned long long>(h->w_stats, 3);
+  PFMM_HIP(hipMemsetAsync(stats, 0, 3 * sizeof(unsigned long long), s));
+  launch_tree_stats(t, h->op.m2l_code, h->op.dorder, h->op.noff, stats, s);
+  unsigned long long st[3];
   {
     void* pin = h->pinned.get(sizeof(st));
     PFMM_HIP(hipMemcpyAsync(pin, stats, sizeof(st), hipMemcpyDeviceToHost, s));
@@ -338,6 +339,7 @@ void build_tree(pfmm_handle* h, int n, const double* pos, const double* q, const
   }
   h->n_m2l = (int64_t)st[0];
   h->n_p2p = (int64_t)st[1];
+  h->m2l_flops = (int64_t)st[2];
   // enough workgroups to fill the device: split each parent tile's colleague offsets when tiles are
   // few (at least 4 offsets per split, so that staging the index table stays a small share)
   h->m2l_tiles = L >= 2 ? m2l_tiles(t, 1, L - 1, 2) : 0;  // workgroups of 32 parents
@@ -568,6 +570,7 @@ pfmm_status solve_impl(pfmm_handle* h, int64_t n64, const double* pos, const dou
   res->n_cells = h->tv.ncell;
   res->n_m2l = h->n_m2l;
   res->n_p2p = h->n_p2p;
+  res->m2l_flops = h->m2l_flops;
   res->n_evals = 3 + hs.iters;  // charge field, initial residual, iterations, final pass
   h->saved = true;
   h->saved_n = n;
@@ -594,6 +597,7 @@ void pfmm_config_default(pfmm_config* c) {
   c->thole_a = 2.0;
   c->coulomb_k = 332.06371;
   c->flags = PFMM_WANT_FORCES | PFMM_WANT_POTENTIALS | PFMM_SAVE_FOR_BACKWARD;
+  c->m2l_order_slack = -1;
 }
 
 pfmm_status pfmm_create(const pfmm_config* cfg, pfmm_handle** out) {
@@ -604,7 +608,7 @@ pfmm_status pfmm_create(const pfmm_config* cfg, pfmm_handle** out) {
     validate_config(cfg);
     h = new pfmm_handle();
     h->cfg = *cfg;
-    h->tab.build(cfg->order_p, cfg->ws);
+    h->tab.build(cfg->order_p, cfg->ws, cfg->m2l_order_slack);
     const HostTables& T = h->tab;
     upload(h->t_mi, T.mi);
     upload(h->t_p2m, T.p2m_coef);
@@ -613,6 +617,7 @@ pfmm_status pfmm_create(const pfmm_config* cfg, pfmm_handle** out) {
     upload(h->t_code, T.m2l_code);
     upload(h->t_dvec, T.dvec);
     upload(h->t_hidx, T.hidx);
+    upload(h->t_dorder, T.dorder);
     if (cfg->precision == PFMM_MIXED) {
       std::vector<float> d32(T.dvec.begin(), T.dvec.end());
       upload(h->t_dvec32, d32);
@@ -628,6 +633,7 @@ pfmm_status pfmm_create(const pfmm_config* cfg, pfmm_handle** out) {
     op.dvec = h->t_dvec.as<double>();
     op.dvec32 = cfg->precision == PFMM_MIXED ? h->t_dvec32.as<float>() : nullptr;
     op.hidx = h->t_hidx.as<unsigned short>();
+    op.dorder = h->t_dorder.as<unsigned char>();
     op.nblocks = T.nblocks;
     PFMM_HIP(hipGetDevice(&h->device));
     *out = h;

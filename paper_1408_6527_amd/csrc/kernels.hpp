@@ -74,8 +74,10 @@ void launch_cells(const uint64_t* keys, int n, int L, int l, const int* cid_l, c
 void launch_cell_counts(const int* cfirst, int off_l, int ncell_l, int n, int* ccount, hipStream_t s);
 void launch_colleagues(const uint64_t* ckey, int off_l, int ncell_l, int l, int ws, int* coll,
                        hipStream_t s);
-void launch_tree_stats(const TreeView& t, const int* m2l_code, int noff, unsigned long long* stats,
-                       hipStream_t s);
+// stats[0] += M2L pairs with a source, stats[1] += ordered near-field particle pairs,
+// stats[2] += useful M2L flops (2 C(q+6, 6) per pair of truncation order q = dorder[slot])
+void launch_tree_stats(const TreeView& t, const int* m2l_code, const unsigned char* dorder, int noff,
+                       unsigned long long* stats, hipStream_t s);
 
 // ---------------------------------------------------------------- expansions.hip
 struct OpTables {
@@ -89,6 +91,7 @@ struct OpTables {
   // rows of sched_dpitch(p) values (float copy only on the mixed path), and the K-entry index table
   // (one index into such a row per MFMA block and lane, schedule.hpp)
   const double* dvec = nullptr; const float* dvec32 = nullptr; const unsigned short* hidx = nullptr;
+  const unsigned char* dorder = nullptr;  // truncation order per offset slot
   int nblocks = 0;
 };
 // sources: 1 = charges (P.w), 2 = dipoles (mu4), 3 = both

@@ -15,6 +15,9 @@
 //     for c in octants: stage the 16 source rows; each wave o with |d| > ws runs the
 //       degree-blocked MFMA schedule (schedule.hpp): A = K_d entries gathered from the LDS copy
 //       of D(d) through the index table, B = source coefficients from LDS.
+// With a per-offset truncation order q(d) <= p (m2l_order_slack >= 0) a wave runs the unrolled
+// schedule of its q: the blocks of the order-p schedule that hold entries of degree <= q, with the
+// entries of degree above q read as zero.
 // Accumulators stay in registers for the whole loop and each target's (partial) F~ is written once:
 // no atomics, deterministic.
 //
@@ -22,6 +25,7 @@
 // float32 accumulation, except for targets at levels <= fp64_max_level.
 #include <algorithm>
 #include <type_traits>
+#include <utility>
 
 #include "kernels.hpp"
 #include "schedule.hpp"
@@ -37,26 +41,81 @@ constexpr int TPB = 512;  // 8 waves, one per target octant
 constexpr int NU = 27;    // u = oB - c in [-1, 1]^3
 
 // (step, row block) of every MFMA block in schedule order (schedule.hpp), as compile-time tables
-template <int P>
+// The blocks of the order-P schedule that a truncation at order Q <= P needs (rows of degree <= Q,
+// steps below count(Q - lowest row degree)), in schedule order, with their position bp in the
+// full order-P block order (which locates their K-entry indices).
+template <int P, int Q>
 struct BlockOrder {
+  int n;
   int s[sched_nblocks(P)];
   int rb[sched_nblocks(P)];
-  constexpr BlockOrder() : s(), rb() {
+  int bp[sched_nblocks(P)];
+  constexpr BlockOrder() : n(0), s(), rb(), bp() {
     int b = 0;
     for (int st = 0; st < sched_maxsteps(P); ++st)
       for (int r = 0; r < sched_nrb(P); ++r)
         if (sched_nsteps(P, r) > st) {
-          s[b] = st;
-          rb[b] = r;
+          const int d0 = sched_deg_of(16 * r);
+          if (d0 <= Q && sched_coef(st, 0) < mi_count(Q - d0)) {
+            s[n] = st;
+            rb[n] = r;
+            bp[n] = b;
+            ++n;
+          }
           ++b;
         }
   }
 };
 
+// One slot of one wave at truncation order Q: A = K_d entries gathered from the staged D(d) at Dv
+// through the index groups sH (entries of degree above Q read the zero at index NC), B = the staged
+// source coefficients at Bp.
+template <int P, bool F32, int NCB, int Q, typename kt, typename kt2, typename acc_t>
+__device__ __forceinline__ void m2l_mfma(const kt* Dv, const kt* Bp, const uint4* sH, int lane,
+                                         acc_t (&acc)[NCB][sched_nrb(P)]) {
+  constexpr BlockOrder<P, Q> order{};
+  constexpr int NB = order.n;
+  constexpr int NC = mi_count(P), NCQ = mi_count(Q);
+  constexpr int BP = sched_stride(P) + 2;
+  kt2 bb[NCB];
+  uint4 hg;
+#pragma unroll
+  for (int k = 0; k < NB; ++k) {
+    const int s = order.s[k], rb = order.rb[k], blk = order.bp[k];
+    if ((s & 1) == 0 && (k == 0 || order.s[k - 1] != s)) {
+      // steps s and s + 1 read coefficients m(s, q) and m(s, q) + 1 of the lane's column
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) bb[cb] = *reinterpret_cast<const kt2*>(Bp + cb * 16 * BP + 4 * s);
+    }
+    if (k == 0 || (order.bp[k - 1] >> 3) != (blk >> 3)) hg = sH[(blk >> 3) * 64 + lane];
+    const unsigned hw[4] = {hg.x, hg.y, hg.z, hg.w};
+    const unsigned hv = hw[(blk & 7) >> 1];
+    unsigned idx = (blk & 1) ? (hv >> 16) : (hv & 0xffffu);
+    if constexpr (Q < P) idx = idx < (unsigned)NCQ ? idx : (unsigned)NC;
+    const kt a = Dv[idx];
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) {
+      const kt b = (s & 1) ? bb[cb].y : bb[cb].x;
+      if constexpr (F32)
+        acc[cb][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[cb][rb], 0, 0, 0);
+      else
+        acc[cb][rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[cb][rb], 0, 0, 0);
+    }
+  }
+}
+
+// Run the slot at a runtime order q < P (one unrolled schedule per order).
+template <int P, bool F32, int NCB, typename kt, typename kt2, typename acc_t, int... Qs>
+__device__ __forceinline__ void m2l_mfma_order(int q, std::integer_sequence<int, Qs...>, const kt* Dv,
+                                               const kt* Bp, const uint4* sH, int lane,
+                                               acc_t (&acc)[NCB][sched_nrb(P)]) {
+  (void)((q == Qs ? (m2l_mfma<P, F32, NCB, Qs, kt, kt2, acc_t>(Dv, Bp, sH, lane, acc), true) : false) || ...);
+}
+
 // 16-parent tiles per workgroup: every K_d entry gathered from LDS feeds NCB MFMAs.  Bounded by
 // the accumulator registers (NCB x NRB tiles of 16 x 16) and the LDS of the staged sources.
 template <int P, bool F32>
-constexpr int m2l_ncb() { return (F32 ? P <= 9 : P <= 7) ? 2 : 1; }
+constexpr int m2l_ncb() { return (F32 ? P <= 8 : P <= 7) ? 2 : 1; }
 // registers per lane: 4 waves per SIMD (two workgroups per CU) only where they fit
 template <int P, bool F32>
 constexpr int m2l_waves_per_eu() { return P <= 4 ? 4 : 2; }
@@ -71,7 +130,6 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(m2l_waves_p
   using acc_t = typename std::conditional<F32, f4, d4>::type;
   constexpr int NCB = m2l_ncb<P, F32>();
   constexpr int NRB = sched_nrb(P);
-  constexpr int NB = sched_nblocks(P);
   constexpr int NC = mi_count(P);
   constexpr int STRIDE = sched_stride(P);
   constexpr int DP = sched_dpitch(P);
@@ -82,13 +140,17 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(m2l_waves_p
   constexpr int NG = sched_hgroups(P);
   constexpr int ROWS = 16 * NCB;
   constexpr int PF = (ROWS * HALF + TPB - 1) / TPB;  // 16-byte source pieces per thread and slot
-  constexpr BlockOrder<P> order{};
   __shared__ uint4 sH[NG * 64];
   __shared__ kt sD[NU * DP];
+  __shared__ int sQ[NU];  // truncation order of the 27 staged offsets
   __shared__ __attribute__((aligned(16))) kt sB[ROWS * BP];
   __shared__ int sSrc[8][ROWS];
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // waves w and w + 4 share a SIMD; giving them complementary octants (o and 7 - o) pairs a target
+  // that sees a source octant at a near offset with one that sees it farther away, which evens out
+  // the per-offset truncation orders between the SIMDs of one slot
+  const int oct = wave < 4 ? wave : 11 - wave;
   const int split = blockIdx.x % nsplit;
   int tile = blockIdx.x / nsplit, lp = lp_lo;
   for (; lp <= lp_hi; ++lp) {
@@ -105,7 +167,7 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(m2l_waves_p
 #pragma unroll
   for (int cb = 0; cb < NCB; ++cb) {
     const int P_ = pbeg + 16 * cb + col;
-    tgt[cb] = P_ < pend ? t.child8[8 * P_ + wave] : -1;
+    tgt[cb] = P_ < pend ? t.child8[8 * P_ + oct] : -1;
     any_tgt |= tgt[cb] >= 0;
   }
   const bool active = __ballot(any_tgt) != 0;
@@ -113,7 +175,7 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(m2l_waves_p
 
   const int ws = t.ws, side = 2 * ws + 1, nn = t.nnear;
   const int R = 2 * ws + 1, cube = 2 * R + 1;
-  const int ob0 = (wave >> 2) & 1, ob1 = (wave >> 1) & 1, ob2 = wave & 1;
+  const int ob0 = (oct >> 2) & 1, ob1 = (oct >> 1) & 1, ob2 = oct & 1;
   const int c0 = (int)((int64_t)nn * split / nsplit);
   const int c1 = (int)((int64_t)nn * (split + 1) / nsplit);
   const kt* dtab;
@@ -184,6 +246,7 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(m2l_waves_p
       if (max(abs(d0), max(abs(d1), abs(d2))) > ws) {
         const int slot = ((d0 + R) * cube + (d1 + R)) * cube + (d2 + R);
         sD[e] = dtab[(int64_t)slot * DP + k];
+        if (k == 0) sQ[v] = op.dorder[slot];
       }
     }
     while (true) {
@@ -196,34 +259,15 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(m2l_waves_p
       const int u0 = ob0 - ((r >> 2) & 1), u1 = ob1 - ((r >> 1) & 1), u2 = ob2 - (r & 1);
       const int d0 = u0 - 2 * e0, d1 = u1 - 2 * e1, d2 = u2 - 2 * e2;
       if (active && max(abs(d0), max(abs(d1), abs(d2))) > ws) {  // wave-uniform
-        const kt* Dv = sD + ((u0 + 1) * 9 + (u1 + 1) * 3 + (u2 + 1)) * DP;
+        const int v = (u0 + 1) * 9 + (u1 + 1) * 3 + (u2 + 1);
+        const kt* Dv = sD + v * DP;
         const kt* Bp = sB + col * BP + 2 * kq;
-        kt2 bb[NCB];
-        uint4 hcur, hnext = sH[lane];
-#pragma unroll
-        for (int blk = 0; blk < NB; ++blk) {
-          const int s = order.s[blk], rb = order.rb[blk];
-          if ((s & 1) == 0 && (blk == 0 || order.s[blk - 1] != s)) {
-            // steps s and s + 1 read coefficients m(s, q) and m(s, q) + 1 of the lane's column
-#pragma unroll
-            for (int cb = 0; cb < NCB; ++cb) bb[cb] = *reinterpret_cast<const kt2*>(Bp + cb * 16 * BP + 4 * s);
-          }
-          if ((blk & 7) == 0) {
-            hcur = hnext;
-            if ((blk >> 3) + 1 < NG) hnext = sH[((blk >> 3) + 1) * 64 + lane];
-          }
-          const unsigned hw[4] = {hcur.x, hcur.y, hcur.z, hcur.w};
-          const unsigned hv = hw[(blk & 7) >> 1];
-          const kt a = Dv[(blk & 1) ? (hv >> 16) : (hv & 0xffffu)];
-#pragma unroll
-          for (int cb = 0; cb < NCB; ++cb) {
-            const kt b = (s & 1) ? bb[cb].y : bb[cb].x;
-            if constexpr (F32)
-              acc[cb][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[cb][rb], 0, 0, 0);
-            else
-              acc[cb][rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[cb][rb], 0, 0, 0);
-          }
-        }
+        const int q = sQ[v];
+        if (q >= P)
+          m2l_mfma<P, F32, NCB, P, kt, kt2, acc_t>(Dv, Bp, sH, lane, acc);
+        else
+          m2l_mfma_order<P, F32, NCB, kt, kt2, acc_t>(q, std::make_integer_sequence<int, P>{}, Dv, Bp, sH,
+                                                      lane, acc);
       }
       if (rn < 0) break;
       r = rn;

@@ -80,7 +80,25 @@ void derivative_tensor_unit(int p, const int* mi, int nc, const int d[3], double
     out[k] = (double)(a[k] * fact_ld(mi[3 * k]) * fact_ld(mi[3 * k + 1]) * fact_ld(mi[3 * k + 2]));
 }
 
-void HostTables::build(int p_, int ws_) {
+int offset_order(const int d[3], int p, int ws, int slack) {
+  if (slack < 0) return p;
+  typedef unsigned __int128 u128;
+  const u128 r2 = (u128)(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+  u128 base = 1;
+  for (int k = 0; k < 2 * (p + 1); ++k) base *= (u128)(ws + 1);
+  u128 three_p1 = 1;
+  for (int k = 0; k < p + 1; ++k) three_p1 *= 3;
+  int q = 0;
+  u128 three_q1 = 3, r2_q1 = r2;  // 3^(q+1), r2^(q+1)
+  while (q < p && three_q1 * base > three_p1 * r2_q1) {
+    ++q;
+    three_q1 *= 3;
+    r2_q1 *= r2;
+  }
+  return std::min(p, q + slack);
+}
+
+void HostTables::build(int p_, int ws_, int order_slack) {
   p = p_;
   ws = ws_;
   MIndex ix(p);
@@ -158,6 +176,7 @@ void HostTables::build(int p_, int ws_) {
   // where |n| + |m| > p or n, m fall in the padding.
   dpitch = sched_dpitch(p);
   dvec.assign((size_t)nslot * dpitch, 0.0);
+  dorder.assign((size_t)nslot, 0);
   std::vector<double> Dn(nc);
   for (int dx = -R; dx <= R; ++dx)
     for (int dy = -R; dy <= R; ++dy)
@@ -167,6 +186,7 @@ void HostTables::build(int p_, int ws_) {
         const int d[3] = {dx, dy, dz};
         derivative_tensor_unit(p, mi.data(), nc, d, Dn.data());
         std::copy(Dn.begin(), Dn.end(), dvec.begin() + (size_t)slot * dpitch);
+        dorder[slot] = (unsigned char)offset_order(d, p, ws, order_slack);
       }
   std::vector<int> degv(nc);
   for (int k = 0; k < nc; ++k) degv[k] = ix.deg(k);

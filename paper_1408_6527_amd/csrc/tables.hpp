@@ -33,8 +33,18 @@ struct HostTables {
   std::vector<double> dvec;      // nslot x dpitch: D_k(d) of every offset slot, zero-padded
   std::vector<unsigned short> hidx;  // index of K[n][m] in a dvec row per block and lane (sched_hpos)
 
-  void build(int p, int ws);
+  // truncation order of the M2L per offset slot (0 for the near slots), see offset_order()
+  std::vector<unsigned char> dorder;
+
+  void build(int p, int ws, int order_slack);
 };
+
+// Truncation order of the M2L at the integer cell offset d: with slack < 0 the fixed order p;
+// otherwise the smallest q whose bound on the relative truncation error at this offset,
+// (sqrt(3)/|d|)^(q+1) (two unit cells of radius sqrt(3)/2, centres |d| apart), does not exceed the
+// bound of the nearest offsets at order p, (sqrt(3)/(ws+1))^(p+1), plus slack, capped at p.
+// Decided exactly in integers: 3^(q+1) (ws+1)^(2(p+1)) <= 3^(p+1) |d|^(2(q+1)).
+int offset_order(const int d[3], int p, int ws, int slack);
 
 // D_n(d) = d^n (1/|d|) for |n| <= p at an integer offset d, by the Taylor-coefficient recurrence
 // |n| r^2 a_n = -(2|n| - 1) sum_i d_i a_{n - e_i} - (|n| - 1) sum_i a_{n - 2 e_i},  D_n = n! a_n.

@@ -193,11 +193,13 @@ __global__ __launch_bounds__(TPB) void k_colleagues(const uint64_t* __restrict__
   }
 }
 
-// stats[0] += M2L pairs with a non-empty source; stats[1] += ordered near-field particle pairs.
+// stats[0] += M2L pairs with a non-empty source; stats[1] += ordered near-field particle pairs;
+// stats[2] += useful M2L flops, 2 C(q+6, 6) per pair at its truncation order q.
 __global__ __launch_bounds__(TPB) void k_tree_stats(TreeView t, const int* __restrict__ m2l_code,
-                                                    int noff, unsigned long long* stats) {
+                                                    const unsigned char* __restrict__ dorder, int noff,
+                                                    unsigned long long* stats) {
   const int first2 = t.L >= 2 ? t.off[2] : t.ncell;
-  unsigned long long m2l = 0, p2p = 0;
+  unsigned long long m2l = 0, p2p = 0, flops = 0;
   for (int g = blockIdx.x * TPB + threadIdx.x; g < t.ncell; g += gridDim.x * TPB) {
     if (g >= first2) {
       const int oct = (int)(t.key[g] & 7);
@@ -205,7 +207,11 @@ __global__ __launch_bounds__(TPB) void k_tree_stats(TreeView t, const int* __res
       for (int j = 0; j < noff; ++j) {
         const int code = m2l_code[oct * noff + j];
         const int pc = t.coll[(int64_t)par * t.nnear + ((code >> 12) & 0xff)];
-        if (pc >= 0 && t.child8[8 * pc + ((code >> 20) & 7)] >= 0) ++m2l;
+        if (pc >= 0 && t.child8[8 * pc + ((code >> 20) & 7)] >= 0) {
+          ++m2l;
+          const unsigned long long q = dorder[code & 0xfff];
+          flops += 2 * ((q + 1) * (q + 2) * (q + 3) * (q + 4) * (q + 5) * (q + 6) / 720);
+        }
       }
     }
     if (g >= t.off[t.L]) {
@@ -219,6 +225,7 @@ __global__ __launch_bounds__(TPB) void k_tree_stats(TreeView t, const int* __res
   }
   if (m2l) atomicAdd(&stats[0], m2l);
   if (p2p) atomicAdd(&stats[1], p2p);
+  if (flops) atomicAdd(&stats[2], flops);
 }
 
 }  // namespace
@@ -312,9 +319,9 @@ void launch_colleagues(const uint64_t* ckey, int off_l, int ncell_l, int l, int 
   PFMM_LAUNCH_CHECK();
 }
 
-void launch_tree_stats(const TreeView& t, const int* m2l_code, int noff, unsigned long long* stats,
-                       hipStream_t s) {
-  hipLaunchKernelGGL(k_tree_stats, dim3(grid_for(t.ncell)), dim3(TPB), 0, s, t, m2l_code, noff,
+void launch_tree_stats(const TreeView& t, const int* m2l_code, const unsigned char* dorder, int noff,
+                       unsigned long long* stats, hipStream_t s) {
+  hipLaunchKernelGGL(k_tree_stats, dim3(grid_for(t.ncell)), dim3(TPB), 0, s, t, m2l_code, dorder, noff,
                      stats);
   PFMM_LAUNCH_CHECK();
 }

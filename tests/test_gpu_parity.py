@@ -95,6 +95,28 @@ def test_field_fmm_matches_oracle_fmm(api, p, ws, lw):
     assert relmax(N(G), ref["G_d"]) < 1e-11
 
 
+@pytest.mark.parametrize("p,ws,lw,slack", [(6, 2, 1.8, 0), (8, 2, 1.8, 1), (4, 1, 1.8, 0), (10, 2, 1.8, 2)])
+def test_field_offset_orders_match_oracle_fmm(api, p, ws, lw, slack):
+    """M2L truncated per offset (m2l_order_slack): the same truncation orders as the oracle's
+    offset_order, so the fields agree to rounding."""
+    print_case(f"field fmm offset orders p={p} ws={ws} slack={slack}")
+    X, q, a, mu = cube(600, 13.0, 2)
+    s = api.Solver(order_p=p, ws=ws, leaf_width=lw, thole_a=0.0, m2l_order_slack=slack)
+    phi, E, Ed, G = s.field(T(X), T(q), T(mu), T(a))
+    ref = FM.fmm_fields(X, q, mu, a, 0.0, p, lw, ws, order_slack=slack)
+    plain = FM.fmm_fields(X, q, mu, a, 0.0, p, lw, ws)
+    assert ref["tree"].L >= 3
+    assert relmax(ref["E_d"], plain["E_d"]) > 1e-9  # the truncation really differs
+    assert relmax(N(phi), ref["phi"]) < 1e-11
+    assert relmax(N(E), ref["E_u"]) < 1e-11
+    assert relmax(N(Ed), ref["E_d"]) < 1e-11
+    assert relmax(N(G), ref["G_d"]) < 1e-11
+    # the float32 M2L runs the same per-order schedules
+    sm = api.Solver(order_p=p, ws=ws, leaf_width=lw, thole_a=0.0, m2l_order_slack=slack, precision="mixed")
+    phm, Em, Edm, Gm = sm.field(T(X), T(q), T(mu), T(a))
+    assert relnorm(N(Edm), ref["E_d"]) < 1e-5
+
+
 def test_field_charges_only_and_dipoles_only(api):
     print_case("field sources split")
     X, q, a, mu = cube(400, 11.0, 3)
@@ -330,14 +352,15 @@ def test_zero_polarizability_is_coulomb(api):
 
 # ------------------------------------------------------------------ large systems on sampled outputs
 
-@pytest.mark.parametrize("p,lw,gate", [(6, 4.0, 3e-4), (8, 6.0, 3e-5), (10, 5.0, 1e-5)])
-def test_globular_50k_sampled(api, p, lw, gate):
+@pytest.mark.parametrize("p,lw,gate,slack", [(6, 4.0, 3e-4, -1), (8, 6.0, 3e-5, -1), (10, 5.0, 1e-5, -1),
+                                              (10, 6.0, 1e-5, 2)])
+def test_globular_50k_sampled(api, p, lw, gate, slack):
     """50,000-particle globular system: at 64 sampled particles the exact forces and dipole
     residual computed by the oracle from the library's own dipoles agree with the library."""
-    print_case(f"globular 50k p={p}")
+    print_case(f"globular 50k p={p} slack={slack}")
     from paper_1408_6527_amd import inputs
     ps = inputs.globular(50_000)
-    s = api.Solver(order_p=p, ws=2, leaf_width=lw, scf_tol=1e-6)
+    s = api.Solver(order_p=p, ws=2, leaf_width=lw, scf_tol=1e-6, m2l_order_slack=slack)
     r = s.solve(T(ps.pos), T(ps.q), T(ps.alpha))
     mu = N(r.mu)
     idx = np.random.default_rng(5).choice(ps.n, 64, replace=False)

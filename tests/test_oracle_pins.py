@@ -3,6 +3,7 @@ high precision and the FMM error decay.  None of these tests needs a GPU.
 
 Each test names the passage of arXiv:1408.6527 it pins.
 """
+import itertools
 import math
 
 import numpy as np
@@ -453,3 +454,92 @@ def test_fmm_pair_accounting_is_complete():
                     for j in members[A]:
                         cover[i, j] += 1
         assert np.all(cover == 1)
+
+
+# ------------------------------------------------------------------ per-offset truncation order
+
+def _offsets(ws):
+    """Every M2L offset d = oB - c - 2e of the ws lists, over all target octants."""
+    out = set()
+    for o in range(8):
+        ob = ((o >> 2) & 1, (o >> 1) & 1, o & 1)
+        for t in itertools.product(range(-2 * ws, 2 * ws + 2), repeat=3):
+            d = tuple(ob[a] - t[a] for a in range(3))
+            if max(abs(x) for x in d) > ws:
+                out.add(d)
+    return sorted(out)
+
+
+@pytest.mark.parametrize("ws", [1, 2])
+def test_offset_order_bound_is_the_smallest_order_meeting_it(ws):
+    """slack 0: q is the least order whose bound (sqrt3/|d|)^(q+1) does not exceed the nearest
+    offsets' bound at order p, (sqrt3/(ws+1))^(p+1) (checked in floating point away from ties);
+    the nearest offsets keep order p; the order never grows with distance."""
+    for p in (2, 6, 8, 10):
+        ref = (p + 1) * math.log(math.sqrt(3) / (ws + 1))
+        by_r2 = {}
+        for d in _offsets(ws):
+            q = FM.offset_order(d, p, ws, 0)
+            r = math.sqrt(sum(x * x for x in d))
+            lr = math.log(math.sqrt(3) / r)
+            assert 0 <= q <= p
+            if q < p:
+                assert (q + 1) * lr <= ref + 1e-12          # bound met at q
+            if q > 0:
+                assert q * lr > ref - 1e-12                 # not met at q - 1
+            if max(abs(x) for x in d) == ws + 1 and sum(x * x for x in d) == (ws + 1) ** 2:
+                assert q == p
+            by_r2.setdefault(sum(x * x for x in d), set()).add(q)
+        qs = [max(v) for k, v in sorted(by_r2.items())]
+        assert all(len(v) == 1 for v in by_r2.values())     # a function of |d| only
+        assert all(a >= b for a, b in zip(qs, qs[1:]))       # non-increasing with distance
+
+
+def test_offset_order_slack_limits():
+    for d in _offsets(2):
+        assert FM.offset_order(d, 8, 2, -1) == 8
+        assert FM.offset_order(d, 8, 2, 8) == 8
+        assert FM.offset_order(d, 8, 2, 1) == min(8, FM.offset_order(d, 8, 2, 0) + 1)
+
+
+def test_m2l_with_orders_truncates_exactly():
+    """Per-pair orders: q = p reproduces the plain M2L (to rounding: the masked product may be
+    summed in another order); q < p keeps exactly the terms with |n| + |m| <= q (checked against a
+    loop over the multi-indices)."""
+    rng = np.random.default_rng(91)
+    p = 5
+    nc = FM.ncoef(p)
+    Ms = rng.normal(size=(4, nc))
+    R = rng.normal(size=(4, 3)) * 3 + np.array([5.0, 0.0, 0.0])
+    plain = FM.m2l(p, Ms, R)
+    assert np.allclose(FM.m2l(p, Ms, R, orders=[p] * 4), plain, rtol=1e-14, atol=1e-14 * np.abs(plain).max())
+    qs = [0, 2, 3, 5]
+    got = FM.m2l(p, Ms, R, orders=qs)
+    mi = FM._mi(p).items
+    D2 = FM.derivative_tensor(R, p)
+    mi2 = FM._mi(2 * p).index
+    for k, q in enumerate(qs):
+        want = np.zeros(nc)
+        for a, n in enumerate(mi):
+            for b, m in enumerate(mi):
+                if sum(n) + sum(m) <= q:
+                    want[a] += D2[k, mi2[(n[0] + m[0], n[1] + m[1], n[2] + m[2])]] * Ms[k, b]
+        assert np.allclose(got[k], want, rtol=1e-13, atol=1e-13 * np.abs(want).max())
+
+
+def test_fmm_with_offset_orders_stays_near_the_fixed_order_error():
+    """The per-offset orders with slack 2 keep the FMM field error within 1.5x of the fixed order
+    (and slack >= p is the fixed order, to rounding)."""
+    X, q, a = rand_system(300, 83, box=14.0, r_min=1.0)
+    mu = np.random.default_rng(5).normal(0, 0.2, (300, 3))
+    _, Eq, _ = D.charge_fields(X, q)
+    _, _, Ed, _ = D.dipole_fields(X, mu, a, 2.0)
+    ref = Eq + Ed
+    fixed = FM.fmm_fields(X, q, mu, a, 2.0, 4, 1.7, 2, want_grad=False)
+    assert fixed["tree"].L >= 3
+    same = FM.fmm_fields(X, q, mu, a, 2.0, 4, 1.7, 2, want_grad=False, order_slack=4)
+    assert np.allclose(same["E_d"], fixed["E_d"], rtol=1e-13, atol=1e-13 * np.abs(fixed["E_d"]).max())
+    adapt = FM.fmm_fields(X, q, mu, a, 2.0, 4, 1.7, 2, want_grad=False, order_slack=2)
+    e_fixed = np.linalg.norm(fixed["E_d"] - ref) / np.linalg.norm(ref)
+    e_adapt = np.linalg.norm(adapt["E_d"] - ref) / np.linalg.norm(ref)
+    assert e_adapt < 1.5 * e_fixed
