@@ -86,6 +86,12 @@ typedef struct pfmm_config {
                           does not exceed that of the nearest offsets at order p,
                           (sqrt(3)/(ws+1))^(p+1), plus this slack, at most p (an extension: it
                           equalises the per-interaction error bound over the offsets of the list)  */
+  double precond_cutoff; /* 0: conjugate gradients on the scaled system (Jacobi preconditioning).
+                          > 0: flexible conjugate gradients preconditioned by precond_iters inner CG
+                          iterations on (I - S T~_near S) z = r, T~_near the damped dipole tensor of
+                          the pairs closer than this radius (Angstrom) in adjacent leaves.  Same
+                          converged dipoles and stopping rule; fewer field evaluations.            */
+  int precond_iters;   /* inner iterations of the preconditioner, 1..64                            */
 } pfmm_config;
 
 typedef struct pfmm_result {
@@ -114,7 +120,8 @@ typedef struct pfmm_handle pfmm_handle;
 
 /* Fill *cfg with the defaults: p = 6, ws = 2, leaf_width = 0, FP64, scf_tol = 1e-6,
    scf_max_iter = 200, graph_iters = 4, thole_a = 2.0, coulomb_k = 332.06371,
-   flags = WANT_FORCES | WANT_POTENTIALS | SAVE_FOR_BACKWARD, m2l_order_slack = -1. */
+   flags = WANT_FORCES | WANT_POTENTIALS | SAVE_FOR_BACKWARD, m2l_order_slack = -1,
+   precond_cutoff = 0, precond_iters = 4. */
 void pfmm_config_default(pfmm_config* cfg);
 
 /* Create a handle for a configuration.  Validates cfg, builds the constant operator tables of

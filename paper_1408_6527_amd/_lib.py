@@ -48,6 +48,8 @@ class Config(ctypes.Structure):
         ("coulomb_k", ctypes.c_double),
         ("flags", ctypes.c_uint),
         ("m2l_order_slack", ctypes.c_int),
+        ("precond_cutoff", ctypes.c_double),
+        ("precond_iters", ctypes.c_int),
     ]
 
 

@@ -160,6 +160,8 @@ struct pfmm_handle {
   DevBuf f_phiq, f_Eq, f_Eq2, f_Gq, f_phim, f_Eum, f_Edm, f_Gm, f_E;
   // solver
   DevBuf cg_y, cg_r, cg_p, cg_Ap, w_red, w_state, w_ep, w_dal;
+  // preconditioner: z, inner residual, direction and product, near field, dipoles
+  DevBuf pc_z, pc_r, pc_p, pc_Ap, pc_E, pc_mu4;
   // saved for backward
   DevBuf s_F, s_phi, s_Etot;
   bool saved = false;
@@ -209,6 +211,10 @@ void validate_config(const pfmm_config* c) {
     throw Error(PFMM_ERR_INVALID_ARG, "thole_a must be >= 0");
   if (!std::isfinite(c->coulomb_k)) throw Error(PFMM_ERR_INVALID_ARG, "coulomb_k must be finite");
   if (c->m2l_order_slack < -1) throw Error(PFMM_ERR_INVALID_ARG, "m2l_order_slack must be >= -1");
+  if (!(c->precond_cutoff >= 0.0) || !std::isfinite(c->precond_cutoff))
+    throw Error(PFMM_ERR_INVALID_ARG, "precond_cutoff must be >= 0");
+  if (c->precond_cutoff > 0.0 && (c->precond_iters < 1 || c->precond_iters > 64))
+    throw Error(PFMM_ERR_INVALID_ARG, "precond_iters must be in 1..64");
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -492,19 +498,57 @@ pfmm_status solve_impl(pfmm_handle* h, int64_t n64, const double* pos, const dou
   double* Ap = dev<double>(h->cg_Ap, 3 * (int64_t)n);
   double* E = dev<double>(h->f_E, 3 * (int64_t)n);
   double* part = dev<double>(h->w_red, RED_BLOCKS * 8);
-  CGState* st = static_cast<CGState*>(h->w_state.reserve(sizeof(CGState)));
+  CGState* st = static_cast<CGState*>(h->w_state.reserve(2 * sizeof(CGState)));
+  CGState* inner = st + 1;
+  const bool pc = c.precond_cutoff > 0.0;
+  double* z = pc ? dev<double>(h->pc_z, 3 * (int64_t)n) : nullptr;
+  double* ri = pc ? dev<double>(h->pc_r, 3 * (int64_t)n) : nullptr;
+  double* pi = pc ? dev<double>(h->pc_p, 3 * (int64_t)n) : nullptr;
+  double* Api = pc ? dev<double>(h->pc_Ap, 3 * (int64_t)n) : nullptr;
+  double* Epc = pc ? dev<double>(h->pc_E, 3 * (int64_t)n) : nullptr;
+  double4* mu4pc = pc ? dev<double4>(h->pc_mu4, n) : nullptr;
+  // z = inner CG approximation of (I - S T~_near S)^-1 r (the near field in float32)
+  auto precondition = [&](hipStream_t q) {
+    int ev = h->kt.begin();
+    launch_pc_init(3 * n, r, z, ri, pi, part, inner, st, q);
+    for (int k = 0; k < c.precond_iters; ++k) {
+      launch_make_dipoles(pa, pi, mu4pc, &inner->done, q);
+      launch_p2p(h->tv, pa, mu4pc, 3, 2, true, FieldOut{nullptr, nullptr, Epc, nullptr}, nullptr, err,
+                 &inner->done, q, c.precond_cutoff);
+      launch_cg_ap(pa, pi, Epc, Api, part, inner, q);
+      launch_cg_update(pa, z, ri, pi, Api, part, inner, -1.0, c.precond_iters, q);
+      launch_cg_direction(3 * n, ri, pi, inner, q);
+    }
+    h->kt.end(KC_SOLVER, ev);
+  };
   const bool warm = (c.flags & PFMM_WARM_START) != 0;
   if (warm) launch_permute_dipoles(h->w_perm.as<int>(), n, mu, pa.tau, mu4, s);
   launch_cg_init(pa, Eq, mu4, warm, y, pv, mu4, part, st, s);
   FieldOut fo{nullptr, nullptr, E, nullptr};
   fmm_pass(h, 2, 0, fo, err, nullptr, s);
   launch_cg_residual0(pa, Eq, E, y, r, pv, part, st, c.scf_tol, s);
+  if (pc) {
+    precondition(s);
+    launch_cg_direction(3 * n, z, pv, st, s);  // b = 0 here: p0 = z0
+  }
   const int* done = &st->done;
   auto iteration = [&](hipStream_t q) {
     int ev = h->kt.begin();
     launch_make_dipoles(pa, pv, mu4, done, q);
     h->kt.end(KC_SOLVER, ev);
     fmm_pass(h, 2, 0, fo, err, done, q);
+    if (pc) {
+      ev = h->kt.begin();
+      launch_pcg_ap(pa, pv, E, r, Ap, part, st, q);
+      launch_cg_update(pa, y, r, pv, Ap, part, st, c.scf_tol, c.scf_max_iter, q);
+      h->kt.end(KC_SOLVER, ev);
+      precondition(q);
+      ev = h->kt.begin();
+      launch_pcg_zq(3 * n, z, Ap, part, st, q);
+      launch_cg_direction(3 * n, z, pv, st, q);
+      h->kt.end(KC_SOLVER, ev);
+      return;
+    }
     ev = h->kt.begin();
     launch_cg_ap(pa, pv, E, Ap, part, st, q);
     launch_cg_update(pa, y, r, pv, Ap, part, st, c.scf_tol, c.scf_max_iter, q);
@@ -598,6 +642,8 @@ void pfmm_config_default(pfmm_config* c) {
   c->coulomb_k = 332.06371;
   c->flags = PFMM_WANT_FORCES | PFMM_WANT_POTENTIALS | PFMM_SAVE_FOR_BACKWARD;
   c->m2l_order_slack = -1;
+  c->precond_cutoff = 0.0;
+  c->precond_iters = 4;
 }
 
 pfmm_status pfmm_create(const pfmm_config* cfg, pfmm_handle** out) {

@@ -119,9 +119,12 @@ void launch_m2l(const TreeView& t, const OpTables& op, int nsplit, const double*
 
 // ---------------------------------------------------------------- p2p.hip
 // mode 0: dipole sources, Ed only (added); mode 1: full outputs (added) from charges and/or dipoles
-// (sources bit 1 = charges, bit 2 = dipoles); mode 2: Thole term of dU/dalpha (written to dal).
+// (sources bit 1 = charges, bit 2 = dipoles); mode 2: Thole term of dU/dalpha (written to dal);
+// mode 3: damped field of the dipoles within rc of each target, over the adjacent leaves only
+// (written to Ed): the operator of the dipole-solve preconditioner.
 void launch_p2p(const TreeView& t, const Particles& pa, const double4* mu4, int mode, int sources,
-                bool fp32, FieldOut out, double* dal, int* err, const int* done, hipStream_t s);
+                bool fp32, FieldOut out, double* dal, int* err, const int* done, hipStream_t s,
+                double rc = 0.0);
 
 // ---------------------------------------------------------------- solver.hip
 struct CGState {
@@ -141,6 +144,12 @@ void launch_cg_ap(const Particles& pa, const double* pvec, const double* E, doub
 void launch_cg_update(const Particles& pa, double* y, double* r, const double* pvec, const double* Ap,
                       double* part, CGState* st, double tol, int max_iter, hipStream_t s);
 void launch_cg_direction(int n3, const double* r, double* pvec, const CGState* st, hipStream_t s);
+// flexible preconditioned CG: q = A p with a = p.r / p.q; b = -z.q / p.q; inner-solve start
+void launch_pcg_ap(const Particles& pa, const double* pvec, const double* E, const double* r, double* Ap,
+                   double* part, CGState* st, hipStream_t s);
+void launch_pcg_zq(int n3, const double* z, const double* Ap, double* part, CGState* st, hipStream_t s);
+void launch_pc_init(int n3, const double* r, double* z, double* ri, double* pi, double* part,
+                    CGState* inner, const CGState* outer, hipStream_t s);
 
 struct EnergyParts { double Uqq, Amu, muEq, muEd, res2, bn2, resmax; };
 void launch_assemble(const Particles& pa, const int* perm, const double4* mu4, const double* phiq,

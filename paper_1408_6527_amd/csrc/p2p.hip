@@ -18,6 +18,9 @@
 //   f_t = v^4, f_e = 4 v^3 - 3 v^4, A = -3 v^4 (v < 1) or -15 (v >= 1), B = 3 v^4.
 // Float32 variant (mixed path): offsets relative to the target leaf centre, float32 arithmetic
 // and accumulation, results added to the float64 fields.
+// Mode 3 is the operator of the dipole-solve preconditioner: the damped dipole field from the
+// sources within a cutoff radius rc (rc <= leaf edge, so the 27 adjacent leaves hold them all),
+// written rather than added.
 #include <type_traits>
 
 #include "kernels.hpp"
@@ -36,7 +39,7 @@ __device__ inline float rsqrt_t(float x) { return rsqrtf(x); }
 template <typename T, int MODE, int SRC>
 __global__ __launch_bounds__(TPB) void k_p2p(TreeView t, Particles pa, const double4* __restrict__ mu4,
                                              FieldOut out, double* __restrict__ dal,
-                                             int* __restrict__ err, const int* done) {
+                                             int* __restrict__ err, const int* done, T rc2) {
   if (done && *done) return;
   constexpr bool HQ = (SRC & 1) != 0;
   constexpr bool HM = (SRC & 2) != 0;
@@ -52,11 +55,17 @@ __global__ __launch_bounds__(TPB) void k_p2p(TreeView t, Particles pa, const dou
   // exclusive prefix of the colleague occupancies (up to 125 entries, two per lane)
   {
     int c0 = 0, c1 = 0, f0 = 0, f1 = 0;
-    if (lane < nn) {
+    // mode 3 walks only the adjacent leaves (colleague offsets with every component in [-1, 1])
+    const int side = 2 * t.ws + 1;
+    auto adjacent = [&](int ci) {
+      return MODE != 3 || (abs(ci / (side * side) - t.ws) <= 1 && abs((ci / side) % side - t.ws) <= 1 &&
+                           abs(ci % side - t.ws) <= 1);
+    };
+    if (lane < nn && adjacent(lane)) {
       const int A = t.coll[(int64_t)g * nn + lane];
       if (A >= 0) { c0 = t.count[A]; f0 = t.first[A]; }
     }
-    if (lane + TPB < nn) {
+    if (lane + TPB < nn && adjacent(lane + TPB)) {
       const int A = t.coll[(int64_t)g * nn + lane + TPB];
       if (A >= 0) { c1 = t.count[A]; f1 = t.first[A]; }
     }
@@ -127,7 +136,7 @@ __global__ __launch_bounds__(TPB) void k_p2p(TreeView t, Particles pa, const dou
       for (int jj = slice; jj < m; jj += G) {
         const T rx = xi - sx[jj], ry = yi - sy[jj], rz = zi - sz[jj];
         const T r2 = rx * rx + ry * ry + rz * rz;
-        const bool valid = r2 > T(0);
+        const bool valid = r2 > T(0) && (MODE != 3 || r2 < rc2);
         if (MODE == 1 && !valid && sidx[jj] != i) bad = 1;
         const T rinv = valid ? rsqrt_t(valid ? r2 : T(1)) : T(0);
         const T rinv2 = rinv * rinv;
@@ -156,7 +165,7 @@ __global__ __launch_bounds__(TPB) void k_p2p(TreeView t, Particles pa, const dou
             dsum += (double)((T(2) * v4 * miu * mju - T(2) * (v3 - v4) * mm) * rinv3);
           }
         }
-        if ((MODE == 0 || MODE == 1) && HM) {
+        if ((MODE == 0 || MODE == 1 || MODE == 3) && HM) {
           const T mx = smx[jj], my = smy[jj], mz = smz[jj];
           const T rmu = rx * mx + ry * my + rz * mz;
           const T ii = iti * sit[jj];
@@ -191,7 +200,7 @@ __global__ __launch_bounds__(TPB) void k_p2p(TreeView t, Particles pa, const dou
     }
     // combine the G slices of every target (lanes slot, slot + T, slot + 2T, ...)
     for (int msk = T_; msk < TPB; msk <<= 1) {
-      if (MODE == 0) {
+      if (MODE == 0 || MODE == 3) {
         edx += __shfl_xor(edx, msk); edy += __shfl_xor(edy, msk); edz += __shfl_xor(edz, msk);
       } else if (MODE == 1) {
         phi += __shfl_xor(phi, msk);
@@ -208,6 +217,8 @@ __global__ __launch_bounds__(TPB) void k_p2p(TreeView t, Particles pa, const dou
     if (bad) atomicOr(err, 1);
     if (MODE == 0) {
       out.Ed[3 * i] += (double)edx; out.Ed[3 * i + 1] += (double)edy; out.Ed[3 * i + 2] += (double)edz;
+    } else if (MODE == 3) {
+      out.Ed[3 * i] = (double)edx; out.Ed[3 * i + 1] = (double)edy; out.Ed[3 * i + 2] = (double)edz;
     } else if (MODE == 1) {
       out.phi[i] += (double)phi;
       out.Eu[3 * i] += (double)eux; out.Eu[3 * i + 1] += (double)euy; out.Eu[3 * i + 2] += (double)euz;
@@ -224,18 +235,19 @@ __global__ __launch_bounds__(TPB) void k_p2p(TreeView t, Particles pa, const dou
 
 template <typename T>
 void p2p_dispatch(const TreeView& t, const Particles& pa, const double4* mu4, int mode, int sources,
-                  FieldOut out, double* dal, int* err, const int* done, hipStream_t s, int nleaf) {
+                  FieldOut out, double* dal, int* err, const int* done, hipStream_t s, int nleaf,
+                  double rc2) {
+  const T r2 = (T)rc2;
   if (mode == 0)
-    hipLaunchKernelGGL((k_p2p<T, 0, 2>), dim3(nleaf), dim3(TPB), 0, s, t, pa, mu4, out, dal, err, done);
+    hipLaunchKernelGGL((k_p2p<T, 0, 2>), dim3(nleaf), dim3(TPB), 0, s, t, pa, mu4, out, dal, err, done, r2);
   else if (mode == 1 && sources == 1)
-    hipLaunchKernelGGL((k_p2p<T, 1, 1>), dim3(nleaf), dim3(TPB), 0, s, t, pa, mu4, out, dal, err, done);
+    hipLaunchKernelGGL((k_p2p<T, 1, 1>), dim3(nleaf), dim3(TPB), 0, s, t, pa, mu4, out, dal, err, done, r2);
   else if (mode == 1 && sources == 2)
-    hipLaunchKernelGGL((k_p2p<T, 1, 2>), dim3(nleaf), dim3(TPB), 0, s, t, pa, mu4, out, dal, err, done);
+    hipLaunchKernelGGL((k_p2p<T, 1, 2>), dim3(nleaf), dim3(TPB), 0, s, t, pa, mu4, out, dal, err, done, r2);
   else if (mode == 1 && sources == 3)
-    hipLaunchKernelGGL((k_p2p<T, 1, 3>), dim3(nleaf), dim3(TPB), 0, s, t, pa, mu4, out, dal, err, done);
-  else if (mode == 2)
-    hipLaunchKernelGGL((k_p2p<double, 2, 2>), dim3(nleaf), dim3(TPB), 0, s, t, pa, mu4, out, dal, err,
-                       done);
+    hipLaunchKernelGGL((k_p2p<T, 1, 3>), dim3(nleaf), dim3(TPB), 0, s, t, pa, mu4, out, dal, err, done, r2);
+  else if (mode == 3)
+    hipLaunchKernelGGL((k_p2p<T, 3, 2>), dim3(nleaf), dim3(TPB), 0, s, t, pa, mu4, out, dal, err, done, r2);
   else
     throw Error(PFMM_ERR_INVALID_ARG, "internal: bad P2P mode");
 }
@@ -243,13 +255,17 @@ void p2p_dispatch(const TreeView& t, const Particles& pa, const double4* mu4, in
 }  // namespace
 
 void launch_p2p(const TreeView& t, const Particles& pa, const double4* mu4, int mode, int sources,
-                bool fp32, FieldOut out, double* dal, int* err, const int* done, hipStream_t s) {
+                bool fp32, FieldOut out, double* dal, int* err, const int* done, hipStream_t s,
+                double rc) {
   const int nleaf = t.off[t.L + 1] - t.off[t.L];
   if (nleaf <= 0) return;
-  if (fp32 && mode != 2)
-    p2p_dispatch<float>(t, pa, mu4, mode, sources, out, dal, err, done, s, nleaf);
+  if (mode == 2)
+    hipLaunchKernelGGL((k_p2p<double, 2, 2>), dim3(nleaf), dim3(TPB), 0, s, t, pa, mu4, out, dal, err,
+                       done, 0.0);
+  else if (fp32)
+    p2p_dispatch<float>(t, pa, mu4, mode, sources, out, dal, err, done, s, nleaf, rc * rc);
   else
-    p2p_dispatch<double>(t, pa, mu4, mode, sources, out, dal, err, done, s, nleaf);
+    p2p_dispatch<double>(t, pa, mu4, mode, sources, out, dal, err, done, s, nleaf, rc * rc);
   PFMM_LAUNCH_CHECK();
 }
 

@@ -204,6 +204,91 @@ __global__ __launch_bounds__(TPB) void k_cg_dir(int n3, const double* __restrict
   GRID_STRIDE(k, n3) pv[k] = r[k] + b * pv[k];
 }
 
+// ---- preconditioned (flexible) conjugate gradients.  The preconditioner is a few inner CG
+// iterations on (I - S T~_near S) z = r, T~_near the damped dipole tensor of the pairs closer than
+// a cutoff; since the inner solve is not a fixed linear map, the outer iteration is the flexible
+// variant with one-step orthogonalisation: a = p.r / p.q, b = -z.q / p.q, p <- z + b p (q = A p).
+
+// q = p - S E(S p); partials p.q and p.r
+__global__ __launch_bounds__(TPB) void k_pcg_ap(Particles pa, const double* __restrict__ pv,
+                                                const double* __restrict__ E, const double* __restrict__ r,
+                                                double* __restrict__ Ap, double* __restrict__ part,
+                                                const CGState* st) {
+  if (st->done) return;
+  double v[2] = {0.0, 0.0};
+  GRID_STRIDE(i, pa.n) {
+    const double s = pa.sqa[i];
+    for (int c = 0; c < 3; ++c) {
+      const int k = 3 * i + c;
+      const double a = pv[k] - s * E[k];
+      Ap[k] = a;
+      v[0] += pv[k] * a;
+      v[1] += pv[k] * r[k];
+    }
+  }
+  block_sum<2>(v, part);
+}
+__global__ __launch_bounds__(TPB) void k_pcg_ap_finish(const double* part, int nblk, CGState* st) {
+  if (st->done) return;
+  double o[2];
+  finish_sum<2>(part, nblk, o);
+  if (threadIdx.x == 0) {
+    st->pAp = o[0];
+    if (!(o[0] > 0.0)) {
+      st->notspd = 1;
+      st->done = 1;
+    } else {
+      st->a = o[1] / o[0];
+    }
+  }
+}
+// b = -z.q / p.q
+__global__ __launch_bounds__(TPB) void k_pcg_zq(int n3, const double* __restrict__ z,
+                                                const double* __restrict__ Ap, double* __restrict__ part,
+                                                const CGState* st) {
+  if (st->done) return;
+  double v[1] = {0.0};
+  GRID_STRIDE(k, n3) v[0] += z[k] * Ap[k];
+  block_sum<1>(v, part);
+}
+__global__ __launch_bounds__(TPB) void k_pcg_zq_finish(const double* part, int nblk, CGState* st) {
+  if (st->done) return;
+  double o[1];
+  finish_sum<1>(part, nblk, o);
+  if (threadIdx.x == 0) st->b = -o[0] / st->pAp;
+}
+// inner solve start: z = 0, r_in = r, p_in = r, rr_in = r.r; the inner state is done at once
+// when the outer one is
+__global__ __launch_bounds__(TPB) void k_pc_init(int n3, const double* __restrict__ r,
+                                                 double* __restrict__ z, double* __restrict__ ri,
+                                                 double* __restrict__ pi, double* __restrict__ part,
+                                                 const CGState* outer) {
+  if (outer->done) return;
+  double v[1] = {0.0};
+  GRID_STRIDE(k, n3) {
+    const double x = r[k];
+    z[k] = 0.0;
+    ri[k] = x;
+    pi[k] = x;
+    v[0] += x * x;
+  }
+  block_sum<1>(v, part);
+}
+__global__ __launch_bounds__(TPB) void k_pc_init_finish(const double* part, int nblk, CGState* inner,
+                                                        const CGState* outer) {
+  const int od = outer->done;  // not written by this kernel: the same value in every thread
+  double o[1] = {0.0};
+  if (!od) finish_sum<1>(part, nblk, o);
+  if (threadIdx.x == 0) {
+    inner->done = od;
+    inner->rr = o[0];
+    inner->bnorm2 = 1.0;
+    inner->iters = 0; inner->notspd = 0; inner->maxed = 0;
+    inner->pAp = inner->a = inner->b = inner->res = 0.0;
+    if (!(o[0] > 0.0)) inner->done = 1;
+  }
+}
+
 __device__ inline double m3(const double4& u, int c) { return c == 0 ? u.x : (c == 1 ? u.y : u.z); }
 
 // Energies, forces, potentials; outputs un-permuted to the caller's order.
@@ -391,6 +476,29 @@ void launch_cg_update(const Particles& pa, double* y, double* r, const double* p
   const int g = grid(pa.n);
   hipLaunchKernelGGL(k_cg_update, dim3(g), dim3(TPB), 0, s, pa, y, r, pvec, Ap, part, st);
   hipLaunchKernelGGL(k_cg_update_finish, dim3(1), dim3(TPB), 0, s, part, g, st, tol, max_iter);
+  PFMM_LAUNCH_CHECK();
+}
+
+void launch_pcg_ap(const Particles& pa, const double* pvec, const double* E, const double* r, double* Ap,
+                   double* part, CGState* st, hipStream_t s) {
+  const int g = grid(pa.n);
+  hipLaunchKernelGGL(k_pcg_ap, dim3(g), dim3(TPB), 0, s, pa, pvec, E, r, Ap, part, st);
+  hipLaunchKernelGGL(k_pcg_ap_finish, dim3(1), dim3(TPB), 0, s, part, g, st);
+  PFMM_LAUNCH_CHECK();
+}
+
+void launch_pcg_zq(int n3, const double* z, const double* Ap, double* part, CGState* st, hipStream_t s) {
+  const int g = grid(n3);
+  hipLaunchKernelGGL(k_pcg_zq, dim3(g), dim3(TPB), 0, s, n3, z, Ap, part, st);
+  hipLaunchKernelGGL(k_pcg_zq_finish, dim3(1), dim3(TPB), 0, s, part, g, st);
+  PFMM_LAUNCH_CHECK();
+}
+
+void launch_pc_init(int n3, const double* r, double* z, double* ri, double* pi, double* part,
+                    CGState* inner, const CGState* outer, hipStream_t s) {
+  const int g = grid(n3);
+  hipLaunchKernelGGL(k_pc_init, dim3(g), dim3(TPB), 0, s, n3, r, z, ri, pi, part, outer);
+  hipLaunchKernelGGL(k_pc_init_finish, dim3(1), dim3(TPB), 0, s, part, g, inner, outer);
   PFMM_LAUNCH_CHECK();
 }
 
