@@ -24,15 +24,17 @@ sys.path.insert(0, ROOT)
 
 # Workload presets: geometry generator, expansion order, separation, leaf edge, dipole tolerance,
 # M2L order slack (-1: fixed order p; s >= 0: per-offset truncation order at the nearest offsets'
-# error bound, plus s).  The 1M-particle preset is the fastest setting measured whose float64
-# force error on the sampled oracle check stays below 1e-5.
+# error bound, plus s), dipole-solve preconditioner cutoff (A, 0: plain scaled CG) and its inner
+# iterations.  The 1M-particle preset is the fastest setting measured whose float64 force error on
+# the sampled oracle check stays below 1e-5.
 WORKLOADS = {
-    "scaling_1m": dict(gen="scaling_1m", p=10, ws=2, leaf=6.0, tol=1e-6, slack=2),
-    "scaling_250k": dict(gen="scaling_250k", p=10, ws=2, leaf=6.0, tol=1e-6, slack=2),
-    "scaling_4m": dict(gen="scaling_4m", p=10, ws=2, leaf=6.0, tol=1e-6, slack=2),
-    "globular_50k": dict(gen="globular_50k", p=6, ws=2, leaf=4.0, tol=1e-6, slack=-1),
-    "uniform_cube_1k": dict(gen="uniform_cube_1k", p=4, ws=1, leaf=5.0, tol=1e-8, slack=-1),
-    "hexamer_shell_160k": dict(gen="hexamer_shell_160k", p=8, ws=2, leaf=4.0, tol=1e-6, slack=-1),
+    "scaling_1m": dict(gen="scaling_1m", p=10, ws=2, leaf=6.0, tol=1e-6, slack=2, pc=5.0, pc_iters=3),
+    "scaling_250k": dict(gen="scaling_250k", p=10, ws=2, leaf=6.0, tol=1e-6, slack=2, pc=5.0, pc_iters=3),
+    "scaling_4m": dict(gen="scaling_4m", p=10, ws=2, leaf=6.0, tol=1e-6, slack=2, pc=5.0, pc_iters=3),
+    "globular_50k": dict(gen="globular_50k", p=6, ws=2, leaf=4.0, tol=1e-6, slack=-1, pc=0.0, pc_iters=4),
+    "uniform_cube_1k": dict(gen="uniform_cube_1k", p=4, ws=1, leaf=5.0, tol=1e-8, slack=-1, pc=0.0, pc_iters=4),
+    "hexamer_shell_160k": dict(gen="hexamer_shell_160k", p=8, ws=2, leaf=4.0, tol=1e-6, slack=-1, pc=0.0,
+                               pc_iters=4),
 }
 
 # HBM traffic of the dominant kernel from rocprofv3 counters (profiles/), valid only while the
@@ -82,6 +84,8 @@ def parse():
     ap.add_argument("--leaf", type=float, default=None)
     ap.add_argument("--tol", type=float, default=None)
     ap.add_argument("--slack", type=int, default=None, help="M2L order slack (-1: fixed order p)")
+    ap.add_argument("--pc", type=float, default=None, help="preconditioner cutoff in A (0: plain CG)")
+    ap.add_argument("--pc-iters", type=int, default=None, help="inner preconditioner iterations")
     ap.add_argument("--oracle-sample", type=int, default=0,
                     help="targets of the sampled oracle check (0: about 2e7 / n, between 8 and 192)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -104,7 +108,7 @@ def main():
     from paper_1408_6527_amd import api, inputs
 
     wl = dict(WORKLOADS[args.workload])
-    for k in ("p", "ws", "leaf", "tol", "slack"):
+    for k in ("p", "ws", "leaf", "tol", "slack", "pc", "pc_iters"):
         if getattr(args, k) is not None:
             wl[k] = getattr(args, k)
     ps = inputs.make(wl["gen"])
@@ -123,7 +127,8 @@ def main():
 
     def make(prec, timing=False):
         return api.Solver(order_p=wl["p"], ws=wl["ws"], leaf_width=wl["leaf"], scf_tol=wl["tol"],
-                          m2l_order_slack=wl["slack"], precision=prec, timing=timing)
+                          m2l_order_slack=wl["slack"], precond_cutoff=wl["pc"], precond_iters=wl["pc_iters"],
+                          precision=prec, timing=timing)
 
     def step(s):
         r = s.solve(pos, q, al)
@@ -229,6 +234,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "order_p": p, "ws": wl["ws"],
                    "leaf_width": wl["leaf"], "scf_tol": wl["tol"], "m2l_order_slack": wl["slack"],
+                   "precond_cutoff": wl["pc"], "precond_iters": wl["pc_iters"],
                    "levels": r0["res"].stats["levels"],
                    "step": "solve (tree, charge field, dipole CG, energy, forces) + backward",
                    "parallelism": "single GPU"},
