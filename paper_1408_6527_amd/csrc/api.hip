@@ -523,10 +523,16 @@ pfmm_status solve_impl(pfmm_handle* h, int64_t n64, const double* pos, const dou
   };
   const bool warm = (c.flags & PFMM_WARM_START) != 0;
   if (warm) launch_permute_dipoles(h->w_perm.as<int>(), n, mu, pa.tau, mu4, s);
-  launch_cg_init(pa, Eq, mu4, warm, y, pv, mu4, part, st, s);
   FieldOut fo{nullptr, nullptr, E, nullptr};
-  fmm_pass(h, 2, 0, fo, err, nullptr, s);
-  launch_cg_residual0(pa, Eq, E, y, r, pv, part, st, c.scf_tol, s);
+  if (pc && !warm) {
+    // the preconditioned solve starts from y0 = 0: r0 = S E^q costs no field evaluation, and
+    // p0 = z0 is a better first direction than the Jacobi guess alpha E^q
+    launch_cg_init_zero(pa, Eq, y, r, part, st, c.scf_tol, s);
+  } else {
+    launch_cg_init(pa, Eq, mu4, warm, y, pv, mu4, part, st, s);
+    fmm_pass(h, 2, 0, fo, err, nullptr, s);
+    launch_cg_residual0(pa, Eq, E, y, r, pv, part, st, c.scf_tol, s);
+  }
   if (pc) {
     precondition(s);
     launch_cg_direction(3 * n, z, pv, st, s);  // b = 0 here: p0 = z0
@@ -615,7 +621,8 @@ pfmm_status solve_impl(pfmm_handle* h, int64_t n64, const double* pos, const dou
   res->n_m2l = h->n_m2l;
   res->n_p2p = h->n_p2p;
   res->m2l_flops = h->m2l_flops;
-  res->n_evals = 3 + hs.iters;  // charge field, initial residual, iterations, final pass
+  // charge field, initial residual (not on the cold-started preconditioned path), iterations, final pass
+  res->n_evals = (pc && !warm ? 2 : 3) + hs.iters;
   h->saved = true;
   h->saved_n = n;
   if (hs.notspd) throw Error(PFMM_ERR_NOT_SPD, "conjugate gradients met p.Ap <= 0: the dipole system is not positive definite");

@@ -144,6 +144,9 @@ void launch_cg_ap(const Particles& pa, const double* pvec, const double* E, doub
 void launch_cg_update(const Particles& pa, double* y, double* r, const double* pvec, const double* Ap,
                       double* part, CGState* st, double tol, int max_iter, hipStream_t s);
 void launch_cg_direction(int n3, const double* r, double* pvec, const CGState* st, hipStream_t s);
+// cold start y0 = 0, r0 = S E^q (no field evaluation)
+void launch_cg_init_zero(const Particles& pa, const double* Eq, double* y, double* r, double* part,
+                         CGState* st, double tol, hipStream_t s);
 // flexible preconditioned CG: q = A p with a = p.r / p.q; b = -z.q / p.q; inner-solve start
 void launch_pcg_ap(const Particles& pa, const double* pvec, const double* E, const double* r, double* Ap,
                    double* part, CGState* st, hipStream_t s);

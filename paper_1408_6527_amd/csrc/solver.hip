@@ -86,6 +86,39 @@ __global__ __launch_bounds__(TPB) void k_cg_init_finish(const double* part, int 
   }
 }
 
+// Cold start of the preconditioned solve: y0 = 0, r0 = S E^q (no field evaluation needed),
+// ||alpha E^q||^2, r.r; the residual is 1 (or the solve is done when E^q = 0).
+__global__ __launch_bounds__(TPB) void k_cg_init_zero(Particles pa, const double* __restrict__ Eq,
+                                                      double* __restrict__ y, double* __restrict__ r,
+                                                      double* __restrict__ part) {
+  double v[2] = {0.0, 0.0};
+  GRID_STRIDE(i, pa.n) {
+    const double s = pa.sqa[i], a = pa.alpha[i];
+    for (int c = 0; c < 3; ++c) {
+      const int k = 3 * i + c;
+      const double e = Eq[k];
+      y[k] = 0.0;
+      r[k] = s * e;
+      v[0] += a * a * e * e;
+      v[1] += a * e * e;
+    }
+  }
+  block_sum<2>(v, part);
+}
+__global__ __launch_bounds__(TPB) void k_cg_init_zero_finish(const double* part, int nblk, CGState* st,
+                                                             double tol) {
+  double o[2];
+  finish_sum<2>(part, nblk, o);
+  if (threadIdx.x == 0) {
+    st->bnorm2 = o[0];
+    st->done = 0; st->iters = 0; st->notspd = 0; st->maxed = 0;
+    st->rr = o[1];
+    st->pAp = st->a = st->b = 0.0;
+    st->res = o[0] > 0.0 ? 1.0 : 0.0;
+    if (o[0] == 0.0 || st->res <= tol) st->done = 1;
+  }
+}
+
 // r0 = S E^q - (y0 - S E(S y0)); p0 = r0; rr = r.r; residual in dipole units.
 __global__ __launch_bounds__(TPB) void k_cg_res0(Particles pa, const double* __restrict__ Eq,
                                                  const double* __restrict__ E, double* __restrict__ y,
@@ -201,7 +234,12 @@ __global__ __launch_bounds__(TPB) void k_cg_dir(int n3, const double* __restrict
                                                 double* __restrict__ pv, const CGState* st) {
   if (st->done) return;
   const double b = st->b;
-  GRID_STRIDE(k, n3) pv[k] = r[k] + b * pv[k];
+  // b = 0 starts a direction afresh (p may be unset then, e.g. on the cold-started solve)
+  if (b == 0.0) {
+    GRID_STRIDE(k, n3) pv[k] = r[k];
+  } else {
+    GRID_STRIDE(k, n3) pv[k] = r[k] + b * pv[k];
+  }
 }
 
 // ---- preconditioned (flexible) conjugate gradients.  The preconditioner is a few inner CG
@@ -476,6 +514,14 @@ void launch_cg_update(const Particles& pa, double* y, double* r, const double* p
   const int g = grid(pa.n);
   hipLaunchKernelGGL(k_cg_update, dim3(g), dim3(TPB), 0, s, pa, y, r, pvec, Ap, part, st);
   hipLaunchKernelGGL(k_cg_update_finish, dim3(1), dim3(TPB), 0, s, part, g, st, tol, max_iter);
+  PFMM_LAUNCH_CHECK();
+}
+
+void launch_cg_init_zero(const Particles& pa, const double* Eq, double* y, double* r, double* part,
+                         CGState* st, double tol, hipStream_t s) {
+  const int g = grid(pa.n);
+  hipLaunchKernelGGL(k_cg_init_zero, dim3(g), dim3(TPB), 0, s, pa, Eq, y, r, part);
+  hipLaunchKernelGGL(k_cg_init_zero_finish, dim3(1), dim3(TPB), 0, s, part, g, st, tol);
   PFMM_LAUNCH_CHECK();
 }
 
