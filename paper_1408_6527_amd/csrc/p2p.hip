@@ -3,11 +3,10 @@
 //
 // One wavefront per target leaf.  The sources of all colleague leaves (Chebyshev distance <= ws)
 // are walked as one concatenated sequence and staged in LDS 64 at a time, densely, whatever the
-// leaf occupancy.  A leaf holds only a few particles at protein density, so each target is served
-// by G = 64 / T lanes (T = its occupancy rounded up to a power of two); every lane sweeps a
-// 1/G slice of each staged chunk, and the G partial sums of a target are combined at the end by a
-// butterfly of cross-lane exchanges (fixed order, deterministic).  Results are added to the
-// far-field values already written by L2P.
+// leaf occupancy.  A leaf holds only a few particles at protein density, so each of its T targets
+// is served by G = floor(64 / T) lanes (lanes t, t + T, t + 2T, ...); every lane sweeps a 1/G slice
+// of each staged chunk, and the G partial sums of a target are combined at the end through LDS in
+// a fixed order (deterministic).  Results are added to the far-field values already written by L2P.
 //
 // Pair kernels, with r = x_i - x_j, u = r/|r|:
 //   charge  q_j:  phi += q/r,  E += q r/r^3,  d_a E_b += q (delta_ab/r^3 - 3 r_a r_b/r^5)
@@ -90,14 +89,14 @@ __global__ __launch_bounds__(TPB) void k_p2p(TreeView t, Particles pa, const dou
     cen[1] = t.origin[1] + ((double)compact3(k >> 1) + 0.5) * t.w;
     cen[2] = t.origin[2] + ((double)compact3(k) + 0.5) * t.w;
   }
-  // lanes per target: T targets per pass (a power of two), G = 64 / T lanes each
-  const int T_ = cnt >= TPB ? TPB : (cnt <= 1 ? 1 : (1 << (32 - __clz(cnt - 1))));
+  // lanes per target: T targets per pass, G = floor(64 / T) lanes each; lanes from G T on idle
+  const int T_ = cnt >= TPB ? TPB : (cnt < 1 ? 1 : cnt);
   const int G = TPB / T_;
-  const int slot = lane & (T_ - 1), slice = lane / T_;
+  const int slot = lane % T_, slice = lane / T_;
 
   for (int t0 = 0; t0 < cnt; t0 += TPB) {
     const int li = t0 + slot;
-    const bool active = li < cnt;
+    const bool active = slice < G && li < cnt;
     const int i = first + (active ? li : 0);
     const double4 Pi = pa.P[i];
     const T xi = (T)(Pi.x - cen[0]), yi = (T)(Pi.y - cen[1]), zi = (T)(Pi.z - cen[2]);
@@ -198,19 +197,39 @@ __global__ __launch_bounds__(TPB) void k_p2p(TreeView t, Particles pa, const dou
         }
       }
     }
-    // combine the G slices of every target (lanes slot, slot + T, slot + 2T, ...)
-    for (int msk = T_; msk < TPB; msk <<= 1) {
-      if (MODE == 0 || MODE == 3) {
-        edx += __shfl_xor(edx, msk); edy += __shfl_xor(edy, msk); edz += __shfl_xor(edz, msk);
-      } else if (MODE == 1) {
-        phi += __shfl_xor(phi, msk);
-        eux += __shfl_xor(eux, msk); euy += __shfl_xor(euy, msk); euz += __shfl_xor(euz, msk);
-        edx += __shfl_xor(edx, msk); edy += __shfl_xor(edy, msk); edz += __shfl_xor(edz, msk);
-        gxx += __shfl_xor(gxx, msk); gyy += __shfl_xor(gyy, msk); gzz += __shfl_xor(gzz, msk);
-        gxy += __shfl_xor(gxy, msk); gxz += __shfl_xor(gxz, msk); gyz += __shfl_xor(gyz, msk);
-        bad |= __shfl_xor(bad, msk);
+    // combine the G slices of every target (lanes slot, slot + T, slot + 2T, ...) in slice order
+    if (G > 1) {
+      constexpr int NR = (MODE == 1) ? 13 : (MODE == 2 ? 1 : 3);
+      __shared__ T red[NR][TPB];
+      __shared__ int redbad[TPB];
+      T v[NR];
+      if constexpr (MODE == 1) {
+        v[0] = phi; v[1] = eux; v[2] = euy; v[3] = euz; v[4] = edx; v[5] = edy; v[6] = edz;
+        v[7] = gxx; v[8] = gyy; v[9] = gzz; v[10] = gxy; v[11] = gxz; v[12] = gyz;
+      } else if constexpr (MODE == 2) {
+        v[0] = (T)dsum;
       } else {
-        dsum += __shfl_xor(dsum, msk);
+        v[0] = edx; v[1] = edy; v[2] = edz;
+      }
+      __syncthreads();  // the staging arrays of the last chunk are no longer read
+#pragma unroll
+      for (int k = 0; k < NR; ++k) red[k][lane] = v[k];
+      redbad[lane] = bad;
+      __syncthreads();
+      if (slice == 0) {
+        for (int c = 1; c < G; ++c) {
+#pragma unroll
+          for (int k = 0; k < NR; ++k) v[k] += red[k][slot + c * T_];
+          bad |= redbad[slot + c * T_];
+        }
+      }
+      if constexpr (MODE == 1) {
+        phi = v[0]; eux = v[1]; euy = v[2]; euz = v[3]; edx = v[4]; edy = v[5]; edz = v[6];
+        gxx = v[7]; gyy = v[8]; gzz = v[9]; gxy = v[10]; gxz = v[11]; gyz = v[12];
+      } else if constexpr (MODE == 2) {
+        dsum = (double)v[0];
+      } else {
+        edx = v[0]; edy = v[1]; edz = v[2];
       }
     }
     if (!active || slice != 0) continue;
