@@ -30,10 +30,10 @@ sys.path.insert(0, ROOT)
 WORKLOADS = {
     "scaling_1m": dict(gen="scaling_1m", p=10, ws=2, leaf=6.0, tol=1e-6, slack=2, pc=5.0, pc_iters=4),
     "scaling_250k": dict(gen="scaling_250k", p=10, ws=2, leaf=6.0, tol=1e-6, slack=2, pc=5.0, pc_iters=4),
-    "scaling_4m": dict(gen="scaling_4m", p=10, ws=2, leaf=6.0, tol=1e-6, slack=2, pc=5.0, pc_iters=4),
-    "globular_50k": dict(gen="globular_50k", p=6, ws=2, leaf=4.0, tol=1e-6, slack=-1, pc=0.0, pc_iters=4),
+    "scaling_4m": dict(gen="scaling_4m", p=10, ws=2, leaf=6.0, tol=1e-6, slack=3, pc=5.0, pc_iters=4),
+    "globular_50k": dict(gen="globular_50k", p=6, ws=2, leaf=4.0, tol=1e-6, slack=-1, pc=4.0, pc_iters=4),
     "uniform_cube_1k": dict(gen="uniform_cube_1k", p=4, ws=1, leaf=5.0, tol=1e-8, slack=-1, pc=0.0, pc_iters=4),
-    "hexamer_shell_160k": dict(gen="hexamer_shell_160k", p=8, ws=2, leaf=4.0, tol=1e-6, slack=-1, pc=0.0,
+    "hexamer_shell_160k": dict(gen="hexamer_shell_160k", p=8, ws=2, leaf=5.0, tol=1e-6, slack=2, pc=5.0,
                                pc_iters=4),
 }
 

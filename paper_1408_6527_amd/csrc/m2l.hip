@@ -77,29 +77,44 @@ __device__ __forceinline__ void m2l_mfma(const kt* Dv, const kt* Bp, const uint4
   constexpr int NB = order.n;
   constexpr int NC = mi_count(P), NCQ = mi_count(Q);
   constexpr int BP = sched_stride(P) + 2;
+  constexpr int GS = 8;  // blocks whose A entries are gathered before their MFMAs are issued
   kt2 bb[NCB];
   uint4 hg;
 #pragma unroll
-  for (int k = 0; k < NB; ++k) {
-    const int s = order.s[k], rb = order.rb[k], blk = order.bp[k];
-    if ((s & 1) == 0 && (k == 0 || order.s[k - 1] != s)) {
-      // steps s and s + 1 read coefficients m(s, q) and m(s, q) + 1 of the lane's column
+  for (int k0 = 0; k0 < NB; k0 += GS) {
+    kt a[GS];
 #pragma unroll
-      for (int cb = 0; cb < NCB; ++cb) bb[cb] = *reinterpret_cast<const kt2*>(Bp + cb * 16 * BP + 4 * s);
+    for (int j = 0; j < GS; ++j) {
+      const int k = k0 + j;
+      if (k < NB) {
+        const int blk = order.bp[k];
+        if (k == 0 || (order.bp[k - 1] >> 3) != (blk >> 3)) hg = sH[(blk >> 3) * 64 + lane];
+        const unsigned hw[4] = {hg.x, hg.y, hg.z, hg.w};
+        const unsigned hv = hw[(blk & 7) >> 1];
+        unsigned idx = (blk & 1) ? (hv >> 16) : (hv & 0xffffu);
+        if constexpr (Q < P) idx = idx < (unsigned)NCQ ? idx : (unsigned)NC;
+        a[j] = Dv[idx];
+      }
     }
-    if (k == 0 || (order.bp[k - 1] >> 3) != (blk >> 3)) hg = sH[(blk >> 3) * 64 + lane];
-    const unsigned hw[4] = {hg.x, hg.y, hg.z, hg.w};
-    const unsigned hv = hw[(blk & 7) >> 1];
-    unsigned idx = (blk & 1) ? (hv >> 16) : (hv & 0xffffu);
-    if constexpr (Q < P) idx = idx < (unsigned)NCQ ? idx : (unsigned)NC;
-    const kt a = Dv[idx];
 #pragma unroll
-    for (int cb = 0; cb < NCB; ++cb) {
-      const kt b = (s & 1) ? bb[cb].y : bb[cb].x;
-      if constexpr (F32)
-        acc[cb][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[cb][rb], 0, 0, 0);
-      else
-        acc[cb][rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[cb][rb], 0, 0, 0);
+    for (int j = 0; j < GS; ++j) {
+      const int k = k0 + j;
+      if (k < NB) {
+        const int s = order.s[k], rb = order.rb[k];
+        if ((s & 1) == 0 && (k == 0 || order.s[k - 1] != s)) {
+          // steps s and s + 1 read coefficients m(s, q) and m(s, q) + 1 of the lane's column
+#pragma unroll
+          for (int cb = 0; cb < NCB; ++cb) bb[cb] = *reinterpret_cast<const kt2*>(Bp + cb * 16 * BP + 4 * s);
+        }
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) {
+          const kt b = (s & 1) ? bb[cb].y : bb[cb].x;
+          if constexpr (F32)
+            acc[cb][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j], b, acc[cb][rb], 0, 0, 0);
+          else
+            acc[cb][rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[j], b, acc[cb][rb], 0, 0, 0);
+        }
+      }
     }
   }
 }
@@ -118,7 +133,7 @@ template <int P, bool F32>
 constexpr int m2l_ncb() { return (F32 ? P <= 8 : P <= 7) ? 2 : 1; }
 // registers per lane: 4 waves per SIMD (two workgroups per CU) only where they fit
 template <int P, bool F32>
-constexpr int m2l_waves_per_eu() { return P <= 4 ? 4 : 2; }
+constexpr int m2l_waves_per_eu() { return P <= 3 ? 4 : 2; }
 
 template <int P, bool F32>
 __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(m2l_waves_per_eu<P, F32>()))) void k_m2l(TreeView t, OpTables op, int lp_lo, int lp_hi, int nsplit,
