@@ -132,6 +132,7 @@ __global__ __launch_bounds__(TPB) void k_p2p(TreeView t, Particles pa, const dou
       }
       __syncthreads();
       if (!active) continue;
+#pragma unroll 4
       for (int jj = slice; jj < m; jj += G) {
         const T rx = xi - sx[jj], ry = yi - sy[jj], rz = zi - sz[jj];
         const T r2 = rx * rx + ry * ry + rz * rz;
