@@ -337,6 +337,54 @@ def test_graph_replay_matches_plain_launches(api):
         assert r0.U == r1.U
 
 
+def test_preconditioned_graph_determinism_and_warm_start(api):
+    """The preconditioned solve is bitwise repeatable, gives bitwise the same result as a graph
+    replay and as plain launches, and a warm start from its own dipoles converges at once to the
+    same answer."""
+    print_case("pcg graph / warm start")
+    X, q, a, _ = cube(900, 17.0, 14)
+    kw = dict(order_p=6, ws=2, leaf_width=1.7, scf_tol=1e-9, precond_cutoff=2.5, precond_iters=3,
+              m2l_order_slack=1)
+    plain = api.Solver(graph_iters=0, **kw)
+    graph = api.Solver(graph_iters=2, **kw)
+    r0 = plain.solve(T(X), T(q), T(a))
+    r1 = graph.solve(T(X), T(q), T(a))
+    r2 = graph.solve(T(X), T(q), T(a))
+    assert r0.iters == r1.iters == r2.iters
+    for r in (r1, r2):
+        assert np.array_equal(N(r0.mu), N(r.mu)) and np.array_equal(N(r0.forces), N(r.forces))
+    warm = api.Solver(warm_start=True, **kw)
+    mu0 = r0.mu.detach().clone()
+    rw = warm.solve(T(X), T(q), T(a), mu_init=mu0)
+    assert rw.iters <= 1
+    assert relnorm(N(rw.mu), N(r0.mu)) < 1e-8
+
+
+def test_preconditioned_edge_cases(api):
+    """Zero polarisabilities (the scaled system is the identity there), a single particle, two
+    particles, and a cutoff beyond the leaf edge all converge with the preconditioner."""
+    print_case("pcg edge cases")
+    X, q, a, _ = cube(300, 12.0, 12)
+    a = a.copy()
+    a[::3] = 0.0
+    kw = dict(order_p=6, ws=2, leaf_width=1.6, scf_tol=1e-10)
+    r0 = api.Solver(**kw).solve(T(X), T(q), T(a))
+    r1 = api.Solver(precond_cutoff=3.0, precond_iters=4, **kw).solve(T(X), T(q), T(a))
+    assert np.all(N(r1.mu)[::3] == 0.0)
+    assert relnorm(N(r1.mu), N(r0.mu)) < 1e-8 and r1.iters < r0.iters
+    s = api.Solver(order_p=4, ws=1, precond_cutoff=4.0)
+    r = s.solve(T([[1.0, 2.0, 3.0]]), T([0.7]), T([1.2]))
+    assert r.U == 0.0 and np.all(N(r.mu) == 0)
+    X2 = np.array([[0.0, 0.0, 0.0], [0.0, 0.0, 3.1]])
+    r = api.Solver(order_p=4, ws=1, scf_tol=1e-14, thole_a=0.0, precond_cutoff=4.0).solve(
+        T(X2), T([0.7, -0.4]), T([1.3, 0.9]))
+    ref = D.solve(X2, np.array([0.7, -0.4]), np.array([1.3, 0.9]), thole_a=0.0)
+    assert relmax(N(r.mu), ref["mu"]) < 1e-12
+    r = api.Solver(order_p=6, ws=2, leaf_width=1.6, scf_tol=1e-10, precond_cutoff=9.0).solve(
+        T(X), T(q), T(a))
+    assert relnorm(N(r.mu), N(r0.mu)) < 1e-8
+
+
 # ------------------------------------------------------------------ edge cases and failure modes
 
 def test_edge_sizes(api):
