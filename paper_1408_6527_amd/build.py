@@ -48,9 +48,14 @@ def _scratch_users(remarks: str):
     return out
 
 
+# The M2L schedule is one fully unrolled, compile-time table-driven loop per truncation order; its
+# unrolled size exceeds the default limit for pragma-directed unrolling at the higher orders.
+EXTRA = {"m2l.hip": ["-mllvm", "-pragma-unroll-threshold=60000"]}
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [hipcc(), *FLAGS, "-Rpass-analysis=kernel-resource-usage", "-x", "hip", "-c",
+    cmd = [hipcc(), *FLAGS, *EXTRA.get(src, []), "-Rpass-analysis=kernel-resource-usage", "-x", "hip", "-c",
            os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:

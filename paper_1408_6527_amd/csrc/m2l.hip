@@ -16,8 +16,8 @@
 //       degree-blocked MFMA schedule (schedule.hpp): A = K_d entries gathered from the LDS copy
 //       of D(d) through the index table, B = source coefficients from LDS.
 // With a per-offset truncation order q(d) <= p (m2l_order_slack >= 0) a wave runs the unrolled
-// schedule of its q: the blocks of the order-p schedule that hold entries of degree <= q, with the
-// entries of degree above q read as zero.
+// schedule of its q: the blocks of the order-p schedule that hold entries of degree <= q, reading a
+// copy of D(d) whose entries above degree q are zero.
 // Accumulators stay in registers for the whole loop and each target's (partial) F~ is written once:
 // no atomics, deterministic.
 //
@@ -40,10 +40,10 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 constexpr int TPB = 512;  // 8 waves, one per target octant
 constexpr int NU = 27;    // u = oB - c in [-1, 1]^3
 
-// (step, row block) of every MFMA block in schedule order (schedule.hpp), as compile-time tables
-// The blocks of the order-P schedule that a truncation at order Q <= P needs (rows of degree <= Q,
-// steps below count(Q - lowest row degree)), in schedule order, with their position bp in the
-// full order-P block order (which locates their K-entry indices).
+// The blocks of the order-P schedule (schedule.hpp) that a truncation at order Q <= P needs (rows
+// of degree <= Q, steps below count(Q - lowest row degree)), in schedule order, as compile-time
+// tables: step s, row block rb, and position bp in the full order-P block order (which locates
+// their K-entry indices).
 template <int P, int Q>
 struct BlockOrder {
   int n;
@@ -65,72 +65,85 @@ struct BlockOrder {
           ++b;
         }
   }
+  // most step pairs (s / 2) met by w consecutive blocks (steps never decrease along the order)
+  constexpr int pair_span(int w) const {
+    int m = 1;
+    for (int k = 0; k < n; ++k) {
+      const int last = k + w - 1 < n ? k + w - 1 : n - 1;
+      const int span = s[last] / 2 - s[k] / 2 + 1;
+      m = span > m ? span : m;
+    }
+    return m;
+  }
 };
 
+// Software pipeline of one slot, in blocks of the schedule: while block k is issued to the matrix
+// core, the K-entry index of block k + DI is read from LDS and the K entry of block k + DG is
+// gathered (with the source coefficients of its step pair), so that no MFMA waits on the
+// two dependent LDS reads that feed it.
+// 16-parent tiles per workgroup: every K_d entry gathered from LDS feeds NCB MFMAs.  Bounded by
+// the accumulator registers (NCB x NRB tiles of 16 x 16) and the LDS of the staged sources.
+template <int P, bool F32>
+constexpr int m2l_ncb() { return (F32 ? P <= 8 : P <= 7) ? 2 : 1; }
+
+// (a shorter distance where the float64 accumulators leave fewer registers)
+template <int P, bool F32>
+constexpr int m2l_dg() { return F32 ? 6 : (P >= 10 || m2l_ncb<P, F32>() > 1 ? 3 : 4); }
+
 // One slot of one wave at truncation order Q: A = K_d entries gathered from the staged D(d) at Dv
-// through the index groups sH (entries of degree above Q read the zero at index NC), B = the staged
-// source coefficients at Bp.
+// through the index table sH, B = the staged source coefficients at Bp.  The staged D(d) holds zeros
+// above degree Q, so the blocks of the order-Q subset read the truncated operator unmasked.
 template <int P, bool F32, int NCB, int Q, typename kt, typename kt2, typename acc_t>
-__device__ __forceinline__ void m2l_mfma(const kt* Dv, const kt* Bp, const uint4* sH, int lane,
+__device__ __forceinline__ void m2l_mfma(const kt* Dv, const kt* Bp, const unsigned short* sH, int lane,
                                          acc_t (&acc)[NCB][sched_nrb(P)]) {
   constexpr BlockOrder<P, Q> order{};
   constexpr int NB = order.n;
-  constexpr int NC = mi_count(P), NCQ = mi_count(Q);
   constexpr int BP = sched_stride(P) + 2;
-  constexpr int GS = 8;  // blocks whose A entries are gathered before their MFMAs are issued
-  kt2 bb[NCB];
-  uint4 hg;
+  constexpr int DG = m2l_dg<P, F32>(), DI = 2 * DG;
+  constexpr int RA = DG + 1, RI = DI - DG + 1;  // live K entries and indices
+  constexpr int RB = order.pair_span(DG + 1);   // live step pairs of source coefficients
+  unsigned ix[RI];
+  kt a[RA];
+  kt2 bb[RB][NCB];
 #pragma unroll
-  for (int k0 = 0; k0 < NB; k0 += GS) {
-    kt a[GS];
+  for (int k = -DI; k < NB; ++k) {
+    const int ki = k + DI, kg = k + DG;
+    if (ki >= 0 && ki < NB) ix[ki % RI] = sH[sched_hpos(order.bp[ki], lane)];
+    if (kg >= 0 && kg < NB) {
+      a[kg % RA] = Dv[ix[kg % RI]];
+      const int sg = order.s[kg];
+      if (kg == 0 || order.s[kg - 1] / 2 != sg / 2) {
+        // steps 2j and 2j + 1 read coefficients m(2j, q) and m(2j, q) + 1 of the lane's column
 #pragma unroll
-    for (int j = 0; j < GS; ++j) {
-      const int k = k0 + j;
-      if (k < NB) {
-        const int blk = order.bp[k];
-        if (k == 0 || (order.bp[k - 1] >> 3) != (blk >> 3)) hg = sH[(blk >> 3) * 64 + lane];
-        const unsigned hw[4] = {hg.x, hg.y, hg.z, hg.w};
-        const unsigned hv = hw[(blk & 7) >> 1];
-        unsigned idx = (blk & 1) ? (hv >> 16) : (hv & 0xffffu);
-        if constexpr (Q < P) idx = idx < (unsigned)NCQ ? idx : (unsigned)NC;
-        a[j] = Dv[idx];
+        for (int cb = 0; cb < NCB; ++cb)
+          bb[(sg / 2) % RB][cb] = *reinterpret_cast<const kt2*>(Bp + cb * 16 * BP + 8 * (sg / 2));
       }
     }
+    if (k >= 0) {
+      const int s = order.s[k], rb = order.rb[k];
 #pragma unroll
-    for (int j = 0; j < GS; ++j) {
-      const int k = k0 + j;
-      if (k < NB) {
-        const int s = order.s[k], rb = order.rb[k];
-        if ((s & 1) == 0 && (k == 0 || order.s[k - 1] != s)) {
-          // steps s and s + 1 read coefficients m(s, q) and m(s, q) + 1 of the lane's column
-#pragma unroll
-          for (int cb = 0; cb < NCB; ++cb) bb[cb] = *reinterpret_cast<const kt2*>(Bp + cb * 16 * BP + 4 * s);
-        }
-#pragma unroll
-        for (int cb = 0; cb < NCB; ++cb) {
-          const kt b = (s & 1) ? bb[cb].y : bb[cb].x;
-          if constexpr (F32)
-            acc[cb][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j], b, acc[cb][rb], 0, 0, 0);
-          else
-            acc[cb][rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[j], b, acc[cb][rb], 0, 0, 0);
-        }
+      for (int cb = 0; cb < NCB; ++cb) {
+        const kt b = (s & 1) ? bb[(s / 2) % RB][cb].y : bb[(s / 2) % RB][cb].x;
+        if constexpr (F32)
+          acc[cb][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[k % RA], b, acc[cb][rb], 0, 0, 0);
+        else
+          acc[cb][rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[k % RA], b, acc[cb][rb], 0, 0, 0);
       }
     }
+    // keep each block's reads in its own issue window: the scheduler would otherwise sink the
+    // gathers down to their MFMAs to shorten register live ranges, which serialises the slot
+    __builtin_amdgcn_sched_barrier(0);
   }
 }
 
 // Run the slot at a runtime order q < P (one unrolled schedule per order).
 template <int P, bool F32, int NCB, typename kt, typename kt2, typename acc_t, int... Qs>
 __device__ __forceinline__ void m2l_mfma_order(int q, std::integer_sequence<int, Qs...>, const kt* Dv,
-                                               const kt* Bp, const uint4* sH, int lane,
+                                               const kt* Bp, const unsigned short* sH, int lane,
                                                acc_t (&acc)[NCB][sched_nrb(P)]) {
   (void)((q == Qs ? (m2l_mfma<P, F32, NCB, Qs, kt, kt2, acc_t>(Dv, Bp, sH, lane, acc), true) : false) || ...);
 }
 
-// 16-parent tiles per workgroup: every K_d entry gathered from LDS feeds NCB MFMAs.  Bounded by
-// the accumulator registers (NCB x NRB tiles of 16 x 16) and the LDS of the staged sources.
-template <int P, bool F32>
-constexpr int m2l_ncb() { return (F32 ? P <= 8 : P <= 7) ? 2 : 1; }
 // registers per lane: 4 waves per SIMD (two workgroups per CU) only where they fit
 template <int P, bool F32>
 constexpr int m2l_waves_per_eu() { return P <= 3 ? 4 : 2; }
@@ -152,13 +165,14 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(m2l_waves_p
   // distinct banks (STRIDE is a multiple of 8)
   constexpr int BP = STRIDE + 2;
   constexpr int HALF = STRIDE / 2;  // 16-byte pieces of one source row
-  constexpr int NG = sched_hgroups(P);
+  constexpr int NBLK = sched_nblocks(P);
   constexpr int ROWS = 16 * NCB;
   constexpr int PF = (ROWS * HALF + TPB - 1) / TPB;  // 16-byte source pieces per thread and slot
-  __shared__ uint4 sH[NG * 64];
+  __shared__ uint4 sHv[NBLK * 8];  // K-entry index table, 64 16-bit indices per block
   __shared__ kt sD[NU * DP];
   __shared__ int sQ[NU];  // truncation order of the 27 staged offsets
-  __shared__ __attribute__((aligned(16))) kt sB[ROWS * BP];
+  // source rows of two slots: the rows of the next slot are stored while the current one is read
+  __shared__ __attribute__((aligned(16))) kt sB[2][ROWS * BP];
   __shared__ int sSrc[8][ROWS];
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -186,7 +200,8 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(m2l_waves_p
     any_tgt |= tgt[cb] >= 0;
   }
   const bool active = __ballot(any_tgt) != 0;
-  for (int e = threadIdx.x; e < NG * 64; e += TPB) sH[e] = reinterpret_cast<const uint4*>(op.hidx)[e];
+  for (int e = threadIdx.x; e < NBLK * 8; e += TPB) sHv[e] = reinterpret_cast<const uint4*>(op.hidx)[e];
+  const unsigned short* sH = reinterpret_cast<const unsigned short*>(sHv);
 
   const int ws = t.ws, side = 2 * ws + 1, nn = t.nnear;
   const int R = 2 * ws + 1, cube = 2 * R + 1;
@@ -202,8 +217,8 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(m2l_waves_p
 #pragma unroll
     for (int rb = 0; rb < NRB; ++rb) acc[cb][rb] = acc_t{0, 0, 0, 0};
 
-  // source rows of one slot pass through registers: loaded one slot ahead, stored to LDS after the
-  // barrier that ends the previous slot
+  // source rows pass through registers: loaded from global memory one slot before they are stored
+  // to LDS, and stored one slot before they are read
   double2 pre[PF];
   auto prefetch = [&](int r) {
 #pragma unroll
@@ -218,7 +233,7 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(m2l_waves_p
       pre[i] = v;
     }
   };
-  auto commit = [&]() {
+  auto commit = [&](kt* dst) {
 #pragma unroll
     for (int i = 0; i < PF; ++i) {
       const int e = threadIdx.x + i * TPB;
@@ -227,9 +242,14 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(m2l_waves_p
         kt2 w;
         w.x = (kt)pre[i].x;
         w.y = (kt)pre[i].y;
-        *reinterpret_cast<kt2*>(sB + row * BP + 2 * h) = w;
+        *reinterpret_cast<kt2*>(dst + row * BP + 2 * h) = w;
       }
     }
+  };
+  // next live source octant after r, or -1
+  auto next_live = [](unsigned live, int r) {
+    const unsigned rest = live & ~((2u << r) - 1u);
+    return rest ? __ffs(rest) - 1 : -1;
   };
 
   for (int ci = c0; ci < c1; ++ci) {
@@ -259,24 +279,33 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(m2l_waves_p
       const int v = e / DP, k = e - v * DP;
       const int d0 = v / 9 - 1 - 2 * e0, d1 = (v / 3) % 3 - 1 - 2 * e1, d2 = v % 3 - 1 - 2 * e2;
       if (max(abs(d0), max(abs(d1), abs(d2))) > ws) {
+        // D_k(d) for |k| <= q(d), zero above: the M2L truncated at order q(d)
         const int slot = ((d0 + R) * cube + (d1 + R)) * cube + (d2 + R);
-        sD[e] = dtab[(int64_t)slot * DP + k];
-        if (k == 0) sQ[v] = op.dorder[slot];
+        const int q = op.dorder[slot];
+        sD[e] = k < mi_count(q) ? dtab[(int64_t)slot * DP + k] : (kt)0;
+        if (k == 0) sQ[v] = q;
       }
     }
+    commit(sB[0]);
+    int rn = next_live(live, r);
+    if (rn >= 0) prefetch(rn);
+    int buf = 0;
     while (true) {
-      __syncthreads();  // previous slot's source rows consumed
-      commit();
-      __syncthreads();  // source rows (and, on the first slot, sD) visible
-      const unsigned rest = live & ~((2u << r) - 1u);
-      const int rn = rest ? __ffs(rest) - 1 : -1;
-      if (rn >= 0) prefetch(rn);
+      // the rows of slot r (and, on the first slot, sD) are visible, and every wave is done with
+      // the slot before r, whose buffer now receives the rows of slot rn
+      __syncthreads();
+      int rnn = -1;
+      if (rn >= 0) {
+        commit(sB[buf ^ 1]);
+        rnn = next_live(live, rn);
+        if (rnn >= 0) prefetch(rnn);
+      }
       const int u0 = ob0 - ((r >> 2) & 1), u1 = ob1 - ((r >> 1) & 1), u2 = ob2 - (r & 1);
       const int d0 = u0 - 2 * e0, d1 = u1 - 2 * e1, d2 = u2 - 2 * e2;
       if (active && max(abs(d0), max(abs(d1), abs(d2))) > ws) {  // wave-uniform
         const int v = (u0 + 1) * 9 + (u1 + 1) * 3 + (u2 + 1);
         const kt* Dv = sD + v * DP;
-        const kt* Bp = sB + col * BP + 2 * kq;
+        const kt* Bp = sB[buf] + col * BP + 2 * kq;
         const int q = sQ[v];
         if (q >= P)
           m2l_mfma<P, F32, NCB, P, kt, kt2, acc_t>(Dv, Bp, sH, lane, acc);
@@ -286,6 +315,8 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(m2l_waves_p
       }
       if (rn < 0) break;
       r = rn;
+      rn = rnn;
+      buf ^= 1;
     }
   }
 #pragma unroll

@@ -45,9 +45,8 @@ __host__ __device__ constexpr int sched_nblocks(int p) {
   for (int rb = 0; rb < sched_nrb(p); ++rb) t += sched_nsteps(p, rb);
   return t;
 }
-// The K-entry index table is stored in groups of 8 consecutive blocks, each lane's 8 indices
-// adjacent (one 16-byte read per lane per group): position of (block, lane).
-__host__ __device__ constexpr int sched_hgroups(int p) { return (sched_nblocks(p) + 7) / 8; }
-__host__ __device__ constexpr int sched_hpos(int blk, int lane) { return ((blk >> 3) * 64 + lane) * 8 + (blk & 7); }
+// The K-entry index table holds one 16-bit index per block and lane, the 64 lanes of a block
+// adjacent (one conflict-free 128-byte LDS read per block): position of (block, lane).
+__host__ __device__ constexpr int sched_hpos(int blk, int lane) { return blk * 64 + lane; }
 
 }  // namespace pfmm

@@ -191,7 +191,7 @@ void HostTables::build(int p_, int ws_, int order_slack) {
   std::vector<int> degv(nc);
   for (int k = 0; k < nc; ++k) degv[k] = ix.deg(k);
   const int nrb = sched_nrb(p);
-  hidx.assign((size_t)sched_hgroups(p) * 8 * 64, (unsigned short)nc);
+  hidx.assign((size_t)nblocks * 64, (unsigned short)nc);
   int blk = 0;
   for (int s = 0; s < sched_maxsteps(p); ++s)
     for (int rb = 0; rb < nrb; ++rb) {
