@@ -41,25 +41,29 @@ constexpr int TPB = 512;  // 8 waves, one per target octant
 constexpr int NU = 27;    // u = oB - c in [-1, 1]^3
 
 // The blocks of the order-P schedule (schedule.hpp) that a truncation at order Q <= P needs (rows
-// of degree <= Q, steps below count(Q - lowest row degree)), in schedule order, as compile-time
-// tables: step s, row block rb, and position bp in the full order-P block order (which locates
-// their K-entry indices).
-template <int P, int Q>
+// of degree <= Q, steps below count(Q - lowest row degree)) and that half H of the row split issues,
+// in schedule order, as compile-time tables: step s, row block rb, and position bp in the full
+// order-P block order (which locates their K-entry indices).
+template <int P, int Q, int H>
 struct BlockOrder {
   int n;
   int s[sched_nblocks(P)];
   int rb[sched_nblocks(P)];
   int bp[sched_nblocks(P)];
-  constexpr BlockOrder() : n(0), s(), rb(), bp() {
+  int loc[sched_nblocks(P)];  // accumulator slot of the row block (sched_halves)
+  constexpr BlockOrder() : n(0), s(), rb(), bp(), loc() {
+    const SchedHalves& hs = SchedHalvesOf<P>::value;
     int b = 0;
     for (int st = 0; st < sched_maxsteps(P); ++st)
       for (int r = 0; r < sched_nrb(P); ++r)
         if (sched_nsteps(P, r) > st) {
           const int d0 = sched_deg_of(16 * r);
-          if (d0 <= Q && sched_coef(st, 0) < mi_count(Q - d0)) {
+          const int owner = r == 0 ? (st / 2) % 2 : hs.half[r];
+          if (d0 <= Q && sched_coef(st, 0) < mi_count(Q - d0) && owner == H) {
             s[n] = st;
             rb[n] = r;
             bp[n] = b;
+            loc[n] = hs.loc[r];
             ++n;
           }
           ++b;
@@ -88,15 +92,15 @@ constexpr int m2l_ncb() { return (F32 ? P <= 8 : P <= 7) ? 2 : 1; }
 
 // (a shorter distance where the float64 accumulators leave fewer registers)
 template <int P, bool F32>
-constexpr int m2l_dg() { return F32 ? 6 : (P >= 10 || m2l_ncb<P, F32>() > 1 ? 3 : 4); }
+constexpr int m2l_dg() { return F32 ? 6 : (P == 9 ? 2 : (P >= 10 || m2l_ncb<P, F32>() > 1 ? 3 : 4)); }
 
 // One slot of one wave at truncation order Q: A = K_d entries gathered from the staged D(d) at Dv
 // through the index table sH, B = the staged source coefficients at Bp.  The staged D(d) holds zeros
 // above degree Q, so the blocks of the order-Q subset read the truncated operator unmasked.
-template <int P, bool F32, int NCB, int Q, typename kt, typename kt2, typename acc_t>
+template <int P, bool F32, int NCB, int Q, int H, typename kt, typename kt2, typename acc_t>
 __device__ __forceinline__ void m2l_mfma(const kt* Dv, const kt* Bp, const unsigned short* sH, int lane,
-                                         acc_t (&acc)[NCB][sched_nrb(P)]) {
-  constexpr BlockOrder<P, Q> order{};
+                                         acc_t (&acc)[NCB][SchedHalvesOf<P>::value.nloc]) {
+  constexpr BlockOrder<P, Q, H> order{};
   constexpr int NB = order.n;
   constexpr int BP = sched_stride(P) + 2;
   constexpr int DG = m2l_dg<P, F32>(), DI = 2 * DG;
@@ -120,14 +124,14 @@ __device__ __forceinline__ void m2l_mfma(const kt* Dv, const kt* Bp, const unsig
       }
     }
     if (k >= 0) {
-      const int s = order.s[k], rb = order.rb[k];
+      const int s = order.s[k], lc = order.loc[k];
 #pragma unroll
       for (int cb = 0; cb < NCB; ++cb) {
         const kt b = (s & 1) ? bb[(s / 2) % RB][cb].y : bb[(s / 2) % RB][cb].x;
         if constexpr (F32)
-          acc[cb][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[k % RA], b, acc[cb][rb], 0, 0, 0);
+          acc[cb][lc] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[k % RA], b, acc[cb][lc], 0, 0, 0);
         else
-          acc[cb][rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[k % RA], b, acc[cb][rb], 0, 0, 0);
+          acc[cb][lc] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[k % RA], b, acc[cb][lc], 0, 0, 0);
       }
     }
     // keep each block's reads in its own issue window: the scheduler would otherwise sink the
@@ -136,17 +140,25 @@ __device__ __forceinline__ void m2l_mfma(const kt* Dv, const kt* Bp, const unsig
   }
 }
 
-// Run the slot at a runtime order q < P (one unrolled schedule per order).
-template <int P, bool F32, int NCB, typename kt, typename kt2, typename acc_t, int... Qs>
+// Run the slot of half H at a runtime order q <= P (one unrolled schedule per order).
+template <int P, bool F32, int NCB, int H, typename kt, typename kt2, typename acc_t, int... Qs>
 __device__ __forceinline__ void m2l_mfma_order(int q, std::integer_sequence<int, Qs...>, const kt* Dv,
                                                const kt* Bp, const unsigned short* sH, int lane,
-                                               acc_t (&acc)[NCB][sched_nrb(P)]) {
-  (void)((q == Qs ? (m2l_mfma<P, F32, NCB, Qs, kt, kt2, acc_t>(Dv, Bp, sH, lane, acc), true) : false) || ...);
+                                               acc_t (&acc)[NCB][SchedHalvesOf<P>::value.nloc]) {
+  (void)((q == Qs ? (m2l_mfma<P, F32, NCB, Qs, H, kt, kt2, acc_t>(Dv, Bp, sH, lane, acc), true) : false) || ...);
+}
+template <int P, bool F32, int NCB, int H, typename kt, typename kt2, typename acc_t>
+__device__ __forceinline__ void m2l_slot(int q, const kt* Dv, const kt* Bp, const unsigned short* sH, int lane,
+                                         acc_t (&acc)[NCB][SchedHalvesOf<P>::value.nloc]) {
+  if (q >= P)
+    m2l_mfma<P, F32, NCB, P, H, kt, kt2, acc_t>(Dv, Bp, sH, lane, acc);
+  else
+    m2l_mfma_order<P, F32, NCB, H, kt, kt2, acc_t>(q, std::make_integer_sequence<int, P>{}, Dv, Bp, sH, lane, acc);
 }
 
 // registers per lane: 4 waves per SIMD (two workgroups per CU) only where they fit
 template <int P, bool F32>
-constexpr int m2l_waves_per_eu() { return P <= 3 ? 4 : 2; }
+constexpr int m2l_waves_per_eu() { return 2; }
 
 template <int P, bool F32>
 __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(m2l_waves_per_eu<P, F32>()))) void k_m2l(TreeView t, OpTables op, int lp_lo, int lp_hi, int nsplit,
@@ -174,48 +186,63 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(m2l_waves_p
   // source rows of two slots: the rows of the next slot are stored while the current one is read
   __shared__ __attribute__((aligned(16))) kt sB[2][ROWS * BP];
   __shared__ int sSrc[8][ROWS];
+  constexpr int NXCH = 2 * 4 * NCB * 64;  // row-block-0 partial sums handed between the halves
+  constexpr bool XCH_IN_SB = NXCH * sizeof(acc_t) <= 2 * ROWS * BP * sizeof(kt);
+  __shared__ acc_t sX[XCH_IN_SB ? 1 : NXCH];
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  // waves w and w + 4 share a SIMD; giving them complementary octants (o and 7 - o) pairs a target
-  // that sees a source octant at a near offset with one that sees it farther away, which evens out
-  // the per-offset truncation orders between the SIMDs of one slot
-  const int oct = wave < 4 ? wave : 11 - wave;
+  // Each wave computes the targets of an octant pair for one half of the row blocks (sched_half).
+  // The pairs (0,3) (5,6) | (1,2) (4,7) form the octant sets {0,3,5,6} and {1,2,4,7}, whose
+  // per-offset orders at any slot nearly balance; waves w and w + 4 share a SIMD, and the SIMD
+  // takes half 0 of one pair and half 1 of the other pair of the same set, so that each SIMD
+  // carries half of one set's work.
+  const int simd = wave & 3, half = wave >> 2;
+  const int pair = half == 0 ? simd : (simd ^ 1);
+  constexpr int PAIRS[4][2] = {{0, 3}, {5, 6}, {1, 2}, {4, 7}};
+  const int oc[2] = {PAIRS[pair][0], PAIRS[pair][1]};
   const int split = blockIdx.x % nsplit;
-  int tile = blockIdx.x / nsplit, lp = lp_lo;
-  for (; lp <= lp_hi; ++lp) {
+  // finest level first: the coarse levels' tiles, fewer and lighter (their colleagues often fall
+  // outside the occupied region), fill the end of the launch
+  int tile = blockIdx.x / nsplit, lp = lp_hi;
+  for (; lp >= lp_lo; --lp) {
     const int nt = (t.off[lp + 1] - t.off[lp] + ROWS - 1) / ROWS;
     if (tile < nt) break;
     tile -= nt;
   }
-  if (lp > lp_hi) return;  // whole workgroup, before any barrier
+  if (lp < lp_lo) return;  // whole workgroup, before any barrier
   const int pbeg = t.off[lp] + ROWS * tile;
   const int pend = min(pbeg + ROWS, t.off[lp + 1]);
   const int col = lane & 15, kq = lane >> 4;
-  int tgt[NCB];
-  bool any_tgt = false;
+  // targets of the two octants (A: octant j, B: octant 7 - j) in the lane's columns
+  int tgtA[NCB], tgtB[NCB];
+  bool anyA = false, anyB = false;
 #pragma unroll
   for (int cb = 0; cb < NCB; ++cb) {
     const int P_ = pbeg + 16 * cb + col;
-    tgt[cb] = P_ < pend ? t.child8[8 * P_ + oct] : -1;
-    any_tgt |= tgt[cb] >= 0;
+    tgtA[cb] = P_ < pend ? t.child8[8 * P_ + oc[0]] : -1;
+    tgtB[cb] = P_ < pend ? t.child8[8 * P_ + oc[1]] : -1;
+    anyA |= tgtA[cb] >= 0;
+    anyB |= tgtB[cb] >= 0;
   }
-  const bool active = __ballot(any_tgt) != 0;
+  const bool activeA = __ballot(anyA) != 0, activeB = __ballot(anyB) != 0;
   for (int e = threadIdx.x; e < NBLK * 8; e += TPB) sHv[e] = reinterpret_cast<const uint4*>(op.hidx)[e];
   const unsigned short* sH = reinterpret_cast<const unsigned short*>(sHv);
 
   const int ws = t.ws, side = 2 * ws + 1, nn = t.nnear;
   const int R = 2 * ws + 1, cube = 2 * R + 1;
-  const int ob0 = (oct >> 2) & 1, ob1 = (oct >> 1) & 1, ob2 = oct & 1;
-  const int c0 = (int)((int64_t)nn * split / nsplit);
-  const int c1 = (int)((int64_t)nn * (split + 1) / nsplit);
   const kt* dtab;
   if constexpr (F32) dtab = op.dvec32; else dtab = op.dvec;
 
-  acc_t acc[NCB][NRB];
+  constexpr const SchedHalves& HS = SchedHalvesOf<P>::value;
+  constexpr int NLOC = HS.nloc;
+  acc_t accA[NCB][NLOC], accB[NCB][NLOC];
 #pragma unroll
   for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
-    for (int rb = 0; rb < NRB; ++rb) acc[cb][rb] = acc_t{0, 0, 0, 0};
+    for (int l = 0; l < NLOC; ++l) {
+      accA[cb][l] = acc_t{0, 0, 0, 0};
+      accB[cb][l] = acc_t{0, 0, 0, 0};
+    }
 
   // source rows pass through registers: loaded from global memory one slot before they are stored
   // to LDS, and stored one slot before they are read
@@ -252,7 +279,9 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(m2l_waves_p
     return rest ? __ffs(rest) - 1 : -1;
   };
 
-  for (int ci = c0; ci < c1; ++ci) {
+  // split s takes the colleague offsets ci = s, s + nsplit, ...: every split then mixes the inner
+  // offsets (mostly near-field, little M2L) with the outer ones, so the splits weigh alike
+  for (int ci = split; ci < nn; ci += nsplit) {
     const int e0 = ci / (side * side) - ws, e1 = (ci / side) % side - ws, e2 = ci % side - ws;
     if (e0 == 0 && e1 == 0 && e2 == 0) continue;  // the parent's own children are all near
     __syncthreads();  // every wave is done with sSrc, sD and sB of the previous offset
@@ -300,38 +329,74 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(m2l_waves_p
         rnn = next_live(live, rn);
         if (rnn >= 0) prefetch(rnn);
       }
-      const int u0 = ob0 - ((r >> 2) & 1), u1 = ob1 - ((r >> 1) & 1), u2 = ob2 - (r & 1);
-      const int d0 = u0 - 2 * e0, d1 = u1 - 2 * e1, d2 = u2 - 2 * e2;
-      if (active && max(abs(d0), max(abs(d1), abs(d2))) > ws) {  // wave-uniform
-        const int v = (u0 + 1) * 9 + (u1 + 1) * 3 + (u2 + 1);
-        const kt* Dv = sD + v * DP;
-        const kt* Bp = sB[buf] + col * BP + 2 * kq;
-        const int q = sQ[v];
-        if (q >= P)
-          m2l_mfma<P, F32, NCB, P, kt, kt2, acc_t>(Dv, Bp, sH, lane, acc);
-        else
-          m2l_mfma_order<P, F32, NCB, kt, kt2, acc_t>(q, std::make_integer_sequence<int, P>{}, Dv, Bp, sH,
-                                                      lane, acc);
-      }
+      // one octant of the pair at this slot (its accumulators are always named statically)
+      auto octant_slot = [&](acc_t(&acc)[NCB][NLOC], int o, bool act) {
+        const int u0 = ((o >> 2) & 1) - ((r >> 2) & 1), u1 = ((o >> 1) & 1) - ((r >> 1) & 1), u2 = (o & 1) - (r & 1);
+        const int d0 = u0 - 2 * e0, d1 = u1 - 2 * e1, d2 = u2 - 2 * e2;
+        if (act && max(abs(d0), max(abs(d1), abs(d2))) > ws) {  // wave-uniform
+          const int v = (u0 + 1) * 9 + (u1 + 1) * 3 + (u2 + 1);
+          const kt* Dv = sD + v * DP;
+          const kt* Bp = sB[buf] + col * BP + 2 * kq;
+          const int q = sQ[v];
+          if (half == 0)
+            m2l_slot<P, F32, NCB, 0, kt, kt2, acc_t>(q, Dv, Bp, sH, lane, acc);
+          else
+            m2l_slot<P, F32, NCB, 1, kt, kt2, acc_t>(q, Dv, Bp, sH, lane, acc);
+        }
+      };
+      octant_slot(accA, oc[0], activeA);
+      octant_slot(accB, oc[1], activeB);
       if (rn < 0) break;
       r = rn;
       rn = rnn;
       buf ^= 1;
     }
   }
+  // row block 0 is split between the halves: half 1 hands its partial sums to half 0 through LDS
+  // (in the source buffers, free once every wave has passed this barrier, where they are large
+  // enough)
+  acc_t* xch = XCH_IN_SB ? reinterpret_cast<acc_t*>(&sB[0][0]) : sX;
+  __syncthreads();
+  if (half == 1) {
 #pragma unroll
-  for (int cb = 0; cb < NCB; ++cb) {
-    if (tgt[cb] < 0) continue;
-    double* Fr = F + (int64_t)split * split_stride + (int64_t)tgt[cb] * STRIDE;
+    for (int cb = 0; cb < NCB; ++cb) {
+      xch[((0 * 4 + pair) * NCB + cb) * 64 + lane] = accA[cb][0];
+      xch[((1 * 4 + pair) * NCB + cb) * 64 + lane] = accB[cb][0];
+    }
+  }
+  __syncthreads();
+  if (half == 0) {
 #pragma unroll
-    for (int rb = 0; rb < NRB; ++rb) {
+    for (int cb = 0; cb < NCB; ++cb) {
+      accA[cb][0] += xch[((0 * 4 + pair) * NCB + cb) * 64 + lane];
+      accB[cb][0] += xch[((1 * 4 + pair) * NCB + cb) * 64 + lane];
+    }
+  }
+  // each half writes the rows of its row blocks (row block 0: half 0, which holds the sum)
+  auto write_rows = [&](const acc_t(&acc)[NCB][NLOC], const int(&tg)[NCB], auto hc) {
+    constexpr int H = decltype(hc)::value;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        // f64 16x16x4: lane l, register q holds row 4 q + l/16; f32 16x16x4: row 4 (l/16) + q
-        const int row = 16 * rb + (F32 ? (4 * kq + q) : (4 * q + kq));
-        if (row < NC) Fr[row] = (double)acc[cb][rb][q];
+    for (int cb = 0; cb < NCB; ++cb) {
+      if (tg[cb] < 0) continue;
+      double* Fr = F + (int64_t)split * split_stride + (int64_t)tg[cb] * STRIDE;
+#pragma unroll
+      for (int rb = 0; rb < NRB; ++rb) {
+        if (SchedHalvesOf<P>::value.half[rb] != H) continue;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          // f64 16x16x4: lane l, register q holds row 4 q + l/16; f32 16x16x4: row 4 (l/16) + q
+          const int row = 16 * rb + (F32 ? (4 * kq + q) : (4 * q + kq));
+          if (row < NC) Fr[row] = (double)acc[cb][SchedHalvesOf<P>::value.loc[rb]][q];
+        }
       }
     }
+  };
+  if (half == 0) {
+    write_rows(accA, tgtA, std::integral_constant<int, 0>{});
+    write_rows(accB, tgtB, std::integral_constant<int, 0>{});
+  } else {
+    write_rows(accA, tgtA, std::integral_constant<int, 1>{});
+    write_rows(accB, tgtB, std::integral_constant<int, 1>{});
   }
 }
 

@@ -33,18 +33,77 @@ __host__ __device__ constexpr int sched_deg_of(int row) {
   while (mi_count(d) <= row) ++d;
   return d;
 }
+// steps s whose quarter-0 coefficient m(s, 0) is below count: ceil(count / 8) even steps
+// (m = 8j) and ceil((count - 1) / 8) odd ones (m = 8j + 1)
+__host__ __device__ constexpr int sched_steps_below(int count) { return count <= 0 ? 0 : (count + 7) / 8 + (count + 6) / 8; }
 // steps s whose quarter-0 coefficient is still inside row block rb's non-zero columns
-__host__ __device__ constexpr int sched_nsteps(int p, int rb) {
-  int s = 0;
-  while (sched_coef(s, 0) < mi_count(p - sched_deg_of(16 * rb))) ++s;
-  return s;
-}
+__host__ __device__ constexpr int sched_nsteps(int p, int rb) { return sched_steps_below(mi_count(p - sched_deg_of(16 * rb))); }
 __host__ __device__ constexpr int sched_maxsteps(int p) { return sched_nsteps(p, 0); }
 __host__ __device__ constexpr int sched_nblocks(int p) {
   int t = 0;
   for (int rb = 0; rb < sched_nrb(p); ++rb) t += sched_nsteps(p, rb);
   return t;
 }
+// Steps of row block rb that a truncation at order q <= p keeps (quarter-0 coefficient below
+// count(q - lowest row degree)).
+__host__ __device__ constexpr int sched_nsteps_q(int p, int q, int rb) {
+  const int d0 = sched_deg_of(16 * rb);
+  return d0 > q || q > p ? 0 : sched_steps_below(mi_count(q - d0));
+}
+// Two waves share the rows of one target: row block 0 is split by step pairs (half (s / 2) % 2),
+// every other row block belongs to one half, assigned in index order to the half that keeps the
+// larger of the two block counts smallest, summed over the truncation orders ceil(p/2) .. p.
+// half[rb] (rb >= 1) is the half of row block rb, loc[rb] its accumulator slot within the half
+// (row block 0 is slot 0 of both halves), nloc the slots of the larger half.
+struct SchedHalves {
+  int half[32];
+  int loc[32];
+  int nloc;
+};
+__host__ __device__ constexpr SchedHalves sched_halves(int p) {
+  SchedHalves hs{};
+  const int lo = (p + 1) / 2, nrb = sched_nrb(p);
+  int ns[16][32] = {};  // steps kept per order q = lo .. p and row block
+  for (int q = lo; q <= p; ++q)
+    for (int rb = 0; rb < nrb; ++rb) ns[q - lo][rb] = sched_nsteps_q(p, q, rb);
+  int load[2][16] = {};
+  for (int q = lo; q <= p; ++q) {
+    const int n0 = ns[q - lo][0];
+    load[0][q - lo] = (n0 + 3) / 4 * 2 - (n0 % 4 == 1 ? 1 : 0);  // steps s < n0 with (s / 2) % 2 == 0
+    load[1][q - lo] = n0 - load[0][q - lo];
+  }
+  int cnt[2] = {1, 1};
+  hs.half[0] = 0;
+  hs.loc[0] = 0;
+  for (int r = 1; r < nrb; ++r) {
+    int best = 0, best_cost = -1;
+    for (int h = 0; h < 2; ++h) {
+      int cost = 0;
+      for (int q = lo; q <= p; ++q) {
+        const int a = load[0][q - lo] + (h == 0 ? ns[q - lo][r] : 0);
+        const int b = load[1][q - lo] + (h == 1 ? ns[q - lo][r] : 0);
+        cost += a > b ? a : b;
+      }
+      if (best_cost < 0 || cost < best_cost) {
+        best = h;
+        best_cost = cost;
+      }
+    }
+    for (int q = lo; q <= p; ++q) load[best][q - lo] += ns[q - lo][r];
+    hs.half[r] = best;
+    hs.loc[r] = cnt[best]++;
+  }
+  hs.nloc = cnt[0] > cnt[1] ? cnt[0] : cnt[1];
+  return hs;
+}
+// evaluated once per order p
+template <int P>
+struct SchedHalvesOf {
+  static constexpr SchedHalves value = sched_halves(P);
+};
+template <int P>
+constexpr SchedHalves SchedHalvesOf<P>::value;
+
 // The K-entry index table holds one 16-bit index per block and lane, the 64 lanes of a block
 // adjacent (one conflict-free 128-byte LDS read per block): position of (block, lane).
 __host__ __device__ constexpr int sched_hpos(int blk, int lane) { return blk * 64 + lane; }
