@@ -92,6 +92,14 @@ typedef struct pfmm_config {
                           the pairs closer than this radius (Angstrom) in adjacent leaves.  Same
                           converged dipoles and stopping rule; fewer field evaluations.            */
   int precond_iters;   /* inner iterations of the preconditioner, 1..64                            */
+  double scf_relax;    /* 0: every dipole-solve field evaluation at the configured orders.  In (0, 1):
+                          once the relative residual r_k falls below scf_relax, the field evaluation
+                          of the next iteration caps every M2L order at p - floor(ln(scf_relax / r_k) /
+                          ln((ws + 1) / sqrt(3))), at least min(p, 2): one order less for every factor
+                          by which the truncation bound of the nearest offsets grows (an extension:
+                          relaxed matrix-vector products in a Krylov solve, whose late corrections are
+                          small).  The stopping rule is checked again on the final dipoles with the
+                          full orders; if it fails, the solve continues from them without the cap.  */
 } pfmm_config;
 
 typedef struct pfmm_result {
@@ -108,12 +116,18 @@ typedef struct pfmm_result {
   int64_t m2l_flops;            /* useful M2L flops per evaluation: 2 C(q+6, 6) per pair of order q */
   int n_evals;                  /* FMM field evaluations performed                                 */
   double t_phase_ms[8];         /* with PFMM_TIMING: tree, charge field, dipole solve, final pass,
-                                   assembly, total, -, -                                           */
+                                   assembly, total, -, - (after a continuation of a relaxed solve,
+                                   phases 2-4 are those of its first pass)                         */
   double t_kernel_ms[8];        /* with PFMM_TIMING: summed device time per kernel class, measured
                                    with HIP events on the call's stream: P2M, M2M, M2L, L2L, L2P,
                                    P2P of the dipole solve (damped field only), P2P of the charge and
                                    final passes (all outputs), dipole-solve vector kernels          */
   int kernel_launches[8];       /* launches per kernel class counted in t_kernel_ms               */
+  int64_t m2l_flops_total;      /* useful M2L flops of all field evaluations of the call, each at the
+                                   orders it used                                                  */
+  int m2l_order_cap_min;        /* lowest M2L order cap of the dipole solve (order_p without
+                                   scf_relax)                                                      */
+  int scf_restarts;             /* continuations without the cap after the final check (scf_relax) */
 } pfmm_result;
 
 typedef struct pfmm_handle pfmm_handle;
@@ -121,7 +135,7 @@ typedef struct pfmm_handle pfmm_handle;
 /* Fill *cfg with the defaults: p = 6, ws = 2, leaf_width = 0, FP64, scf_tol = 1e-6,
    scf_max_iter = 200, graph_iters = 4, thole_a = 2.0, coulomb_k = 332.06371,
    flags = WANT_FORCES | WANT_POTENTIALS | SAVE_FOR_BACKWARD, m2l_order_slack = -1,
-   precond_cutoff = 0, precond_iters = 4. */
+   precond_cutoff = 0, precond_iters = 4, scf_relax = 0. */
 void pfmm_config_default(pfmm_config* cfg);
 
 /* Create a handle for a configuration.  Validates cfg, builds the constant operator tables of

@@ -50,6 +50,7 @@ class Config(ctypes.Structure):
         ("m2l_order_slack", ctypes.c_int),
         ("precond_cutoff", ctypes.c_double),
         ("precond_iters", ctypes.c_int),
+        ("scf_relax", ctypes.c_double),
     ]
 
 
@@ -72,6 +73,9 @@ class Result(ctypes.Structure):
         ("t_phase_ms", ctypes.c_double * 8),
         ("t_kernel_ms", ctypes.c_double * 8),
         ("kernel_launches", ctypes.c_int * 8),
+        ("m2l_flops_total", ctypes.c_int64),
+        ("m2l_order_cap_min", ctypes.c_int),
+        ("scf_restarts", ctypes.c_int),
     ]
 
 KERNEL_CLASSES = ["p2m", "m2m", "m2l", "l2l", "l2p", "p2p_scf", "p2p_full", "solver"]

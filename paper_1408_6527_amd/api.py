@@ -28,8 +28,8 @@ def config(**kw) -> _lib.Config:
     """A pfmm_config with the library defaults, overridden by keyword arguments.
 
     Keywords: order_p, ws, leaf_width, precision ("fp64" | "mixed"), scf_tol, scf_max_iter,
-    graph_iters, thole_a, coulomb_k, forces (bool), potentials (bool), save_for_backward (bool),
-    warm_start (bool), timing (bool).
+    graph_iters, thole_a, coulomb_k, m2l_order_slack, precond_cutoff, precond_iters, scf_relax,
+    forces (bool), potentials (bool), save_for_backward (bool), warm_start (bool), timing (bool).
     """
     c = _lib.Config()
     lib.pfmm_config_default(ctypes.byref(c))
@@ -139,6 +139,8 @@ class Solver:
         self._n_last = n
         stats = dict(levels=res.levels, leaf_width=res.leaf_width, n_leaves=res.n_leaves,
                      n_cells=res.n_cells, n_m2l=res.n_m2l, n_p2p=res.n_p2p, m2l_flops=res.m2l_flops, n_evals=res.n_evals,
+                     m2l_flops_total=res.m2l_flops_total, m2l_order_cap_min=res.m2l_order_cap_min,
+                     scf_restarts=res.scf_restarts,
                      t_phase_ms=list(res.t_phase_ms), status=_lib.STATUS[st],
                      t_kernel_ms=dict(zip(_lib.KERNEL_CLASSES, res.t_kernel_ms)),
                      kernel_launches=dict(zip(_lib.KERNEL_CLASSES, res.kernel_launches)))

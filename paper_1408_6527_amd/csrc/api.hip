@@ -173,6 +173,7 @@ struct pfmm_handle {
   int m2l_tiles = 0, nsplit = 1;
   int64_t split_stride = 0;
   int64_t n_m2l = 0, n_p2p = 0, m2l_flops = 0;
+  int64_t m2l_flops_cap[11] = {};  // useful M2L flops per evaluation with every order capped at c
   int n_evals = 0;
 };
 
@@ -213,6 +214,8 @@ void validate_config(const pfmm_config* c) {
   if (c->m2l_order_slack < -1) throw Error(PFMM_ERR_INVALID_ARG, "m2l_order_slack must be >= -1");
   if (!(c->precond_cutoff >= 0.0) || !std::isfinite(c->precond_cutoff))
     throw Error(PFMM_ERR_INVALID_ARG, "precond_cutoff must be >= 0");
+  if (!(c->scf_relax >= 0.0 && c->scf_relax < 1.0))
+    throw Error(PFMM_ERR_INVALID_ARG, "scf_relax must be in [0, 1)");
   if (c->precond_cutoff > 0.0 && (c->precond_iters < 1 || c->precond_iters > 64))
     throw Error(PFMM_ERR_INVALID_ARG, "precond_iters must be in 1..64");
 }
@@ -333,10 +336,10 @@ void build_tree(pfmm_handle* h, int n, const double* pos, const double* q, const
   Particles& pa = h->pa;
   pa.n = n; pa.P = P; pa.alpha = al; pa.sqa = sqa; pa.tau = tau; pa.itau = itau;
 
-  unsigned long long* stats = dev<unsigned long long>(h->w_stats, 3);
-  PFMM_HIP(hipMemsetAsync(stats, 0, 3 * sizeof(unsigned long long), s));
-  launch_tree_stats(t, h->op.m2l_code, h->op.dorder, h->op.noff, stats, s);
-  unsigned long long st[3];
+  unsigned long long* stats = dev<unsigned long long>(h->w_stats, 14);
+  PFMM_HIP(hipMemsetAsync(stats, 0, 14 * sizeof(unsigned long long), s));
+  launch_tree_stats(t, h->op.m2l_code, h->op.dorder, h->op.noff, h->op.p, stats, s);
+  unsigned long long st[14];
   {
     void* pin = h->pinned.get(sizeof(st));
     PFMM_HIP(hipMemcpyAsync(pin, stats, sizeof(st), hipMemcpyDeviceToHost, s));
@@ -346,6 +349,7 @@ void build_tree(pfmm_handle* h, int n, const double* pos, const double* q, const
   h->n_m2l = (int64_t)st[0];
   h->n_p2p = (int64_t)st[1];
   h->m2l_flops = (int64_t)st[2];
+  for (int c = 0; c <= 10; ++c) h->m2l_flops_cap[c] = c <= h->op.p ? (int64_t)st[3 + c] : 0;
   // enough workgroups to fill the device: split each parent tile's colleague offsets when tiles are
   // few (at least 4 offsets per split, so that staging the index table stays a small share)
   h->m2l_tiles = L >= 2 ? m2l_tiles(t, 1, L - 1, 2) : 0;  // workgroups of 32 parents
@@ -367,7 +371,7 @@ void build_tree(pfmm_handle* h, int n, const double* pos, const double* q, const
 // One FMM evaluation: sources 1 = charges, 2 = dipoles (mu4), 3 = both.
 // mode 0: Ed only; mode 1: phi, Eu, Ed, G.
 void fmm_pass(pfmm_handle* h, int sources, int mode, FieldOut out, int* err, const int* done,
-              hipStream_t s) {
+              hipStream_t s, const int* qcap = nullptr) {
   const TreeView& t = h->tv;
   const OpTables& op = h->op;
   const bool fp32 = h->cfg.precision == PFMM_MIXED;
@@ -384,7 +388,7 @@ void fmm_pass(pfmm_handle* h, int sources, int mode, FieldOut out, int* err, con
     for (int lp = t.L - 1; lp >= 2; --lp) launch_m2m(t, op, lp, M, done, s);
     kt.end(KC_M2M, e);
     e = kt.begin();
-    launch_m2l(t, op, h->nsplit, M, F, h->split_stride, fp32, 3, done, s);
+    launch_m2l(t, op, h->nsplit, M, F, h->split_stride, fp32, 3, done, qcap, s);
     kt.end(KC_M2L, e);
     e = kt.begin();
     for (int lc = 2; lc <= t.L; ++lc) launch_l2l(t, op, lc, F, h->nsplit, h->split_stride, done, s);
@@ -524,86 +528,115 @@ pfmm_status solve_impl(pfmm_handle* h, int64_t n64, const double* pos, const dou
   const bool warm = (c.flags & PFMM_WARM_START) != 0;
   if (warm) launch_permute_dipoles(h->w_perm.as<int>(), n, mu, pa.tau, mu4, s);
   FieldOut fo{nullptr, nullptr, E, nullptr};
-  if (pc && !warm) {
-    // the preconditioned solve starts from y0 = 0: r0 = S E^q costs no field evaluation, and
-    // p0 = z0 is a better first direction than the Jacobi guess alpha E^q
-    launch_cg_init_zero(pa, Eq, y, r, part, st, c.scf_tol, s);
-  } else {
-    launch_cg_init(pa, Eq, mu4, warm, y, pv, mu4, part, st, s);
-    fmm_pass(h, 2, 0, fo, err, nullptr, s);
-    launch_cg_residual0(pa, Eq, E, y, r, pv, part, st, c.scf_tol, s);
-  }
-  if (pc) {
-    precondition(s);
-    launch_cg_direction(3 * n, z, pv, st, s);  // b = 0 here: p0 = z0
-  }
+  // relaxed field evaluations: the update kernel of each iteration picks the order cap of the next
+  RelaxParams rp;
+  rp.p = c.order_p;
+  rp.qmin = (c.order_p + 1) / 2;
+  rp.track = 1;
+  rp.start = c.scf_relax;
+  rp.lrho = 2.0 * std::log((c.ws + 1.0) / std::sqrt(3.0));
+  launch_fill_int(&st->qcap, 1, c.order_p, s);
+  launch_fill_int(st->ncap, 16, 0, s);
   const int* done = &st->done;
-  auto iteration = [&](hipStream_t q) {
-    int ev = h->kt.begin();
-    launch_make_dipoles(pa, pv, mu4, done, q);
-    h->kt.end(KC_SOLVER, ev);
-    fmm_pass(h, 2, 0, fo, err, done, q);
-    if (pc) {
-      ev = h->kt.begin();
-      launch_pcg_ap(pa, pv, E, r, Ap, part, st, q);
-      launch_cg_update(pa, y, r, pv, Ap, part, st, c.scf_tol, c.scf_max_iter, q);
-      h->kt.end(KC_SOLVER, ev);
-      precondition(q);
-      ev = h->kt.begin();
-      launch_pcg_zq(3 * n, z, Ap, part, st, q);
-      launch_cg_direction(3 * n, z, pv, st, q);
-      h->kt.end(KC_SOLVER, ev);
-      return;
-    }
-    ev = h->kt.begin();
-    launch_cg_ap(pa, pv, E, Ap, part, st, q);
-    launch_cg_update(pa, y, r, pv, Ap, part, st, c.scf_tol, c.scf_max_iter, q);
-    launch_cg_direction(3 * n, r, pv, st, q);
-    h->kt.end(KC_SOLVER, ev);
-  };
   const bool timing = (c.flags & PFMM_TIMING) != 0;
   // with timing, test convergence after every iteration so that no launch runs past it
   const int chunk = timing ? 1 : (c.graph_iters > 0 ? c.graph_iters : 4);
   const bool use_graph = c.graph_iters > 0 && !timing;
-  CGState hs{};
-  sync_read(h, st, &hs, sizeof(hs), s);
-  int launched = 0;
-  if (use_graph && !hs.done) {
-    // chunk iterations captured once per solve as one HIP graph; every kernel in it returns at
-    // once when the device-side `done` flag is set, so replays past convergence are no-ops
-    h->graph.capture([&]() {
-      for (int k = 0; k < chunk; ++k) iteration(h->graph.cap);
-    });
-    while (!hs.done && launched < c.scf_max_iter) {
-      h->graph.launch(s);
-      launched += chunk;
-      sync_read(h, st, &hs, sizeof(hs), s);
-    }
-  } else {
-    while (!hs.done && launched < c.scf_max_iter) {
-      for (int k = 0; k < chunk && launched < c.scf_max_iter; ++k, ++launched) iteration(s);
-      sync_read(h, st, &hs, sizeof(hs), s);
-    }
-  }
-  tm.mark();
-
-  // stage 3: field of the converged dipoles, energy and forces
-  launch_make_dipoles(pa, y, mu4, nullptr, s);
   double* phim = dev<double>(h->f_phim, n);
   double* Eum = dev<double>(h->f_Eum, 3 * (int64_t)n);
   double* Edm = dev<double>(h->f_Edm, 3 * (int64_t)n);
   double* Gm = dev<double>(h->f_Gm, 6 * (int64_t)n);
-  fmm_pass(h, 2, 1, FieldOut{phim, Eum, Edm, Gm}, err, nullptr, s);
-  tm.mark();
   double* Fs = dev<double>(h->s_F, 3 * (int64_t)n);
   double* phs = dev<double>(h->s_phi, n);
   double* Ets = dev<double>(h->s_Etot, 3 * (int64_t)n);
   EnergyParts* ep = static_cast<EnergyParts*>(h->w_ep.reserve(sizeof(EnergyParts)));
-  launch_assemble(pa, h->w_perm.as<int>(), mu4, phiq, Eq, Gq, phim, Eum, Edm, Gm, c.coulomb_k, mu,
-                  want_f ? forces : nullptr, want_phi ? phi : nullptr, Fs, phs, Ets, part, ep, s);
-  tm.mark();
+  CGState hs{};
   EnergyParts he{};
-  sync_read(h, ep, &he, sizeof(he), s);
+  int total_iters = 0, restarts = 0, full_evals = 1;  // the charge pass
+  bool warm_now = warm;
+  for (;;) {
+    const bool relaxed = rp.start > 0.0;
+    const int* qcap = relaxed ? &st->qcap : nullptr;
+    if (pc && !warm_now) {
+      // the preconditioned solve starts from y0 = 0: r0 = S E^q costs no field evaluation, and
+      // p0 = z0 is a better first direction than the Jacobi guess alpha E^q
+      launch_cg_init_zero(pa, Eq, y, r, part, st, c.scf_tol, s);
+    } else {
+      launch_cg_init(pa, Eq, mu4, warm_now, y, pv, mu4, part, st, s);
+      fmm_pass(h, 2, 0, fo, err, nullptr, s);
+      ++full_evals;
+      launch_cg_residual0(pa, Eq, E, y, r, pv, part, st, c.scf_tol, s);
+    }
+    if (pc) {
+      precondition(s);
+      launch_cg_direction(3 * n, z, pv, st, s);  // b = 0 here: p0 = z0
+    }
+    auto iteration = [&](hipStream_t q) {
+      int ev = h->kt.begin();
+      launch_make_dipoles(pa, pv, mu4, done, q);
+      h->kt.end(KC_SOLVER, ev);
+      fmm_pass(h, 2, 0, fo, err, done, q, qcap);
+      if (pc) {
+        ev = h->kt.begin();
+        launch_pcg_ap(pa, pv, E, r, Ap, part, st, q);
+        launch_cg_update(pa, y, r, pv, Ap, part, st, c.scf_tol, c.scf_max_iter, q, rp);
+        h->kt.end(KC_SOLVER, ev);
+        precondition(q);
+        ev = h->kt.begin();
+        launch_pcg_zq(3 * n, z, Ap, part, st, q);
+        launch_cg_direction(3 * n, z, pv, st, q);
+        h->kt.end(KC_SOLVER, ev);
+        return;
+      }
+      ev = h->kt.begin();
+      launch_cg_ap(pa, pv, E, Ap, part, st, q);
+      launch_cg_update(pa, y, r, pv, Ap, part, st, c.scf_tol, c.scf_max_iter, q, rp);
+      launch_cg_direction(3 * n, r, pv, st, q);
+      h->kt.end(KC_SOLVER, ev);
+    };
+    sync_read(h, st, &hs, sizeof(hs), s);
+    int launched = 0;
+    if (use_graph && !hs.done) {
+      // chunk iterations captured as one HIP graph; every kernel in it returns at once when the
+      // device-side `done` flag is set, so replays past convergence are no-ops
+      h->graph.capture([&]() {
+        for (int k = 0; k < chunk; ++k) iteration(h->graph.cap);
+      });
+      while (!hs.done && launched < c.scf_max_iter) {
+        h->graph.launch(s);
+        launched += chunk;
+        sync_read(h, st, &hs, sizeof(hs), s);
+      }
+    } else {
+      while (!hs.done && launched < c.scf_max_iter) {
+        for (int k = 0; k < chunk && launched < c.scf_max_iter; ++k, ++launched) iteration(s);
+        sync_read(h, st, &hs, sizeof(hs), s);
+      }
+    }
+    total_iters += hs.iters;
+    tm.mark();
+
+    // stage 3: field of the converged dipoles (full orders), energy and forces
+    launch_make_dipoles(pa, y, mu4, nullptr, s);
+    fmm_pass(h, 2, 1, FieldOut{phim, Eum, Edm, Gm}, err, nullptr, s);
+    ++full_evals;
+    tm.mark();
+    launch_assemble(pa, h->w_perm.as<int>(), mu4, phiq, Eq, Gq, phim, Eum, Edm, Gm, c.coulomb_k, mu,
+                    want_f ? forces : nullptr, want_phi ? phi : nullptr, Fs, phs, Ets, part, ep, s);
+    tm.mark();
+    sync_read(h, ep, &he, sizeof(he), s);
+    const double true_res = he.bn2 > 0.0 ? std::sqrt(he.res2 / he.bn2) : 0.0;
+    // a relaxed solve must meet the stopping rule with the full orders too; otherwise continue from
+    // the final dipoles (in mu4) without the cap
+    if (relaxed && !hs.notspd && !hs.maxed && true_res > c.scf_tol && restarts == 0) {
+      ++restarts;
+      rp.start = 0.0;
+      launch_fill_int(&st->qcap, 1, c.order_p, s);
+      warm_now = true;
+      continue;
+    }
+    break;
+  }
   tm.fill(res->t_phase_ms);
   h->kt.collect(res->t_kernel_ms, res->kernel_launches);
 
@@ -611,7 +644,7 @@ pfmm_status solve_impl(pfmm_handle* h, int64_t n64, const double* pos, const dou
   res->U_qq = ke * he.Uqq;
   res->U_pol = ke * (he.Amu - he.muEq - 0.5 * he.muEd);
   res->U_total = res->U_qq + res->U_pol;
-  res->iters = hs.iters;
+  res->iters = total_iters;
   res->residual = he.bn2 > 0.0 ? std::sqrt(he.res2 / he.bn2) : 0.0;
   res->residual_max_debye = he.resmax * EANG_TO_DEBYE;
   res->levels = h->tv.L;
@@ -621,8 +654,24 @@ pfmm_status solve_impl(pfmm_handle* h, int64_t n64, const double* pos, const dou
   res->n_m2l = h->n_m2l;
   res->n_p2p = h->n_p2p;
   res->m2l_flops = h->m2l_flops;
-  // charge field, initial residual (not on the cold-started preconditioned path), iterations, final pass
-  res->n_evals = (pc && !warm ? 2 : 3) + hs.iters;
+  // charge field, initial residuals (not on the cold-started preconditioned path), final passes: full
+  // orders; the iterations at the caps they used
+  int ncap[16];
+  {
+    CGState hc{};
+    sync_read(h, st, &hc, sizeof(hc), s);
+    std::memcpy(ncap, hc.ncap, sizeof(ncap));
+  }
+  int64_t flops_total = (int64_t)full_evals * h->m2l_flops;
+  int cap_min = c.order_p;
+  for (int q = 0; q <= c.order_p; ++q) {
+    flops_total += (int64_t)ncap[q] * (q == c.order_p ? h->m2l_flops : h->m2l_flops_cap[q]);
+    if (ncap[q] > 0) cap_min = std::min(cap_min, q);
+  }
+  res->n_evals = full_evals + total_iters;
+  res->m2l_flops_total = flops_total;
+  res->m2l_order_cap_min = cap_min;
+  res->scf_restarts = restarts;
   h->saved = true;
   h->saved_n = n;
   if (hs.notspd) throw Error(PFMM_ERR_NOT_SPD, "conjugate gradients met p.Ap <= 0: the dipole system is not positive definite");
@@ -651,6 +700,7 @@ void pfmm_config_default(pfmm_config* c) {
   c->m2l_order_slack = -1;
   c->precond_cutoff = 0.0;
   c->precond_iters = 4;
+  c->scf_relax = 0.0;
 }
 
 pfmm_status pfmm_create(const pfmm_config* cfg, pfmm_handle** out) {

@@ -75,9 +75,10 @@ void launch_cell_counts(const int* cfirst, int off_l, int ncell_l, int n, int* c
 void launch_colleagues(const uint64_t* ckey, int off_l, int ncell_l, int l, int ws, int* coll,
                        hipStream_t s);
 // stats[0] += M2L pairs with a source, stats[1] += ordered near-field particle pairs,
-// stats[2] += useful M2L flops (2 C(q+6, 6) per pair of truncation order q = dorder[slot])
+// stats[2] += useful M2L flops (2 C(q+6, 6) per pair of truncation order q = dorder[slot]),
+// stats[3 + c] += the same flops with every order capped at c, c = 0 .. p
 void launch_tree_stats(const TreeView& t, const int* m2l_code, const unsigned char* dorder, int noff,
-                       unsigned long long* stats, hipStream_t s);
+                       int p, unsigned long long* stats, hipStream_t s);
 
 // ---------------------------------------------------------------- expansions.hip
 struct OpTables {
@@ -114,8 +115,10 @@ int m2l_tiles(const TreeView& t, int lp_lo, int lp_hi, int ncb = 1);
 // Split s of the colleague-offset range writes its partial F~ at F + s * split_stride (s = 0: F
 // itself); the downward pass (launch_l2l) adds the partials of splits 1.. to F.  On the mixed path,
 // targets at levels <= fp64_max_level still run in float64.
+// qcap (device, may be NULL): every offset's order is capped at *qcap.
 void launch_m2l(const TreeView& t, const OpTables& op, int nsplit, const double* M, double* F,
-                int64_t split_stride, bool fp32, int fp64_max_level, const int* done, hipStream_t s);
+                int64_t split_stride, bool fp32, int fp64_max_level, const int* done, const int* qcap,
+                hipStream_t s);
 
 // ---------------------------------------------------------------- p2p.hip
 // mode 0: dipole sources, Ed only (added); mode 1: full outputs (added) from charges and/or dipoles
@@ -130,6 +133,15 @@ void launch_p2p(const TreeView& t, const Particles& pa, const double4* mu4, int 
 struct CGState {
   double rr, pAp, a, b, bnorm2, res, res_true, res_max;
   int done, iters, notspd, maxed;
+  int qcap;      // M2L order cap of the next field evaluation (relaxed solve)
+  int ncap[16];  // field evaluations of the solve per order cap (not reset by the init kernels)
+};
+// Relaxed field evaluations of the outer solve: after each update with relative residual r >= 0,
+// qcap = max(qmin, p - floor(ln(start / r) / lrho)) when r < start; track = 0 leaves qcap and ncap
+// alone (inner solves).
+struct RelaxParams {
+  int p = 0, qmin = 0, track = 0;
+  double start = 0.0, lrho = 1.0;
 };
 constexpr int RED_BLOCKS = 512;   // partial sums per reduction
 void launch_cg_init(const Particles& pa, const double* Eq, const double4* mu_warm, bool warm,
@@ -142,7 +154,8 @@ void launch_make_dipoles(const Particles& pa, const double* v, double4* mu4, con
 void launch_cg_ap(const Particles& pa, const double* pvec, const double* E, double* Ap, double* part,
                   CGState* st, hipStream_t s);
 void launch_cg_update(const Particles& pa, double* y, double* r, const double* pvec, const double* Ap,
-                      double* part, CGState* st, double tol, int max_iter, hipStream_t s);
+                      double* part, CGState* st, double tol, int max_iter, hipStream_t s,
+                      const RelaxParams& rp = RelaxParams());
 void launch_cg_direction(int n3, const double* r, double* pvec, const CGState* st, hipStream_t s);
 // cold start y0 = 0, r0 = S E^q (no field evaluation)
 void launch_cg_init_zero(const Particles& pa, const double* Eq, double* y, double* r, double* part,

@@ -163,8 +163,9 @@ constexpr int m2l_waves_per_eu() { return 2; }
 template <int P, bool F32>
 __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(m2l_waves_per_eu<P, F32>()))) void k_m2l(TreeView t, OpTables op, int lp_lo, int lp_hi, int nsplit,
                                              const double* __restrict__ M, double* __restrict__ F,
-                                             int64_t split_stride, const int* done) {
+                                             int64_t split_stride, const int* done, const int* qcap) {
   if (done && *done) return;
+  const int qc = qcap ? *qcap : P;  // order cap of a relaxed evaluation
   using kt = typename std::conditional<F32, float, double>::type;
   using kt2 = typename std::conditional<F32, float2, double2>::type;
   using acc_t = typename std::conditional<F32, f4, d4>::type;
@@ -310,7 +311,7 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(m2l_waves_p
       if (max(abs(d0), max(abs(d1), abs(d2))) > ws) {
         // D_k(d) for |k| <= q(d), zero above: the M2L truncated at order q(d)
         const int slot = ((d0 + R) * cube + (d1 + R)) * cube + (d2 + R);
-        const int q = op.dorder[slot];
+        const int q = min((int)op.dorder[slot], qc);
         sD[e] = k < mi_count(q) ? dtab[(int64_t)slot * DP + k] : (kt)0;
         if (k == 0) sQ[v] = q;
       }
@@ -402,7 +403,8 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(m2l_waves_p
 
 template <int P>
 void m2l_dispatch(const TreeView& t, const OpTables& op, int nsplit, const double* M, double* F,
-                  int64_t split_stride, bool fp32, int fp64_max_level, const int* done, hipStream_t s) {
+                  int64_t split_stride, bool fp32, int fp64_max_level, const int* done, const int* qcap,
+                  hipStream_t s) {
   // parents of levels [1, L - 1]; float64 for targets at levels <= fp64_max_level on the mixed path
   const int lo = 1, hi = t.L - 1;
   const int hi64 = fp32 ? std::min(hi, fp64_max_level - 1) : hi;
@@ -410,7 +412,7 @@ void m2l_dispatch(const TreeView& t, const OpTables& op, int nsplit, const doubl
     const int nt = m2l_tiles(t, lo, hi64, m2l_ncb<P, false>());
     if (nt > 0)
       hipLaunchKernelGGL((k_m2l<P, false>), dim3(nt * nsplit), dim3(TPB), 0, s, t, op, lo, hi64, nsplit,
-                         M, F, split_stride, done);
+                         M, F, split_stride, done, qcap);
   }
   if (fp32) {
     const int lo32 = std::max(lo, hi64 + 1);
@@ -418,7 +420,7 @@ void m2l_dispatch(const TreeView& t, const OpTables& op, int nsplit, const doubl
       const int nt = m2l_tiles(t, lo32, hi, m2l_ncb<P, true>());
       if (nt > 0)
         hipLaunchKernelGGL((k_m2l<P, true>), dim3(nt * nsplit), dim3(TPB), 0, s, t, op, lo32, hi, nsplit,
-                           M, F, split_stride, done);
+                           M, F, split_stride, done, qcap);
     }
   }
 }
@@ -433,14 +435,15 @@ int m2l_tiles(const TreeView& t, int lp_lo, int lp_hi, int ncb) {
 }
 
 void launch_m2l(const TreeView& t, const OpTables& op, int nsplit, const double* M, double* F,
-                int64_t split_stride, bool fp32, int fp64_max_level, const int* done, hipStream_t s) {
+                int64_t split_stride, bool fp32, int fp64_max_level, const int* done, const int* qcap,
+                hipStream_t s) {
   if (t.L < 2) return;
   if (nsplit < 1 || nsplit > t.nnear) throw Error(PFMM_ERR_INVALID_ARG, "internal: M2L split out of range");
   if (fp32 && !op.dvec32) throw Error(PFMM_ERR_INVALID_ARG, "internal: float32 M2L tables missing");
   switch (op.p) {
 #define PFMM_M2L_CASE(PP)                                                                          \
   case PP:                                                                                         \
-    m2l_dispatch<PP>(t, op, nsplit, M, F, split_stride, fp32, fp64_max_level, done, s);            \
+    m2l_dispatch<PP>(t, op, nsplit, M, F, split_stride, fp32, fp64_max_level, done, qcap, s);      \
     break;
     PFMM_M2L_CASE(1) PFMM_M2L_CASE(2) PFMM_M2L_CASE(3) PFMM_M2L_CASE(4) PFMM_M2L_CASE(5)
     PFMM_M2L_CASE(6) PFMM_M2L_CASE(7) PFMM_M2L_CASE(8) PFMM_M2L_CASE(9) PFMM_M2L_CASE(10)

@@ -216,7 +216,7 @@ __global__ __launch_bounds__(TPB) void k_cg_update(Particles pa, double* __restr
 }
 
 __global__ __launch_bounds__(TPB) void k_cg_update_finish(const double* part, int nblk, CGState* st,
-                                                          double tol, int max_iter) {
+                                                          double tol, int max_iter, RelaxParams rp) {
   if (st->done) return;
   double o[2];
   finish_sum<2>(part, nblk, o);
@@ -225,6 +225,17 @@ __global__ __launch_bounds__(TPB) void k_cg_update_finish(const double* part, in
     st->rr = o[0];
     st->iters += 1;
     st->res = st->bnorm2 > 0.0 ? sqrt(o[1] / st->bnorm2) : 0.0;
+    if (rp.track) {
+      // the evaluation of this iteration used st->qcap; choose the cap of the next one
+      const int used = st->qcap;
+      if (used >= 0 && used < 16) st->ncap[used] += 1;
+      int q = rp.p;
+      if (rp.start > 0.0 && st->res < rp.start) {
+        const double lower = st->res > 0.0 ? floor(log(rp.start / st->res) / rp.lrho) : (double)rp.p;
+        q = lower >= (double)(rp.p - rp.qmin) ? rp.qmin : rp.p - (int)lower;
+      }
+      st->qcap = q;
+    }
     if (st->res <= tol) st->done = 1;
     else if (st->iters >= max_iter) { st->maxed = 1; st->done = 1; }
   }
@@ -510,10 +521,11 @@ void launch_cg_ap(const Particles& pa, const double* pvec, const double* E, doub
 }
 
 void launch_cg_update(const Particles& pa, double* y, double* r, const double* pvec, const double* Ap,
-                      double* part, CGState* st, double tol, int max_iter, hipStream_t s) {
+                      double* part, CGState* st, double tol, int max_iter, hipStream_t s,
+                      const RelaxParams& rp) {
   const int g = grid(pa.n);
   hipLaunchKernelGGL(k_cg_update, dim3(g), dim3(TPB), 0, s, pa, y, r, pvec, Ap, part, st);
-  hipLaunchKernelGGL(k_cg_update_finish, dim3(1), dim3(TPB), 0, s, part, g, st, tol, max_iter);
+  hipLaunchKernelGGL(k_cg_update_finish, dim3(1), dim3(TPB), 0, s, part, g, st, tol, max_iter, rp);
   PFMM_LAUNCH_CHECK();
 }
 

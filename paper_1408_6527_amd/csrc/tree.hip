@@ -195,11 +195,16 @@ __global__ __launch_bounds__(TPB) void k_colleagues(const uint64_t* __restrict__
 
 // stats[0] += M2L pairs with a non-empty source; stats[1] += ordered near-field particle pairs;
 // stats[2] += useful M2L flops, 2 C(q+6, 6) per pair at its truncation order q.
+__device__ __forceinline__ unsigned long long m2l_pair_flops(unsigned long long q) {
+  return 2 * ((q + 1) * (q + 2) * (q + 3) * (q + 4) * (q + 5) * (q + 6) / 720);
+}
+
 __global__ __launch_bounds__(TPB) void k_tree_stats(TreeView t, const int* __restrict__ m2l_code,
-                                                    const unsigned char* __restrict__ dorder, int noff,
+                                                    const unsigned char* __restrict__ dorder, int noff, int p,
                                                     unsigned long long* stats) {
   const int first2 = t.L >= 2 ? t.off[2] : t.ncell;
   unsigned long long m2l = 0, p2p = 0, flops = 0;
+  unsigned long long fcap[11] = {};  // p <= 10
   for (int g = blockIdx.x * TPB + threadIdx.x; g < t.ncell; g += gridDim.x * TPB) {
     if (g >= first2) {
       const int oct = (int)(t.key[g] & 7);
@@ -210,7 +215,10 @@ __global__ __launch_bounds__(TPB) void k_tree_stats(TreeView t, const int* __res
         if (pc >= 0 && t.child8[8 * pc + ((code >> 20) & 7)] >= 0) {
           ++m2l;
           const unsigned long long q = dorder[code & 0xfff];
-          flops += 2 * ((q + 1) * (q + 2) * (q + 3) * (q + 4) * (q + 5) * (q + 6) / 720);
+          flops += m2l_pair_flops(q);
+#pragma unroll
+          for (int c = 0; c <= 10; ++c)
+            if (c <= p) fcap[c] += m2l_pair_flops(q < (unsigned long long)c ? q : (unsigned long long)c);
         }
       }
     }
@@ -226,6 +234,9 @@ __global__ __launch_bounds__(TPB) void k_tree_stats(TreeView t, const int* __res
   if (m2l) atomicAdd(&stats[0], m2l);
   if (p2p) atomicAdd(&stats[1], p2p);
   if (flops) atomicAdd(&stats[2], flops);
+#pragma unroll
+  for (int c = 0; c <= 10; ++c)
+    if (c <= p && fcap[c]) atomicAdd(&stats[3 + c], fcap[c]);
 }
 
 }  // namespace
@@ -320,8 +331,9 @@ void launch_colleagues(const uint64_t* ckey, int off_l, int ncell_l, int l, int 
 }
 
 void launch_tree_stats(const TreeView& t, const int* m2l_code, const unsigned char* dorder, int noff,
-                       unsigned long long* stats, hipStream_t s) {
-  hipLaunchKernelGGL(k_tree_stats, dim3(grid_for(t.ncell)), dim3(TPB), 0, s, t, m2l_code, dorder, noff,
+                       int p, unsigned long long* stats, hipStream_t s) {
+  if (p < 0 || p > 10) throw Error(PFMM_ERR_INVALID_ARG, "internal: order out of range in tree stats");
+  hipLaunchKernelGGL(k_tree_stats, dim3(grid_for(t.ncell)), dim3(TPB), 0, s, t, m2l_code, dorder, noff, p,
                      stats);
   PFMM_LAUNCH_CHECK();
 }

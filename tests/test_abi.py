@@ -45,11 +45,13 @@ def test_status_strings_and_defaults(lib):
     lib.pfmm_config_default(ctypes.byref(c))
     assert (c.order_p, c.ws, c.precision, c.scf_max_iter) == (6, 2, 0, 200)
     assert c.scf_tol == 1e-6 and c.thole_a == 2.0 and c.coulomb_k == 332.06371
+    assert (c.m2l_order_slack, c.precond_cutoff, c.precond_iters, c.scf_relax) == (-1, 0.0, 4, 0.0)
 
 
 @pytest.mark.parametrize("field,value", [("order_p", 0), ("order_p", 11), ("ws", 3), ("precision", 5),
                                          ("scf_tol", 0.0), ("scf_max_iter", 0), ("thole_a", -1.0),
-                                         ("leaf_width", -2.0)])
+                                         ("leaf_width", -2.0), ("m2l_order_slack", -2),
+                                         ("precond_cutoff", -1.0), ("scf_relax", -0.1), ("scf_relax", 1.0)])
 def test_create_rejects_bad_config(lib, field, value):
     from paper_1408_6527_amd import _lib
     c = _lib.Config()
@@ -64,3 +66,30 @@ def test_null_handle_is_rejected(lib):
     lib.pfmm_solve.restype = ctypes.c_int
     assert lib.pfmm_solve(None, 0, None, None, None, None, None, None, None, None) == 1
     lib.pfmm_destroy(None)
+
+
+def test_struct_layout_matches_header(tmp_path):
+    """The ctypes mirrors of pfmm_config and pfmm_result have the C layout of include/pfmm.h: every
+    field at the same offset, the same total size (checked with the host C compiler)."""
+    import shutil
+    import subprocess
+    from paper_1408_6527_amd import _lib
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "pfmm.h"', "int main(void) {"]
+    for cname, cls in [("pfmm_config", _lib.Config), ("pfmm_result", _lib.Result)]:
+        lines.append(f'  printf("{cname} sizeof %zu\\n", sizeof({cname}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines.append("  return 0;\n}")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, cls in [("pfmm_config", _lib.Config), ("pfmm_result", _lib.Result)]:
+        assert got[(cname, "sizeof")] == ctypes.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert got[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)

@@ -360,6 +360,44 @@ def test_preconditioned_graph_determinism_and_warm_start(api):
     assert relnorm(N(rw.mu), N(r0.mu)) < 1e-8
 
 
+def test_relaxed_solve_meets_full_order_rule(api):
+    """Relaxed field evaluations (scf_relax): the late iterations of the dipole solve run with capped
+    M2L orders, the stopping rule holds for the final dipoles at the full orders, the answer matches
+    the unrelaxed solve to within the solver tolerance, with less M2L work, and graph replays and
+    plain launches agree bitwise."""
+    print_case("relaxed solve")
+    X, q, a, _ = cube(2000, 20.0, 3)
+    kw = dict(order_p=10, ws=2, leaf_width=1.7, scf_tol=1e-6, precond_cutoff=2.5, precond_iters=3,
+              m2l_order_slack=2)
+    r0 = api.Solver(**kw).solve(T(X), T(q), T(a))
+    r1 = api.Solver(scf_relax=1e-3, **kw).solve(T(X), T(q), T(a))
+    r2 = api.Solver(scf_relax=1e-3, graph_iters=0, **kw).solve(T(X), T(q), T(a))
+    assert r0.stats["m2l_order_cap_min"] == 10 and r0.stats["scf_restarts"] == 0
+    assert r0.stats["m2l_flops_total"] == r0.stats["n_evals"] * r0.stats["m2l_flops"]
+    assert r1.stats["scf_restarts"] == 0 and 5 <= r1.stats["m2l_order_cap_min"] < 10
+    assert r1.residual <= 1e-6 and r1.iters <= r0.iters + 1
+    assert r1.stats["m2l_flops_total"] < 0.9 * r0.stats["m2l_flops_total"]
+    assert relnorm(N(r1.mu), N(r0.mu)) < 1e-6
+    assert relnorm(N(r1.forces), N(r0.forces)) < 1e-6
+    assert r2.iters == r1.iters
+    assert np.array_equal(N(r1.mu), N(r2.mu)) and np.array_equal(N(r1.forces), N(r2.forces))
+
+
+def test_relaxed_solve_continues_when_final_check_fails(api):
+    """With a relaxation start far above what the tolerance allows, the final full-order check fails
+    and the solve continues from the final dipoles without the cap: one continuation, the stopping
+    rule met, the unrelaxed answer to within the tolerance."""
+    print_case("relaxed solve, continuation")
+    X, q, a, _ = cube(2000, 20.0, 3)
+    kw = dict(order_p=8, ws=2, leaf_width=1.7, scf_tol=1e-7, precond_cutoff=2.5, precond_iters=3,
+              m2l_order_slack=1)
+    r0 = api.Solver(**kw).solve(T(X), T(q), T(a))
+    r1 = api.Solver(scf_relax=1e-2, **kw).solve(T(X), T(q), T(a))
+    assert r1.stats["scf_restarts"] == 1 and r1.stats["m2l_order_cap_min"] < 8
+    assert r1.residual <= 1e-7
+    assert relnorm(N(r1.mu), N(r0.mu)) < 1e-6
+
+
 def test_preconditioned_edge_cases(api):
     """Zero polarisabilities (the scaled system is the identity there), a single particle, two
     particles, and a cutoff beyond the leaf edge all converge with the preconditioner."""
