@@ -171,6 +171,7 @@ struct pfmm_handle {
   TreeView tv;
   Particles pa;
   int m2l_tiles = 0, nsplit = 1;
+  int n_cu = 0;  // compute units of the device (M2L workgroup rounds)
   int64_t split_stride = 0;
   int64_t n_m2l = 0, n_p2p = 0, m2l_flops = 0;
   int64_t m2l_flops_cap[11] = {};  // useful M2L flops per evaluation with every order capped at c
@@ -226,6 +227,8 @@ void validate_config(const pfmm_config* c) {
 void build_tree(pfmm_handle* h, int n, const double* pos, const double* q, const double* alpha,
                 hipStream_t s) {
   const pfmm_config& c = h->cfg;
+  PFMM_HIP(hipGetDevice(&h->device));
+  PFMM_HIP(hipDeviceGetAttribute(&h->n_cu, hipDeviceAttributeMultiprocessorCount, h->device));
   const int nblk = std::min(1024, std::max(1, (n + 255) / 256));
   double* partial = dev<double>(h->w_partial, (int64_t)nblk * NRED);
   int* flags = dev<int>(h->w_flags, 4);
@@ -350,14 +353,26 @@ void build_tree(pfmm_handle* h, int n, const double* pos, const double* q, const
   h->n_p2p = (int64_t)st[1];
   h->m2l_flops = (int64_t)st[2];
   for (int c = 0; c <= 10; ++c) h->m2l_flops_cap[c] = c <= h->op.p ? (int64_t)st[3 + c] : 0;
-  // enough workgroups to fill the device: split each parent tile's colleague offsets when tiles are
-  // few (at least 4 offsets per split, so that staging the index table stays a small share)
-  h->m2l_tiles = L >= 2 ? m2l_tiles(t, 1, L - 1, 2) : 0;  // workgroups of 32 parents
+  // Split each parent tile's colleague offsets over nsplit workgroups (one per CU at a time).  The
+  // launch takes ceil(tiles * nsplit / CUs) rounds of workgroups, each 1/nsplit of a tile's work,
+  // plus a fixed cost per round (staging the index table, the first offset's loads): choose the
+  // nsplit that minimises rounds / nsplit + 0.004 rounds, with at least one round of workgroups and
+  // at least 4 offsets per split.
+  h->m2l_tiles = L >= 2 ? m2l_tiles(t, 1, L - 1, m2l_tile_ncb(c.order_p, c.precision == PFMM_MIXED)) : 0;
   h->nsplit = 1;
   if (h->m2l_tiles > 0) {
-    const int want_wg = 2048;
-    h->nsplit = std::max(1, std::min(32, (want_wg + h->m2l_tiles - 1) / h->m2l_tiles));
-    h->nsplit = std::min(h->nsplit, std::max(1, t.nnear / 4));
+    const int64_t T = h->m2l_tiles, C = std::max(1, h->n_cu);
+    const int hi = std::max(1, std::min(32, t.nnear / 4));
+    const int lo = (int)std::min<int64_t>(hi, std::max<int64_t>(1, (C + T - 1) / T));
+    double best = 0.0;
+    for (int ns = lo; ns <= hi; ++ns) {
+      const int64_t rounds = (T * ns + C - 1) / C;
+      const double cost = (double)rounds / ns + 0.004 * (double)rounds;
+      if (ns == lo || cost < best - 1e-12) {
+        best = cost;
+        h->nsplit = ns;
+      }
+    }
   }
   // expansions (one extra zero row serves empty M2L sources); F holds nsplit partial copies
   const int64_t rows = (int64_t)ncell + 1;

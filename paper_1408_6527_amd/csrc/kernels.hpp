@@ -112,6 +112,8 @@ void launch_l2p(const TreeView& t, const OpTables& op, const Particles& pa, cons
 // Targets are the cells of levels >= 2, taken as the children of 16-parent tiles; a launch covers
 // the parents of levels [lp_lo, lp_hi].  Workgroup tiles of 16 ncb parents over those levels:
 int m2l_tiles(const TreeView& t, int lp_lo, int lp_hi, int ncb = 1);
+// 16-parent tiles per M2L workgroup for order p on the float64 or float32 path
+int m2l_tile_ncb(int p, bool fp32);
 // Split s of the colleague-offset range writes its partial F~ at F + s * split_stride (s = 0: F
 // itself); the downward pass (launch_l2l) adds the partials of splits 1.. to F.  On the mixed path,
 // targets at levels <= fp64_max_level still run in float64.

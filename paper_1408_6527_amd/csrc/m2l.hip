@@ -427,6 +427,18 @@ void m2l_dispatch(const TreeView& t, const OpTables& op, int nsplit, const doubl
 
 }  // namespace
 
+int m2l_tile_ncb(int p, bool fp32) {
+  switch (p) {
+#define PFMM_NCB_CASE(PP) \
+  case PP:                \
+    return fp32 ? m2l_ncb<PP, true>() : m2l_ncb<PP, false>();
+    PFMM_NCB_CASE(1) PFMM_NCB_CASE(2) PFMM_NCB_CASE(3) PFMM_NCB_CASE(4) PFMM_NCB_CASE(5)
+    PFMM_NCB_CASE(6) PFMM_NCB_CASE(7) PFMM_NCB_CASE(8) PFMM_NCB_CASE(9) PFMM_NCB_CASE(10)
+#undef PFMM_NCB_CASE
+    default: throw Error(PFMM_ERR_INVALID_ARG, "order_p out of range");
+  }
+}
+
 int m2l_tiles(const TreeView& t, int lp_lo, int lp_hi, int ncb) {
   int n = 0;
   for (int lp = std::max(lp_lo, 0); lp <= lp_hi && lp < t.L; ++lp)
