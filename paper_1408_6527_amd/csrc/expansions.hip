@@ -244,10 +244,22 @@ __global__ __launch_bounds__(L2P_TPB) void k_l2p(TreeView t, OpTables op, Partic
   if (done && *done) return;
   __shared__ double sF[MAX_NC];
   __shared__ double pw[3][MAX_P + 1][L2P_TPB];
+  // the per-coefficient table, packed, and 1/k!: read from LDS (a broadcast per slice) rather
+  // than from global memory in the inner loop
+  __shared__ int4 sT[MAX_NC];    // nx | ny << 8 | nz << 16 | deg << 24, e_x | e_y << 16, e_z | ee_xx << 16, ee_yy | ee_zz << 16
+  __shared__ int2 sU[MAX_NC];    // ee_xy | ee_xz << 16, ee_yz
+  __shared__ double sIF[MAX_NC];
   const int g = t.off[t.L] + blockIdx.x;
   const int first = t.first[g], cnt = t.count[g];
   const int p = op.p, nc = op.nc;
-  for (int k = threadIdx.x; k < nc; k += L2P_TPB) sF[k] = F[(int64_t)g * op.stride + k];
+  for (int k = threadIdx.x; k < nc; k += L2P_TPB) {
+    sF[k] = F[(int64_t)g * op.stride + k];
+    const int* tk = op.l2p_tab + 16 * k;
+    sT[k] = make_int4(tk[0] | (tk[1] << 8) | (tk[2] << 16) | (tk[3] << 24), tk[4] | (tk[5] << 16),
+                      tk[6] | (tk[7] << 16), tk[8] | (tk[9] << 16));
+    sU[k] = make_int2(tk[10] | (tk[11] << 16), tk[12]);
+    sIF[k] = op.inv_fact[k];
+  }
   double c[3], w;
   cell_centre(t, g, t.L, c, w);
   const double iw = 1.0 / w;
@@ -273,21 +285,23 @@ __global__ __launch_bounds__(L2P_TPB) void k_l2p(TreeView t, OpTables op, Partic
     double phi = 0.0, ex = 0.0, ey = 0.0, ez = 0.0;
     double gxx = 0.0, gyy = 0.0, gzz = 0.0, gxy = 0.0, gxz = 0.0, gyz = 0.0;
     for (int k = slice; k < nc; k += G) {
-      const int* tk = op.l2p_tab + 16 * k;
-      const int deg = tk[3];
-      const double m = pw[0][tk[0]][slot] * pw[1][tk[1]][slot] * pw[2][tk[2]][slot] * op.inv_fact[k];
+      const int4 tk = sT[k];
+      const int deg = (tk.x >> 24) & 0xff;
+      const double m = pw[0][tk.x & 0xff][slot] * pw[1][(tk.x >> 8) & 0xff][slot] *
+                       pw[2][(tk.x >> 16) & 0xff][slot] * sIF[k];
       phi += m * sF[k];
       if (deg <= p - 1) {
-        ex -= m * sF[tk[4]];
-        ey -= m * sF[tk[5]];
-        ez -= m * sF[tk[6]];
+        ex -= m * sF[tk.y & 0xffff];
+        ey -= m * sF[tk.y >> 16];
+        ez -= m * sF[tk.z & 0xffff];
         if (mode == 1 && deg <= p - 2) {
-          gxx -= m * sF[tk[7]];
-          gyy -= m * sF[tk[8]];
-          gzz -= m * sF[tk[9]];
-          gxy -= m * sF[tk[10]];
-          gxz -= m * sF[tk[11]];
-          gyz -= m * sF[tk[12]];
+          const int2 tu = sU[k];
+          gxx -= m * sF[tk.z >> 16];
+          gyy -= m * sF[tk.w & 0xffff];
+          gzz -= m * sF[tk.w >> 16];
+          gxy -= m * sF[tu.x & 0xffff];
+          gxz -= m * sF[tu.x >> 16];
+          gyz -= m * sF[tu.y];
         }
       }
     }
