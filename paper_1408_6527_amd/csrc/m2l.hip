@@ -5,21 +5,22 @@
 // K_d[n][m] = D_{n+m}(d) is fixed by the vector of C(p + 3, 3) derivatives D_k(d), |k| <= p.
 //
 // Work unit: a tile of 16 parents on one level (the 16 columns of the MFMA tiles) and their
-// children, one wave per child octant (8 waves).  A target B = 2 P + oB meets its sources
+// children, in 8 waves: each wave computes the targets of one pair of child octants for one half of
+// the row blocks of F~ (schedule.hpp, sched_halves).  A target B = 2 P + oB meets its sources
 // A = 2 (P + e) + c, the children of P's colleagues P + e, at d = oB - c - 2 e whenever the
-// Chebyshev norm of d exceeds ws.  For one colleague offset e and one source octant c, the 16
-// source expansions are the same rows for all eight target octants, so the workgroup stages them
-// in LDS once (coalesced row loads) and every wave multiplies them by its own K_d:
+// Chebyshev norm of d exceeds ws.  For one colleague offset e and one source octant c (a slot), the
+// 16 source expansions are the same rows for all eight target octants, so the workgroup stages them
+// in LDS once (coalesced row loads) and every wave multiplies them by the K_d of its octants:
 //   for e in the split's share of colleague offsets:
 //     stage D(d) for the 27 offsets d = u - 2 e, u = oB - c in [-1, 1]^3
-//     for c in octants: stage the 16 source rows; each wave o with |d| > ws runs the
-//       degree-blocked MFMA schedule (schedule.hpp): A = K_d entries gathered from the LDS copy
-//       of D(d) through the index table, B = source coefficients from LDS.
-// With a per-offset truncation order q(d) <= p (m2l_order_slack >= 0) a wave runs the unrolled
-// schedule of its q: the blocks of the order-p schedule that hold entries of degree <= q, reading a
-// copy of D(d) whose entries above degree q are zero.
-// Accumulators stay in registers for the whole loop and each target's (partial) F~ is written once:
-// no atomics, deterministic.
+//     for c in octants: stage the 16 source rows; each wave runs, for each octant of its pair
+//       with |d| > ws, its half of the degree-blocked MFMA schedule: A = K_d entries gathered from
+//       the LDS copy of D(d) through the index table, B = source coefficients from LDS.
+// With a per-offset truncation order q(d) <= p (m2l_order_slack >= 0, or a cap set by a relaxed
+// dipole solve) a wave runs the unrolled schedule of that q: the blocks of the order-p schedule
+// that hold entries of degree <= q, reading a copy of D(d) whose entries above degree q are zero.
+// Accumulators stay in registers for the whole loop and each target's (partial) F~ is written once
+// (the two halves' shares of row block 0 are added through LDS first): no atomics, deterministic.
 //
 // FP64 path: v_mfma_f64_16x16x4f64.  Mixed path: v_mfma_f32_16x16x4f32 with float32 operands and
 // float32 accumulation, except for targets at levels <= fp64_max_level.
@@ -37,7 +38,7 @@ namespace {
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-constexpr int TPB = 512;  // 8 waves, one per target octant
+constexpr int TPB = 512;  // 8 waves: 4 octant pairs x 2 row halves
 constexpr int NU = 27;    // u = oB - c in [-1, 1]^3
 
 // The blocks of the order-P schedule (schedule.hpp) that a truncation at order Q <= P needs (rows
@@ -156,7 +157,7 @@ __device__ __forceinline__ void m2l_slot(int q, const kt* Dv, const kt* Bp, cons
     m2l_mfma_order<P, F32, NCB, H, kt, kt2, acc_t>(q, std::make_integer_sequence<int, P>{}, Dv, Bp, sH, lane, acc);
 }
 
-// registers per lane: 4 waves per SIMD (two workgroups per CU) only where they fit
+// registers per lane: 2 waves per SIMD, one workgroup per CU
 template <int P, bool F32>
 constexpr int m2l_waves_per_eu() { return 2; }
 
