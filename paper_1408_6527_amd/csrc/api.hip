@@ -155,7 +155,7 @@ struct pfmm_handle {
   // particles
   DevBuf w_P, w_al, w_sqa, w_tau, w_itau, w_mu4;
   // expansions
-  DevBuf w_M, w_F;
+  DevBuf w_M, w_F, w_M32;
   // fields (sorted order)
   DevBuf f_phiq, f_Eq, f_Eq2, f_Gq, f_phim, f_Eum, f_Edm, f_Gm, f_E;
   // solver
@@ -379,6 +379,7 @@ void build_tree(pfmm_handle* h, int n, const double* pos, const double* q, const
   h->split_stride = rows * h->op.stride;
   double* M = dev<double>(h->w_M, rows * h->op.stride);
   dev<double>(h->w_F, rows * h->op.stride * h->nsplit);
+  if (c.precision == PFMM_MIXED) dev<float>(h->w_M32, rows * h->op.stride);
   launch_fill_double(M + (int64_t)ncell * h->op.stride, h->op.stride, 0.0, s);
   h->n_evals = 0;
 }
@@ -403,7 +404,12 @@ void fmm_pass(pfmm_handle* h, int sources, int mode, FieldOut out, int* err, con
     for (int lp = t.L - 1; lp >= 2; --lp) launch_m2m(t, op, lp, M, done, s);
     kt.end(KC_M2M, e);
     e = kt.begin();
-    launch_m2l(t, op, h->nsplit, M, F, h->split_stride, fp32, 3, done, qcap, s);
+    float* M32 = nullptr;
+    if (fp32) {
+      M32 = h->w_M32.as<float>();
+      launch_to_float(M, M32, ((int64_t)t.ncell + 1) * op.stride, done, s);
+    }
+    launch_m2l(t, op, h->nsplit, M, M32, F, h->split_stride, fp32, 3, done, qcap, s);
     kt.end(KC_M2L, e);
     e = kt.begin();
     for (int lc = 2; lc <= t.L; ++lc) launch_l2l(t, op, lc, F, h->nsplit, h->split_stride, done, s);

@@ -117,10 +117,12 @@ int m2l_tile_ncb(int p, bool fp32);
 // Split s of the colleague-offset range writes its partial F~ at F + s * split_stride (s = 0: F
 // itself); the downward pass (launch_l2l) adds the partials of splits 1.. to F.  On the mixed path,
 // targets at levels <= fp64_max_level still run in float64.
-// qcap (device, may be NULL): every offset's order is capped at *qcap.
-void launch_m2l(const TreeView& t, const OpTables& op, int nsplit, const double* M, double* F,
-                int64_t split_stride, bool fp32, int fp64_max_level, const int* done, const int* qcap,
-                hipStream_t s);
+// qcap (device, may be NULL): every offset's order is capped at *qcap.  M32: float32 copy of M,
+// read by the float32 launches of the mixed path (launch_to_float).
+void launch_m2l(const TreeView& t, const OpTables& op, int nsplit, const double* M, const float* M32,
+                double* F, int64_t split_stride, bool fp32, int fp64_max_level, const int* done,
+                const int* qcap, hipStream_t s);
+void launch_to_float(const double* in, float* out, int64_t count, const int* done, hipStream_t s);
 
 // ---------------------------------------------------------------- p2p.hip
 // mode 0: dipole sources, Ed only (added); mode 1: full outputs (added) from charges and/or dipoles

@@ -89,11 +89,11 @@ struct BlockOrder {
 // 16-parent tiles per workgroup: every K_d entry gathered from LDS feeds NCB MFMAs.  Bounded by
 // the accumulator registers (NCB x NRB tiles of 16 x 16) and the LDS of the staged sources.
 template <int P, bool F32>
-constexpr int m2l_ncb() { return (F32 ? P <= 8 : P <= 7) ? 2 : 1; }
+constexpr int m2l_ncb() { return (F32 ? P <= 10 : P <= 7) ? 2 : 1; }
 
 // (a shorter distance where the float64 accumulators leave fewer registers)
 template <int P, bool F32>
-constexpr int m2l_dg() { return F32 ? 6 : (P == 9 ? 2 : (P >= 10 || m2l_ncb<P, F32>() > 1 ? 3 : 4)); }
+constexpr int m2l_dg() { return F32 ? (P >= 9 ? 3 : 6) : (P == 9 ? 2 : (P >= 10 || m2l_ncb<P, F32>() > 1 ? 3 : 4)); }
 
 // One slot of one wave at truncation order Q: A = K_d entries gathered from the staged D(d) at Dv
 // through the index table sH, B = the staged source coefficients at Bp.  The staged D(d) holds zeros
@@ -163,7 +163,8 @@ constexpr int m2l_waves_per_eu() { return 2; }
 
 template <int P, bool F32>
 __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(m2l_waves_per_eu<P, F32>()))) void k_m2l(TreeView t, OpTables op, int lp_lo, int lp_hi, int nsplit,
-                                             const double* __restrict__ M, double* __restrict__ F,
+                                             const double* __restrict__ M, const float* __restrict__ M32,
+                                             double* __restrict__ F,
                                              int64_t split_stride, const int* done, const int* qcap) {
   if (done && *done) return;
   const int qc = qcap ? *qcap : P;  // order cap of a relaxed evaluation
@@ -182,6 +183,8 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(m2l_waves_p
   constexpr int NBLK = sched_nblocks(P);
   constexpr int ROWS = 16 * NCB;
   constexpr int PF = (ROWS * HALF + TPB - 1) / TPB;  // 16-byte source pieces per thread and slot
+  constexpr int QUART = STRIDE / 4;                   // 16-byte pieces of a float32 source row
+  constexpr int PF4 = (ROWS * QUART + TPB - 1) / TPB;
   __shared__ uint4 sHv[NBLK * 8];  // K-entry index table, 64 16-bit indices per block
   __shared__ kt sD[NU * DP];
   __shared__ int sQ[NU];  // truncation order of the 27 staged offsets
@@ -247,31 +250,58 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(m2l_waves_p
     }
 
   // source rows pass through registers: loaded from global memory one slot before they are stored
-  // to LDS, and stored one slot before they are read
-  double2 pre[PF];
+  // to LDS, and stored one slot before they are read.  The float32 path reads the float32 copy of
+  // the multipoles (half the registers and bytes of the float64 rows).
+  double2 pre[F32 ? 1 : PF];
+  float4 pre4[F32 ? PF4 : 1];
   auto prefetch = [&](int r) {
+    if constexpr (F32) {
 #pragma unroll
-    for (int i = 0; i < PF; ++i) {
-      const int e = threadIdx.x + i * TPB;
-      double2 v = make_double2(0.0, 0.0);
-      if (e < ROWS * HALF) {
-        const int row = e / HALF, h = e - row * HALF;
-        const int src = sSrc[r][row];
-        if (src >= 0) v = reinterpret_cast<const double2*>(M + (int64_t)src * STRIDE)[h];
+      for (int i = 0; i < PF4; ++i) {
+        const int e = threadIdx.x + i * TPB;
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (e < ROWS * QUART) {
+          const int row = e / QUART, h = e - row * QUART;
+          const int src = sSrc[r][row];
+          if (src >= 0) v = reinterpret_cast<const float4*>(M32 + (int64_t)src * STRIDE)[h];
+        }
+        pre4[i] = v;
       }
-      pre[i] = v;
+    } else {
+#pragma unroll
+      for (int i = 0; i < PF; ++i) {
+        const int e = threadIdx.x + i * TPB;
+        double2 v = make_double2(0.0, 0.0);
+        if (e < ROWS * HALF) {
+          const int row = e / HALF, h = e - row * HALF;
+          const int src = sSrc[r][row];
+          if (src >= 0) v = reinterpret_cast<const double2*>(M + (int64_t)src * STRIDE)[h];
+        }
+        pre[i] = v;
+      }
     }
   };
   auto commit = [&](kt* dst) {
+    if constexpr (F32) {
+      // rows start at 8-byte multiples (pitch STRIDE + 2 floats): two 8-byte stores per piece
 #pragma unroll
-    for (int i = 0; i < PF; ++i) {
-      const int e = threadIdx.x + i * TPB;
-      if (e < ROWS * HALF) {
-        const int row = e / HALF, h = e - row * HALF;
-        kt2 w;
-        w.x = (kt)pre[i].x;
-        w.y = (kt)pre[i].y;
-        *reinterpret_cast<kt2*>(dst + row * BP + 2 * h) = w;
+      for (int i = 0; i < PF4; ++i) {
+        const int e = threadIdx.x + i * TPB;
+        if (e < ROWS * QUART) {
+          const int row = e / QUART, h = e - row * QUART;
+          float2* d = reinterpret_cast<float2*>(dst + row * BP + 4 * h);
+          d[0] = make_float2(pre4[i].x, pre4[i].y);
+          d[1] = make_float2(pre4[i].z, pre4[i].w);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < PF; ++i) {
+        const int e = threadIdx.x + i * TPB;
+        if (e < ROWS * HALF) {
+          const int row = e / HALF, h = e - row * HALF;
+          *reinterpret_cast<kt2*>(dst + row * BP + 2 * h) = kt2{(kt)pre[i].x, (kt)pre[i].y};
+        }
       }
     }
   };
@@ -403,9 +433,9 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(m2l_waves_p
 }
 
 template <int P>
-void m2l_dispatch(const TreeView& t, const OpTables& op, int nsplit, const double* M, double* F,
-                  int64_t split_stride, bool fp32, int fp64_max_level, const int* done, const int* qcap,
-                  hipStream_t s) {
+void m2l_dispatch(const TreeView& t, const OpTables& op, int nsplit, const double* M, const float* M32,
+                  double* F, int64_t split_stride, bool fp32, int fp64_max_level, const int* done,
+                  const int* qcap, hipStream_t s) {
   // parents of levels [1, L - 1]; float64 for targets at levels <= fp64_max_level on the mixed path
   const int lo = 1, hi = t.L - 1;
   const int hi64 = fp32 ? std::min(hi, fp64_max_level - 1) : hi;
@@ -413,7 +443,7 @@ void m2l_dispatch(const TreeView& t, const OpTables& op, int nsplit, const doubl
     const int nt = m2l_tiles(t, lo, hi64, m2l_ncb<P, false>());
     if (nt > 0)
       hipLaunchKernelGGL((k_m2l<P, false>), dim3(nt * nsplit), dim3(TPB), 0, s, t, op, lo, hi64, nsplit,
-                         M, F, split_stride, done, qcap);
+                         M, M32, F, split_stride, done, qcap);
   }
   if (fp32) {
     const int lo32 = std::max(lo, hi64 + 1);
@@ -421,12 +451,25 @@ void m2l_dispatch(const TreeView& t, const OpTables& op, int nsplit, const doubl
       const int nt = m2l_tiles(t, lo32, hi, m2l_ncb<P, true>());
       if (nt > 0)
         hipLaunchKernelGGL((k_m2l<P, true>), dim3(nt * nsplit), dim3(TPB), 0, s, t, op, lo32, hi, nsplit,
-                           M, F, split_stride, done, qcap);
+                           M, M32, F, split_stride, done, qcap);
     }
   }
 }
 
 }  // namespace
+
+__global__ __launch_bounds__(256) void k_to_float(const double* __restrict__ in, float* __restrict__ out,
+                                                   int64_t count, const int* done) {
+  if (done && *done) return;
+  for (int64_t k = blockIdx.x * 256 + threadIdx.x; k < count; k += (int64_t)gridDim.x * 256) out[k] = (float)in[k];
+}
+
+void launch_to_float(const double* in, float* out, int64_t count, const int* done, hipStream_t s) {
+  if (count <= 0) return;
+  const int64_t blocks = std::min<int64_t>((count + 255) / 256, 16384);
+  hipLaunchKernelGGL(k_to_float, dim3((unsigned)blocks), dim3(256), 0, s, in, out, count, done);
+  PFMM_LAUNCH_CHECK();
+}
 
 int m2l_tile_ncb(int p, bool fp32) {
   switch (p) {
@@ -447,16 +490,16 @@ int m2l_tiles(const TreeView& t, int lp_lo, int lp_hi, int ncb) {
   return n;
 }
 
-void launch_m2l(const TreeView& t, const OpTables& op, int nsplit, const double* M, double* F,
-                int64_t split_stride, bool fp32, int fp64_max_level, const int* done, const int* qcap,
-                hipStream_t s) {
+void launch_m2l(const TreeView& t, const OpTables& op, int nsplit, const double* M, const float* M32,
+                double* F, int64_t split_stride, bool fp32, int fp64_max_level, const int* done,
+                const int* qcap, hipStream_t s) {
   if (t.L < 2) return;
   if (nsplit < 1 || nsplit > t.nnear) throw Error(PFMM_ERR_INVALID_ARG, "internal: M2L split out of range");
-  if (fp32 && !op.dvec32) throw Error(PFMM_ERR_INVALID_ARG, "internal: float32 M2L tables missing");
+  if (fp32 && (!op.dvec32 || !M32)) throw Error(PFMM_ERR_INVALID_ARG, "internal: float32 M2L inputs missing");
   switch (op.p) {
 #define PFMM_M2L_CASE(PP)                                                                          \
   case PP:                                                                                         \
-    m2l_dispatch<PP>(t, op, nsplit, M, F, split_stride, fp32, fp64_max_level, done, qcap, s);      \
+    m2l_dispatch<PP>(t, op, nsplit, M, M32, F, split_stride, fp32, fp64_max_level, done, qcap, s); \
     break;
     PFMM_M2L_CASE(1) PFMM_M2L_CASE(2) PFMM_M2L_CASE(3) PFMM_M2L_CASE(4) PFMM_M2L_CASE(5)
     PFMM_M2L_CASE(6) PFMM_M2L_CASE(7) PFMM_M2L_CASE(8) PFMM_M2L_CASE(9) PFMM_M2L_CASE(10)
