@@ -117,6 +117,26 @@ def test_field_offset_orders_match_oracle_fmm(api, p, ws, lw, slack):
     assert relnorm(N(Edm), ref["E_d"]) < 1e-5
 
 
+@pytest.mark.parametrize("p", [9, 10])
+def test_mixed_field_deep_tree_matches_fp64(api, p):
+    """The float32 M2L (levels below 4 of a deep tree, two 16-parent tiles per workgroup, float32
+    copy of the multipoles) against the float64 path on the same tree, which the oracle pins at
+    these orders: they differ by float32 rounding only."""
+    print_case(f"mixed field deep tree p={p}")
+    X, q, a, mu = cube(3000, 24.0, 5)
+    extent, L = float((X.max(0) - X.min(0)).max()), 0
+    while 0.7 * 2.0**L < extent * (1.0 + 2.0**-20):
+        L += 1
+    assert L >= 5  # M2L targets below level 4 exist, so the float32 launches run
+    kw = dict(order_p=p, ws=2, leaf_width=0.7, thole_a=0.0, m2l_order_slack=2)
+    s64 = api.Solver(**kw)
+    s32 = api.Solver(precision="mixed", **kw)
+    f64 = s64.field(T(X), T(q), T(mu), T(a))
+    f32 = s32.field(T(X), T(q), T(mu), T(a))
+    for a64, a32 in zip(f64, f32):
+        assert relnorm(N(a32), N(a64)) < 2e-6
+
+
 def test_field_charges_only_and_dipoles_only(api):
     print_case("field sources split")
     X, q, a, mu = cube(400, 11.0, 3)
