@@ -355,9 +355,10 @@ void build_tree(pfmm_handle* h, int n, const double* pos, const double* q, const
   for (int c = 0; c <= 10; ++c) h->m2l_flops_cap[c] = c <= h->op.p ? (int64_t)st[3 + c] : 0;
   // Split each parent tile's colleague offsets over nsplit workgroups (one per CU at a time).  The
   // launch takes ceil(tiles * nsplit / CUs) rounds of workgroups, each 1/nsplit of a tile's work,
-  // plus a fixed cost per round (staging the index table, the first offset's loads): choose the
-  // nsplit that minimises rounds / nsplit + 0.004 rounds, with at least one round of workgroups and
-  // at least 4 offsets per split.
+  // plus a fixed cost per round (staging the index table, the first offset's loads), and L2L reads
+  // one partial copy of F~ per split: choose the nsplit that minimises
+  // rounds / nsplit + 0.004 rounds + 0.006 nsplit (in units of one round of whole tiles), with at
+  // least one round of workgroups and at least 4 offsets per split.
   h->m2l_tiles = L >= 2 ? m2l_tiles(t, 1, L - 1, m2l_tile_ncb(c.order_p, c.precision == PFMM_MIXED)) : 0;
   h->nsplit = 1;
   if (h->m2l_tiles > 0) {
@@ -367,7 +368,7 @@ void build_tree(pfmm_handle* h, int n, const double* pos, const double* q, const
     double best = 0.0;
     for (int ns = lo; ns <= hi; ++ns) {
       const int64_t rounds = (T * ns + C - 1) / C;
-      const double cost = (double)rounds / ns + 0.004 * (double)rounds;
+      const double cost = (double)rounds / ns + 0.004 * (double)rounds + 0.006 * ns;
       if (ns == lo || cost < best - 1e-12) {
         best = cost;
         h->nsplit = ns;

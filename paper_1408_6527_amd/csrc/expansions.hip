@@ -238,9 +238,13 @@ constexpr int MAX_NC = 286;  // multi-indices of degree <= 10
 // exchanges.  The leaf's F~ is staged in LDS, each particle's powers of its scaled offset sit in its
 // own LDS column, and the coefficient table (exponents, degree, indices of n + e_c and n + e_a + e_b)
 // is read through the scalar cache.
+// MODE 0 (dipole-solve evaluations): E only, so the coefficients of degree p, which feed only the
+// potential, are skipped; MODE 1: potential, field and field gradient.
+template <int MODE>
 __global__ __launch_bounds__(L2P_TPB) void k_l2p(TreeView t, OpTables op, Particles pa,
-                                                 const double* __restrict__ F, int mode, FieldOut out,
+                                                 const double* __restrict__ F, FieldOut out,
                                                  const int* done) {
+  constexpr int mode = MODE;
   if (done && *done) return;
   __shared__ double sF[MAX_NC];
   __shared__ double pw[3][MAX_P + 1][L2P_TPB];
@@ -284,12 +288,14 @@ __global__ __launch_bounds__(L2P_TPB) void k_l2p(TreeView t, OpTables op, Partic
     __syncthreads();
     double phi = 0.0, ex = 0.0, ey = 0.0, ez = 0.0;
     double gxx = 0.0, gyy = 0.0, gzz = 0.0, gxy = 0.0, gxz = 0.0, gyz = 0.0;
-    for (int k = slice; k < nc; k += G) {
+    // degree-ordered coefficients: those of degree <= p - 1 are the first ncE
+    const int ncE = mode == 1 ? nc : (p * (p + 1) * (p + 2)) / 6;
+    for (int k = slice; k < ncE; k += G) {
       const int4 tk = sT[k];
       const int deg = (tk.x >> 24) & 0xff;
       const double m = pw[0][tk.x & 0xff][slot] * pw[1][(tk.x >> 8) & 0xff][slot] *
                        pw[2][(tk.x >> 16) & 0xff][slot] * sIF[k];
-      phi += m * sF[k];
+      if (mode == 1) phi += m * sF[k];
       if (deg <= p - 1) {
         ex -= m * sF[tk.y & 0xffff];
         ey -= m * sF[tk.y >> 16];
@@ -360,7 +366,10 @@ void launch_l2p(const TreeView& t, const OpTables& op, const Particles& pa, cons
   const int nleaf = t.off[t.L + 1] - t.off[t.L];
   if (nleaf <= 0) return;
   if (op.nc > MAX_NC) throw Error(PFMM_ERR_INVALID_ARG, "order_p out of range");
-  hipLaunchKernelGGL(k_l2p, dim3(nleaf), dim3(L2P_TPB), 0, s, t, op, pa, F, mode, out, done);
+  if (mode == 1)
+    hipLaunchKernelGGL(k_l2p<1>, dim3(nleaf), dim3(L2P_TPB), 0, s, t, op, pa, F, out, done);
+  else
+    hipLaunchKernelGGL(k_l2p<0>, dim3(nleaf), dim3(L2P_TPB), 0, s, t, op, pa, F, out, done);
   PFMM_LAUNCH_CHECK();
 }
 
