@@ -521,3 +521,38 @@ def test_globular_50k_sampled(api, p, lw, gate, slack):
     # the exact residual of the library's dipoles is the FMM error of the field, not the SCF error
     assert res < 10 * gate
     assert r.residual <= 1e-6
+
+
+def test_scaling_1m_sampled(api):
+    """The benchmarked 1,000,000-particle system in the benchmark's own solver settings (order 10,
+    per-offset M2L orders, preconditioned and relaxed dipole solve): at 8 sampled particles the
+    oracle's exact forces, from all sources and the float64 path's dipoles, agree with the float64
+    path to 1e-5 and with the mixed path to 1e-4 (relative l2 over the sample)."""
+    import bench
+    wl = bench.WORKLOADS["scaling_1m"]
+    print_case(f"scaling 1m {wl}")
+    from paper_1408_6527_amd import inputs
+    ps = inputs.make(wl["gen"])
+    pos, q, al = T(ps.pos), T(ps.q), T(ps.alpha)
+    res = {}
+    for prec in ("fp64", "mixed"):
+        s = api.Solver(order_p=wl["p"], ws=wl["ws"], leaf_width=wl["leaf"], scf_tol=wl["tol"],
+                       m2l_order_slack=wl["slack"], precond_cutoff=wl["pc"], precond_iters=wl["pc_iters"],
+                       scf_relax=wl["relax"], precision=prec)
+        r = s.solve(pos, q, al)
+        res[prec] = (N(r.forces), N(r.mu), r.residual, r.iters)
+        print(f"scaling 1m {prec}: residual {r.residual:.2e}, iters {r.iters}, levels {r.stats['levels']}", flush=True)
+        del s, r
+    mu = res["fp64"][1]
+    idx = np.sort(np.random.default_rng(11).choice(ps.n, 8, replace=False))
+    phi, Eu, Ed, G = D.fields_at(idx, ps.pos, ps.q, mu, ps.alpha, 2.0)
+    F = D.COULOMB_K * (ps.q[idx, None] * Eu + np.einsum("ia,iab->ib", mu[idx], G))
+    err = {k: relnorm(v[0][idx], F) for k, v in res.items()}
+    rd = np.linalg.norm(ps.alpha[idx, None] * Ed - mu[idx]) / np.linalg.norm(ps.alpha[idx, None] * Ed)
+    print(f"scaling 1m sampled force err fp64 {err['fp64']:.2e} mixed {err['mixed']:.2e}, "
+          f"exact dipole residual {rd:.2e}", flush=True)
+    assert err["fp64"] < 1e-5
+    assert err["mixed"] < 1e-4
+    assert rd < 1e-4
+    for prec in res:
+        assert res[prec][2] <= wl["tol"]
