@@ -10,7 +10,8 @@ notation, one operator at a time and with no blocking or fusion:
 
   P2M  M_n(z_A) = sum_a q_a (-1)^|n| r_a^n / n!                 (Sec. II.B, multipole equation)
        plus, for a point dipole mu_a (the delta-l -> 0 limit of the +/- q^mu pair, Sec. II.C),
-       M_n += (-1)^|n| / n! * mu_a . grad(r^n) at r_a
+       M_n += (-1)^|n| / n! * mu_a . grad(r^n) at r_a; or, on request, the pair itself: charges
+       +/- |mu_a| / (2 dl) at r_a +/- dl mu_a / |mu_a|
   M2M  M_n(z + x) = sum_{k <= n} x^k / k! M_{n-k}(z)             (Sec. II.B, shifting operator)
   M2L  F_n(z_B) = sum_{|m| <= p-|n|} M_m(z_A) D_{n+m}(z_B - z_A)  (Sec. II.B, local expansion)
   L2L  F_n(z + x) = sum_{|k| <= p-|n|} x^k / k! F_{n+k}(z)        (Sec. II.B, field-tensor shift)
@@ -132,6 +133,23 @@ def p2m(p, centre, X, q=None, mu=None):
                     acc += n[j] * np.sum(mu[:, j] * r[:, 0] ** e[0] * r[:, 1] ** e[1] * r[:, 2] ** e[2])
             M[k] += sign[k] / mi.fact[k] * acc
     return M
+
+
+def p2m_pair(p, centre, X, mu, dl):
+    """Multipole expansion about `centre` of point dipoles mu at X, each taken as the pair of
+    charges +/- q^mu at X +/- delta-l of Sec. II.C: mu = 2 |q^mu| delta-l with |delta-l| = dl along
+    mu, so q^mu = |mu| / (2 dl) at X + dl mu/|mu| and -q^mu at X - dl mu/|mu|.  A zero dipole has no
+    pair and adds nothing."""
+    X = np.atleast_2d(np.asarray(X, np.float64))
+    mu = np.atleast_2d(np.asarray(mu, np.float64))
+    norm = np.linalg.norm(mu, axis=1)
+    keep = norm > 0
+    if not np.any(keep):
+        return np.zeros(ncoef(p))
+    u = mu[keep] / norm[keep, None]
+    qmu = norm[keep] / (2.0 * dl)
+    Xpm = np.concatenate([X[keep] + dl * u, X[keep] - dl * u])
+    return p2m(p, centre, Xpm, np.concatenate([qmu, -qmu]))
 
 
 @lru_cache(maxsize=None)
@@ -305,8 +323,12 @@ class Octree:
 # Field evaluation.
 # ----------------------------------------------------------------------------------------------
 
-def fmm_fields(X, q, mu, alpha, thole_a, p, leaf_width, ws=1, want_grad=True, order_slack=-1):
+def fmm_fields(X, q, mu, alpha, thole_a, p, leaf_width, ws=1, want_grad=True, order_slack=-1,
+               pair_dl=0.0):
     """FMM fields of charges q and point dipoles mu at every particle.
+
+    pair_dl > 0 builds the multipoles of the dipoles from their +/- q^mu pairs (Sec. II.C, p2m_pair)
+    instead of the point-dipole limit; the near field keeps the point dipoles.
 
     Returns a dict with
       phi  total potential (undamped),
@@ -328,7 +350,11 @@ def fmm_fields(X, q, mu, alpha, thole_a, p, leaf_width, ws=1, want_grad=True, or
     # upward pass
     M = [dict() for _ in range(L + 1)]
     for cc, idx in tree.leaves.items():
-        M[L][cc] = p2m(p, tree.centre(L, cc), X[idx], qq[idx], mm[idx])
+        if pair_dl > 0:
+            M[L][cc] = p2m(p, tree.centre(L, cc), X[idx], qq[idx]) + p2m_pair(p, tree.centre(L, cc), X[idx],
+                                                                                 mm[idx], pair_dl)
+        else:
+            M[L][cc] = p2m(p, tree.centre(L, cc), X[idx], qq[idx], mm[idx])
     for l in range(L, 0, -1):
         for cc, Mc in M[l].items():
             par = (cc[0] >> 1, cc[1] >> 1, cc[2] >> 1)
@@ -392,17 +418,20 @@ def fmm_fields(X, q, mu, alpha, thole_a, p, leaf_width, ws=1, want_grad=True, or
     return dict(phi=phi, E_u=E_u, E_d=E_d, G_d=G_d, tree=tree)
 
 
-def fmm_solve(X, q, alpha, thole_a, p, leaf_width, ws=1, tol=1e-12, max_iter=500, k_e=direct.COULOMB_K):
+def fmm_solve(X, q, alpha, thole_a, p, leaf_width, ws=1, tol=1e-12, max_iter=500, k_e=direct.COULOMB_K,
+              pair_dl=0.0):
     """The three stages of Sec. III on the FMM fields: (1) charge field, (2) conjugate-gradient
-    dipole solve with one FMM evaluation per iteration, (3) energy and forces at the solution."""
+    dipole solve with one FMM evaluation per iteration, (3) energy and forces at the solution.
+    pair_dl > 0: dipole multipoles from the +/- q^mu pairs of Sec. II.C (see fmm_fields)."""
     X = np.asarray(X, np.float64); q = np.asarray(q, np.float64); alpha = np.asarray(alpha, np.float64)
     st1 = fmm_fields(X, q, None, alpha, thole_a, p, leaf_width, ws)
 
     def apply_T(m):
-        return fmm_fields(X, None, m, alpha, thole_a, p, leaf_width, ws, want_grad=False)["E_d"]
+        return fmm_fields(X, None, m, alpha, thole_a, p, leaf_width, ws, want_grad=False,
+                          pair_dl=pair_dl)["E_d"]
 
     mu, iters, res = direct.cg_scaled(apply_T, st1["E_d"], alpha, tol=tol, max_iter=max_iter)
-    st3 = fmm_fields(X, None, mu, alpha, thole_a, p, leaf_width, ws)
+    st3 = fmm_fields(X, None, mu, alpha, thole_a, p, leaf_width, ws, pair_dl=pair_dl)
     charge = (st1["phi"], st1["E_d"], st1["G_d"])
     dip = (st3["phi"], st3["E_u"], st3["E_d"], st3["G_d"])
     out = direct.evaluate(X, q, alpha, mu, thole_a, k_e, charge=charge, dip=dip)

@@ -208,6 +208,60 @@ def test_dipole_limit_matches_charge_pair():
     assert errs[1] < errs[0] / 50  # quadratic convergence in delta-l
 
 
+def test_pair_p2m_axis_closed_form():
+    """A dipole mu_a e_a at the expansion centre, taken as the +/- q^mu pair of Sec. II.C (charges
+    +/- |mu| / (2 dl) at +/- dl mu/|mu|, so mu = 2 |q^mu| delta-l), has at any finite dl the
+    multipoles M_{k e_a} = (-1)^k / k! q^mu (dl^k - (-dl)^k) s^k, s = sign(mu_a): -mu_a dl^(k-1) / k!
+    for odd k, zero for even k and for every mixed multi-index."""
+    p = 7
+    items = FM._mi(p).items
+    for a in range(3):
+        for sgn in (1.0, -1.0):
+            mu = np.zeros(3); mu[a] = 0.8 * sgn
+            for dl in (0.3, 1e-2):
+                M = FM.p2m_pair(p, np.zeros(3), np.zeros((1, 3)), mu[None], dl)
+                expect = np.zeros(len(items))
+                for k, n in enumerate(items):
+                    if n[a] == sum(n) and n[a] % 2 == 1:
+                        expect[k] = -mu[a] * dl ** (n[a] - 1) / math.factorial(n[a])
+                np.testing.assert_allclose(M, expect, rtol=1e-13, atol=1e-15)
+
+
+def test_pair_p2m_tends_to_point_dipole():
+    """The pair multipoles approach the point-dipole P2M quadratically in dl (Sec. II.C: the point
+    dipole is the pair's dl -> 0 limit); a zero dipole has no pair and adds nothing."""
+    p = 6
+    rng = np.random.default_rng(19)
+    X = rng.uniform(-0.4, 0.4, (3, 3)); mu = rng.normal(size=(3, 3)); mu[1] = 0.0
+    Mpt = FM.p2m(p, np.zeros(3), X, None, mu)
+    errs = [np.abs(FM.p2m_pair(p, np.zeros(3), X, mu, dl) - Mpt).max() for dl in (1e-2, 1e-3)]
+    assert 80 < errs[0] / errs[1] < 120
+    assert not np.any(FM.p2m_pair(p, np.zeros(3), X, np.zeros((3, 3)), 1e-4))
+
+
+def test_fmm_pair_dipoles_insensitive_to_dl():
+    """FMM fields with the dipole multipoles built from the +/- q^mu pairs (order 5, as in the
+    paper's sphere tests): for dl = 1e-5 .. 1e-3 A they differ from the point-dipole FMM by far less
+    than the FMM's own error against the direct sums, so that error does not change with dl (the
+    paper's finding over five decades of dl); the departure grows as dl^2."""
+    X, q, a = rand_system(300, 83, box=14.0, r_min=1.0)
+    mu = np.random.default_rng(5).normal(0, 0.2, (300, 3))
+    _, Eq, _ = D.charge_fields(X, q)
+    _, _, Ed, _ = D.dipole_fields(X, mu, a, 2.0)
+    ref = Eq + Ed
+    base = FM.fmm_fields(X, q, mu, a, 2.0, 5, 1.7, 1, want_grad=False)["E_d"]
+    assert FM.Octree(X, 1.7, 1).L >= 3
+    e0 = np.linalg.norm(base - ref) / np.linalg.norm(ref)
+    dev = {}
+    for dl in (1e-5, 1e-4, 1e-3, 1e-2):
+        E = FM.fmm_fields(X, q, mu, a, 2.0, 5, 1.7, 1, want_grad=False, pair_dl=dl)["E_d"]
+        dev[dl] = np.linalg.norm(E - base) / np.linalg.norm(ref)
+        e = np.linalg.norm(E - ref) / np.linalg.norm(ref)
+        if dl <= 1e-3:
+            assert dev[dl] < 1e-4 * e0 and abs(e - e0) < 1e-4 * e0
+    assert 60 < dev[1e-2] / dev[1e-3] < 140
+
+
 # ---------------------------------------------------------------- identities and invariants
 
 def test_energy_identity_at_convergence():
