@@ -94,6 +94,8 @@ def parse():
     ap.add_argument("--pc-iters", type=int, default=None, help="inner preconditioner iterations")
     ap.add_argument("--relax", type=float, default=None,
                     help="residual below which the dipole solve caps the M2L order (0: never)")
+    ap.add_argument("--pair-dl", type=float, default=0.0,
+                    help="dipole multipoles from +/- q^mu charge pairs this far apart (A; 0: point dipoles)")
     ap.add_argument("--oracle-sample", type=int, default=0,
                     help="targets of the sampled oracle check (0: about 2e7 / n, between 8 and 192)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -136,7 +138,7 @@ def main():
     def make(prec, timing=False):
         return api.Solver(order_p=wl["p"], ws=wl["ws"], leaf_width=wl["leaf"], scf_tol=wl["tol"],
                           m2l_order_slack=wl["slack"], precond_cutoff=wl["pc"], precond_iters=wl["pc_iters"],
-                          scf_relax=wl["relax"], precision=prec, timing=timing)
+                          scf_relax=wl["relax"], dipole_pair_dl=args.pair_dl, precision=prec, timing=timing)
 
     def step(s):
         r = s.solve(pos, q, al)
@@ -246,7 +248,7 @@ def main():
         "config": {"workload": args.workload, "n": n, "order_p": p, "ws": wl["ws"],
                    "leaf_width": wl["leaf"], "scf_tol": wl["tol"], "m2l_order_slack": wl["slack"],
                    "precond_cutoff": wl["pc"], "precond_iters": wl["pc_iters"], "scf_relax": wl["relax"],
-                   "levels": r0["res"].stats["levels"],
+                   "dipole_pair_dl": args.pair_dl, "levels": r0["res"].stats["levels"],
                    "step": "solve (tree, charge field, dipole CG, energy, forces) + backward",
                    "parallelism": "single GPU"},
         "errors": errs,

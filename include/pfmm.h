@@ -100,6 +100,13 @@ typedef struct pfmm_config {
                           relaxed matrix-vector products in a Krylov solve, whose late corrections are
                           small).  The stopping rule is checked again on the final dipoles with the
                           full orders; if it fails, the solve continues from them without the cap.  */
+  double dipole_pair_dl; /* 0: the multipoles of the induced dipoles are those of point dipoles (the
+                          limit of Sec. II.C).  > 0 (Angstrom, at most 1): each dipole's multipole
+                          expansion is that of the pair of charges +/- |mu| / (2 dl) at x +/- dl mu/|mu|
+                          of Sec. II.C (mu = 2 |q^mu| delta-l); the near field keeps the point dipoles.
+                          Applies to every field evaluation with dipole sources, on both paths.  At
+                          finite dl this field is not additive in the dipoles, so the solve checks
+                          its stopping rule on the final dipoles and continues from them if needed. */
 } pfmm_config;
 
 typedef struct pfmm_result {
@@ -127,7 +134,9 @@ typedef struct pfmm_result {
                                    orders it used                                                  */
   int m2l_order_cap_min;        /* lowest M2L order cap of the dipole solve (order_p without
                                    scf_relax)                                                      */
-  int scf_restarts;             /* continuations without the cap after the final check (scf_relax) */
+  int scf_restarts;             /* continuations from the final dipoles after the final check of the
+                                   stopping rule (scf_relax: without the cap; dipole_pair_dl: the
+                                   pair field is not additive in the dipoles; at most 1 and 2)      */
 } pfmm_result;
 
 typedef struct pfmm_handle pfmm_handle;

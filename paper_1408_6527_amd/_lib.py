@@ -51,6 +51,7 @@ class Config(ctypes.Structure):
         ("precond_cutoff", ctypes.c_double),
         ("precond_iters", ctypes.c_int),
         ("scf_relax", ctypes.c_double),
+        ("dipole_pair_dl", ctypes.c_double),
     ]
 
 

@@ -217,6 +217,8 @@ void validate_config(const pfmm_config* c) {
     throw Error(PFMM_ERR_INVALID_ARG, "precond_cutoff must be >= 0");
   if (!(c->scf_relax >= 0.0 && c->scf_relax < 1.0))
     throw Error(PFMM_ERR_INVALID_ARG, "scf_relax must be in [0, 1)");
+  if (!(c->dipole_pair_dl >= 0.0 && c->dipole_pair_dl <= 1.0))
+    throw Error(PFMM_ERR_INVALID_ARG, "dipole_pair_dl must be in [0, 1] Angstrom");
   if (c->precond_cutoff > 0.0 && (c->precond_iters < 1 || c->precond_iters > 64))
     throw Error(PFMM_ERR_INVALID_ARG, "precond_iters must be in 1..64");
 }
@@ -399,7 +401,7 @@ void fmm_pass(pfmm_handle* h, int sources, int mode, FieldOut out, int* err, con
   KernelTimer& kt = h->kt;
   if (t.L >= 2) {
     int e = kt.begin();
-    launch_p2m(t, op, h->pa, mu4, sources, M, done, s);
+    launch_p2m(t, op, h->pa, mu4, sources, h->cfg.dipole_pair_dl, M, done, s);
     kt.end(KC_P2M, e);
     e = kt.begin();
     for (int lp = t.L - 1; lp >= 2; --lp) launch_m2m(t, op, lp, M, done, s);
@@ -649,8 +651,13 @@ pfmm_status solve_impl(pfmm_handle* h, int64_t n64, const double* pos, const dou
     sync_read(h, ep, &he, sizeof(he), s);
     const double true_res = he.bn2 > 0.0 ? std::sqrt(he.res2 / he.bn2) : 0.0;
     // a relaxed solve must meet the stopping rule with the full orders too; otherwise continue from
-    // the final dipoles (in mu4) without the cap
-    if (relaxed && !hs.notspd && !hs.maxed && true_res > c.scf_tol && restarts == 0) {
+    // the final dipoles (in mu4) without the cap.  With charge-pair multipoles the field is not
+    // additive in the dipoles (the pair departs from the point dipole by O((dl/w)^2), differently for
+    // a sum than for its terms), so the recursive residual of the conjugate gradients can converge
+    // while the true one has not: continue the same way, each time on a correction that is smaller
+    // by the residual's factor, so that the non-additive part shrinks with it.
+    const bool pair = c.dipole_pair_dl > 0.0;
+    if ((relaxed || pair) && !hs.notspd && !hs.maxed && true_res > c.scf_tol && restarts < (pair ? 2 : 1)) {
       ++restarts;
       rp.start = 0.0;
       launch_fill_int(&st->qcap, 1, c.order_p, s);
@@ -723,6 +730,7 @@ void pfmm_config_default(pfmm_config* c) {
   c->precond_cutoff = 0.0;
   c->precond_iters = 4;
   c->scf_relax = 0.0;
+  c->dipole_pair_dl = 0.0;
 }
 
 pfmm_status pfmm_create(const pfmm_config* cfg, pfmm_handle** out) {

@@ -1,6 +1,7 @@
 // Upward and downward passes of the Cartesian FMM (Sec. II.B-II.C) on level-scaled expansions:
 //   P2M  M~_n = (-1)^|n|/n! sum_a [ q_a rho_a^n + (mu_a / w) . grad(rho^n)(rho_a) ],  rho = (x - z)/w
-//        (point dipoles enter through the delta-l -> 0 limit of the +/- q^mu pair of Sec. II.C)
+//        (point dipoles enter through the delta-l -> 0 limit of the +/- q^mu pair of Sec. II.C, or,
+//        on request, as the pair itself: charges +/- |mu_a| / (2 dl) at rho_a +/- (dl / w) mu_a/|mu_a|)
 //   M2M  M~_n(parent) = sum_{k <= n} xt^k/k! 2^-(|n|-|k|) M~_{n-k}(child)
 //   L2L  F~_n(child) += sum_{|k| <= p-|n|} xt'^k/k! 2^-(|n|+1) F~_{n+k}(parent)
 //   L2P  phi = (1/w) sum rho^n/n! F~_n,  E_c = -(1/w^2) sum rho^n/n! F~_{n+e_c},
@@ -27,9 +28,12 @@ constexpr int P2M_TPB = 128;
 constexpr int P2M_CHUNK = 64;
 
 // One block per leaf; particles staged in LDS with the powers of their scaled offsets, one thread
-// per coefficient.
+// per coefficient.  PAIR: each dipole enters as its pair of Sec. II.C, the charges +/- |mu| / (2 dl)
+// at rho +/- (dl / w) mu/|mu|, staged as two more point charges after the particle's own charge (a
+// zero dipole stages two zero charges); otherwise through the point-dipole term above.
+template <bool PAIR>
 __global__ __launch_bounds__(P2M_TPB) void k_p2m(TreeView t, OpTables op, Particles pa,
-                                                 const double4* __restrict__ mu4, int sources,
+                                                 const double4* __restrict__ mu4, int sources, double pair_dl,
                                                  double* __restrict__ M, const int* done) {
   if (done && *done) return;
   __shared__ double pw[P2M_CHUNK][3][MAX_P + 1];
@@ -48,37 +52,64 @@ __global__ __launch_bounds__(P2M_TPB) void k_p2m(TreeView t, OpTables op, Partic
     const int k = threadIdx.x + r * P2M_TPB;
     for (int a = 0; a < 3; ++a) ex[r][a] = k < nc ? op.mi[3 * k + a] : 0;
   }
-  for (int s0 = 0; s0 < cnt; s0 += P2M_CHUNK) {
-    const int m = min(P2M_CHUNK, cnt - s0);
+  auto stage = [&](int v, const double* rho) {
+    for (int a = 0; a < 3; ++a) {
+      double x = 1.0;
+      pw[v][a][0] = 1.0;
+      for (int e = 1; e <= p; ++e) { x *= rho[a]; pw[v][a][e] = x; }
+    }
+  };
+  // staged points per particle and particles per chunk (PAIR requires dipole sources)
+  const int per = PAIR ? ((sources & 1) ? 3 : 2) : 1;
+  const int rc = P2M_CHUNK / per;
+  for (int s0 = 0; s0 < cnt; s0 += rc) {
+    const int m = min(rc, cnt - s0);
     if (threadIdx.x < m) {
       const int j = threadIdx.x;
       const double4 P = pa.P[first + s0 + j];
       const double rho[3] = {(P.x - c[0]) * iw, (P.y - c[1]) * iw, (P.z - c[2]) * iw};
-      for (int a = 0; a < 3; ++a) {
-        double v = 1.0;
-        pw[j][a][0] = 1.0;
-        for (int e = 1; e <= p; ++e) { v *= rho[a]; pw[j][a][e] = v; }
-      }
-      sq[j] = (sources & 1) ? P.w : 0.0;
-      if (sources & 2) {
-        const double4 u = mu4[first + s0 + j];
-        sm[j][0] = u.x * iw; sm[j][1] = u.y * iw; sm[j][2] = u.z * iw;
+      if (!PAIR) {
+        stage(j, rho);
+        sq[j] = (sources & 1) ? P.w : 0.0;
+        if (sources & 2) {
+          const double4 u = mu4[first + s0 + j];
+          sm[j][0] = u.x * iw; sm[j][1] = u.y * iw; sm[j][2] = u.z * iw;
+        } else {
+          sm[j][0] = sm[j][1] = sm[j][2] = 0.0;
+        }
       } else {
-        sm[j][0] = sm[j][1] = sm[j][2] = 0.0;
+        int v = per * j;
+        if (sources & 1) {
+          stage(v, rho);
+          sq[v++] = P.w;
+        }
+        const double4 u = mu4[first + s0 + j];
+        const double nrm = sqrt(u.x * u.x + u.y * u.y + u.z * u.z);
+        const double qm = nrm > 0.0 ? nrm / (2.0 * pair_dl) : 0.0;
+        const double f = nrm > 0.0 ? pair_dl * iw / nrm : 0.0;
+        const double rp[3] = {rho[0] + u.x * f, rho[1] + u.y * f, rho[2] + u.z * f};
+        const double rm[3] = {rho[0] - u.x * f, rho[1] - u.y * f, rho[2] - u.z * f};
+        stage(v, rp);
+        sq[v] = qm;
+        stage(v + 1, rm);
+        sq[v + 1] = -qm;
       }
     }
     __syncthreads();
+    const int mv = per * m;
     for (int r = 0; r < KPT; ++r) {
       const int k = threadIdx.x + r * P2M_TPB;
       if (k >= nc) break;
       const int nx = ex[r][0], ny = ex[r][1], nz = ex[r][2];
       double a = 0.0;
-      for (int j = 0; j < m; ++j) {
+      for (int j = 0; j < mv; ++j) {
         const double X = pw[j][0][nx], Y = pw[j][1][ny], Z = pw[j][2][nz];
         double v = sq[j] * X * Y * Z;
-        if (nx) v += sm[j][0] * nx * pw[j][0][nx - 1] * Y * Z;
-        if (ny) v += sm[j][1] * ny * X * pw[j][1][ny - 1] * Z;
-        if (nz) v += sm[j][2] * nz * X * Y * pw[j][2][nz - 1];
+        if (!PAIR) {
+          if (nx) v += sm[j][0] * nx * pw[j][0][nx - 1] * Y * Z;
+          if (ny) v += sm[j][1] * ny * X * pw[j][1][ny - 1] * Z;
+          if (nz) v += sm[j][2] * nz * X * Y * pw[j][2][nz - 1];
+        }
         a += v;
       }
       acc[r] += a;
@@ -336,10 +367,15 @@ __global__ __launch_bounds__(L2P_TPB) void k_l2p(TreeView t, OpTables op, Partic
 }  // namespace
 
 void launch_p2m(const TreeView& t, const OpTables& op, const Particles& pa, const double4* mu4,
-                int sources, double* M, const int* done, hipStream_t s) {
+                int sources, double pair_dl, double* M, const int* done, hipStream_t s) {
   const int nleaf = t.off[t.L + 1] - t.off[t.L];
   if (nleaf <= 0) return;
-  hipLaunchKernelGGL(k_p2m, dim3(nleaf), dim3(P2M_TPB), 0, s, t, op, pa, mu4, sources, M, done);
+  if (pair_dl > 0.0 && (sources & 2))
+    hipLaunchKernelGGL(k_p2m<true>, dim3(nleaf), dim3(P2M_TPB), 0, s, t, op, pa, mu4, sources, pair_dl, M,
+                       done);
+  else
+    hipLaunchKernelGGL(k_p2m<false>, dim3(nleaf), dim3(P2M_TPB), 0, s, t, op, pa, mu4, sources, pair_dl, M,
+                       done);
   PFMM_LAUNCH_CHECK();
 }
 

@@ -96,8 +96,9 @@ struct OpTables {
   int nblocks = 0;
 };
 // sources: 1 = charges (P.w), 2 = dipoles (mu4), 3 = both
+// pair_dl > 0 with dipole sources: dipole multipoles from the +/- q^mu pairs of Sec. II.C
 void launch_p2m(const TreeView& t, const OpTables& op, const Particles& pa, const double4* mu4,
-                int sources, double* M, const int* done, hipStream_t s);
+                int sources, double pair_dl, double* M, const int* done, hipStream_t s);
 void launch_m2m(const TreeView& t, const OpTables& op, int parent_level, double* M, const int* done,
                 hipStream_t s);
 // F~(child) += partial M2L sums of splits 1..nsplit-1 (at F + s * split_stride) and, from level 3

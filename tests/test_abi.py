@@ -46,12 +46,15 @@ def test_status_strings_and_defaults(lib):
     assert (c.order_p, c.ws, c.precision, c.scf_max_iter) == (6, 2, 0, 200)
     assert c.scf_tol == 1e-6 and c.thole_a == 2.0 and c.coulomb_k == 332.06371
     assert (c.m2l_order_slack, c.precond_cutoff, c.precond_iters, c.scf_relax) == (-1, 0.0, 4, 0.0)
+    assert c.dipole_pair_dl == 0.0
 
 
 @pytest.mark.parametrize("field,value", [("order_p", 0), ("order_p", 11), ("ws", 3), ("precision", 5),
                                          ("scf_tol", 0.0), ("scf_max_iter", 0), ("thole_a", -1.0),
                                          ("leaf_width", -2.0), ("m2l_order_slack", -2),
-                                         ("precond_cutoff", -1.0), ("scf_relax", -0.1), ("scf_relax", 1.0)])
+                                         ("precond_cutoff", -1.0), ("scf_relax", -0.1), ("scf_relax", 1.0),
+                                         ("dipole_pair_dl", -1e-4), ("dipole_pair_dl", 1.5),
+                                         ("dipole_pair_dl", float("nan"))])
 def test_create_rejects_bad_config(lib, field, value):
     from paper_1408_6527_amd import _lib
     c = _lib.Config()

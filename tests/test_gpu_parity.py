@@ -117,6 +117,68 @@ def test_field_offset_orders_match_oracle_fmm(api, p, ws, lw, slack):
     assert relnorm(N(Edm), ref["E_d"]) < 1e-5
 
 
+@pytest.mark.parametrize("p,ws,dl", [(5, 1, 1e-4), (6, 2, 1e-2), (8, 2, 0.3)])
+def test_field_pair_dipoles_match_oracle_fmm(api, p, ws, dl):
+    """Dipole multipoles from the +/- q^mu charge pairs of Sec. II.C (dipole_pair_dl): the same
+    pairs as the oracle, so the fields agree to rounding (at dl = 1e-4 A the pair's cancellation costs
+    a factor w/dl of the multipoles' precision on both sides, hence the wider bound there)."""
+    print_case(f"field pair dipoles p={p} ws={ws} dl={dl}")
+    X, q, a, mu = cube(600, 13.0, 2)
+    s = api.Solver(order_p=p, ws=ws, leaf_width=1.8, thole_a=0.0, dipole_pair_dl=dl)
+    phi, E, Ed, G = s.field(T(X), T(q), T(mu), T(a))
+    ref = FM.fmm_fields(X, q, mu, a, 0.0, p, 1.8, ws, pair_dl=dl)
+    assert ref["tree"].L >= 3
+    if dl >= 1e-2:
+        plain = FM.fmm_fields(X, q, mu, a, 0.0, p, 1.8, ws, want_grad=False)
+        assert relmax(ref["E_d"], plain["E_d"]) > 1e-9  # the pair multipoles really differ
+    tol = 1e-9 if dl < 1e-3 else 1e-11
+    assert relmax(N(phi), ref["phi"]) < tol
+    assert relmax(N(E), ref["E_u"]) < tol
+    assert relmax(N(Ed), ref["E_d"]) < tol
+    assert relmax(N(G), ref["G_d"]) < tol
+    # dipoles only (the sources of the dipole solve's evaluations: two staged charges per particle)
+    phi2, E2, Ed2, G2 = s.field(T(X), T(np.zeros_like(q)), T(mu), T(a))
+    ref2 = FM.fmm_fields(X, None, mu, a, 0.0, p, 1.8, ws, pair_dl=dl)
+    assert relmax(N(Ed2), ref2["E_d"]) < tol
+    assert relmax(N(G2), ref2["G_d"]) < tol
+    sm = api.Solver(order_p=p, ws=ws, leaf_width=1.8, thole_a=0.0, dipole_pair_dl=dl, precision="mixed")
+    assert relnorm(N(sm.field(T(X), T(q), T(mu), T(a))[2]), ref["E_d"]) < 1e-5
+
+
+@pytest.mark.parametrize("dl", [1e-4, 0.05])
+def test_solve_pair_dipoles_matches_oracle_fmm(api, dl):
+    """A solve with the pair multipoles: the oracle's FMM with the same pairs, applied to the
+    library's converged dipoles, gives the same residual, energy and forces; the force error
+    against the direct sums stays that of the point-dipole solve (the paper's dl-insensitivity at
+    order 4, whose truncation error is far larger than the pair's O(dl^2) departure)."""
+    print_case(f"solve pair dipoles dl={dl}")
+    from paper_1408_6527_amd import inputs
+    ps = inputs.uniform_cube(1000)
+    lw = 2.6
+    s = api.Solver(order_p=4, ws=1, leaf_width=lw, scf_tol=1e-10, dipole_pair_dl=dl)
+    r = s.solve(T(ps.pos), T(ps.q), T(ps.alpha))
+    mu = N(r.mu)
+    st1 = FM.fmm_fields(ps.pos, ps.q, None, ps.alpha, 2.0, 4, lw, 1)
+    st3 = FM.fmm_fields(ps.pos, None, mu, ps.alpha, 2.0, 4, lw, 1, pair_dl=dl)
+    res = np.linalg.norm(ps.alpha[:, None] * (st1["E_d"] + st3["E_d"]) - mu) / np.linalg.norm(ps.alpha[:, None] * st1["E_d"])
+    assert res < 2e-10
+    assert abs(res - r.residual) < 1e-11
+    ev = D.evaluate(ps.pos, ps.q, ps.alpha, mu, 2.0, D.COULOMB_K,
+                    charge=(st1["phi"], st1["E_d"], st1["G_d"]),
+                    dip=(st3["phi"], st3["E_u"], st3["E_d"], st3["G_d"]))
+    assert abs(r.U - ev["U"]) < 1e-11 * abs(ev["U"])
+    assert relmax(N(r.forces), ev["F"]) < 1e-10
+    # at dl = 0.05 A the pair field's non-additivity (O((dl/w)^2)) leaves the conjugate gradients'
+    # own residual short of the true one: the solve continues from its final dipoles
+    if dl > 1e-3:
+        assert r.stats["scf_restarts"] >= 1
+    point = api.Solver(order_p=4, ws=1, leaf_width=lw, scf_tol=1e-10).solve(T(ps.pos), T(ps.q), T(ps.alpha))
+    ref = D.solve(ps.pos, ps.q, ps.alpha, thole_a=2.0)
+    e_pair, e_point = relnorm(N(r.forces), ref["F"]), relnorm(N(point.forces), ref["F"])
+    print(f"pair dl={dl}: force err {e_pair:.4e} (point dipoles {e_point:.4e}), iters {r.iters}", flush=True)
+    assert abs(e_pair - e_point) < 0.01 * e_point
+
+
 @pytest.mark.parametrize("p", [9, 10])
 def test_mixed_field_deep_tree_matches_fp64(api, p):
     """The float32 M2L (levels below 4 of a deep tree, two 16-parent tiles per workgroup, float32
