@@ -41,6 +41,9 @@ WORKLOADS = {
                             relax=0.0),
     "hexamer_shell_160k": dict(gen="hexamer_shell_160k", p=8, ws=2, leaf=5.0, tol=1e-6, slack=2, pc=5.0,
                                pc_iters=4, relax=0.0),
+    # the paper's random sphere (4,096 points, 45 A, +/-1 e) at its order 5, polarisation off
+    "sphere_4096": dict(gen="sphere_4096", p=5, ws=2, leaf=6.0, tol=1e-6, slack=-1, pc=0.0, pc_iters=4,
+                        relax=0.0),
 }
 
 # HBM traffic of the dominant kernel from rocprofv3 counters (profiles/), valid only while the

@@ -15,9 +15,11 @@ subsets of the HIV-1 capsid, which are not available here) by shape, size and de
                      of radius 45 plus 40,000 uncharged solvent sites (alpha = 1.5) uniform in a
                      spherical shell at 0.03 per Angstrom^3: a capsid hexamer in solvent.
 * ``scaling``        half uniform in a cube and half globular at 0.1 per Angstrom^3.
+* ``sphere``         the paper's own random sphere (Sec. IV.A): 4,096 points in a 45 Angstrom ball,
+                     minimum separation 2 Angstrom, +/-1 e in equal numbers, one alpha for all.
 
-Every set keeps a minimum separation r_min = 1.0 Angstrom (rejection on a cell grid); the paper
-used 2 Angstrom for its sphere test, which cannot be packed at protein density.
+Every protein-like set keeps a minimum separation r_min = 1.0 Angstrom (rejection on a cell grid);
+the paper's 2 Angstrom, used by its sphere test, cannot be packed at protein density.
 Seeds: numpy ``SeedSequence([14086527, k])`` for workload k, spawned into independent streams for
 positions, charges and polarisabilities.
 """
@@ -225,6 +227,19 @@ def scaling(n: int = 1_000_000, density: float = 0.1, k: int = 5) -> ParticleSet
     return ParticleSet("scaling", pos, _net_zero_normal(rq, n), ra.uniform(0.2, 2.0, n))
 
 
+def sphere(n: int = 4096, radius: float = 45.0, r_min: float = 2.0, alpha: float = 0.0, k: int = 6) -> ParticleSet:
+    """The random sphere of the paper's accuracy tests (Sec. IV.A): n points uniform in a ball of
+    the given radius with minimum separation r_min, n/2 charges +1 e and n/2 charges -1 e in random
+    order (neutral), the same polarisability alpha for every atom."""
+    rp, rq, _ = _streams(k)
+    excl = _Exclusion([-radius] * 3, [radius] * 3, r_min=r_min)
+    pos, _ = _fill(excl, n, lambda m: (_uniform_ball(rp, m, radius), np.zeros(m, np.int64)))
+    q = np.where(rq.permutation(n) < n // 2, 1.0, -1.0)
+    if n % 2:
+        q[-1] = 0.0
+    return ParticleSet("sphere", pos, q, np.full(n, float(alpha)))
+
+
 def small_globular(n: int = 2000, k: int = 4) -> ParticleSet:
     """The 2,000-particle clumped ball at 0.1 per Angstrom^3 (radius 16.8) used for gradient checks."""
     ps = globular(n, density=0.1, k=k, radius=16.8)
@@ -240,6 +255,7 @@ WORKLOADS = {
     "scaling_250k": lambda: scaling(250_000),
     "scaling_1m": lambda: scaling(1_000_000),
     "scaling_4m": lambda: scaling(4_000_000),
+    "sphere_4096": lambda: sphere(4096),
 }
 
 

@@ -618,3 +618,68 @@ def test_scaling_1m_sampled(api):
     assert rd < 1e-4
     for prec in res:
         assert res[prec][2] <= wl["tol"]
+
+
+def _sphere_reference():
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "sphere_4096_direct.npz")
+    return np.load(path)
+
+
+def _per_atom_force_error(F, Fref):
+    return np.linalg.norm(F - Fref, axis=1) / np.linalg.norm(Fref, axis=1)
+
+
+def test_sphere_4096_alpha_sweep(api):
+    """The paper's random-sphere accuracy test (Sec. IV.A): 4,096 points in a 45 A ball, 2 A apart,
+    +/-1 e, alpha = 0, 1, 2, 3 A^3 for every atom, per-atom relative force errors against the exact
+    direct solve (tests/golden/make_sphere_reference.py, oracle only).  As in the paper the error
+    distribution does not change significantly with alpha.  The paper's figures for its accurate
+    setting (80 % of the atoms below 1e-4, all below 1e-2 at order 5, polarisation off) need order
+    8 here (order 9 with every alpha): the
+    octree accepts an M2L by box separation, not by the particles' enclosing radii, which are much
+    smaller than the box in a sparse sphere (about 2 atoms per leaf)."""
+    print_case("sphere 4096 alpha sweep")
+    from paper_1408_6527_amd import inputs
+    ref = _sphere_reference()
+    stats = {}
+    for ws, p in ((1, 5), (2, 5), (2, 6), (2, 7), (2, 8), (2, 9)):
+        for a in (0, 1, 2, 3):
+            ps = inputs.sphere(4096, alpha=float(a))
+            s = api.Solver(order_p=p, ws=ws, leaf_width=6.0, scf_tol=1e-8)
+            r = s.solve(T(ps.pos), T(ps.q), T(ps.alpha))
+            e = _per_atom_force_error(N(r.forces), ref[f"F_a{a}"])
+            st = (np.percentile(e, 50), np.percentile(e, 80), e.max())
+            stats[(ws, p, a)] = st
+            dU = abs(r.U - float(ref[f"U_a{a}"])) / abs(float(ref[f"U_a{a}"]))
+            print(f"sphere ws={ws} p={p} alpha={a}: force error median {st[0]:.2e} p80 {st[1]:.2e} "
+                  f"max {st[2]:.2e}, energy {dU:.1e}, iters {r.iters}", flush=True)
+    for (ws, p, a), st in stats.items():
+        assert st[0] < 3 * stats[(ws, p, 0)][0]  # no significant change with alpha
+    p50, p80, emax = stats[(2, 8, 0)]  # the paper's figures are for polarisation off
+    assert p80 < 1e-4 and emax < 1e-2
+    for a in (0, 1, 2, 3):
+        p50, p80, emax = stats[(2, 9, a)]
+        assert p80 < 1e-4 and emax < 1e-2
+
+
+def test_sphere_4096_dipole_pair_sweep(api):
+    """The paper's dl sweep on the random sphere (Sec. IV.A, alpha = 1), at order 8: dipole
+    multipoles from the +/- q^mu pairs at dl = 1e-5 .. 1e-3 A give the per-atom force errors of the
+    point dipoles; wider pairs are reported."""
+    print_case("sphere 4096 dl sweep")
+    from paper_1408_6527_amd import inputs
+    ref = _sphere_reference()["F_a1"]
+    ps = inputs.sphere(4096, alpha=1.0)
+    base = None
+    for dl in (0.0, 1e-5, 1e-4, 1e-3, 1e-2, 1e-1):
+        s = api.Solver(order_p=8, ws=2, leaf_width=6.0, scf_tol=1e-8, dipole_pair_dl=dl)
+        r = s.solve(T(ps.pos), T(ps.q), T(ps.alpha))
+        e = _per_atom_force_error(N(r.forces), ref)
+        print(f"sphere dl={dl}: force error median {np.median(e):.4e} p80 {np.percentile(e, 80):.4e} "
+              f"max {e.max():.2e}, continuations {r.stats['scf_restarts']}", flush=True)
+        if dl == 0.0:
+            base = e
+        elif dl <= 1e-3:
+            assert abs(np.median(e) - np.median(base)) < 0.05 * np.median(base)
+            assert e.max() < 1e-2
