@@ -242,15 +242,18 @@ def cg_scaled(apply_T, E_q, alpha, tol=1e-12, max_iter=1000, mu0=None):
 # Energy, forces and gradients at given dipoles.
 # ----------------------------------------------------------------------------------------------
 
-def evaluate(X, q, alpha, mu, thole_a=2.0, k_e=COULOMB_K, charge=None, dip=None):
+def evaluate(X, q, alpha, mu, thole_a=2.0, k_e=COULOMB_K, charge=None, dip=None, qE=None, charge_E=None):
     """Energies, forces, potentials and dU/dalpha for given dipoles (exact if mu is converged).
 
+    The static field that polarises the dipoles comes from the charges q^E (Sec. III: they may
+    differ from the Coulomb charges q; qE=None means q^E = q, the same charges):
     U^{qq'} = 1/2 sum_i q_i phi^q_i
-    U^pol   = 1/2 sum |mu_i|^2/alpha_i - sum mu_i.E^q_i - 1/2 sum mu_i.E^mu_i   (E^mu damped)
-    F_i     = q_i (E^q_i + E^mu_u,i) + (mu_i . grad)(E^q + E^mu_d)_i
+    U^pol   = 1/2 sum |mu_i|^2/alpha_i - sum mu_i.E^{qE}_i - 1/2 sum mu_i.E^mu_i   (E^mu damped)
+    F_i     = q_i E^q_i + qE_i E^mu_u,i + (mu_i . grad)(E^{qE} + E^mu_d)_i
               (charges feel the undamped dipole field; dipoles feel the damped one)
-    phi_i   = phi^q_i + phi^mu_i  (= dU/dq_i, both undamped)
-    dU/dalpha_i = -|mu_i|^2/(2 alpha_i^2) (= -|E_i|^2/2 when alpha_i = 0)
+    phi_i   = dU/dq_i: phi^q_i + phi^mu_i when q^E = q, phi^q_i otherwise (both undamped)
+    phi_E_i = dU/dqE_i = phi^mu_i (returned when qE is given)
+    dU/dalpha_i = -|mu_i|^2/(2 alpha_i^2) (= -|E_i|^2/2 when alpha_i = 0, E = E^{qE} + E^mu_d)
                   - sum_{j: r_ij < s_ij} mu_i . (dT~_ij/ds_ij) mu_j * s_ij/(6 alpha_i)
     Energies, forces, potentials and gradients are multiplied by k_e.
     """
@@ -258,21 +261,31 @@ def evaluate(X, q, alpha, mu, thole_a=2.0, k_e=COULOMB_K, charge=None, dip=None)
     alpha = np.asarray(alpha, np.float64); mu = np.asarray(mu, np.float64)
     n = X.shape[0]
     phi_q, E_q, G_q = charge if charge is not None else charge_fields(X, q)
+    tied = qE is None
+    if tied:
+        qE = q
+        E_e, G_e = E_q, G_q
+    else:
+        qE = np.asarray(qE, np.float64)
+        _, E_e, G_e = charge_E if charge_E is not None else charge_fields(X, qE)
     phi_m, Eu_m, Ed_m, Gd_m = dip if dip is not None else dipole_fields(X, mu, alpha, thole_a)
     pos = alpha > 0
     U_qq = 0.5 * np.sum(q * phi_q)
     A_mu = 0.5 * np.sum(np.sum(mu[pos] ** 2, axis=1) / alpha[pos])
-    U_pol = A_mu - np.sum(mu * E_q) - 0.5 * np.sum(mu * Ed_m)
-    G = G_q + Gd_m
-    F = q[:, None] * (E_q + Eu_m) + np.einsum("ia,iab->ib", mu, G)
-    phi = phi_q + phi_m
-    E_tot = E_q + Ed_m
+    U_pol = A_mu - np.sum(mu * E_e) - 0.5 * np.sum(mu * Ed_m)
+    G = G_e + Gd_m
+    F = q[:, None] * E_q + qE[:, None] * Eu_m + np.einsum("ia,iab->ib", mu, G)
+    phi = phi_q + phi_m if tied else phi_q
+    E_tot = E_e + Ed_m
     g_alpha = np.empty(n)
     g_alpha[pos] = -np.sum(mu[pos] ** 2, axis=1) / (2.0 * alpha[pos] ** 2)
     g_alpha[~pos] = -0.5 * np.sum(E_tot[~pos] ** 2, axis=1)
     g_alpha += thole_alpha_term(X, alpha, mu, thole_a)
-    return dict(U=k_e * (U_qq + U_pol), U_qq=k_e * U_qq, U_pol=k_e * U_pol, F=k_e * F, phi=k_e * phi,
-                grad_alpha=k_e * g_alpha, E_q=E_q, E_mu=Ed_m, E_mu_undamped=Eu_m, G=G)
+    out = dict(U=k_e * (U_qq + U_pol), U_qq=k_e * U_qq, U_pol=k_e * U_pol, F=k_e * F, phi=k_e * phi,
+               grad_alpha=k_e * g_alpha, E_q=E_q, E_mu=Ed_m, E_mu_undamped=Eu_m, G=G)
+    if not tied:
+        out.update(phi_E=k_e * phi_m, E_qE=E_e)
+    return out
 
 
 def thole_alpha_term(X, alpha, mu, thole_a):
@@ -307,24 +320,27 @@ def thole_alpha_term(X, alpha, mu, thole_a):
     return out
 
 
-def solve(X, q, alpha, thole_a=2.0, k_e=COULOMB_K):
-    """Full oracle: exact dipoles (dense LU), energies, forces, potentials and gradients."""
+def solve(X, q, alpha, thole_a=2.0, k_e=COULOMB_K, qE=None):
+    """Full oracle: exact dipoles (dense LU), energies, forces, potentials and gradients.
+    qE: the charges of the static field that polarises the dipoles (None: q)."""
     X = np.asarray(X, np.float64)
     _check_distinct(X)
     charge = charge_fields(X, q)
-    mu = solve_dipoles_dense(X, q, alpha, thole_a, E_q=charge[1])
+    charge_E = None if qE is None else charge_fields(X, qE)
+    mu = solve_dipoles_dense(X, q, alpha, thole_a, E_q=(charge if qE is None else charge_E)[1])
     dip = dipole_fields(X, mu, alpha, thole_a)
-    out = evaluate(X, q, alpha, mu, thole_a, k_e, charge=charge, dip=dip)
+    out = evaluate(X, q, alpha, mu, thole_a, k_e, charge=charge, dip=dip, qE=qE, charge_E=charge_E)
     out["mu"] = mu
     return out
 
 
-def energy_only(X, q, alpha, thole_a=2.0, k_e=COULOMB_K):
-    """Total U at the exact dipoles; U^pol = -1/2 sum mu.E^q holds at the solution."""
-    _, E_q, _ = charge_fields(X, q, want_grad=False)
+def energy_only(X, q, alpha, thole_a=2.0, k_e=COULOMB_K, qE=None):
+    """Total U at the exact dipoles; U^pol = -1/2 sum mu.E^{qE} holds at the solution (qE: the
+    charges of the polarising field, None: q)."""
     phi_q, _, _ = charge_fields(X, q, want_grad=False)
-    mu = solve_dipoles_dense(X, q, alpha, thole_a, E_q=E_q)
-    return k_e * (0.5 * np.sum(np.asarray(q) * phi_q) - 0.5 * np.sum(mu * E_q))
+    _, E_e, _ = charge_fields(X, q if qE is None else qE, want_grad=False)
+    mu = solve_dipoles_dense(X, q, alpha, thole_a, E_q=E_e)
+    return k_e * (0.5 * np.sum(np.asarray(q) * phi_q) - 0.5 * np.sum(mu * E_e))
 
 
 def fields_at(idx, X, q=None, mu=None, alpha=None, thole_a=2.0):

@@ -336,6 +336,61 @@ def test_forces_potentials_alpha_gradients_by_finite_differences(thole):
     assert np.linalg.norm(ga - out["grad_alpha"]) / np.linalg.norm(ga) < 1e-7
 
 
+def test_field_charges_two_sites_closed_form():
+    """Separate charges q^E for the polarising field (Sec. III): on the z axis the dipoles follow
+    the 2x2 closed form with E_1 = -qE_2/r^2, E_2 = qE_1/r^2, and U = q_1 q_2 / r - 1/2 (mu_1 E_1 +
+    mu_2 E_2); with q^E = q it is the plain system."""
+    q = np.array([0.7, -0.4]); qE = np.array([-0.3, 0.5]); a = np.array([1.3, 0.9]); r = 3.1
+    X = np.array([[0.0, 0.0, 0.0], [0.0, 0.0, r]])
+    out = D.solve(X, q, a, thole_a=0.0, k_e=1.0, qE=qE)
+    E1, E2, c = -qE[1] / r**2, qE[0] / r**2, 2 / r**3
+    mu1 = a[0] * (E1 + c * a[1] * E2) / (1 - c * c * a[0] * a[1])
+    mu2 = a[1] * (E2 + c * a[0] * E1) / (1 - c * c * a[0] * a[1])
+    assert out["mu"][0][2] == pytest.approx(mu1, rel=1e-14)
+    assert out["mu"][1][2] == pytest.approx(mu2, rel=1e-14)
+    assert out["U"] == pytest.approx(q[0] * q[1] / r - 0.5 * (mu1 * E1 + mu2 * E2), rel=1e-13)
+    tied = D.solve(X, q, a, thole_a=0.0, k_e=1.0)
+    same = D.solve(X, q, a, thole_a=0.0, k_e=1.0, qE=q.copy())
+    assert same["U"] == pytest.approx(tied["U"], rel=1e-15)
+    assert np.allclose(same["F"], tied["F"], rtol=1e-14, atol=0)
+    assert np.allclose(same["phi"] + same["phi_E"], tied["phi"], rtol=1e-14, atol=0)
+
+
+def test_zero_field_charges_leave_coulomb():
+    """With every q^E zero no atom generates the polarising field: mu = 0, U = U^qq, F = q E^q."""
+    X, q, a = rand_system(8, 31)
+    out = D.solve(X, q, a, thole_a=2.0, k_e=1.0, qE=np.zeros_like(q))
+    assert not np.any(out["mu"])
+    phi, E, _ = D.charge_fields(X, q)
+    assert out["U"] == pytest.approx(0.5 * np.sum(q * phi), rel=1e-14)
+    assert np.allclose(out["F"], q[:, None] * E, rtol=1e-14, atol=0)
+
+
+@pytest.mark.parametrize("thole", [0.0, 2.0])
+def test_field_charges_gradients_by_finite_differences(thole):
+    """With q^E != q: F = -dU/dx, dU/dq = phi, dU/dqE = phi_E = phi^mu and dU/dalpha agree with
+    central differences of the energy at re-converged dipoles."""
+    X, q, a = rand_system(6, 41 if thole else 42, box=5.0, r_min=1.0)
+    qE = np.random.default_rng(43).normal(0, 0.6, q.size)
+    out = D.solve(X, q, a, thole_a=thole, k_e=1.0, qE=qE)
+    h = 1e-5
+    E = lambda X_, q_, e_, a_: D.energy_only(X_, q_, a_, thole, 1.0, qE=e_)
+    n = X.shape[0]
+    Ffd = np.zeros((n, 3)); gq = np.zeros(n); ge = np.zeros(n); ga = np.zeros(n)
+    for i in range(n):
+        for c in range(3):
+            Xp = X.copy(); Xp[i, c] += h; Xm = X.copy(); Xm[i, c] -= h
+            Ffd[i, c] = -(E(Xp, q, qE, a) - E(Xm, q, qE, a)) / (2 * h)
+        d = np.zeros(n); d[i] = h
+        gq[i] = (E(X, q + d, qE, a) - E(X, q - d, qE, a)) / (2 * h)
+        ge[i] = (E(X, q, qE + d, a) - E(X, q, qE - d, a)) / (2 * h)
+        ga[i] = (E(X, q, qE, a + d) - E(X, q, qE, a - d)) / (2 * h)
+    assert np.linalg.norm(Ffd - out["F"]) / np.linalg.norm(Ffd) < 1e-7
+    assert np.linalg.norm(gq - out["phi"]) / np.linalg.norm(gq) < 1e-8
+    assert np.linalg.norm(ge - out["phi_E"]) / np.linalg.norm(ge) < 1e-8
+    assert np.linalg.norm(ga - out["grad_alpha"]) / np.linalg.norm(ga) < 1e-7
+
+
 def test_alpha_gradient_at_zero_polarizability():
     """For alpha_i = 0 the gradient is -|E_i|^2/2 (the limit of -|mu|^2/(2 alpha^2) with mu = alpha E)."""
     X, q, a = rand_system(6, 31)
