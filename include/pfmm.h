@@ -165,6 +165,18 @@ pfmm_status pfmm_solve(pfmm_handle* h, int64_t n, const double* pos, const doubl
                        const double* alpha, double* mu, double* forces, double* phi,
                        pfmm_result* res, void* stream);
 
+/* pfmm_solve with separate charges qE (n, e; device) for the static field that polarises the
+   dipoles (Sec. III: the charges generating the field may differ from the Coulomb ones, and atoms
+   with qE_i = 0 do not contribute to it).  U = U^qq(q) + U^pol with U^pol = sum |mu|^2/(2 alpha)
+   - sum mu.E^{qE} - 1/2 sum mu.E^mu; forces F_i = q_i E^q_i + qE_i E^mu_i + (mu_i.grad)(E^{qE} +
+   E^mu_damped)_i; phi receives dU/dq_i = k_e phi^q_i (the potential of the charges q alone) and
+   phi_E (n, or NULL) dU/dqE_i = k_e phi^mu_i (the potential of the dipoles).  qE = NULL is
+   pfmm_solve (qE = q; phi_E must then be NULL).  Non-finite qE: PFMM_ERR_NONFINITE.  The charges of
+   both sets share the tree, so this costs one more charge pass. */
+pfmm_status pfmm_solve_qe(pfmm_handle* h, int64_t n, const double* pos, const double* q, const double* qE,
+                          const double* alpha, double* mu, double* forces, double* phi, double* phi_E,
+                          pfmm_result* res, void* stream);
+
 /* Gradients of g * U at the state saved by the last successful pfmm_solve on h (needs
    PFMM_SAVE_FOR_BACKWARD).  By stationarity of U^pol in mu (Sec. II.A), no derivative of the
    dipole solve is needed: grad_pos = -g F, grad_q = g phi, grad_alpha = g dU/dalpha with
@@ -172,6 +184,11 @@ pfmm_status pfmm_solve(pfmm_handle* h, int64_t n, const double* pos, const doubl
    (-|E_i|^2/2 for alpha_i = 0).  Each output is n-sized (n x 3 for positions) or NULL to skip. */
 pfmm_status pfmm_backward(pfmm_handle* h, double g, double* grad_pos, double* grad_q,
                           double* grad_alpha, void* stream);
+
+/* pfmm_backward after pfmm_solve_qe: grad_q = g dU/dq (the charges' own potential), grad_qE = g
+   dU/dqE = g k_e phi^mu (n, or NULL).  grad_qE after a solve without qE: PFMM_ERR_INVALID_ARG. */
+pfmm_status pfmm_backward_qe(pfmm_handle* h, double g, double* grad_pos, double* grad_q, double* grad_qE,
+                             double* grad_alpha, void* stream);
 
 /* One FMM field evaluation of fixed sources (Sec. II.B-II.C and the direct part of Sec. III),
    without any scaling by k_e.  Sources: charges q (n, or NULL) and point dipoles mu (n x 3, or

@@ -98,6 +98,10 @@ def _load():
     lib.pfmm_solve.restype = ctypes.c_int
     lib.pfmm_backward.argtypes = [vp, ctypes.c_double, vp, vp, vp, vp]
     lib.pfmm_backward.restype = ctypes.c_int
+    lib.pfmm_solve_qe.argtypes = [vp, ctypes.c_int64, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(Result), vp]
+    lib.pfmm_solve_qe.restype = ctypes.c_int
+    lib.pfmm_backward_qe.argtypes = [vp, ctypes.c_double, vp, vp, vp, vp, vp]
+    lib.pfmm_backward_qe.restype = ctypes.c_int
     lib.pfmm_field.argtypes = [vp, ctypes.c_int64, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.pfmm_field.restype = ctypes.c_int
     lib.pfmm_status_string.argtypes = [ctypes.c_int]

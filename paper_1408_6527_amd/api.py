@@ -86,6 +86,7 @@ class SolveResult:
     residual: float
     residual_max_debye: float
     stats: dict = field(default_factory=dict)
+    phi_E: torch.Tensor | None = None  # dU/dqE with separate field charges (potentials wanted)
 
 
 class Solver:
@@ -116,11 +117,14 @@ class Solver:
     def _raise(self, st):
         raise PFMMError(st, lib.pfmm_last_error(self._h).decode())
 
-    def solve(self, pos, q, alpha, mu_init=None, allow_unconverged=False) -> SolveResult:
+    def solve(self, pos, q, alpha, mu_init=None, allow_unconverged=False, qE=None) -> SolveResult:
+        """qE: separate charges of the static field that polarises the dipoles (None: q)."""
         n = pos.shape[0]
         _check_tensor("pos", pos, (n, 3))
         _check_tensor("q", q, (n,))
         _check_tensor("alpha", alpha, (n,))
+        if qE is not None:
+            _check_tensor("qE", qE, (n,))
         want_f = bool(self.cfg.flags & _lib.PFMM_WANT_FORCES)
         want_p = bool(self.cfg.flags & _lib.PFMM_WANT_POTENTIALS)
         mu = torch.empty((n, 3), dtype=torch.float64, device=pos.device)
@@ -131,9 +135,10 @@ class Solver:
             mu.copy_(mu_init)
         F = torch.empty((n, 3), dtype=torch.float64, device=pos.device) if want_f else None
         phi = torch.empty((n,), dtype=torch.float64, device=pos.device) if want_p else None
+        phiE = torch.empty((n,), dtype=torch.float64, device=pos.device) if (want_p and qE is not None) else None
         res = _lib.Result()
-        st = lib.pfmm_solve(self._h, n, _ptr(pos), _ptr(q), _ptr(alpha), _ptr(mu), _ptr(F), _ptr(phi),
-                            ctypes.byref(res), _stream())
+        st = lib.pfmm_solve_qe(self._h, n, _ptr(pos), _ptr(q), _ptr(qE), _ptr(alpha), _ptr(mu), _ptr(F),
+                               _ptr(phi), _ptr(phiE), ctypes.byref(res), _stream())
         if st != 0 and not (allow_unconverged and st == 4):
             self._raise(st)
         self.last_result = res
@@ -146,18 +151,21 @@ class Solver:
                      t_kernel_ms=dict(zip(_lib.KERNEL_CLASSES, res.t_kernel_ms)),
                      kernel_launches=dict(zip(_lib.KERNEL_CLASSES, res.kernel_launches)))
         return SolveResult(res.U_total, res.U_qq, res.U_pol, mu, F, phi, res.iters, res.residual,
-                           res.residual_max_debye, stats)
+                           res.residual_max_debye, stats, phiE)
 
-    def backward(self, g=1.0, want_pos=True, want_q=True, want_alpha=True, n=None):
+    def backward(self, g=1.0, want_pos=True, want_q=True, want_alpha=True, n=None, want_qE=False):
+        """Gradients of g U: (grad_pos, grad_q, grad_alpha), plus grad_qE last with want_qE (after a
+        solve with qE)."""
         n = n if n is not None else self._n_last
         dev = torch.device("cuda", torch.cuda.current_device())
         gp = torch.empty((n, 3), dtype=torch.float64, device=dev) if want_pos else None
         gq = torch.empty((n,), dtype=torch.float64, device=dev) if want_q else None
         ga = torch.empty((n,), dtype=torch.float64, device=dev) if want_alpha else None
-        st = lib.pfmm_backward(self._h, float(g), _ptr(gp), _ptr(gq), _ptr(ga), _stream())
+        ge = torch.empty((n,), dtype=torch.float64, device=dev) if want_qE else None
+        st = lib.pfmm_backward_qe(self._h, float(g), _ptr(gp), _ptr(gq), _ptr(ge), _ptr(ga), _stream())
         if st != 0:
             self._raise(st)
-        return gp, gq, ga
+        return (gp, gq, ga, ge) if want_qE else (gp, gq, ga)
 
     def field(self, pos, q=None, mu=None, alpha=None):
         """phi, E (undamped dipole part), E_damped and grad E_damped (n x 3 x 3) of the sources."""

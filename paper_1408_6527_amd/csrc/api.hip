@@ -158,13 +158,15 @@ struct pfmm_handle {
   DevBuf w_M, w_F, w_M32;
   // fields (sorted order)
   DevBuf f_phiq, f_Eq, f_Eq2, f_Gq, f_phim, f_Eum, f_Edm, f_Gm, f_E;
+  DevBuf f_phiqE, f_EqE, f_EqE2, f_GqE, w_PE, w_qEs;  // the field charges q^E and their field
   // solver
   DevBuf cg_y, cg_r, cg_p, cg_Ap, w_red, w_state, w_ep, w_dal;
   // preconditioner: z, inner residual, direction and product, near field, dipoles
   DevBuf pc_z, pc_r, pc_p, pc_Ap, pc_E, pc_mu4;
   // saved for backward
-  DevBuf s_F, s_phi, s_Etot;
+  DevBuf s_F, s_phi, s_Etot, s_phiE;
   bool saved = false;
+  bool saved_qE = false;  // the saved solve had separate field charges q^E
   int saved_n = 0;
   HostPinned pinned;
   std::string err;
@@ -389,8 +391,11 @@ void build_tree(pfmm_handle* h, int n, const double* pos, const double* q, const
 
 // One FMM evaluation: sources 1 = charges, 2 = dipoles (mu4), 3 = both.
 // mode 0: Ed only; mode 1: phi, Eu, Ed, G.
+// pa_src replaces the handle's particles as sources and targets (same positions and order; the
+// field charges q^E in place of q).
 void fmm_pass(pfmm_handle* h, int sources, int mode, FieldOut out, int* err, const int* done,
-              hipStream_t s, const int* qcap = nullptr) {
+              hipStream_t s, const int* qcap = nullptr, const Particles* pa_src = nullptr) {
+  const Particles& pa = pa_src ? *pa_src : h->pa;
   const TreeView& t = h->tv;
   const OpTables& op = h->op;
   const bool fp32 = h->cfg.precision == PFMM_MIXED;
@@ -401,7 +406,7 @@ void fmm_pass(pfmm_handle* h, int sources, int mode, FieldOut out, int* err, con
   KernelTimer& kt = h->kt;
   if (t.L >= 2) {
     int e = kt.begin();
-    launch_p2m(t, op, h->pa, mu4, sources, h->cfg.dipole_pair_dl, M, done, s);
+    launch_p2m(t, op, pa, mu4, sources, h->cfg.dipole_pair_dl, M, done, s);
     kt.end(KC_P2M, e);
     e = kt.begin();
     for (int lp = t.L - 1; lp >= 2; --lp) launch_m2m(t, op, lp, M, done, s);
@@ -418,7 +423,7 @@ void fmm_pass(pfmm_handle* h, int sources, int mode, FieldOut out, int* err, con
     for (int lc = 2; lc <= t.L; ++lc) launch_l2l(t, op, lc, F, h->nsplit, h->split_stride, done, s);
     kt.end(KC_L2L, e);
     e = kt.begin();
-    launch_l2p(t, op, h->pa, F, mode, out, done, s);
+    launch_l2p(t, op, pa, F, mode, out, done, s);
     kt.end(KC_L2P, e);
   } else {
     launch_fill_double(out.Ed, 3 * (int64_t)n, 0.0, s);
@@ -429,7 +434,7 @@ void fmm_pass(pfmm_handle* h, int sources, int mode, FieldOut out, int* err, con
     }
   }
   int e = kt.begin();
-  launch_p2p(t, h->pa, mu4, mode == 0 ? 0 : 1, sources, fp32, out, nullptr, err, done, s);
+  launch_p2p(t, pa, mu4, mode == 0 ? 0 : 1, sources, fp32, out, nullptr, err, done, s);
   kt.end(mode == 0 ? KC_P2P_SCF : KC_P2P_FULL, e);
   h->n_evals += 1;
 }
@@ -475,9 +480,9 @@ void check_flag(pfmm_handle* h, int* dflag, hipStream_t s) {
   if (f) throw Error(PFMM_ERR_COINCIDENT, "two particles share the same position");
 }
 
-pfmm_status solve_impl(pfmm_handle* h, int64_t n64, const double* pos, const double* q,
-                       const double* alpha, double* mu, double* forces, double* phi, pfmm_result* res,
-                       hipStream_t s) {
+pfmm_status solve_impl(pfmm_handle* h, int64_t n64, const double* pos, const double* q, const double* qE,
+                       const double* alpha, double* mu, double* forces, double* phi, double* phi_E,
+                       pfmm_result* res, hipStream_t s) {
   const pfmm_config& c = h->cfg;
   if (n64 < 0 || n64 > INT_MAX / 8) throw Error(PFMM_ERR_INVALID_ARG, "n out of range");
   if (!res) throw Error(PFMM_ERR_INVALID_ARG, "res is NULL");
@@ -487,6 +492,7 @@ pfmm_status solve_impl(pfmm_handle* h, int64_t n64, const double* pos, const dou
   const bool want_f = (c.flags & PFMM_WANT_FORCES) != 0;
   const bool want_phi = (c.flags & PFMM_WANT_POTENTIALS) != 0;
   if (n > 0 && (!pos || !q || !alpha || !mu)) throw Error(PFMM_ERR_INVALID_ARG, "NULL input or mu");
+  if (phi_E && !qE) throw Error(PFMM_ERR_INVALID_ARG, "phi_E needs the field charges qE");
   if (n > 0 && want_f && !forces) throw Error(PFMM_ERR_INVALID_ARG, "forces is NULL with PFMM_WANT_FORCES");
   if (n > 0 && want_phi && !phi) throw Error(PFMM_ERR_INVALID_ARG, "phi is NULL with PFMM_WANT_POTENTIALS");
   if (n == 0) return PFMM_OK;
@@ -503,6 +509,14 @@ pfmm_status solve_impl(pfmm_handle* h, int64_t n64, const double* pos, const dou
     sync_read(h, fl, &f, sizeof(int), s);
     if (f) throw Error(PFMM_ERR_NONFINITE, "non-finite warm-start dipole");
   }
+  if (qE) {
+    int* fl = dev<int>(h->w_flags, 4);
+    launch_fill_int(fl, 1, 0, s);
+    launch_check_finite(qE, n64, fl, s);
+    int f = 0;
+    sync_read(h, fl, &f, sizeof(int), s);
+    if (f) throw Error(PFMM_ERR_NONFINITE, "non-finite field charge qE");
+  }
   build_tree(h, n, pos, q, alpha, s);
   tm.mark();
   const Particles& pa = h->pa;
@@ -517,6 +531,23 @@ pfmm_status solve_impl(pfmm_handle* h, int64_t n64, const double* pos, const dou
   double* Gq = dev<double>(h->f_Gq, 6 * (int64_t)n);
   fmm_pass(h, 1, 1, FieldOut{phiq, Eq, Eq2, Gq}, err, nullptr, s);
   check_flag(h, err, s);
+  // the static field that polarises the dipoles: that of the field charges q^E when they are given
+  // (a second charge pass over the same tree), else that of q
+  FieldCharges fc{nullptr, Eq, Gq};
+  if (qE) {
+    double4* PE = dev<double4>(h->w_PE, n);
+    double* qEs = dev<double>(h->w_qEs, n);
+    launch_field_charges(h->w_perm.as<int>(), n, pa.P, qE, PE, qEs, s);
+    Particles pe = pa;
+    pe.P = PE;
+    double* EqE = dev<double>(h->f_EqE, 3 * (int64_t)n);
+    double* GqE = dev<double>(h->f_GqE, 6 * (int64_t)n);
+    fmm_pass(h, 1, 1, FieldOut{dev<double>(h->f_phiqE, n), EqE, dev<double>(h->f_EqE2, 3 * (int64_t)n), GqE},
+             err, nullptr, s, nullptr, &pe);
+    check_flag(h, err, s);
+    fc = FieldCharges{qEs, EqE, GqE};
+  }
+  const double* Ee = fc.E;
   tm.mark();
 
   // stage 2: conjugate gradients
@@ -572,6 +603,7 @@ pfmm_status solve_impl(pfmm_handle* h, int64_t n64, const double* pos, const dou
   double* Gm = dev<double>(h->f_Gm, 6 * (int64_t)n);
   double* Fs = dev<double>(h->s_F, 3 * (int64_t)n);
   double* phs = dev<double>(h->s_phi, n);
+  double* phEs = dev<double>(h->s_phiE, n);
   double* Ets = dev<double>(h->s_Etot, 3 * (int64_t)n);
   EnergyParts* ep = static_cast<EnergyParts*>(h->w_ep.reserve(sizeof(EnergyParts)));
   CGState hs{};
@@ -584,12 +616,12 @@ pfmm_status solve_impl(pfmm_handle* h, int64_t n64, const double* pos, const dou
     if (pc && !warm_now) {
       // the preconditioned solve starts from y0 = 0: r0 = S E^q costs no field evaluation, and
       // p0 = z0 is a better first direction than the Jacobi guess alpha E^q
-      launch_cg_init_zero(pa, Eq, y, r, part, st, c.scf_tol, s);
+      launch_cg_init_zero(pa, Ee, y, r, part, st, c.scf_tol, s);
     } else {
-      launch_cg_init(pa, Eq, mu4, warm_now, y, pv, mu4, part, st, s);
+      launch_cg_init(pa, Ee, mu4, warm_now, y, pv, mu4, part, st, s);
       fmm_pass(h, 2, 0, fo, err, nullptr, s);
       ++full_evals;
-      launch_cg_residual0(pa, Eq, E, y, r, pv, part, st, c.scf_tol, s);
+      launch_cg_residual0(pa, Ee, E, y, r, pv, part, st, c.scf_tol, s);
     }
     if (pc) {
       precondition(s);
@@ -645,8 +677,9 @@ pfmm_status solve_impl(pfmm_handle* h, int64_t n64, const double* pos, const dou
     fmm_pass(h, 2, 1, FieldOut{phim, Eum, Edm, Gm}, err, nullptr, s);
     ++full_evals;
     tm.mark();
-    launch_assemble(pa, h->w_perm.as<int>(), mu4, phiq, Eq, Gq, phim, Eum, Edm, Gm, c.coulomb_k, mu,
-                    want_f ? forces : nullptr, want_phi ? phi : nullptr, Fs, phs, Ets, part, ep, s);
+    launch_assemble(pa, h->w_perm.as<int>(), mu4, phiq, Eq, fc, phim, Eum, Edm, Gm, c.coulomb_k, mu,
+                    want_f ? forces : nullptr, want_phi ? phi : nullptr, phi_E, Fs, phs, phEs, Ets, part, ep,
+                    s);
     tm.mark();
     sync_read(h, ep, &he, sizeof(he), s);
     const double true_res = he.bn2 > 0.0 ? std::sqrt(he.res2 / he.bn2) : 0.0;
@@ -703,6 +736,7 @@ pfmm_status solve_impl(pfmm_handle* h, int64_t n64, const double* pos, const dou
   res->scf_restarts = restarts;
   h->saved = true;
   h->saved_n = n;
+  h->saved_qE = qE != nullptr;
   if (hs.notspd) throw Error(PFMM_ERR_NOT_SPD, "conjugate gradients met p.Ap <= 0: the dipole system is not positive definite");
   if (!hs.done || (hs.maxed && hs.res > c.scf_tol))
     throw Error(PFMM_ERR_NOT_CONVERGED, "dipole solve did not converge: residual " + std::to_string(hs.res) +
@@ -784,10 +818,16 @@ void pfmm_destroy(pfmm_handle* h) { delete h; }
 
 pfmm_status pfmm_solve(pfmm_handle* h, int64_t n, const double* pos, const double* q, const double* alpha,
                        double* mu, double* forces, double* phi, pfmm_result* res, void* stream) {
+  return pfmm_solve_qe(h, n, pos, q, nullptr, alpha, mu, forces, phi, nullptr, res, stream);
+}
+
+pfmm_status pfmm_solve_qe(pfmm_handle* h, int64_t n, const double* pos, const double* q, const double* qE,
+                          const double* alpha, double* mu, double* forces, double* phi, double* phi_E,
+                          pfmm_result* res, void* stream) {
   if (!h) return PFMM_ERR_INVALID_ARG;
   h->err.clear();
   try {
-    return solve_impl(h, n, pos, q, alpha, mu, forces, phi, res, (hipStream_t)stream);
+    return solve_impl(h, n, pos, q, qE, alpha, mu, forces, phi, phi_E, res, (hipStream_t)stream);
   } catch (const Error& e) {
     return fail(h, e);
   } catch (const std::bad_alloc&) {
@@ -798,12 +838,19 @@ pfmm_status pfmm_solve(pfmm_handle* h, int64_t n, const double* pos, const doubl
 
 pfmm_status pfmm_backward(pfmm_handle* h, double g, double* grad_pos, double* grad_q, double* grad_alpha,
                           void* stream) {
+  return pfmm_backward_qe(h, g, grad_pos, grad_q, nullptr, grad_alpha, stream);
+}
+
+pfmm_status pfmm_backward_qe(pfmm_handle* h, double g, double* grad_pos, double* grad_q, double* grad_qE,
+                             double* grad_alpha, void* stream) {
   if (!h) return PFMM_ERR_INVALID_ARG;
   h->err.clear();
   try {
     if (!h->saved || !(h->cfg.flags & PFMM_SAVE_FOR_BACKWARD))
       throw Error(PFMM_ERR_NO_STATE, "pfmm_backward needs a preceding successful pfmm_solve with PFMM_SAVE_FOR_BACKWARD");
     if (!std::isfinite(g)) throw Error(PFMM_ERR_NONFINITE, "non-finite upstream gradient");
+    if (grad_qE && !h->saved_qE)
+      throw Error(PFMM_ERR_INVALID_ARG, "grad_qE needs a preceding solve with field charges qE");
     hipStream_t s = (hipStream_t)stream;
     const int n = h->saved_n;
     if (n == 0) return PFMM_OK;
@@ -813,8 +860,8 @@ pfmm_status pfmm_backward(pfmm_handle* h, double g, double* grad_pos, double* gr
       launch_p2p(h->tv, h->pa, h->w_mu4.as<double4>(), 2, 2, false, FieldOut{}, dal, nullptr, nullptr, s);
     }
     launch_backward(h->pa, h->w_perm.as<int>(), h->w_mu4.as<double4>(), h->s_F.as<double>(),
-                    h->s_phi.as<double>(), h->s_Etot.as<double>(), dal, h->cfg.coulomb_k, g, grad_pos,
-                    grad_q, grad_alpha, s);
+                    h->s_phi.as<double>(), h->s_Etot.as<double>(), h->s_phiE.as<double>(), dal,
+                    h->cfg.coulomb_k, g, grad_pos, grad_q, grad_qE, grad_alpha, s);
     return PFMM_OK;
   } catch (const Error& e) {
     return fail(h, e);

@@ -173,14 +173,25 @@ void launch_pc_init(int n3, const double* r, double* z, double* ri, double* pi, 
                     CGState* inner, const CGState* outer, hipStream_t s);
 
 struct EnergyParts { double Uqq, Amu, muEq, muEd, res2, bn2, resmax; };
+// The static field that polarises the dipoles, from the charges q^E (Sec. III): qE (sorted) or
+// nullptr when q^E = q, and that field E (n x 3) and its gradient G (n x 6).
+struct FieldCharges {
+  const double* qE = nullptr;
+  const double* E = nullptr;
+  const double* G = nullptr;
+};
 void launch_assemble(const Particles& pa, const int* perm, const double4* mu4, const double* phiq,
-                     const double* Eq, const double* Gq, const double* phim, const double* Eum,
+                     const double* Eq, const FieldCharges& fc, const double* phim, const double* Eum,
                      const double* Edm, const double* Gm, double k_e, double* mu_out,
-                     double* F_out, double* phi_out, double* F_s, double* phi_s, double* Etot_s,
-                     double* part, EnergyParts* ep, hipStream_t s);
+                     double* F_out, double* phi_out, double* phiE_out, double* F_s, double* phi_s,
+                     double* phiE_s, double* Etot_s, double* part, EnergyParts* ep, hipStream_t s);
 void launch_backward(const Particles& pa, const int* perm, const double4* mu4, const double* F_s,
-                     const double* phi_s, const double* Etot_s, const double* dal_thole, double k_e,
-                     double g, double* gpos, double* gq, double* galpha, hipStream_t s);
+                     const double* phi_s, const double* Etot_s, const double* phiE_s, const double* dal_thole,
+                     double k_e, double g, double* gpos, double* gq, double* gqE, double* galpha,
+                     hipStream_t s);
+// PE[i] = (P[i].xyz, qE[perm[i]]), qEs[i] = qE[perm[i]]
+void launch_field_charges(const int* perm, int n, const double4* P, const double* qE, double4* PE,
+                          double* qEs, hipStream_t s);
 void launch_unpermute_field(const int* perm, int n, const FieldOut& src, double* phi, double* E,
                             double* Ed, double* G9, hipStream_t s);
 void launch_permute_dipoles(const int* perm, int n, const double* mu_in, const double* tau,

@@ -341,39 +341,48 @@ __global__ __launch_bounds__(TPB) void k_pc_init_finish(const double* part, int 
 __device__ inline double m3(const double4& u, int c) { return c == 0 ? u.x : (c == 1 ? u.y : u.z); }
 
 // Energies, forces, potentials; outputs un-permuted to the caller's order.
+// Energies, forces and potentials at the converged dipoles (Sec. II.A), with the static field
+// E^{qE} of the charges q^E that polarise the dipoles (Sec. III; fc.qE == nullptr: q^E = q and
+// fc.E, fc.G are the Coulomb charges' own field):
+//   U^qq = 1/2 sum q phi^q,  U^pol = sum |mu|^2/(2 alpha) - sum mu.E^{qE} - 1/2 sum mu.E^mu_d,
+//   F_i = q_i E^q_i + qE_i E^mu_u,i + (mu_i.grad)(E^{qE} + E^mu_d)_i,
+//   dU/dq_i = phi^q_i (+ phi^mu_i when q^E = q),  dU/dqE_i = phi^mu_i.
 __global__ __launch_bounds__(TPB) void k_assemble(
     Particles pa, const int* __restrict__ perm, const double4* __restrict__ mu4,
-    const double* __restrict__ phiq, const double* __restrict__ Eq, const double* __restrict__ Gq,
+    const double* __restrict__ phiq, const double* __restrict__ Eq, FieldCharges fc,
     const double* __restrict__ phim, const double* __restrict__ Eum, const double* __restrict__ Edm,
     const double* __restrict__ Gm, double k_e, double* __restrict__ mu_out, double* __restrict__ F_out,
-    double* __restrict__ phi_out, double* __restrict__ F_s, double* __restrict__ phi_s,
-    double* __restrict__ Etot_s, double* __restrict__ part) {
+    double* __restrict__ phi_out, double* __restrict__ phiE_out, double* __restrict__ F_s,
+    double* __restrict__ phi_s, double* __restrict__ phiE_s, double* __restrict__ Etot_s,
+    double* __restrict__ part) {
   double v[6] = {0, 0, 0, 0, 0, 0};
   double vmax = 0.0;
+  const bool sep = fc.qE != nullptr;
   GRID_STRIDE(i, pa.n) {
     const int o = perm[i];
     const double q = pa.P[i].w, a = pa.alpha[i];
+    const double qe = sep ? fc.qE[i] : q;
     const double4 u = mu4[i];
     const double mu[3] = {u.x, u.y, u.z};
     v[0] += 0.5 * q * phiq[i];
     double mm = mu[0] * mu[0] + mu[1] * mu[1] + mu[2] * mu[2];
     if (a > 0.0) v[1] += 0.5 * mm / a;
     double G[6];
-    for (int k = 0; k < 6; ++k) G[k] = Gq[6 * i + k] + Gm[6 * i + k];
+    for (int k = 0; k < 6; ++k) G[k] = fc.G[6 * i + k] + Gm[6 * i + k];
     // G as xx, yy, zz, xy, xz, yz; (mu.grad) E_b = sum_a mu_a d_a E_b
     const double gm[3] = {mu[0] * G[0] + mu[1] * G[3] + mu[2] * G[4],
                           mu[0] * G[3] + mu[1] * G[1] + mu[2] * G[5],
                           mu[0] * G[4] + mu[1] * G[5] + mu[2] * G[2]};
     double rl2 = 0.0;
     for (int c = 0; c < 3; ++c) {
-      const double eq = Eq[3 * i + c], ed = Edm[3 * i + c], eu = Eum[3 * i + c];
-      v[2] += mu[c] * eq;
+      const double eq = Eq[3 * i + c], ee = fc.E[3 * i + c], ed = Edm[3 * i + c], eu = Eum[3 * i + c];
+      v[2] += mu[c] * ee;
       v[3] += mu[c] * ed;
-      const double et = eq + ed;
+      const double et = ee + ed;
       const double rc = a * et - mu[c];
       rl2 += rc * rc;
-      v[5] += a * a * eq * eq;
-      const double f = k_e * (q * (eq + eu) + gm[c]);
+      v[5] += a * a * ee * ee;
+      const double f = k_e * ((sep ? q * eq + qe * eu : q * (eq + eu)) + gm[c]);
       if (F_out) F_out[3 * o + c] = f;
       F_s[3 * i + c] = f;
       Etot_s[3 * i + c] = et;
@@ -381,9 +390,12 @@ __global__ __launch_bounds__(TPB) void k_assemble(
     }
     v[4] += rl2;
     vmax = fmax(vmax, sqrt(rl2));
-    const double ph = k_e * (phiq[i] + phim[i]);
+    const double ph = k_e * (sep ? phiq[i] : phiq[i] + phim[i]);
     phi_s[i] = ph;
     if (phi_out) phi_out[o] = ph;
+    const double pe = k_e * phim[i];
+    phiE_s[i] = pe;
+    if (phiE_out) phiE_out[o] = pe;
   }
   block_sum<6>(v, part);
   __shared__ double mx[TPB];
@@ -419,14 +431,16 @@ __global__ __launch_bounds__(TPB) void k_backward(Particles pa, const int* __res
                                                   const double* __restrict__ F_s,
                                                   const double* __restrict__ phi_s,
                                                   const double* __restrict__ Etot_s,
+                                                  const double* __restrict__ phiE_s,
                                                   const double* __restrict__ dal, double k_e, double g,
                                                   double* __restrict__ gpos, double* __restrict__ gq,
-                                                  double* __restrict__ ga) {
+                                                  double* __restrict__ gqE, double* __restrict__ ga) {
   GRID_STRIDE(i, pa.n) {
     const int o = perm[i];
     if (gpos)
       for (int c = 0; c < 3; ++c) gpos[3 * o + c] = -g * F_s[3 * i + c];
     if (gq) gq[o] = g * phi_s[i];
+    if (gqE) gqE[o] = g * phiE_s[i];
     if (ga) {
       const double a = pa.alpha[i];
       const double4 u = mu4[i];
@@ -469,6 +483,19 @@ __global__ __launch_bounds__(TPB) void k_permute_dipoles(const int* __restrict__
   GRID_STRIDE(i, n) {
     const int o = perm[i];
     mu4[i] = make_double4(mu[3 * o], mu[3 * o + 1], mu[3 * o + 2], tau[i]);
+  }
+}
+
+// sorted copy of the field charges: PE = (x, y, z, qE) of each sorted particle, qEs = qE sorted
+__global__ __launch_bounds__(TPB) void k_field_charges(const int* __restrict__ perm, int n,
+                                                       const double4* __restrict__ P,
+                                                       const double* __restrict__ qE,
+                                                       double4* __restrict__ PE, double* __restrict__ qEs) {
+  GRID_STRIDE(i, n) {
+    const double e = qE[perm[i]];
+    const double4 p = P[i];
+    PE[i] = make_double4(p.x, p.y, p.z, e);
+    qEs[i] = e;
   }
 }
 
@@ -566,22 +593,29 @@ void launch_cg_direction(int n3, const double* r, double* pvec, const CGState* s
 }
 
 void launch_assemble(const Particles& pa, const int* perm, const double4* mu4, const double* phiq,
-                     const double* Eq, const double* Gq, const double* phim, const double* Eum,
+                     const double* Eq, const FieldCharges& fc, const double* phim, const double* Eum,
                      const double* Edm, const double* Gm, double k_e, double* mu_out, double* F_out,
-                     double* phi_out, double* F_s, double* phi_s, double* Etot_s, double* part,
-                     EnergyParts* ep, hipStream_t s) {
+                     double* phi_out, double* phiE_out, double* F_s, double* phi_s, double* phiE_s,
+                     double* Etot_s, double* part, EnergyParts* ep, hipStream_t s) {
   const int g = grid(pa.n);
-  hipLaunchKernelGGL(k_assemble, dim3(g), dim3(TPB), 0, s, pa, perm, mu4, phiq, Eq, Gq, phim, Eum, Edm,
-                     Gm, k_e, mu_out, F_out, phi_out, F_s, phi_s, Etot_s, part);
+  hipLaunchKernelGGL(k_assemble, dim3(g), dim3(TPB), 0, s, pa, perm, mu4, phiq, Eq, fc, phim, Eum, Edm,
+                     Gm, k_e, mu_out, F_out, phi_out, phiE_out, F_s, phi_s, phiE_s, Etot_s, part);
   hipLaunchKernelGGL(k_assemble_finish, dim3(1), dim3(TPB), 0, s, part, g, ep);
   PFMM_LAUNCH_CHECK();
 }
 
 void launch_backward(const Particles& pa, const int* perm, const double4* mu4, const double* F_s,
-                     const double* phi_s, const double* Etot_s, const double* dal_thole, double k_e,
-                     double g, double* gpos, double* gq, double* galpha, hipStream_t s) {
+                     const double* phi_s, const double* Etot_s, const double* phiE_s, const double* dal_thole,
+                     double k_e, double g, double* gpos, double* gq, double* gqE, double* galpha,
+                     hipStream_t s) {
   hipLaunchKernelGGL(k_backward, dim3(grid(pa.n)), dim3(TPB), 0, s, pa, perm, mu4, F_s, phi_s, Etot_s,
-                     dal_thole, k_e, g, gpos, gq, galpha);
+                     phiE_s, dal_thole, k_e, g, gpos, gq, gqE, galpha);
+  PFMM_LAUNCH_CHECK();
+}
+
+void launch_field_charges(const int* perm, int n, const double4* P, const double* qE, double4* PE,
+                          double* qEs, hipStream_t s) {
+  hipLaunchKernelGGL(k_field_charges, dim3(grid(n)), dim3(TPB), 0, s, perm, n, P, qE, PE, qEs);
   PFMM_LAUNCH_CHECK();
 }
 

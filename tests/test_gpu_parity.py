@@ -349,6 +349,71 @@ def test_backward_gradients_match_oracle(api):
     assert relmax(N(ga), 2.0 * ref["grad_alpha"]) < 1e-9
 
 
+def test_field_charges_one_leaf_equals_dense_oracle(api):
+    """Separate charges q^E for the polarising field (Sec. III), everything direct (one leaf): dipoles,
+    energy, forces, dU/dq, dU/dqE and every backward gradient equal the dense oracle's; some q^E are
+    zero (atoms that do not generate the field) and one site is not polarisable."""
+    print_case("field charges one leaf n=120")
+    X, q, a, _ = cube(120, 7.5, 11)
+    a[3] = 0.0
+    qE = np.random.default_rng(12).normal(0, 0.6, 120)
+    qE[::7] = 0.0
+    ref = D.solve(X, q, a, thole_a=2.0, qE=qE)
+    s = api.Solver(order_p=4, ws=1, leaf_width=50.0, scf_tol=1e-13, scf_max_iter=300)
+    r = s.solve(T(X), T(q), T(a), qE=T(qE))
+    assert r.stats["levels"] == 0
+    assert relmax(N(r.mu), ref["mu"]) < 1e-10
+    assert abs(r.U - ref["U"]) < 1e-10 * abs(ref["U"])
+    assert abs(r.U_qq - ref["U_qq"]) < 1e-11 * abs(ref["U_qq"])
+    assert relmax(N(r.forces), ref["F"]) < 1e-10
+    assert relmax(N(r.phi), ref["phi"]) < 1e-10
+    assert relmax(N(r.phi_E), ref["phi_E"]) < 1e-10
+    assert r.residual < 1e-12
+    gp, gq, ga, ge = s.backward(2.0, want_qE=True)
+    assert relmax(N(gp), -2.0 * ref["F"]) < 1e-10
+    assert relmax(N(gq), 2.0 * ref["phi"]) < 1e-10
+    assert relmax(N(ge), 2.0 * ref["phi_E"]) < 1e-10
+    assert relmax(N(ga), 2.0 * ref["grad_alpha"]) < 1e-9
+    # q^E = q is the plain solve; grad_qE needs a solve with q^E
+    tied = api.Solver(order_p=4, ws=1, leaf_width=50.0, scf_tol=1e-13, scf_max_iter=300)
+    rt = tied.solve(T(X), T(q), T(a))
+    rs = s.solve(T(X), T(q), T(a), qE=T(q))
+    assert abs(rs.U - rt.U) < 1e-13 * abs(rt.U)
+    assert relmax(N(rs.forces), N(rt.forces)) < 1e-13
+    assert relmax(N(rs.phi) + N(rs.phi_E), N(rt.phi)) < 1e-13
+    with pytest.raises(api.PFMMError):
+        tied.backward(1.0, want_qE=True)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_field_charges_fmm_solve_matches_oracle_fmm(api, precision):
+    """Separate q^E with the FMM (1,000 particles, p = 4, ws = 1): the oracle's FMM fields of q, of
+    q^E and of the library's dipoles give the library's residual, energy, forces and both
+    potentials (float64 path); the mixed path stays within its float32 error of them."""
+    print_case(f"field charges fmm solve {precision}")
+    from paper_1408_6527_amd import inputs
+    ps = inputs.uniform_cube(1000)
+    qE = np.random.default_rng(13).normal(0, 0.8, ps.n)
+    lw = 2.6
+    s = api.Solver(order_p=4, ws=1, leaf_width=lw, scf_tol=1e-10, precision=precision)
+    r = s.solve(T(ps.pos), T(ps.q), T(ps.alpha), qE=T(qE))
+    mu = N(r.mu)
+    st1 = FM.fmm_fields(ps.pos, ps.q, None, ps.alpha, 2.0, 4, lw, 1)
+    stE = FM.fmm_fields(ps.pos, qE, None, ps.alpha, 2.0, 4, lw, 1)
+    st3 = FM.fmm_fields(ps.pos, None, mu, ps.alpha, 2.0, 4, lw, 1)
+    res = np.linalg.norm(ps.alpha[:, None] * (stE["E_d"] + st3["E_d"]) - mu) / np.linalg.norm(ps.alpha[:, None] * stE["E_d"])
+    ev = D.evaluate(ps.pos, ps.q, ps.alpha, mu, 2.0, D.COULOMB_K,
+                    charge=(st1["phi"], st1["E_d"], st1["G_d"]),
+                    dip=(st3["phi"], st3["E_u"], st3["E_d"], st3["G_d"]),
+                    qE=qE, charge_E=(stE["phi"], stE["E_d"], stE["G_d"]))
+    tol = 1e-10 if precision == "fp64" else 1e-5
+    assert res < (2e-10 if precision == "fp64" else 1e-5)
+    assert abs(r.U - ev["U"]) < tol * abs(ev["U"])
+    assert relnorm(N(r.forces), ev["F"]) < tol
+    assert relnorm(N(r.phi), ev["phi"]) < tol
+    assert relnorm(N(r.phi_E), ev["phi_E"]) < tol
+
+
 def test_autograd_function_against_finite_differences(api):
     import torch
     print_case("autograd fd")
