@@ -108,17 +108,34 @@ def _check_distinct(X):
             raise ValueError("coincident particles")
 
 
-def charge_fields(X: np.ndarray, q: np.ndarray, want_grad: bool = True):
-    """Potential, field and field gradient of the point charges at every particle, j != i.
+def exclusion_matrix(n, excl=None):
+    """n x n boolean matrix of the excluded pairs: the starred sums of Sec. II.A skip them (bonded
+    pairs in a force field).  excl lists unordered pairs (i, j), i != j, as an (m, 2) array."""
+    M = np.zeros((n, n), bool)
+    if excl is not None and len(excl):
+        e = np.asarray(excl, np.int64).reshape(-1, 2)
+        M[e[:, 0], e[:, 1]] = True
+        M[e[:, 1], e[:, 0]] = True
+    return M
 
-    phi_i = sum_j q_j / r_ij;  E_i = -grad phi_i = sum_j q_j r_ij / r_ij^3;
-    G_i[a, b] = d_a E_b.  No exclusions (every pair j != i counts).
+
+def _partners(n, i, ex):
+    return (np.arange(n) != i) & ~ex[i]
+
+
+def charge_fields(X: np.ndarray, q: np.ndarray, want_grad: bool = True, excl=None):
+    """Potential, field and field gradient of the point charges at every particle, j != i and
+    (i, j) not excluded.
+
+    phi_i = sum*_j q_j / r_ij;  E_i = -grad phi_i = sum*_j q_j r_ij / r_ij^3;
+    G_i[a, b] = d_a E_b.
     """
     X = np.asarray(X, np.float64); q = np.asarray(q, np.float64)
     n = X.shape[0]
+    ex = exclusion_matrix(n, excl)
     phi = np.zeros(n); E = np.zeros((n, 3)); G = np.zeros((n, 3, 3))
     for i in range(n):
-        mask = np.arange(n) != i
+        mask = _partners(n, i, ex)
         rv = X[i] - X[mask]
         g, grad, H, _ = hessian_and_third(rv)
         phi[i] = np.sum(q[mask] * g)
@@ -128,17 +145,18 @@ def charge_fields(X: np.ndarray, q: np.ndarray, want_grad: bool = True):
     return phi, E, G
 
 
-def dipole_fields(X, mu, alpha, thole_a, want_grad: bool = True):
-    """Fields of the point dipoles mu_j at every particle, j != i.
+def dipole_fields(X, mu, alpha, thole_a, want_grad: bool = True, excl=None):
+    """Fields of the point dipoles mu_j at every particle, j != i and (i, j) not excluded.
 
     Returns phi (undamped potential mu_j . r / r^3), E_u (undamped field, what acts on charges),
     E_d (damped field T~ mu, what acts on dipoles) and G_d[a, b] = d_a (E_d)_b (damped).
     """
     X = np.asarray(X, np.float64); mu = np.asarray(mu, np.float64); alpha = np.asarray(alpha, np.float64)
     n = X.shape[0]
+    ex = exclusion_matrix(n, excl)
     phi = np.zeros(n); Eu = np.zeros((n, 3)); Ed = np.zeros((n, 3)); Gd = np.zeros((n, 3, 3))
     for i in range(n):
-        mask = np.arange(n) != i
+        mask = _partners(n, i, ex)
         rv = X[i] - X[mask]
         m = mu[mask]
         _, grad_u, H_u, _ = hessian_and_third(rv)
@@ -152,13 +170,15 @@ def dipole_fields(X, mu, alpha, thole_a, want_grad: bool = True):
     return phi, Eu, Ed, Gd
 
 
-def dipole_matrix(X, alpha, thole_a):
-    """Dense 3N x 3N damped dipole field tensor: E_d = T mu, block (i, j) = Hessian of g at x_i - x_j."""
+def dipole_matrix(X, alpha, thole_a, excl=None):
+    """Dense 3N x 3N damped dipole field tensor: E_d = T mu, block (i, j) = Hessian of g at x_i - x_j
+    (zero for excluded pairs)."""
     X = np.asarray(X, np.float64); alpha = np.asarray(alpha, np.float64)
     n = X.shape[0]
+    ex = exclusion_matrix(n, excl)
     T = np.zeros((3 * n, 3 * n))
     for i in range(n):
-        mask = np.arange(n) != i
+        mask = _partners(n, i, ex)
         idx = np.nonzero(mask)[0]
         rv = X[i] - X[mask]
         s = thole_radius(alpha[i], alpha[mask], thole_a)
@@ -172,7 +192,7 @@ def dipole_matrix(X, alpha, thole_a):
 # Induced dipoles.
 # ----------------------------------------------------------------------------------------------
 
-def solve_dipoles_dense(X, q, alpha, thole_a, E_q=None):
+def solve_dipoles_dense(X, q, alpha, thole_a, E_q=None, excl=None):
     """Exact solution of mu = alpha (E^q + T~ mu) by a dense LU solve of the scaled system.
 
     (I - S T S) y = S E^q with S = diag(sqrt(alpha)) repeated per component; mu = S y.
@@ -181,8 +201,8 @@ def solve_dipoles_dense(X, q, alpha, thole_a, E_q=None):
     X = np.asarray(X, np.float64); alpha = np.asarray(alpha, np.float64)
     n = X.shape[0]
     if E_q is None:
-        _, E_q, _ = charge_fields(X, q, want_grad=False)
-    T = dipole_matrix(X, alpha, thole_a)
+        _, E_q, _ = charge_fields(X, q, want_grad=False, excl=excl)
+    T = dipole_matrix(X, alpha, thole_a, excl)
     S = np.repeat(np.sqrt(alpha), 3)
     A = np.eye(3 * n) - S[:, None] * T * S[None, :]
     y = np.linalg.solve(A, S * E_q.reshape(-1))
@@ -242,7 +262,8 @@ def cg_scaled(apply_T, E_q, alpha, tol=1e-12, max_iter=1000, mu0=None):
 # Energy, forces and gradients at given dipoles.
 # ----------------------------------------------------------------------------------------------
 
-def evaluate(X, q, alpha, mu, thole_a=2.0, k_e=COULOMB_K, charge=None, dip=None, qE=None, charge_E=None):
+def evaluate(X, q, alpha, mu, thole_a=2.0, k_e=COULOMB_K, charge=None, dip=None, qE=None, charge_E=None,
+             excl=None):
     """Energies, forces, potentials and dU/dalpha for given dipoles (exact if mu is converged).
 
     The static field that polarises the dipoles comes from the charges q^E (Sec. III: they may
@@ -260,15 +281,15 @@ def evaluate(X, q, alpha, mu, thole_a=2.0, k_e=COULOMB_K, charge=None, dip=None,
     X = np.asarray(X, np.float64); q = np.asarray(q, np.float64)
     alpha = np.asarray(alpha, np.float64); mu = np.asarray(mu, np.float64)
     n = X.shape[0]
-    phi_q, E_q, G_q = charge if charge is not None else charge_fields(X, q)
+    phi_q, E_q, G_q = charge if charge is not None else charge_fields(X, q, excl=excl)
     tied = qE is None
     if tied:
         qE = q
         E_e, G_e = E_q, G_q
     else:
         qE = np.asarray(qE, np.float64)
-        _, E_e, G_e = charge_E if charge_E is not None else charge_fields(X, qE)
-    phi_m, Eu_m, Ed_m, Gd_m = dip if dip is not None else dipole_fields(X, mu, alpha, thole_a)
+        _, E_e, G_e = charge_E if charge_E is not None else charge_fields(X, qE, excl=excl)
+    phi_m, Eu_m, Ed_m, Gd_m = dip if dip is not None else dipole_fields(X, mu, alpha, thole_a, excl=excl)
     pos = alpha > 0
     U_qq = 0.5 * np.sum(q * phi_q)
     A_mu = 0.5 * np.sum(np.sum(mu[pos] ** 2, axis=1) / alpha[pos])
@@ -280,7 +301,7 @@ def evaluate(X, q, alpha, mu, thole_a=2.0, k_e=COULOMB_K, charge=None, dip=None,
     g_alpha = np.empty(n)
     g_alpha[pos] = -np.sum(mu[pos] ** 2, axis=1) / (2.0 * alpha[pos] ** 2)
     g_alpha[~pos] = -0.5 * np.sum(E_tot[~pos] ** 2, axis=1)
-    g_alpha += thole_alpha_term(X, alpha, mu, thole_a)
+    g_alpha += thole_alpha_term(X, alpha, mu, thole_a, excl)
     out = dict(U=k_e * (U_qq + U_pol), U_qq=k_e * U_qq, U_pol=k_e * U_pol, F=k_e * F, phi=k_e * phi,
                grad_alpha=k_e * g_alpha, E_q=E_q, E_mu=Ed_m, E_mu_undamped=Eu_m, G=G)
     if not tied:
@@ -288,7 +309,7 @@ def evaluate(X, q, alpha, mu, thole_a=2.0, k_e=COULOMB_K, charge=None, dip=None,
     return out
 
 
-def thole_alpha_term(X, alpha, mu, thole_a):
+def thole_alpha_term(X, alpha, mu, thole_a, excl=None):
     """Second term of dU/dalpha_i: derivative of -1/2 sum mu.T~ mu through s_ij = a (alpha_i alpha_j)^(1/6).
 
     With v = r/s < 1: T~ = (3 v^4 u u - (4 v^3 - 3 v^4) I)/r^3, so
@@ -299,10 +320,11 @@ def thole_alpha_term(X, alpha, mu, thole_a):
     out = np.zeros(n)
     if thole_a <= 0:
         return out
+    ex = exclusion_matrix(n, excl)
     for i in range(n):
         if alpha[i] <= 0:
             continue
-        mask = np.arange(n) != i
+        mask = _partners(n, i, ex)
         rv = X[i] - X[mask]
         r = np.linalg.norm(rv, axis=1)
         s = thole_radius(alpha[i], alpha[mask], thole_a)
@@ -320,26 +342,27 @@ def thole_alpha_term(X, alpha, mu, thole_a):
     return out
 
 
-def solve(X, q, alpha, thole_a=2.0, k_e=COULOMB_K, qE=None):
+def solve(X, q, alpha, thole_a=2.0, k_e=COULOMB_K, qE=None, excl=None):
     """Full oracle: exact dipoles (dense LU), energies, forces, potentials and gradients.
-    qE: the charges of the static field that polarises the dipoles (None: q)."""
+    qE: the charges of the static field that polarises the dipoles (None: q).  excl: excluded
+    pairs, left out of every sum (exclusion_matrix)."""
     X = np.asarray(X, np.float64)
     _check_distinct(X)
-    charge = charge_fields(X, q)
-    charge_E = None if qE is None else charge_fields(X, qE)
-    mu = solve_dipoles_dense(X, q, alpha, thole_a, E_q=(charge if qE is None else charge_E)[1])
-    dip = dipole_fields(X, mu, alpha, thole_a)
-    out = evaluate(X, q, alpha, mu, thole_a, k_e, charge=charge, dip=dip, qE=qE, charge_E=charge_E)
+    charge = charge_fields(X, q, excl=excl)
+    charge_E = None if qE is None else charge_fields(X, qE, excl=excl)
+    mu = solve_dipoles_dense(X, q, alpha, thole_a, E_q=(charge if qE is None else charge_E)[1], excl=excl)
+    dip = dipole_fields(X, mu, alpha, thole_a, excl=excl)
+    out = evaluate(X, q, alpha, mu, thole_a, k_e, charge=charge, dip=dip, qE=qE, charge_E=charge_E, excl=excl)
     out["mu"] = mu
     return out
 
 
-def energy_only(X, q, alpha, thole_a=2.0, k_e=COULOMB_K, qE=None):
+def energy_only(X, q, alpha, thole_a=2.0, k_e=COULOMB_K, qE=None, excl=None):
     """Total U at the exact dipoles; U^pol = -1/2 sum mu.E^{qE} holds at the solution (qE: the
     charges of the polarising field, None: q)."""
-    phi_q, _, _ = charge_fields(X, q, want_grad=False)
-    _, E_e, _ = charge_fields(X, q if qE is None else qE, want_grad=False)
-    mu = solve_dipoles_dense(X, q, alpha, thole_a, E_q=E_e)
+    phi_q, _, _ = charge_fields(X, q, want_grad=False, excl=excl)
+    _, E_e, _ = charge_fields(X, q if qE is None else qE, want_grad=False, excl=excl)
+    mu = solve_dipoles_dense(X, q, alpha, thole_a, E_q=E_e, excl=excl)
     return k_e * (0.5 * np.sum(np.asarray(q) * phi_q) - 0.5 * np.sum(mu * E_e))
 
 

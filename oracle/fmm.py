@@ -324,11 +324,13 @@ class Octree:
 # ----------------------------------------------------------------------------------------------
 
 def fmm_fields(X, q, mu, alpha, thole_a, p, leaf_width, ws=1, want_grad=True, order_slack=-1,
-               pair_dl=0.0):
+               pair_dl=0.0, excl=None):
     """FMM fields of charges q and point dipoles mu at every particle.
 
     pair_dl > 0 builds the multipoles of the dipoles from their +/- q^mu pairs (Sec. II.C, p2m_pair)
     instead of the point-dipole limit; the near field keeps the point dipoles.
+    excl: excluded pairs (direct.exclusion_matrix); the exact terms of each excluded pair are taken
+    off the result, wherever the pair was counted (near field, or M2L to within its truncation).
 
     Returns a dict with
       phi  total potential (undamped),
@@ -415,6 +417,19 @@ def fmm_fields(X, q, mu, alpha, thole_a, p, leaf_width, ws=1, want_grad=True, or
             E_d[i] += Eq + np.einsum("jab,jb->a", Hd, mm[src])
             if want_grad:
                 G_d[i] += Gq + np.einsum("jabc,jc->ab", T3d, mm[src])
+    if excl is not None and len(excl):
+        e = np.asarray(excl, np.int64).reshape(-1, 2)
+        for i, j in np.concatenate([e, e[:, ::-1]]):
+            rv = (X[i] - X[j])[None, :]
+            g, grad, H, T3 = direct.hessian_and_third(rv)
+            s = direct.thole_radius(alpha[i], alpha[j:j + 1], thole_a)
+            _, _, Hd, T3d = direct.hessian_and_third(rv, s)
+            phi[i] -= qq[j] * g[0] - grad[0] @ mm[j]
+            Eq = -qq[j] * grad[0]
+            E_u[i] -= Eq + H[0] @ mm[j]
+            E_d[i] -= Eq + Hd[0] @ mm[j]
+            if want_grad:
+                G_d[i] -= -qq[j] * H[0] + T3d[0] @ mm[j]
     return dict(phi=phi, E_u=E_u, E_d=E_d, G_d=G_d, tree=tree)
 
 

@@ -391,6 +391,76 @@ def test_field_charges_gradients_by_finite_differences(thole):
     assert np.linalg.norm(ga - out["grad_alpha"]) / np.linalg.norm(ga) < 1e-7
 
 
+def test_exclusions_three_sites_closed_form():
+    """Three sites on the z axis with the pair (0, 1) excluded (the starred sums of Sec. II.A):
+    the charge energy keeps q0 q2 / r02 + q1 q2 / r12, site 2 is polarised by q0 and q1, sites 0 and
+    1 by q2 only, and the dipoles couple 0-2 and 1-2 only (undamped on-axis coupling 2 / r^3), a
+    3 x 3 linear system; U = U^qq - 1/2 sum mu E^q."""
+    z = np.array([0.0, 2.2, 5.1]); q = np.array([0.6, -0.5, 0.3]); a = np.array([1.1, 0.7, 1.6])
+    X = np.stack([np.zeros(3), np.zeros(3), z], axis=1)
+    out = D.solve(X, q, a, thole_a=0.0, k_e=1.0, excl=[(0, 1)])
+    r02, r12 = z[2] - z[0], z[2] - z[1]
+    E = np.array([-q[2] / r02**2, -q[2] / r12**2, q[0] / r02**2 + q[1] / r12**2])
+    C = np.zeros((3, 3))
+    C[0, 2] = C[2, 0] = 2 / r02**3
+    C[1, 2] = C[2, 1] = 2 / r12**3
+    mu = np.linalg.solve(np.eye(3) - a[:, None] * C, a * E)
+    np.testing.assert_allclose(out["mu"][:, 2], mu, rtol=1e-13)
+    assert np.allclose(out["mu"][:, :2], 0.0, atol=1e-16)
+    U = q[0] * q[2] / r02 + q[1] * q[2] / r12 - 0.5 * np.sum(mu * E)
+    assert out["U"] == pytest.approx(U, rel=1e-13)
+
+
+def test_excluding_every_pair_removes_all_interactions():
+    X, q, a = rand_system(6, 51)
+    allp = [(i, j) for i in range(6) for j in range(i + 1, 6)]
+    out = D.solve(X, q, a, thole_a=2.0, k_e=1.0, excl=allp)
+    assert out["U"] == 0.0 and not np.any(out["mu"]) and not np.any(out["F"]) and not np.any(out["phi"])
+
+
+@pytest.mark.parametrize("thole", [0.0, 2.0])
+def test_exclusions_gradients_by_finite_differences(thole):
+    """With a chain of bonded (1-2) and angle (1-3) exclusions, F = -dU/dx, dU/dq = phi and
+    dU/dalpha agree with central differences of the energy at re-converged dipoles."""
+    X, q, a = rand_system(7, 52 if thole else 53, box=5.0, r_min=1.0)
+    excl = [(i, i + 1) for i in range(6)] + [(i, i + 2) for i in range(5)]
+    out = D.solve(X, q, a, thole_a=thole, k_e=1.0, excl=excl)
+    h = 1e-5
+    E = lambda X_, q_, a_: D.energy_only(X_, q_, a_, thole, 1.0, excl=excl)
+    n = X.shape[0]
+    Ffd = np.zeros((n, 3)); gq = np.zeros(n); ga = np.zeros(n)
+    for i in range(n):
+        for c in range(3):
+            Xp = X.copy(); Xp[i, c] += h; Xm = X.copy(); Xm[i, c] -= h
+            Ffd[i, c] = -(E(Xp, q, a) - E(Xm, q, a)) / (2 * h)
+        d = np.zeros(n); d[i] = h
+        gq[i] = (E(X, q + d, a) - E(X, q - d, a)) / (2 * h)
+        ga[i] = (E(X, q, a + d) - E(X, q, a - d)) / (2 * h)
+    assert np.linalg.norm(Ffd - out["F"]) / np.linalg.norm(Ffd) < 1e-7
+    assert np.linalg.norm(gq - out["phi"]) / np.linalg.norm(gq) < 1e-8
+    assert np.linalg.norm(ga - out["grad_alpha"]) / np.linalg.norm(ga) < 1e-7
+
+
+def test_fmm_exclusions_match_direct():
+    """The FMM with exclusions: with one leaf it is the direct sum with the pairs left out (to
+    rounding); on a deeper tree it differs from it by the FMM's truncation error only."""
+    X, q, a = rand_system(120, 54, box=9.0, r_min=1.0)
+    mu = np.random.default_rng(55).normal(0, 0.2, (120, 3))
+    excl = [(i, i + 1) for i in range(119)] + [(3, 60), (7, 100)]
+    _, Eq, Gq = D.charge_fields(X, q, excl=excl)
+    ph, Eu, Ed, Gd = D.dipole_fields(X, mu, a, 2.0, excl=excl)
+    one = FM.fmm_fields(X, q, mu, a, 2.0, 4, 100.0, 1, excl=excl)
+    assert one["tree"].L == 0
+    assert np.abs(one["E_d"] - (Eq + Ed)).max() < 1e-12 * np.abs(Eq + Ed).max()
+    assert np.abs(one["G_d"] - (Gq + Gd)).max() < 1e-12 * np.abs(Gq + Gd).max()
+    deep = FM.fmm_fields(X, q, mu, a, 2.0, 6, 1.5, 2, excl=excl)
+    plain = FM.fmm_fields(X, q, mu, a, 2.0, 6, 1.5, 2)
+    assert deep["tree"].L >= 3
+    err = np.linalg.norm(deep["E_d"] - (Eq + Ed)) / np.linalg.norm(Eq + Ed)
+    err_plain = np.linalg.norm(plain["E_d"] - (Eq + Ed)) / np.linalg.norm(Eq + Ed)
+    assert err < 1e-3 < err_plain  # the exclusions are really applied
+
+
 def test_alpha_gradient_at_zero_polarizability():
     """For alpha_i = 0 the gradient is -|E_i|^2/2 (the limit of -|mu|^2/(2 alpha^2) with mu = alpha E)."""
     X, q, a = rand_system(6, 31)
