@@ -190,6 +190,18 @@ pfmm_status pfmm_backward(pfmm_handle* h, double g, double* grad_pos, double* gr
 pfmm_status pfmm_backward_qe(pfmm_handle* h, double g, double* grad_pos, double* grad_q, double* grad_qE,
                              double* grad_alpha, void* stream);
 
+/* Excluded pairs (the starred sums of Sec. II.A: bonded 1-2 and 1-3 pairs of a force field leave
+   every sum: Coulomb energy, static field, dipole field, forces and gradients).  Host arrays in the
+   caller's particle order, CSR form: the partners of particle i are xidx[xptr[i] .. xptr[i+1]-1];
+   every pair must appear once in both of its rows, no self pairs.  They apply to every later
+   pfmm_solve, pfmm_solve_qe, pfmm_backward and pfmm_field on h with this n (another n:
+   PFMM_ERR_INVALID_ARG); n = 0 or xptr = NULL removes them.  The arrays are copied (synchronously);
+   the caller keeps ownership.  Each evaluation takes the exact terms of the excluded pairs off what
+   it summed, so a pair farther apart than the near field leaves the M2L truncation error of its
+   interaction behind.  The preconditioner's near-field operator (precond_cutoff) keeps them: it
+   only shapes the convergence.  Invalid lists: PFMM_ERR_INVALID_ARG, nothing changed. */
+pfmm_status pfmm_set_exclusions(pfmm_handle* h, int64_t n, const int* xptr, const int* xidx);
+
 /* One FMM field evaluation of fixed sources (Sec. II.B-II.C and the direct part of Sec. III),
    without any scaling by k_e.  Sources: charges q (n, or NULL) and point dipoles mu (n x 3, or
    NULL); alpha (n) sets the Thole radius of dipole-dipole pairs.  Outputs at every particle

@@ -102,6 +102,8 @@ def _load():
     lib.pfmm_solve_qe.restype = ctypes.c_int
     lib.pfmm_backward_qe.argtypes = [vp, ctypes.c_double, vp, vp, vp, vp, vp]
     lib.pfmm_backward_qe.restype = ctypes.c_int
+    lib.pfmm_set_exclusions.argtypes = [vp, ctypes.c_int64, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+    lib.pfmm_set_exclusions.restype = ctypes.c_int
     lib.pfmm_field.argtypes = [vp, ctypes.c_int64, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.pfmm_field.restype = ctypes.c_int
     lib.pfmm_status_string.argtypes = [ctypes.c_int]

@@ -9,6 +9,7 @@ from __future__ import annotations
 import ctypes
 from dataclasses import dataclass, field
 
+import numpy as np
 import torch
 
 from . import _lib
@@ -152,6 +153,27 @@ class Solver:
                      kernel_launches=dict(zip(_lib.KERNEL_CLASSES, res.kernel_launches)))
         return SolveResult(res.U_total, res.U_qq, res.U_pol, mu, F, phi, res.iters, res.residual,
                            res.residual_max_debye, stats, phiE)
+
+    def set_exclusions(self, n, pairs):
+        """Exclude the unordered particle pairs (an (m, 2) integer array, or None to clear) from every
+        sum of later solves and field evaluations of n particles."""
+        if pairs is None:
+            st = lib.pfmm_set_exclusions(self._h, 0, None, None)
+        else:
+            e = np.asarray(pairs, dtype=np.int64).reshape(-1, 2)
+            rows = np.concatenate([e[:, 0], e[:, 1]])
+            cols = np.concatenate([e[:, 1], e[:, 0]])
+            order = np.lexsort((cols, rows))
+            rows, cols = rows[order], cols[order]
+            ptr = np.zeros(n + 1, dtype=np.int32)
+            np.add.at(ptr, rows + 1, 1)
+            ptr = np.cumsum(ptr).astype(np.int32)
+            idx = np.ascontiguousarray(cols, dtype=np.int32)
+            ip = ctypes.POINTER(ctypes.c_int)
+            st = lib.pfmm_set_exclusions(self._h, int(n), ptr.ctypes.data_as(ip),
+                                         idx.ctypes.data_as(ip) if idx.size else None)
+        if st != 0:
+            self._raise(st)
 
     def backward(self, g=1.0, want_pos=True, want_q=True, want_alpha=True, n=None, want_qE=False):
         """Gradients of g U: (grad_pos, grad_q, grad_alpha), plus grad_qE last with want_qE (after a

@@ -167,6 +167,11 @@ struct pfmm_handle {
   DevBuf s_F, s_phi, s_Etot, s_phiE;
   bool saved = false;
   bool saved_qE = false;  // the saved solve had separate field charges q^E
+  // excluded pairs (rows in the caller's particle order) for systems of x_n particles; x_active:
+  // they apply to the current tree, whose sorted position of each caller index is in w_inv
+  DevBuf x_ptr, x_idx, w_inv;
+  int x_n = -1;
+  bool x_active = false;
   int saved_n = 0;
   HostPinned pinned;
   std::string err;
@@ -435,8 +440,22 @@ void fmm_pass(pfmm_handle* h, int sources, int mode, FieldOut out, int* err, con
   }
   int e = kt.begin();
   launch_p2p(t, pa, mu4, mode == 0 ? 0 : 1, sources, fp32, out, nullptr, err, done, s);
+  if (h->x_active)
+    launch_exclusions(pa, h->w_perm.as<int>(), h->w_inv.as<int>(), h->x_ptr.as<int>(), h->x_idx.as<int>(), mu4,
+                      mode == 0 ? 0 : 1, sources, out, nullptr, done, s);
   kt.end(mode == 0 ? KC_P2P_SCF : KC_P2P_FULL, e);
   h->n_evals += 1;
+}
+
+// The handle's exclusions apply to systems of the size they were given for (after build_tree).
+void activate_exclusions(pfmm_handle* h, int n, hipStream_t s) {
+  h->x_active = false;
+  if (h->x_n < 0) return;
+  if (h->x_n != n)
+    throw Error(PFMM_ERR_INVALID_ARG, "exclusions were set for " + std::to_string(h->x_n) + " particles, not " +
+                                          std::to_string(n));
+  launch_inverse_perm(h->w_perm.as<int>(), n, dev<int>(h->w_inv, n), s);
+  h->x_active = true;
 }
 
 struct Timer {
@@ -518,6 +537,7 @@ pfmm_status solve_impl(pfmm_handle* h, int64_t n64, const double* pos, const dou
     if (f) throw Error(PFMM_ERR_NONFINITE, "non-finite field charge qE");
   }
   build_tree(h, n, pos, q, alpha, s);
+  activate_exclusions(h, n, s);
   tm.mark();
   const Particles& pa = h->pa;
   double4* mu4 = dev<double4>(h->w_mu4, n);
@@ -858,6 +878,9 @@ pfmm_status pfmm_backward_qe(pfmm_handle* h, double g, double* grad_pos, double*
     if (grad_alpha && h->cfg.thole_a > 0.0) {
       dal = dev<double>(h->w_dal, n);
       launch_p2p(h->tv, h->pa, h->w_mu4.as<double4>(), 2, 2, false, FieldOut{}, dal, nullptr, nullptr, s);
+      if (h->x_active)
+        launch_exclusions(h->pa, h->w_perm.as<int>(), h->w_inv.as<int>(), h->x_ptr.as<int>(), h->x_idx.as<int>(),
+                          h->w_mu4.as<double4>(), 2, 2, FieldOut{}, dal, nullptr, s);
     }
     launch_backward(h->pa, h->w_perm.as<int>(), h->w_mu4.as<double4>(), h->s_F.as<double>(),
                     h->s_phi.as<double>(), h->s_Etot.as<double>(), h->s_phiE.as<double>(), dal,
@@ -865,6 +888,53 @@ pfmm_status pfmm_backward_qe(pfmm_handle* h, double g, double* grad_pos, double*
     return PFMM_OK;
   } catch (const Error& e) {
     return fail(h, e);
+  }
+}
+
+pfmm_status pfmm_set_exclusions(pfmm_handle* h, int64_t n64, const int* xptr, const int* xidx) {
+  if (!h) return PFMM_ERR_INVALID_ARG;
+  h->err.clear();
+  try {
+    if (n64 == 0 || !xptr) {
+      h->saved = false;
+      h->x_n = -1;
+      h->x_active = false;
+      return PFMM_OK;
+    }
+    if (n64 < 0 || n64 > INT_MAX / 8) throw Error(PFMM_ERR_INVALID_ARG, "n out of range");
+    const int n = (int)n64;
+    if (xptr[0] != 0) throw Error(PFMM_ERR_INVALID_ARG, "exclusion rows must start at 0");
+    for (int i = 0; i < n; ++i)
+      if (xptr[i + 1] < xptr[i]) throw Error(PFMM_ERR_INVALID_ARG, "exclusion row starts must not decrease");
+    const int nnz = xptr[n];
+    if (nnz > 0 && !xidx) throw Error(PFMM_ERR_INVALID_ARG, "exclusion indices are NULL");
+    // every pair listed once in each of its two rows, no self pairs, indices in range
+    std::vector<uint64_t> keys;
+    keys.reserve(nnz);
+    for (int i = 0; i < n; ++i)
+      for (int k = xptr[i]; k < xptr[i + 1]; ++k) {
+        const int j = xidx[k];
+        if (j < 0 || j >= n || j == i) throw Error(PFMM_ERR_INVALID_ARG, "exclusion index out of range or self");
+        const uint64_t a = (uint64_t)std::min(i, j), b = (uint64_t)std::max(i, j);
+        keys.push_back((a << 32) | b);
+      }
+    std::sort(keys.begin(), keys.end());
+    for (size_t k = 0; k < keys.size(); k += 2)
+      if (k + 1 >= keys.size() || keys[k] != keys[k + 1] || (k + 2 < keys.size() && keys[k + 2] == keys[k]))
+        throw Error(PFMM_ERR_INVALID_ARG, "each excluded pair must appear once in both of its rows");
+    int* dp = dev<int>(h->x_ptr, n + 1);
+    int* di = dev<int>(h->x_idx, std::max(nnz, 1));
+    PFMM_HIP(hipMemcpy(dp, xptr, sizeof(int) * (size_t)(n + 1), hipMemcpyHostToDevice));
+    if (nnz > 0) PFMM_HIP(hipMemcpy(di, xidx, sizeof(int) * (size_t)nnz, hipMemcpyHostToDevice));
+    h->x_n = n;
+    h->x_active = false;
+    h->saved = false;  // a saved solve no longer matches the handle's exclusions
+    return PFMM_OK;
+  } catch (const Error& e) {
+    return fail(h, e);
+  } catch (const std::bad_alloc&) {
+    h->err = "host allocation failed";
+    return PFMM_ERR_OOM;
   }
 }
 
@@ -881,6 +951,7 @@ pfmm_status pfmm_field(pfmm_handle* h, int64_t n64, const double* pos, const dou
     if (n == 0) return PFMM_OK;
     if (!pos || !alpha) throw Error(PFMM_ERR_INVALID_ARG, "NULL positions or polarizabilities");
     build_tree(h, n, pos, q, alpha, s);
+    activate_exclusions(h, n, s);
     double4* mu4 = dev<double4>(h->w_mu4, n);
     int* err = dev<int>(h->w_flags, 4);
     launch_fill_int(err, 4, 0, s);

@@ -133,6 +133,12 @@ void launch_to_float(const double* in, float* out, int64_t count, const int* don
 void launch_p2p(const TreeView& t, const Particles& pa, const double4* mu4, int mode, int sources,
                 bool fp32, FieldOut out, double* dal, int* err, const int* done, hipStream_t s,
                 double rc = 0.0);
+// takes the exact terms of the excluded pairs (rows xptr/xidx in the caller's order) off an
+// evaluation of P2P mode 0, 1 or 2; inv = sorted position of each caller index
+void launch_exclusions(const Particles& pa, const int* perm, const int* inv, const int* xptr, const int* xidx,
+                       const double4* mu4, int mode, int sources, FieldOut out, double* dal, const int* done,
+                       hipStream_t s);
+void launch_inverse_perm(const int* perm, int n, int* inv, hipStream_t s);
 
 // ---------------------------------------------------------------- solver.hip
 struct CGState {

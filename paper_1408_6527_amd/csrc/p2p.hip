@@ -20,6 +20,7 @@
 // Mode 3 is the operator of the dipole-solve preconditioner: the damped dipole field from the
 // sources within a cutoff radius rc (rc <= leaf edge, so the 27 adjacent leaves hold them all),
 // written rather than added.
+#include <algorithm>
 #include <type_traits>
 
 #include "kernels.hpp"
@@ -272,7 +273,111 @@ void p2p_dispatch(const TreeView& t, const Particles& pa, const double4* mu4, in
     throw Error(PFMM_ERR_INVALID_ARG, "internal: bad P2P mode");
 }
 
+// Excluded pairs (the starred sums of Sec. II.A): one thread per sorted target i takes the exact
+// terms of each of its excluded partners off what the evaluation summed (the same pair kernels as
+// above, in float64), in the order of the caller's list.  xptr/xidx are the exclusion rows in the
+// caller's particle order; inv maps a caller index to its sorted position.  Modes as in k_p2p:
+// 0 damped dipole field, 1 all outputs of the given sources, 2 the Thole term of dU/dalpha.
+__global__ __launch_bounds__(256) void k_exclusions(Particles pa, const int* __restrict__ perm,
+                                                    const int* __restrict__ inv, const int* __restrict__ xptr,
+                                                    const int* __restrict__ xidx,
+                                                    const double4* __restrict__ mu4, int mode, int sources,
+                                                    FieldOut out, double* __restrict__ dal, const int* done) {
+  if (done && *done) return;
+  const bool hq = (sources & 1) != 0, hm = (sources & 2) != 0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < pa.n; i += gridDim.x * blockDim.x) {
+    const int o = perm[i];
+    const int k0 = xptr[o], k1 = xptr[o + 1];
+    if (k0 == k1) continue;
+    const double4 Pi = pa.P[i];
+    const double iti = pa.itau[i];
+    const double4 mi = mode == 2 ? mu4[i] : make_double4(0, 0, 0, 0);
+    double phi = 0, eu[3] = {0, 0, 0}, ed[3] = {0, 0, 0}, g[6] = {0, 0, 0, 0, 0, 0}, ds = 0;
+    for (int k = k0; k < k1; ++k) {
+      const int j = inv[xidx[k]];
+      const double4 Pj = pa.P[j];
+      const double r[3] = {Pi.x - Pj.x, Pi.y - Pj.y, Pi.z - Pj.z};
+      const double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+      const double rinv = 1.0 / sqrt(r2), rinv2 = rinv * rinv, rinv3 = rinv * rinv2;
+      const double ii = iti * pa.itau[j];
+      const double v = ii > 0.0 ? fmin(r2 * rinv * ii, 1.0) : 1.0;
+      const double v3 = v * v * v, v4 = v3 * v;
+      if (mode == 1 && hq) {
+        const double qj = Pj.w, qr3 = qj * rinv3, c5 = 3.0 * qr3 * rinv2;
+        phi += qj * rinv;
+        for (int c = 0; c < 3; ++c) {
+          eu[c] += qr3 * r[c];
+          ed[c] += qr3 * r[c];
+        }
+        g[0] += qr3 - c5 * r[0] * r[0]; g[1] += qr3 - c5 * r[1] * r[1]; g[2] += qr3 - c5 * r[2] * r[2];
+        g[3] -= c5 * r[0] * r[1]; g[4] -= c5 * r[0] * r[2]; g[5] -= c5 * r[1] * r[2];
+      }
+      if ((mode == 0 || mode == 1) && hm) {
+        const double4 mj = mu4[j];
+        const double m[3] = {mj.x, mj.y, mj.z};
+        const double rmu = r[0] * m[0] + r[1] * m[1] + r[2] * m[2];
+        const double fe = v3 * (4.0 - 3.0 * v), c3 = 3.0 * v4 * rmu * rinv2;
+        for (int c = 0; c < 3; ++c) ed[c] += (c3 * r[c] - fe * m[c]) * rinv3;
+        if (mode == 1) {
+          phi += rmu * rinv3;
+          const double cu = 3.0 * rmu * rinv2;
+          for (int c = 0; c < 3; ++c) eu[c] += (cu * r[c] - m[c]) * rinv3;
+          const double Ac = v < 1.0 ? -3.0 * v4 : -15.0, Bc = 3.0 * v4;
+          const double rinv5 = rinv3 * rinv2, a7 = Ac * rmu * rinv5 * rinv2, b5 = Bc * rinv5;
+          g[0] += a7 * r[0] * r[0] + b5 * (rmu + 2.0 * r[0] * m[0]);
+          g[1] += a7 * r[1] * r[1] + b5 * (rmu + 2.0 * r[1] * m[1]);
+          g[2] += a7 * r[2] * r[2] + b5 * (rmu + 2.0 * r[2] * m[2]);
+          g[3] += a7 * r[0] * r[1] + b5 * (r[0] * m[1] + r[1] * m[0]);
+          g[4] += a7 * r[0] * r[2] + b5 * (r[0] * m[2] + r[2] * m[0]);
+          g[5] += a7 * r[1] * r[2] + b5 * (r[1] * m[2] + r[2] * m[1]);
+        }
+      }
+      if (mode == 2 && v < 1.0) {
+        const double4 mj = mu4[j];
+        const double miu = (mi.x * r[0] + mi.y * r[1] + mi.z * r[2]) * rinv;
+        const double mju = (mj.x * r[0] + mj.y * r[1] + mj.z * r[2]) * rinv;
+        const double mm = mi.x * mj.x + mi.y * mj.y + mi.z * mj.z;
+        ds += (2.0 * v4 * miu * mju - 2.0 * (v3 - v4) * mm) * rinv3;
+      }
+    }
+    if (mode == 0) {
+      for (int c = 0; c < 3; ++c) out.Ed[3 * i + c] -= ed[c];
+    } else if (mode == 1) {
+      out.phi[i] -= phi;
+      for (int c = 0; c < 3; ++c) {
+        out.Eu[3 * i + c] -= eu[c];
+        out.Ed[3 * i + c] -= ed[c];
+      }
+      for (int c = 0; c < 6; ++c) out.G[6 * i + c] -= g[c];
+    } else {
+      const double ai = pa.alpha[i];
+      if (ai > 0.0) dal[i] -= ds / ai;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_inverse_perm(const int* __restrict__ perm, int n, int* __restrict__ inv) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) inv[perm[i]] = i;
+}
+
+int grid256(int n) { return std::max(1, std::min((n + 255) / 256, 4096)); }
+
 }  // namespace
+
+void launch_exclusions(const Particles& pa, const int* perm, const int* inv, const int* xptr, const int* xidx,
+                       const double4* mu4, int mode, int sources, FieldOut out, double* dal, const int* done,
+                       hipStream_t s) {
+  if (pa.n <= 0) return;
+  hipLaunchKernelGGL(k_exclusions, dim3(grid256(pa.n)), dim3(256), 0, s, pa, perm, inv, xptr, xidx, mu4, mode,
+                     sources, out, dal, done);
+  PFMM_LAUNCH_CHECK();
+}
+
+void launch_inverse_perm(const int* perm, int n, int* inv, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_inverse_perm, dim3(grid256(n)), dim3(256), 0, s, perm, n, inv);
+  PFMM_LAUNCH_CHECK();
+}
 
 void launch_p2p(const TreeView& t, const Particles& pa, const double4* mu4, int mode, int sources,
                 bool fp32, FieldOut out, double* dal, int* err, const int* done, hipStream_t s,

@@ -414,6 +414,105 @@ def test_field_charges_fmm_solve_matches_oracle_fmm(api, precision):
     assert relnorm(N(r.phi_E), ev["phi_E"]) < tol
 
 
+def _chain_exclusions(n, far=((3, 60), (7, 100))):
+    """1-2 and 1-3 pairs of a chain through the particle order, plus a few arbitrary pairs."""
+    return [(i, i + 1) for i in range(n - 1)] + [(i, i + 2) for i in range(n - 2)] + list(far)
+
+
+def test_exclusions_one_leaf_equal_dense_oracle(api):
+    """Excluded pairs (the starred sums of Sec. II.A), everything direct (one leaf): fields of fixed
+    sources, the solved dipoles, energy, forces, potentials and every backward gradient equal the
+    oracle's with the same pairs left out; clearing the exclusions restores the plain solve."""
+    print_case("exclusions one leaf n=120")
+    X, q, a, mu = cube(120, 7.5, 15)
+    excl = _chain_exclusions(120)
+    s = api.Solver(order_p=4, ws=1, leaf_width=50.0, scf_tol=1e-13, scf_max_iter=300)
+    s.set_exclusions(120, excl)
+    phi, E, Ed, G = s.field(T(X), T(q), T(mu), T(a))
+    pq, Eq, Gq = D.charge_fields(X, q, excl=excl)
+    pm, Eu, Edm, Gd = D.dipole_fields(X, mu, a, 2.0, excl=excl)
+    assert relmax(N(phi), pq + pm) < 1e-12
+    assert relmax(N(E), Eq + Eu) < 1e-12
+    assert relmax(N(Ed), Eq + Edm) < 1e-12
+    assert relmax(N(G), Gq + Gd) < 1e-12
+    ref = D.solve(X, q, a, thole_a=2.0, excl=excl)
+    r = s.solve(T(X), T(q), T(a))
+    assert relmax(N(r.mu), ref["mu"]) < 1e-10
+    assert abs(r.U - ref["U"]) < 1e-10 * abs(ref["U"])
+    assert relmax(N(r.forces), ref["F"]) < 1e-10
+    assert relmax(N(r.phi), ref["phi"]) < 1e-10
+    gp, gq, ga = s.backward(2.0)
+    assert relmax(N(gp), -2.0 * ref["F"]) < 1e-10
+    assert relmax(N(gq), 2.0 * ref["phi"]) < 1e-10
+    assert relmax(N(ga), 2.0 * ref["grad_alpha"]) < 1e-9
+    s.set_exclusions(120, None)
+    plain = D.solve(X, q, a, thole_a=2.0)
+    r0 = s.solve(T(X), T(q), T(a))
+    assert abs(r0.U - plain["U"]) < 1e-10 * abs(plain["U"])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_exclusions_fmm_match_oracle_fmm(api, precision):
+    """Excluded pairs with the FMM: fields of fixed sources equal the oracle's FMM with the same
+    exclusions element by element (two excluded pairs lie in the far field, where the exact pair
+    terms are taken off the M2L result), and a 1,000-particle solve agrees with the oracle's FMM fields
+    at the library's dipoles (residual, energy, forces, potentials)."""
+    print_case(f"exclusions fmm {precision}")
+    X, q, a, mu = cube(600, 13.0, 2)
+    excl = _chain_exclusions(600, far=((3, 500), (10, 590)))
+    s = api.Solver(order_p=6, ws=2, leaf_width=1.8, thole_a=2.0, precision=precision)
+    s.set_exclusions(600, excl)
+    phi, E, Ed, G = s.field(T(X), T(q), T(mu), T(a))
+    ref = FM.fmm_fields(X, q, mu, a, 2.0, 6, 1.8, 2, excl=excl)
+    assert ref["tree"].L >= 3
+    tol = 1e-11 if precision == "fp64" else 2e-5
+    for got, want in ((phi, ref["phi"]), (E, ref["E_u"]), (Ed, ref["E_d"]), (G, ref["G_d"])):
+        assert relmax(N(got), want) < tol
+    from paper_1408_6527_amd import inputs
+    ps = inputs.uniform_cube(1000)
+    excl = _chain_exclusions(1000, far=((5, 900),))
+    lw = 2.6
+    s = api.Solver(order_p=4, ws=1, leaf_width=lw, scf_tol=1e-10, precision=precision)
+    s.set_exclusions(1000, excl)
+    r = s.solve(T(ps.pos), T(ps.q), T(ps.alpha))
+    m = N(r.mu)
+    st1 = FM.fmm_fields(ps.pos, ps.q, None, ps.alpha, 2.0, 4, lw, 1, excl=excl)
+    st3 = FM.fmm_fields(ps.pos, None, m, ps.alpha, 2.0, 4, lw, 1, excl=excl)
+    res = np.linalg.norm(ps.alpha[:, None] * (st1["E_d"] + st3["E_d"]) - m) / np.linalg.norm(ps.alpha[:, None] * st1["E_d"])
+    ev = D.evaluate(ps.pos, ps.q, ps.alpha, m, 2.0, D.COULOMB_K,
+                    charge=(st1["phi"], st1["E_d"], st1["G_d"]),
+                    dip=(st3["phi"], st3["E_u"], st3["E_d"], st3["G_d"]), excl=excl)
+    tol = 1e-10 if precision == "fp64" else 1e-5
+    assert res < (2e-10 if precision == "fp64" else 1e-5)
+    assert abs(r.U - ev["U"]) < tol * abs(ev["U"])
+    assert relnorm(N(r.forces), ev["F"]) < tol
+    assert relnorm(N(r.phi), ev["phi"]) < tol
+
+
+def test_exclusions_errors(api):
+    """Invalid exclusion lists and a system of another size are refused with an error."""
+    print_case("exclusions errors")
+    import ctypes
+    from paper_1408_6527_amd._lib import lib
+    X, q, a, _ = cube(20, 5.0, 16)
+    s = api.Solver(order_p=4, ws=1, leaf_width=50.0)
+    ip = ctypes.POINTER(ctypes.c_int)
+
+    def raw(ptr, idx):
+        p = np.asarray(ptr, np.int32); i = np.asarray(idx, np.int32)
+        return lib.pfmm_set_exclusions(s._h, 3, p.ctypes.data_as(ip), i.ctypes.data_as(ip))
+
+    assert raw([0, 1, 1, 1], [1]) == 1          # pair (0, 1) missing from row 1
+    assert raw([0, 1, 2, 2], [0, 0]) == 1       # self pair
+    assert raw([0, 1, 2, 2], [5, 0]) == 1       # index out of range
+    assert raw([0, 2, 4, 4], [1, 1, 0, 0]) == 1  # duplicate pair
+    assert raw([0, 1, 2, 2], [1, 0]) == 0
+    with pytest.raises(api.PFMMError):
+        s.solve(T(X), T(q), T(a))  # exclusions were given for 3 particles
+    s.set_exclusions(20, [(0, 1)])
+    s.solve(T(X), T(q), T(a))
+
+
 def test_autograd_function_against_finite_differences(api):
     import torch
     print_case("autograd fd")
