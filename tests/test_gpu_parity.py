@@ -489,6 +489,29 @@ def test_exclusions_fmm_match_oracle_fmm(api, precision):
     assert relnorm(N(r.phi), ev["phi"]) < tol
 
 
+@pytest.mark.parametrize("pc", [0.0, 3.0])
+def test_exclusions_and_field_charges_together(api, pc):
+    """Excluded pairs and separate field charges q^E in one solve, with and without the near-field
+    preconditioner (whose operator keeps the excluded pairs: it may only change the iteration count):
+    the dense oracle's solve with both gives the same dipoles, energy, forces and gradients."""
+    print_case(f"exclusions + qE, precond {pc}")
+    X, q, a, _ = cube(120, 7.5, 17)
+    qE = np.random.default_rng(18).normal(0, 0.6, 120)
+    excl = _chain_exclusions(120)
+    ref = D.solve(X, q, a, thole_a=2.0, qE=qE, excl=excl)
+    s = api.Solver(order_p=4, ws=1, leaf_width=50.0, scf_tol=1e-13, scf_max_iter=300, precond_cutoff=pc)
+    s.set_exclusions(120, excl)
+    r = s.solve(T(X), T(q), T(a), qE=T(qE))
+    assert relmax(N(r.mu), ref["mu"]) < 1e-10
+    assert abs(r.U - ref["U"]) < 1e-10 * abs(ref["U"])
+    assert relmax(N(r.forces), ref["F"]) < 1e-10
+    assert relmax(N(r.phi), ref["phi"]) < 1e-10
+    assert relmax(N(r.phi_E), ref["phi_E"]) < 1e-10
+    gp, gq, ga, ge = s.backward(1.0, want_qE=True)
+    assert relmax(N(ge), ref["phi_E"]) < 1e-10
+    assert relmax(N(ga), ref["grad_alpha"]) < 1e-9
+
+
 def test_exclusions_errors(api):
     """Invalid exclusion lists and a system of another size are refused with an error."""
     print_case("exclusions errors")
