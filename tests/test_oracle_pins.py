@@ -82,7 +82,7 @@ def test_two_polarizable_sites_on_axis(r, damped):
     assert out["U_pol"] == pytest.approx(Upol, rel=1e-13)
 
 
-def test_survey_two_site_value():
+def test_two_site_exact_rational_value():
     """An independent numeric value of the undamped two-site system (q = 0.7/-0.4, alpha = 1.3/0.9,
     r = 3.1) recomputed from the 2x2 closed form with exact rational steps."""
     from fractions import Fraction as Fr
