@@ -16,7 +16,8 @@ subsets of the HIV-1 capsid, which are not available here) by shape, size and de
                      spherical shell at 0.03 per Angstrom^3: a capsid hexamer in solvent.
 * ``scaling``        half uniform in a cube and half globular at 0.1 per Angstrom^3.
 * ``sphere``         the paper's own random sphere (Sec. IV.A): 4,096 points in a 45 Angstrom ball,
-                     minimum separation 2 Angstrom, +/-1 e in equal numbers, one alpha for all.
+                     minimum separation 2 Angstrom, +/-1 e in equal numbers, independent +/-1 e field
+                     charges qE, one alpha for all.
 
 Every protein-like set keeps a minimum separation r_min = 1.0 Angstrom (rejection on a cell grid);
 the paper's 2 Angstrom, used by its sphere test, cannot be packed at protein density.
@@ -40,6 +41,7 @@ class ParticleSet:
     pos: np.ndarray      # (n, 3) float64, Angstrom
     q: np.ndarray        # (n,)   float64, e
     alpha: np.ndarray    # (n,)   float64, Angstrom^3
+    qE: np.ndarray | None = None  # (n,) charges of the polarising field where they differ from q
 
     @property
     def n(self) -> int:
@@ -230,14 +232,17 @@ def scaling(n: int = 1_000_000, density: float = 0.1, k: int = 5) -> ParticleSet
 def sphere(n: int = 4096, radius: float = 45.0, r_min: float = 2.0, alpha: float = 0.0, k: int = 6) -> ParticleSet:
     """The random sphere of the paper's accuracy tests (Sec. IV.A): n points uniform in a ball of
     the given radius with minimum separation r_min, n/2 charges +1 e and n/2 charges -1 e in random
-    order (neutral), the same polarisability alpha for every atom."""
-    rp, rq, _ = _streams(k)
+    order (neutral), independently drawn field charges qE = +/-1 e (also neutral), the same
+    polarisability alpha for every atom."""
+    rp, rq, re = _streams(k)
     excl = _Exclusion([-radius] * 3, [radius] * 3, r_min=r_min)
     pos, _ = _fill(excl, n, lambda m: (_uniform_ball(rp, m, radius), np.zeros(m, np.int64)))
     q = np.where(rq.permutation(n) < n // 2, 1.0, -1.0)
+    qE = np.where(re.permutation(n) < n // 2, 1.0, -1.0)
     if n % 2:
         q[-1] = 0.0
-    return ParticleSet("sphere", pos, q, np.full(n, float(alpha)))
+        qE[-1] = 0.0
+    return ParticleSet("sphere", pos, q, np.full(n, float(alpha)), qE)
 
 
 def small_globular(n: int = 2000, k: int = 4) -> ParticleSet:
