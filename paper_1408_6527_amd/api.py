@@ -90,6 +90,19 @@ class SolveResult:
     phi_E: torch.Tensor | None = None  # dU/dqE with separate field charges (potentials wanted)
 
 
+def exclusion_rows(n, pairs):
+    """CSR rows (ptr of n + 1, idx) of the unordered pairs: each pair in both of its rows, the
+    partners of a row in increasing order (the form pfmm_set_exclusions takes)."""
+    e = np.asarray(pairs, dtype=np.int64).reshape(-1, 2)
+    rows = np.concatenate([e[:, 0], e[:, 1]])
+    cols = np.concatenate([e[:, 1], e[:, 0]])
+    order = np.lexsort((cols, rows))
+    rows, cols = rows[order], cols[order]
+    ptr = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(ptr, rows + 1, 1)
+    return np.cumsum(ptr).astype(np.int32), np.ascontiguousarray(cols, dtype=np.int32)
+
+
 class Solver:
     """Owns one pfmm handle (device tables and workspace) for a fixed configuration."""
 
@@ -160,15 +173,7 @@ class Solver:
         if pairs is None:
             st = lib.pfmm_set_exclusions(self._h, 0, None, None)
         else:
-            e = np.asarray(pairs, dtype=np.int64).reshape(-1, 2)
-            rows = np.concatenate([e[:, 0], e[:, 1]])
-            cols = np.concatenate([e[:, 1], e[:, 0]])
-            order = np.lexsort((cols, rows))
-            rows, cols = rows[order], cols[order]
-            ptr = np.zeros(n + 1, dtype=np.int32)
-            np.add.at(ptr, rows + 1, 1)
-            ptr = np.cumsum(ptr).astype(np.int32)
-            idx = np.ascontiguousarray(cols, dtype=np.int32)
+            ptr, idx = exclusion_rows(n, pairs)
             ip = ctypes.POINTER(ctypes.c_int)
             st = lib.pfmm_set_exclusions(self._h, int(n), ptr.ctypes.data_as(ip),
                                          idx.ctypes.data_as(ip) if idx.size else None)

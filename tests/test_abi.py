@@ -68,6 +68,16 @@ def test_create_rejects_bad_config(lib, field, value):
 def test_null_handle_is_rejected(lib):
     lib.pfmm_solve.restype = ctypes.c_int
     assert lib.pfmm_solve(None, 0, None, None, None, None, None, None, None, None) == 1
+    vp = ctypes.c_void_p
+    lib.pfmm_solve_qe.restype = ctypes.c_int
+    lib.pfmm_solve_qe.argtypes = [vp, ctypes.c_int64] + [vp] * 10
+    assert lib.pfmm_solve_qe(None, 0, *([None] * 10)) == 1
+    lib.pfmm_backward_qe.restype = ctypes.c_int
+    lib.pfmm_backward_qe.argtypes = [vp, ctypes.c_double] + [vp] * 5
+    assert lib.pfmm_backward_qe(None, 1.0, *([None] * 5)) == 1
+    lib.pfmm_set_exclusions.restype = ctypes.c_int
+    lib.pfmm_set_exclusions.argtypes = [vp, ctypes.c_int64, vp, vp]
+    assert lib.pfmm_set_exclusions(None, 0, None, None) == 1
     lib.pfmm_destroy(None)
 
 
@@ -96,3 +106,16 @@ def test_struct_layout_matches_header(tmp_path):
         assert got[(cname, "sizeof")] == ctypes.sizeof(cls), cname
         for fname, _ in cls._fields_:
             assert got[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)
+
+
+def test_exclusion_rows_are_symmetric_csr():
+    """The binding's CSR form of excluded pairs: each pair in both rows, partners sorted, empty rows
+    kept (the form pfmm_set_exclusions validates)."""
+    import numpy as np
+    from paper_1408_6527_amd.api import exclusion_rows
+    ptr, idx = exclusion_rows(5, [(0, 1), (3, 1), (4, 0)])
+    assert ptr.tolist() == [0, 2, 4, 4, 5, 6]
+    assert idx.tolist() == [1, 4, 0, 3, 1, 0]
+    assert ptr.dtype == np.int32 and idx.dtype == np.int32
+    ptr, idx = exclusion_rows(3, np.zeros((0, 2), np.int64))
+    assert ptr.tolist() == [0, 0, 0, 0] and idx.size == 0
