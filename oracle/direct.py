@@ -263,7 +263,7 @@ def cg_scaled(apply_T, E_q, alpha, tol=1e-12, max_iter=1000, mu0=None):
 # ----------------------------------------------------------------------------------------------
 
 def evaluate(X, q, alpha, mu, thole_a=2.0, k_e=COULOMB_K, charge=None, dip=None, qE=None, charge_E=None,
-             excl=None):
+             excl=None, want_grad_alpha=True):
     """Energies, forces, potentials and dU/dalpha for given dipoles (exact if mu is converged).
 
     The static field that polarises the dipoles comes from the charges q^E (Sec. III: they may
@@ -276,7 +276,8 @@ def evaluate(X, q, alpha, mu, thole_a=2.0, k_e=COULOMB_K, charge=None, dip=None,
     phi_E_i = dU/dqE_i = phi^mu_i (returned when qE is given)
     dU/dalpha_i = -|mu_i|^2/(2 alpha_i^2) (= -|E_i|^2/2 when alpha_i = 0, E = E^{qE} + E^mu_d)
                   - sum_{j: r_ij < s_ij} mu_i . (dT~_ij/ds_ij) mu_j * s_ij/(6 alpha_i)
-    Energies, forces, potentials and gradients are multiplied by k_e.
+    Energies, forces, potentials and gradients are multiplied by k_e.  want_grad_alpha=False skips
+    dU/dalpha (its Thole term is a pairwise sum, too slow here for large systems).
     """
     X = np.asarray(X, np.float64); q = np.asarray(q, np.float64)
     alpha = np.asarray(alpha, np.float64); mu = np.asarray(mu, np.float64)
@@ -298,12 +299,14 @@ def evaluate(X, q, alpha, mu, thole_a=2.0, k_e=COULOMB_K, charge=None, dip=None,
     F = q[:, None] * E_q + qE[:, None] * Eu_m + np.einsum("ia,iab->ib", mu, G)
     phi = phi_q + phi_m if tied else phi_q
     E_tot = E_e + Ed_m
-    g_alpha = np.empty(n)
-    g_alpha[pos] = -np.sum(mu[pos] ** 2, axis=1) / (2.0 * alpha[pos] ** 2)
-    g_alpha[~pos] = -0.5 * np.sum(E_tot[~pos] ** 2, axis=1)
-    g_alpha += thole_alpha_term(X, alpha, mu, thole_a, excl)
     out = dict(U=k_e * (U_qq + U_pol), U_qq=k_e * U_qq, U_pol=k_e * U_pol, F=k_e * F, phi=k_e * phi,
-               grad_alpha=k_e * g_alpha, E_q=E_q, E_mu=Ed_m, E_mu_undamped=Eu_m, G=G)
+               E_q=E_q, E_mu=Ed_m, E_mu_undamped=Eu_m, G=G)
+    if want_grad_alpha:
+        g_alpha = np.empty(n)
+        g_alpha[pos] = -np.sum(mu[pos] ** 2, axis=1) / (2.0 * alpha[pos] ** 2)
+        g_alpha[~pos] = -0.5 * np.sum(E_tot[~pos] ** 2, axis=1)
+        g_alpha += thole_alpha_term(X, alpha, mu, thole_a, excl)
+        out["grad_alpha"] = k_e * g_alpha
     if not tied:
         out.update(phi_E=k_e * phi_m, E_qE=E_e)
     return out

@@ -431,24 +431,3 @@ def fmm_fields(X, q, mu, alpha, thole_a, p, leaf_width, ws=1, want_grad=True, or
             if want_grad:
                 G_d[i] -= -qq[j] * H[0] + T3d[0] @ mm[j]
     return dict(phi=phi, E_u=E_u, E_d=E_d, G_d=G_d, tree=tree)
-
-
-def fmm_solve(X, q, alpha, thole_a, p, leaf_width, ws=1, tol=1e-12, max_iter=500, k_e=direct.COULOMB_K,
-              pair_dl=0.0):
-    """The three stages of Sec. III on the FMM fields: (1) charge field, (2) conjugate-gradient
-    dipole solve with one FMM evaluation per iteration, (3) energy and forces at the solution.
-    pair_dl > 0: dipole multipoles from the +/- q^mu pairs of Sec. II.C (see fmm_fields)."""
-    X = np.asarray(X, np.float64); q = np.asarray(q, np.float64); alpha = np.asarray(alpha, np.float64)
-    st1 = fmm_fields(X, q, None, alpha, thole_a, p, leaf_width, ws)
-
-    def apply_T(m):
-        return fmm_fields(X, None, m, alpha, thole_a, p, leaf_width, ws, want_grad=False,
-                          pair_dl=pair_dl)["E_d"]
-
-    mu, iters, res = direct.cg_scaled(apply_T, st1["E_d"], alpha, tol=tol, max_iter=max_iter)
-    st3 = fmm_fields(X, None, mu, alpha, thole_a, p, leaf_width, ws, pair_dl=pair_dl)
-    charge = (st1["phi"], st1["E_d"], st1["G_d"])
-    dip = (st3["phi"], st3["E_u"], st3["E_d"], st3["G_d"])
-    out = direct.evaluate(X, q, alpha, mu, thole_a, k_e, charge=charge, dip=dip)
-    out.update(mu=mu, iters=iters, residual=res)
-    return out
