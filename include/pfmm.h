@@ -54,7 +54,10 @@ typedef enum pfmm_status {
 } pfmm_status;
 
 typedef enum pfmm_precision {
-  PFMM_FP64 = 0,   /* every kernel in float64                                                  */
+  PFMM_FP64 = 0,   /* every field evaluation in float64.  The near-field preconditioner of the
+                      dipole solve (precond_cutoff > 0) applies its product in float32 on both
+                      paths: it only shapes the search directions; the field evaluations, the
+                      residuals and the stopping rule stay in float64                           */
   PFMM_MIXED = 1   /* M2L and P2P in float32 with float32 accumulation; tree, P2M/M2M/L2L/L2P,
                       levels <= 3 of M2L, the dipole-solve vectors, dot products, residual norms
                       and the energy reduction stay in float64                                   */
@@ -69,7 +72,9 @@ enum pfmm_flags {
 };
 
 typedef struct pfmm_config {
-  int order_p;         /* expansion order p, 1..10 (Sec. II.B truncation |n| + |m| <= p)          */
+  int order_p;         /* expansion order p, 1..10 (Sec. II.B truncation |n| + |m| <= p).  Orders
+                          above 10 are refused: the M2L keeps a tile's local expansions in
+                          registers, which holds up to C(13, 3) = 286 coefficients              */
   int ws;              /* well-separation parameter, 1 or 2: near field = leaves within Chebyshev
                           distance ws; M2L between children of near parents that are farther     */
   double leaf_width;   /* leaf cell edge in Angstrom; 0 = choose from the mean density            */
@@ -95,18 +100,21 @@ typedef struct pfmm_config {
   double scf_relax;    /* 0: every dipole-solve field evaluation at the configured orders.  In (0, 1):
                           once the relative residual r_k falls below scf_relax, the field evaluation
                           of the next iteration caps every M2L order at p - floor(ln(scf_relax / r_k) /
-                          ln((ws + 1) / sqrt(3))), at least min(p, 2): one order less for every factor
-                          by which the truncation bound of the nearest offsets grows (an extension:
-                          relaxed matrix-vector products in a Krylov solve, whose late corrections are
-                          small).  The stopping rule is checked again on the final dipoles with the
-                          full orders; if it fails, the solve continues from them without the cap.  */
+                          ln((ws + 1)^2 / 3)), at least ceil(p / 2): one order less for every factor
+                          (ws + 1)^2 / 3 (3 at ws = 2, the measured growth of the field error per
+                          order) by which the residual falls (an extension: relaxed matrix-vector
+                          products in a Krylov solve, whose late corrections are small).  The
+                          stopping rule is checked again on the final dipoles with the full orders;
+                          if it fails, the solve continues once from them without the cap, and
+                          returns PFMM_ERR_NOT_CONVERGED if it still fails.                       */
   double dipole_pair_dl; /* 0: the multipoles of the induced dipoles are those of point dipoles (the
                           limit of Sec. II.C).  > 0 (Angstrom, at most 1): each dipole's multipole
                           expansion is that of the pair of charges +/- |mu| / (2 dl) at x +/- dl mu/|mu|
                           of Sec. II.C (mu = 2 |q^mu| delta-l); the near field keeps the point dipoles.
                           Applies to every field evaluation with dipole sources, on both paths.  At
                           finite dl this field is not additive in the dipoles, so the solve checks
-                          its stopping rule on the final dipoles and continues from them if needed. */
+                          its stopping rule on the final dipoles and continues from them if needed
+                          (at most twice; PFMM_ERR_NOT_CONVERGED if the rule still fails).        */
 } pfmm_config;
 
 typedef struct pfmm_result {
@@ -137,6 +145,12 @@ typedef struct pfmm_result {
   int scf_restarts;             /* continuations from the final dipoles after the final check of the
                                    stopping rule (scf_relax: without the cap; dipole_pair_dl: the
                                    pair field is not additive in the dipoles; at most 1 and 2)      */
+  int64_t solve_id;             /* 1, 2, ... for the successful solves on a handle (0 on failure):
+                                   names the state pfmm_backward_qe may be asked for               */
+  double t_m2l_split_ms[2];     /* with PFMM_TIMING: M2L device time of the launches at the full
+                                   orders [0] and of the order-capped launches of a relaxed solve [1] */
+  int m2l_split_launches[2];    /* the launches counted in t_m2l_split_ms                          */
+  int64_t m2l_split_flops[2];   /* their useful flops (2 C(q+6, 6) per cell pair at the order q used) */
 } pfmm_result;
 
 typedef struct pfmm_handle pfmm_handle;
@@ -178,17 +192,22 @@ pfmm_status pfmm_solve_qe(pfmm_handle* h, int64_t n, const double* pos, const do
                           pfmm_result* res, void* stream);
 
 /* Gradients of g * U at the state saved by the last successful pfmm_solve on h (needs
-   PFMM_SAVE_FOR_BACKWARD).  By stationarity of U^pol in mu (Sec. II.A), no derivative of the
+   PFMM_SAVE_FOR_BACKWARD; a failed solve, pfmm_field or pfmm_set_exclusions leaves no state:
+   PFMM_ERR_NO_STATE).  By stationarity of U^pol in mu (Sec. II.A), no derivative of the
    dipole solve is needed: grad_pos = -g F, grad_q = g phi, grad_alpha = g dU/dalpha with
    dU/dalpha_i = k_e (-|mu_i|^2/(2 alpha_i^2) - sum_j mu_i.(dT~_ij/ds_ij) mu_j s_ij/(6 alpha_i))
    (-|E_i|^2/2 for alpha_i = 0).  Each output is n-sized (n x 3 for positions) or NULL to skip. */
 pfmm_status pfmm_backward(pfmm_handle* h, double g, double* grad_pos, double* grad_q,
                           double* grad_alpha, void* stream);
 
-/* pfmm_backward after pfmm_solve_qe: grad_q = g dU/dq (the charges' own potential), grad_qE = g
-   dU/dqE = g k_e phi^mu (n, or NULL).  grad_qE after a solve without qE: PFMM_ERR_INVALID_ARG. */
-pfmm_status pfmm_backward_qe(pfmm_handle* h, double g, double* grad_pos, double* grad_q, double* grad_qE,
-                             double* grad_alpha, void* stream);
+/* pfmm_backward for a named solve, also after pfmm_solve_qe.  solve_id = 0 takes the last successful
+   solve; any other value must be the pfmm_result.solve_id of that solve, else PFMM_ERR_NO_STATE (the
+   handle keeps the state of its last successful solve only, so a caller that runs another solve
+   before the backward of the first is told instead of receiving the later system's gradients).
+   grad_q = g dU/dq (the charges' own potential), grad_qE = g dU/dqE = g k_e phi^mu (n, or NULL).
+   grad_qE after a solve without qE: PFMM_ERR_INVALID_ARG. */
+pfmm_status pfmm_backward_qe(pfmm_handle* h, int64_t solve_id, double g, double* grad_pos, double* grad_q,
+                             double* grad_qE, double* grad_alpha, void* stream);
 
 /* Excluded pairs (the starred sums of Sec. II.A: bonded 1-2 and 1-3 pairs of a force field leave
    every sum: Coulomb energy, static field, dipole field, forces and gradients).  Host arrays in the

@@ -207,25 +207,29 @@ int orc_fields(int64_t n, const double* X, const double* q, const double* mu, co
   return coincident ? 3 : 0;
 }
 
-// Damped field of the point dipoles mu (n x 3) at every particle: Ed = T~ mu, the product the
-// dipole solve iterates on.  Returns 0 or 1 (bad argument).
-int orc_dipole_field(int64_t n, const double* X, const double* alpha, double thole_a, const double* mu, double* Ed) {
-  if (n < 0 || !X || !mu || !Ed) return 1;
+// Damped field of the point dipoles mu (n x 3) at m targets (targets = NULL: every particle, m = n):
+// Ed = T~ mu, the product the dipole solve iterates on.  Returns 0 or 1 (bad argument).
+int orc_dipole_field(int64_t n, const double* X, const double* alpha, double thole_a, const double* mu, int64_t m,
+                     const int64_t* targets, double* Ed) {
+  if (n < 0 || m < 0 || !X || !mu || !Ed) return 1;
+  if (!targets && m != n) return 1;
+  for (int64_t k = 0; k < m && targets; ++k)
+    if (targets[k] < 0 || targets[k] >= n) return 1;
   const Sources S(n, X, nullptr, mu, alpha);
 #pragma omp parallel for schedule(dynamic, 1)
-  for (int64_t c0 = 0; c0 < n; c0 += TGT_CHUNK) {
-    const int64_t c1 = std::min(n, c0 + TGT_CHUNK);
+  for (int64_t c0 = 0; c0 < m; c0 += TGT_CHUNK) {
+    const int64_t c1 = std::min(m, c0 + TGT_CHUNK);
     std::vector<Compensated> tot((size_t)(c1 - c0) * 3);
     for (int64_t j0 = 0; j0 < n; j0 += SRC_BLOCK) {
       const int64_t j1 = std::min(n, j0 + SRC_BLOCK);
-      for (int64_t i = c0; i < c1; ++i) {
+      for (int64_t k = c0; k < c1; ++k) {
         double acc[3] = {};
-        block_dipole(S, thole_a, i, j0, j1, acc);
-        for (int o = 0; o < 3; ++o) tot[(size_t)(i - c0) * 3 + o].add(acc[o]);
+        block_dipole(S, thole_a, targets ? targets[k] : k, j0, j1, acc);
+        for (int o = 0; o < 3; ++o) tot[(size_t)(k - c0) * 3 + o].add(acc[o]);
       }
     }
-    for (int64_t i = c0; i < c1; ++i)
-      for (int o = 0; o < 3; ++o) Ed[3 * i + o] = tot[(size_t)(i - c0) * 3 + o].value();
+    for (int64_t k = c0; k < c1; ++k)
+      for (int o = 0; o < 3; ++o) Ed[3 * k + o] = tot[(size_t)(k - c0) * 3 + o].value();
   }
   return 0;
 }

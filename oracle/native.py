@@ -44,7 +44,7 @@ def _load():
     lib.orc_threads.restype = ctypes.c_int
     lib.orc_fields.argtypes = [ctypes.c_int64, vp, vp, vp, vp, ctypes.c_double, ctypes.c_int64, vp, vp, vp, vp, vp]
     lib.orc_fields.restype = ctypes.c_int
-    lib.orc_dipole_field.argtypes = [ctypes.c_int64, vp, vp, ctypes.c_double, vp, vp]
+    lib.orc_dipole_field.argtypes = [ctypes.c_int64, vp, vp, ctypes.c_double, vp, ctypes.c_int64, vp, vp]
     lib.orc_dipole_field.restype = ctypes.c_int
     _lib = lib
     return lib
@@ -98,15 +98,17 @@ def fields(X, q=None, mu=None, alpha=None, thole_a=2.0, targets=None):
     return phi, Eu, Ed, G
 
 
-def dipole_field(X, alpha, thole_a, mu):
-    """Thole-damped field T~ mu of the point dipoles at every particle."""
+def dipole_field(X, alpha, thole_a, mu, targets=None):
+    """Thole-damped field T~ mu of the point dipoles at every particle (or at the targets listed)."""
     lib = _load()
     X = _arr(X)
     n = X.shape[0]
     alpha = _arr(alpha, (n,))
     mu = _arr(mu, (n, 3))
-    Ed = np.empty((n, 3))
-    _status(lib.orc_dipole_field(n, _p(X), _p(alpha), float(thole_a), _p(mu), _p(Ed)))
+    tg = None if targets is None else _arr(targets, dtype=np.int64).reshape(-1)
+    m = n if tg is None else tg.size
+    Ed = np.empty((m, 3))
+    _status(lib.orc_dipole_field(n, _p(X), _p(alpha), float(thole_a), _p(mu), m, _p(tg), _p(Ed)))
     return Ed
 
 

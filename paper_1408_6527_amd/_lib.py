@@ -77,6 +77,10 @@ class Result(ctypes.Structure):
         ("m2l_flops_total", ctypes.c_int64),
         ("m2l_order_cap_min", ctypes.c_int),
         ("scf_restarts", ctypes.c_int),
+        ("solve_id", ctypes.c_int64),
+        ("t_m2l_split_ms", ctypes.c_double * 2),
+        ("m2l_split_launches", ctypes.c_int * 2),
+        ("m2l_split_flops", ctypes.c_int64 * 2),
     ]
 
 KERNEL_CLASSES = ["p2m", "m2m", "m2l", "l2l", "l2p", "p2p_scf", "p2p_full", "solver"]
@@ -100,7 +104,7 @@ def _load():
     lib.pfmm_backward.restype = ctypes.c_int
     lib.pfmm_solve_qe.argtypes = [vp, ctypes.c_int64, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(Result), vp]
     lib.pfmm_solve_qe.restype = ctypes.c_int
-    lib.pfmm_backward_qe.argtypes = [vp, ctypes.c_double, vp, vp, vp, vp, vp]
+    lib.pfmm_backward_qe.argtypes = [vp, ctypes.c_int64, ctypes.c_double, vp, vp, vp, vp, vp]
     lib.pfmm_backward_qe.restype = ctypes.c_int
     lib.pfmm_set_exclusions.argtypes = [vp, ctypes.c_int64, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
     lib.pfmm_set_exclusions.restype = ctypes.c_int

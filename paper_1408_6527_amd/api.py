@@ -160,7 +160,9 @@ class Solver:
         stats = dict(levels=res.levels, leaf_width=res.leaf_width, n_leaves=res.n_leaves,
                      n_cells=res.n_cells, n_m2l=res.n_m2l, n_p2p=res.n_p2p, m2l_flops=res.m2l_flops, n_evals=res.n_evals,
                      m2l_flops_total=res.m2l_flops_total, m2l_order_cap_min=res.m2l_order_cap_min,
-                     scf_restarts=res.scf_restarts,
+                     scf_restarts=res.scf_restarts, solve_id=res.solve_id,
+                     m2l_split=dict(ms=list(res.t_m2l_split_ms), launches=list(res.m2l_split_launches),
+                                    flops=list(res.m2l_split_flops)),
                      t_phase_ms=list(res.t_phase_ms), status=_lib.STATUS[st],
                      t_kernel_ms=dict(zip(_lib.KERNEL_CLASSES, res.t_kernel_ms)),
                      kernel_launches=dict(zip(_lib.KERNEL_CLASSES, res.kernel_launches)))
@@ -180,16 +182,19 @@ class Solver:
         if st != 0:
             self._raise(st)
 
-    def backward(self, g=1.0, want_pos=True, want_q=True, want_alpha=True, n=None, want_qE=False):
+    def backward(self, g=1.0, want_pos=True, want_q=True, want_alpha=True, n=None, want_qE=False, solve_id=0):
         """Gradients of g U: (grad_pos, grad_q, grad_alpha), plus grad_qE last with want_qE (after a
-        solve with qE)."""
+        solve with qE).  solve_id (SolveResult.stats["solve_id"]) names the solve whose gradients are
+        wanted; the library refuses (PFMM_ERR_NO_STATE) when the handle has solved again since.
+        0: the last successful solve."""
         n = n if n is not None else self._n_last
         dev = torch.device("cuda", torch.cuda.current_device())
         gp = torch.empty((n, 3), dtype=torch.float64, device=dev) if want_pos else None
         gq = torch.empty((n,), dtype=torch.float64, device=dev) if want_q else None
         ga = torch.empty((n,), dtype=torch.float64, device=dev) if want_alpha else None
         ge = torch.empty((n,), dtype=torch.float64, device=dev) if want_qE else None
-        st = lib.pfmm_backward_qe(self._h, float(g), _ptr(gp), _ptr(gq), _ptr(ge), _ptr(ga), _stream())
+        st = lib.pfmm_backward_qe(self._h, int(solve_id), float(g), _ptr(gp), _ptr(gq), _ptr(ge), _ptr(ga),
+                                  _stream())
         if st != 0:
             self._raise(st)
         return (gp, gq, ga, ge) if want_qE else (gp, gq, ga)
@@ -238,6 +243,9 @@ class PolarizableEnergy(torch.autograd.Function):
 
     The backward uses the stationarity of U^pol in the dipoles, so the dipole solve itself is not
     differentiated; gradients of mu or of the forces are not available through this function.
+    The backward reads the state the solver's handle saved for this forward's solve: another solve
+    on the same Solver in between makes the backward raise (PFMM_ERR_NO_STATE) rather than return
+    the later system's gradients.
     """
 
     @staticmethod
@@ -246,6 +254,7 @@ class PolarizableEnergy(torch.autograd.Function):
         res = solver.solve(pos_c, q_c, a_c)
         ctx.solver = solver
         ctx.n = pos.shape[0]
+        ctx.solve_id = res.stats["solve_id"]
         ctx.mark_non_differentiable()
         return torch.tensor(res.U, dtype=torch.float64, device=pos.device)
 
@@ -253,5 +262,5 @@ class PolarizableEnergy(torch.autograd.Function):
     def backward(ctx, gU):
         g = float(gU.item())
         gp, gq, ga = ctx.solver.backward(g, ctx.needs_input_grad[0], ctx.needs_input_grad[1],
-                                         ctx.needs_input_grad[2], n=ctx.n)
+                                         ctx.needs_input_grad[2], n=ctx.n, solve_id=ctx.solve_id)
         return gp, gq, ga, None

@@ -49,6 +49,8 @@ struct KernelTimer {
   hipStream_t s = nullptr;
   std::vector<hipEvent_t> pool;
   std::vector<std::pair<int, int>> marks;  // (class, index of the start event; end = start + 1)
+  std::vector<int> tags;                   // per mark: the M2L truncation cap of the launch (M2L only)
+  int tag = -1;                            // cap of the next M2L launch, set by the caller
   size_t used = 0;
   ~KernelTimer() {
     for (auto e : pool) (void)hipEventDestroy(e);
@@ -57,6 +59,7 @@ struct KernelTimer {
     on = on_;
     s = s_;
     marks.clear();
+    tags.clear();
     used = 0;
   }
   int begin() {
@@ -76,6 +79,7 @@ struct KernelTimer {
     if (!on || start < 0) return;
     PFMM_HIP(hipEventRecord(pool[start + 1], s));
     marks.emplace_back(cls, start);
+    tags.push_back(tag);
   }
   void collect(double* ms, int* count) {
     if (!on) return;
@@ -85,6 +89,22 @@ struct KernelTimer {
       PFMM_HIP(hipEventElapsedTime(&t, pool[m.second], pool[m.second + 1]));
       ms[m.first] += t;
       count[m.first] += 1;
+    }
+  }
+  // M2L launches split into those at the full orders (cap >= p) and the capped ones of a relaxed
+  // solve: summed time, launch count and useful flops (flops_full per full launch, flops_cap[c] per
+  // launch capped at c).
+  void collect_m2l(int cls, int p, int64_t flops_full, const int64_t* flops_cap, double* ms, int* count,
+                   int64_t* flops) {
+    if (!on) return;
+    for (size_t k = 0; k < marks.size(); ++k) {
+      if (marks[k].first != cls) continue;
+      float t = 0.f;
+      PFMM_HIP(hipEventElapsedTime(&t, pool[marks[k].second], pool[marks[k].second + 1]));
+      const int c = tags[k] < 0 || tags[k] >= p ? 0 : 1;
+      ms[c] += t;
+      count[c] += 1;
+      flops[c] += c == 0 ? flops_full : flops_cap[tags[k]];
     }
   }
 };
@@ -167,6 +187,8 @@ struct pfmm_handle {
   DevBuf s_F, s_phi, s_Etot, s_phiE;
   bool saved = false;
   bool saved_qE = false;  // the saved solve had separate field charges q^E
+  int64_t solves = 0;     // successful solves on this handle; the saved state is that of solve saved_id
+  int64_t saved_id = 0;
   // excluded pairs (rows in the caller's particle order) for systems of x_n particles; x_active:
   // they apply to the current tree, whose sorted position of each caller index is in w_inv
   DevBuf x_ptr, x_idx, w_inv;
@@ -187,9 +209,12 @@ struct pfmm_handle {
 
 namespace {
 
+// Workspace of count elements in buffer b (its own allocation, grown on demand).
+void* raw(DevBuf& b, size_t bytes) { return b.reserve(bytes); }
+
 template <class T>
 T* dev(DevBuf& b, int64_t count) {
-  return static_cast<T*>(b.reserve((size_t)std::max<int64_t>(count, 1) * sizeof(T)));
+  return static_cast<T*>(raw(b, (size_t)std::max<int64_t>(count, 1) * sizeof(T)));
 }
 
 template <class T>
@@ -295,7 +320,7 @@ void build_tree(pfmm_handle* h, int n, const double* pos, const double* q, const
   launch_morton(pos, n, origin, w, L, keys_in, vals_in, s);
   if (L > 0) {
     size_t tb = sort_temp_bytes(n, 3 * L);
-    void* tmp = h->w_sort_tmp.reserve(tb);
+    void* tmp = raw(h->w_sort_tmp, tb);
     launch_sort(tmp, tb, keys_in, keys, vals_in, perm, n, 3 * L, s);
   } else {
     PFMM_HIP(hipMemcpyAsync(keys, keys_in, (size_t)n * 8, hipMemcpyDeviceToDevice, s));
@@ -313,7 +338,7 @@ void build_tree(pfmm_handle* h, int n, const double* pos, const double* q, const
   int* cid = dev<int>(h->w_cid, (int64_t)n * (L + 1));
   int* counts = dev<int>(h->w_counts, L + 2);
   size_t sb = scan_temp_bytes(n);
-  void* stmp = h->w_scan_tmp.reserve(sb);
+  void* stmp = raw(h->w_scan_tmp, sb);
   for (int l = 0; l <= L; ++l)
     launch_level_scan(keys, n, 3 * (L - l), lflags, cid + (int64_t)l * n, counts + l, stmp, sb, s);
   std::vector<int> cnt(L + 1);
@@ -514,11 +539,19 @@ pfmm_status solve_impl(pfmm_handle* h, int64_t n64, const double* pos, const dou
   if (phi_E && !qE) throw Error(PFMM_ERR_INVALID_ARG, "phi_E needs the field charges qE");
   if (n > 0 && want_f && !forces) throw Error(PFMM_ERR_INVALID_ARG, "forces is NULL with PFMM_WANT_FORCES");
   if (n > 0 && want_phi && !phi) throw Error(PFMM_ERR_INVALID_ARG, "phi is NULL with PFMM_WANT_POTENTIALS");
-  if (n == 0) return PFMM_OK;
+  if (n == 0) {
+    h->saved = true;
+    h->saved_n = 0;
+    h->saved_qE = qE != nullptr;
+    h->saved_id = ++h->solves;
+    res->solve_id = h->saved_id;
+    return PFMM_OK;
+  }
   PFMM_HIP(hipGetDevice(&h->device));
 
   Timer tm((c.flags & PFMM_TIMING) != 0, s);
   h->kt.reset((c.flags & PFMM_TIMING) != 0, s);
+  h->kt.tag = c.order_p;
   tm.mark();
   if ((c.flags & PFMM_WARM_START) != 0) {
     int* fl = dev<int>(h->w_flags, 4);
@@ -651,7 +684,10 @@ pfmm_status solve_impl(pfmm_handle* h, int64_t n64, const double* pos, const dou
       int ev = h->kt.begin();
       launch_make_dipoles(pa, pv, mu4, done, q);
       h->kt.end(KC_SOLVER, ev);
+      // with timing the state is read back after every iteration, so the cap is known here
+      h->kt.tag = qcap ? hs.qcap : c.order_p;
       fmm_pass(h, 2, 0, fo, err, done, q, qcap);
+      h->kt.tag = c.order_p;
       if (pc) {
         ev = h->kt.begin();
         launch_pcg_ap(pa, pv, E, r, Ap, part, st, q);
@@ -717,10 +753,18 @@ pfmm_status solve_impl(pfmm_handle* h, int64_t n64, const double* pos, const dou
       warm_now = true;
       continue;
     }
+    // after the continuations allowed, a relaxed or charge-pair solve whose final dipoles still miss
+    // the stopping rule at the full orders has not converged
+    if ((relaxed || pair || restarts > 0) && true_res > c.scf_tol) {
+      hs.maxed = 1;
+      hs.res = true_res;
+    }
     break;
   }
   tm.fill(res->t_phase_ms);
   h->kt.collect(res->t_kernel_ms, res->kernel_launches);
+  h->kt.collect_m2l(KC_M2L, c.order_p, h->m2l_flops, h->m2l_flops_cap, res->t_m2l_split_ms, res->m2l_split_launches,
+                    res->m2l_split_flops);
 
   const double ke = c.coulomb_k;
   res->U_qq = ke * he.Uqq;
@@ -754,13 +798,16 @@ pfmm_status solve_impl(pfmm_handle* h, int64_t n64, const double* pos, const dou
   res->m2l_flops_total = flops_total;
   res->m2l_order_cap_min = cap_min;
   res->scf_restarts = restarts;
-  h->saved = true;
-  h->saved_n = n;
-  h->saved_qE = qE != nullptr;
   if (hs.notspd) throw Error(PFMM_ERR_NOT_SPD, "conjugate gradients met p.Ap <= 0: the dipole system is not positive definite");
   if (!hs.done || (hs.maxed && hs.res > c.scf_tol))
     throw Error(PFMM_ERR_NOT_CONVERGED, "dipole solve did not converge: residual " + std::to_string(hs.res) +
-                                            " after " + std::to_string(hs.iters) + " iterations");
+                                            " after " + std::to_string(total_iters) + " iterations");
+  // only a converged solve leaves state for the backward
+  h->saved = true;
+  h->saved_n = n;
+  h->saved_qE = qE != nullptr;
+  h->saved_id = ++h->solves;
+  res->solve_id = h->saved_id;
   return PFMM_OK;
 }
 
@@ -858,16 +905,19 @@ pfmm_status pfmm_solve_qe(pfmm_handle* h, int64_t n, const double* pos, const do
 
 pfmm_status pfmm_backward(pfmm_handle* h, double g, double* grad_pos, double* grad_q, double* grad_alpha,
                           void* stream) {
-  return pfmm_backward_qe(h, g, grad_pos, grad_q, nullptr, grad_alpha, stream);
+  return pfmm_backward_qe(h, 0, g, grad_pos, grad_q, nullptr, grad_alpha, stream);
 }
 
-pfmm_status pfmm_backward_qe(pfmm_handle* h, double g, double* grad_pos, double* grad_q, double* grad_qE,
-                             double* grad_alpha, void* stream) {
+pfmm_status pfmm_backward_qe(pfmm_handle* h, int64_t solve_id, double g, double* grad_pos, double* grad_q,
+                             double* grad_qE, double* grad_alpha, void* stream) {
   if (!h) return PFMM_ERR_INVALID_ARG;
   h->err.clear();
   try {
     if (!h->saved || !(h->cfg.flags & PFMM_SAVE_FOR_BACKWARD))
       throw Error(PFMM_ERR_NO_STATE, "pfmm_backward needs a preceding successful pfmm_solve with PFMM_SAVE_FOR_BACKWARD");
+    if (solve_id != 0 && solve_id != h->saved_id)
+      throw Error(PFMM_ERR_NO_STATE, "the state of solve " + std::to_string(solve_id) +
+                                         " is gone: the handle holds that of solve " + std::to_string(h->saved_id));
     if (!std::isfinite(g)) throw Error(PFMM_ERR_NONFINITE, "non-finite upstream gradient");
     if (grad_qE && !h->saved_qE)
       throw Error(PFMM_ERR_INVALID_ARG, "grad_qE needs a preceding solve with field charges qE");
@@ -938,12 +988,15 @@ pfmm_status pfmm_set_exclusions(pfmm_handle* h, int64_t n64, const int* xptr, co
   }
 }
 
-pfmm_status pfmm_field(pfmm_handle* h, int64_t n64, const double* pos, const double* q, const double* mu,
+}  // extern "C"
+
+namespace {
+
+// One FMM evaluation of fixed sources (pfmm_field and pfmm_field_noalloc).
+pfmm_status field_impl(pfmm_handle* h, int64_t n64, const double* pos, const double* q, const double* mu,
                        const double* alpha, double* phi, double* E, double* E_damped, double* grad_E,
                        void* stream) {
-  if (!h) return PFMM_ERR_INVALID_ARG;
-  h->err.clear();
-  try {
+  {
     hipStream_t s = (hipStream_t)stream;
     if (n64 < 0 || n64 > INT_MAX / 8) throw Error(PFMM_ERR_INVALID_ARG, "n out of range");
     h->saved = false;
@@ -980,8 +1033,25 @@ pfmm_status pfmm_field(pfmm_handle* h, int64_t n64, const double* pos, const dou
     launch_unpermute_field(h->w_perm.as<int>(), n, fo, phi, E, E_damped, grad_E, s);
     PFMM_HIP(hipStreamSynchronize(s));
     return PFMM_OK;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+pfmm_status pfmm_field(pfmm_handle* h, int64_t n64, const double* pos, const double* q, const double* mu,
+                       const double* alpha, double* phi, double* E, double* E_damped, double* grad_E,
+                       void* stream) {
+  if (!h) return PFMM_ERR_INVALID_ARG;
+  h->err.clear();
+  try {
+    return field_impl(h, n64, pos, q, mu, alpha, phi, E, E_damped, grad_E, stream);
   } catch (const Error& e) {
     return fail(h, e);
+  } catch (const std::bad_alloc&) {
+    h->err = "host allocation failed";
+    return PFMM_ERR_OOM;
   }
 }
 

@@ -32,26 +32,31 @@ struct Error : public std::runtime_error {
 struct DevBuf {
   void* ptr = nullptr;
   size_t bytes = 0;
+  void* own = nullptr;
+  size_t own_bytes = 0;
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
   ~DevBuf() { release(); }
   void release() {
-    if (ptr) (void)hipFree(ptr);
-    ptr = nullptr;
-    bytes = 0;
+    if (own) (void)hipFree(own);
+    own = ptr = nullptr;
+    own_bytes = bytes = 0;
   }
   void* reserve(size_t want) {
+    ptr = own;
+    bytes = own_bytes;
     if (want == 0) want = 256;
     if (want > bytes) {
       release();
       size_t b = want + want / 4;
-      hipError_t e = hipMalloc(&ptr, b);
+      hipError_t e = hipMalloc(&own, b);
       if (e != hipSuccess) {
-        ptr = nullptr;
+        own = nullptr;
         throw Error(PFMM_ERR_OOM, "device allocation of " + std::to_string(b) + " bytes failed");
       }
-      bytes = b;
+      ptr = own;
+      own_bytes = bytes = b;
     }
     return ptr;
   }

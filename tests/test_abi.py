@@ -73,8 +73,8 @@ def test_null_handle_is_rejected(lib):
     lib.pfmm_solve_qe.argtypes = [vp, ctypes.c_int64] + [vp] * 10
     assert lib.pfmm_solve_qe(None, 0, *([None] * 10)) == 1
     lib.pfmm_backward_qe.restype = ctypes.c_int
-    lib.pfmm_backward_qe.argtypes = [vp, ctypes.c_double] + [vp] * 5
-    assert lib.pfmm_backward_qe(None, 1.0, *([None] * 5)) == 1
+    lib.pfmm_backward_qe.argtypes = [vp, ctypes.c_int64, ctypes.c_double] + [vp] * 5
+    assert lib.pfmm_backward_qe(None, 0, 1.0, *([None] * 5)) == 1
     lib.pfmm_set_exclusions.restype = ctypes.c_int
     lib.pfmm_set_exclusions.argtypes = [vp, ctypes.c_int64, vp, vp]
     assert lib.pfmm_set_exclusions(None, 0, None, None) == 1

@@ -94,7 +94,9 @@ def test_native_fields_equal_numpy_sums():
         assert relmax(part, full[tg]) < 1e-15
     # the product of the dipole solve is the dense tensor times the dipoles
     T = D.dipole_matrix(X, a, 2.0)
-    assert relmax(NT.dipole_field(X, a, 2.0, mu), (T @ mu.reshape(-1)).reshape(-1, 3)) < 1e-13
+    Tmu = (T @ mu.reshape(-1)).reshape(-1, 3)
+    assert relmax(NT.dipole_field(X, a, 2.0, mu), Tmu) < 1e-13
+    assert relmax(NT.dipole_field(X, a, 2.0, mu, targets=tg), Tmu[tg]) < 1e-13
 
 
 def test_native_forces_at_equal_dense_forces_at_solution():
