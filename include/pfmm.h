@@ -34,6 +34,7 @@
 #ifndef PFMM_H
 #define PFMM_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -230,6 +231,27 @@ pfmm_status pfmm_set_exclusions(pfmm_handle* h, int64_t n, const int* xptr, cons
 pfmm_status pfmm_field(pfmm_handle* h, int64_t n, const double* pos, const double* q,
                        const double* mu, const double* alpha, double* phi, double* E,
                        double* E_damped, double* grad_E, void* stream);
+
+/* Bytes of device scratch that pfmm_field_noalloc may use (128 MiB per GPU). */
+#define PFMM_SCRATCH_BYTES ((size_t)128 << 20)
+
+/* pfmm_field for callers that cannot allocate memory (code under HIP graph capture, tight serving
+   loops, harnesses that forbid allocation): the same evaluation, arguments and results, but every
+   device workspace buffer (tree, sort and scan temporaries, expansions, fields in sorted order) is
+   carved from a fixed scratch array of PFMM_SCRATCH_BYTES that the library holds on each GPU it
+   runs on until the process ends, and the call makes no hipMalloc, hipFree, host pinned
+   allocation or allocating library call.  The handle must come from pfmm_create (which allocates
+   its operator tables and a small host staging buffer).  An evaluation whose workspace would
+   exceed PFMM_SCRATCH_BYTES returns PFMM_ERR_INVALID_ARG before any kernel uses the scratch.  The
+   workspace is about 300 bytes per particle plus (1 + s) 8 C(p+3, 3) + 600 bytes per occupied cell
+   (s <= 32 the offset splits of the M2L): a p = 6 evaluation of 40,000 particles at 3 per leaf fits,
+   600,000 particles at 6 per leaf do not.  Every call on a GPU
+   shares that GPU's scratch array and leaves its contents behind: calls that overlap on one GPU (two
+   threads, or two streams whose work interleaves) race and must be serialised by the caller.
+   pfmm_backward has no state from this call (PFMM_ERR_NO_STATE). */
+pfmm_status pfmm_field_noalloc(pfmm_handle* h, int64_t n, const double* pos, const double* q,
+                               const double* mu, const double* alpha, double* phi, double* E,
+                               double* E_damped, double* grad_E, void* stream);
 
 /* Static description of a status code. */
 const char* pfmm_status_string(pfmm_status s);

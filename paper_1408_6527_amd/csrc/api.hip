@@ -12,6 +12,7 @@
 #include <climits>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -26,12 +27,42 @@ namespace {
 constexpr int NRED = 7;  // bbox partial width (tree.hip)
 constexpr double EANG_TO_DEBYE = 4.80320;
 
+// Device scratch of pfmm_field_noalloc: one array on every GPU the library runs on, held until the
+// process ends.  In host code `scratch` names a host-side stand-in, not device memory: its device
+// address comes from hipGetSymbolAddress, once per device (scratch_address), and only that address
+// is handed to kernels and copies.
+constexpr size_t SCRATCH_BYTES = PFMM_SCRATCH_BYTES;
+constexpr int MAX_DEVICES = 64;
+__device__ __align__(256) char scratch[SCRATCH_BYTES];
+std::mutex g_scratch_mutex;
+char* g_scratch[MAX_DEVICES] = {};
+
+// Device address of the scratch array on the current device (looked up on the first call per device).
+char* scratch_address() {
+  int d = 0;
+  PFMM_HIP(hipGetDevice(&d));
+  if (d < 0 || d >= MAX_DEVICES) throw Error(PFMM_ERR_INVALID_ARG, "device ordinal out of range for the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch[d]) {
+    void* p = nullptr;
+    PFMM_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) throw Error(PFMM_ERR_HIP, "hipGetSymbolAddress returned no address for the scratch array");
+    g_scratch[d] = static_cast<char*>(p);
+  }
+  return g_scratch[d];
+}
+
+// While a pfmm_field_noalloc call runs on this thread, every workspace buffer is carved from the
+// scratch array instead of being allocated.
+thread_local Arena* g_arena = nullptr;
+
 struct HostPinned {
   void* p = nullptr;
   size_t bytes = 0;
   ~HostPinned() { if (p) (void)hipHostFree(p); }
   void* get(size_t b) {
     if (b > bytes) {
+      if (g_arena) throw Error(PFMM_ERR_INVALID_ARG, "host staging buffer too small for an allocation-free call");
       if (p) (void)hipHostFree(p);
       p = nullptr;
       PFMM_HIP(hipHostMalloc(&p, b, hipHostMallocDefault));
@@ -209,8 +240,16 @@ struct pfmm_handle {
 
 namespace {
 
-// Workspace of count elements in buffer b (its own allocation, grown on demand).
-void* raw(DevBuf& b, size_t bytes) { return b.reserve(bytes); }
+// Workspace of count elements in buffer b: its own (grown) allocation, or a region of the scratch
+// array during an allocation-free call.
+void* raw(DevBuf& b, size_t bytes) {
+  if (g_arena) {
+    void* p = g_arena->take(bytes, "workspace");
+    b.borrow(p, bytes);
+    return p;
+  }
+  return b.reserve(bytes);
+}
 
 template <class T>
 T* dev(DevBuf& b, int64_t count) {
@@ -870,6 +909,10 @@ pfmm_status pfmm_create(const pfmm_config* cfg, pfmm_handle** out) {
     op.dorder = h->t_dorder.as<unsigned char>();
     op.nblocks = T.nblocks;
     PFMM_HIP(hipGetDevice(&h->device));
+    // host staging for the small read-backs, so that later calls need not allocate it
+    h->pinned.get(4096);
+    // the device address of the scratch array on this device (pfmm_field_noalloc)
+    (void)scratch_address();
     *out = h;
     return PFMM_OK;
   } catch (const Error& e) {
@@ -1036,6 +1079,17 @@ pfmm_status field_impl(pfmm_handle* h, int64_t n64, const double* pos, const dou
   }
 }
 
+// Makes the workspace of the calls on this thread come from a region of device memory.
+struct ArenaScope {
+  Arena arena;
+  explicit ArenaScope(char* base, size_t cap) {
+    arena.base = base;
+    arena.cap = cap;
+    g_arena = &arena;
+  }
+  ~ArenaScope() { g_arena = nullptr; }
+};
+
 }  // namespace
 
 extern "C" {
@@ -1046,6 +1100,22 @@ pfmm_status pfmm_field(pfmm_handle* h, int64_t n64, const double* pos, const dou
   if (!h) return PFMM_ERR_INVALID_ARG;
   h->err.clear();
   try {
+    return field_impl(h, n64, pos, q, mu, alpha, phi, E, E_damped, grad_E, stream);
+  } catch (const Error& e) {
+    return fail(h, e);
+  } catch (const std::bad_alloc&) {
+    h->err = "host allocation failed";
+    return PFMM_ERR_OOM;
+  }
+}
+
+pfmm_status pfmm_field_noalloc(pfmm_handle* h, int64_t n64, const double* pos, const double* q, const double* mu,
+                               const double* alpha, double* phi, double* E, double* E_damped, double* grad_E,
+                               void* stream) {
+  if (!h) return PFMM_ERR_INVALID_ARG;
+  h->err.clear();
+  try {
+    ArenaScope scope(scratch_address(), SCRATCH_BYTES);
     return field_impl(h, n64, pos, q, mu, alpha, phi, E, E_damped, grad_E, stream);
   } catch (const Error& e) {
     return fail(h, e);

@@ -29,6 +29,9 @@ struct Error : public std::runtime_error {
 #define PFMM_LAUNCH_CHECK() PFMM_HIP(hipGetLastError())
 
 // A device allocation that only grows.  Contents are not preserved across growth.
+// `ptr` is the storage in use: normally the buffer's own allocation; borrow() points it at memory
+// the buffer does not own (a region of the library's static scratch array) without releasing its
+// own, and the next reserve() returns to the own allocation.
 struct DevBuf {
   void* ptr = nullptr;
   size_t bytes = 0;
@@ -60,8 +63,29 @@ struct DevBuf {
     }
     return ptr;
   }
+  void borrow(void* p, size_t b) {
+    ptr = p;
+    bytes = b;
+  }
   template <class T>
   T* as() const { return static_cast<T*>(ptr); }
+};
+
+// Carves consecutive 256-byte-aligned regions out of a fixed device range (the static scratch
+// array); never allocates.  Asking for more than is left throws before anything uses the memory.
+struct Arena {
+  char* base = nullptr;
+  size_t cap = 0, used = 0;
+  void* take(size_t want, const char* what) {
+    const size_t b = (want == 0 ? 256 : want + 255) / 256 * 256;
+    if (used + b > cap)
+      throw Error(PFMM_ERR_INVALID_ARG, std::string("workspace for this evaluation exceeds the scratch maximum of ") +
+                                            std::to_string(cap) + " bytes (" + what + ": " + std::to_string(used) +
+                                            " used, " + std::to_string(b) + " more needed)");
+    void* p = base + used;
+    used += b;
+    return p;
+  }
 };
 
 inline int ncoef(int p) { return (p + 1) * (p + 2) * (p + 3) / 6; }
