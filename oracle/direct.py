@@ -396,3 +396,71 @@ def fields_at(idx, X, q=None, mu=None, alpha=None, thole_a=2.0):
         Ed[k] = Eq + np.einsum("jab,jb->a", Hd, ms)
         Gd[k] = -np.sum(qs[:, None, None] * H, axis=0) + np.einsum("jabc,jc->ab", T3d, ms)
     return phi, Eu, Ed, Gd
+
+
+# ----------------------------------------------------------------------------------------------
+# Gradients of a loss that depends on the dipoles (the adjoint of the dipole equations).
+# ----------------------------------------------------------------------------------------------
+
+def thole_alpha_pair(X, alpha, a, b, thole_a, excl=None):
+    """sum_j a_i . (dT~_ij/ds_ij) b_j * ds_ij/dalpha_i for every i (zero where alpha_i = 0), with
+    s_ij = a (alpha_i alpha_j)^(1/6), ds_ij/dalpha_i = s_ij / (6 alpha_i); by the formula of
+    thole_alpha_term, (a . dT~/ds b) = (-12 v^4 (a.u)(b.u) + 12 (v^3 - v^4) a.b) / (s r^3) for v = r/s < 1."""
+    X = np.asarray(X, np.float64); alpha = np.asarray(alpha, np.float64)
+    a = np.asarray(a, np.float64); b = np.asarray(b, np.float64)
+    n = X.shape[0]
+    out = np.zeros(n)
+    if thole_a <= 0:
+        return out
+    ex = exclusion_matrix(n, excl)
+    for i in range(n):
+        if alpha[i] <= 0:
+            continue
+        mask = _partners(n, i, ex)
+        rv = X[i] - X[mask]
+        r = np.linalg.norm(rv, axis=1)
+        s = thole_radius(alpha[i], alpha[mask], thole_a)
+        inside = (s > 0) & (r < s)
+        if not np.any(inside):
+            continue
+        rv = rv[inside]; r = r[inside]; s = s[inside]; bj = b[mask][inside]
+        u = rv / r[:, None]
+        v = r / s
+        dTds = (-12.0 * v**4 * (u @ a[i]) * np.sum(bj * u, axis=1) + 12.0 * (v**3 - v**4) * (bj @ a[i])) / (s * r**3)
+        out[i] = np.sum(dTds * s / (6.0 * alpha[i]))
+    return out
+
+
+def dipole_adjoint(X, q, alpha, G, thole_a=2.0, qE=None, excl=None):
+    """Gradients of a loss L(mu) through the induced dipoles, given G = dL/dmu (n x 3) at the solution.
+
+    The dipoles solve A mu = E^{qE} with A = diag(1/alpha) - T~ (Sec. II.A, dipole-moment equation;
+    qE=None: the field of the charges q).  A is symmetric, so the adjoint lambda = A^-1 G solves the
+    same system with G in place of E^{qE} (in the scaled form, (I - S T~ S) z = S G, lambda = S z,
+    lambda_i = 0 where alpha_i = 0), and dL = lambda . (dE^{qE} + dT~ mu - d(diag(1/alpha)) mu):
+      dL/dx_i     = qE_i E^lambda_u,i + (lambda_i . grad)(E^{qE} + E^mu_d)_i + (mu_i . grad) E^lambda_d,i
+      dL/dqE_i    = -phi^lambda_i                      (minus the undamped potential of the dipoles lambda)
+      dL/dalpha_i = (G_i + E^lambda_d,i) . E_i + sum_j [lambda_i . dT~_ij/ds mu_j + mu_i . dT~_ij/ds lambda_j] ds_ij/dalpha_i
+    with E = E^{qE} + E^mu_d the total damped field (for alpha_i > 0, G_i + E^lambda_d,i = lambda_i / alpha_i).
+    Returns dict(mu, lam, grad_pos, grad_q, grad_alpha[, grad_qE]); with qE given, L does not depend on q.
+    """
+    X = np.asarray(X, np.float64); q = np.asarray(q, np.float64); alpha = np.asarray(alpha, np.float64)
+    G = np.asarray(G, np.float64).reshape(-1, 3)
+    tied = qE is None
+    qf = q if tied else np.asarray(qE, np.float64)
+    _, E_e, G_e = charge_fields(X, qf, excl=excl)
+    mu = solve_dipoles_dense(X, q, alpha, thole_a, E_q=E_e, excl=excl)
+    lam = solve_dipoles_dense(X, q, alpha, thole_a, E_q=G, excl=excl)
+    _, _, Ed_m, Gd_m = dipole_fields(X, mu, alpha, thole_a, excl=excl)
+    phi_l, Eu_l, Ed_l, Gd_l = dipole_fields(X, lam, alpha, thole_a, excl=excl)
+    gx = (qf[:, None] * Eu_l + np.einsum("ia,iab->ib", lam, G_e + Gd_m) + np.einsum("ia,iab->ib", mu, Gd_l))
+    E_tot = E_e + Ed_m
+    ga = np.sum((G + Ed_l) * E_tot, axis=1)
+    ga += thole_alpha_pair(X, alpha, lam, mu, thole_a, excl) + thole_alpha_pair(X, alpha, mu, lam, thole_a, excl)
+    out = dict(mu=mu, lam=lam, grad_pos=gx, grad_alpha=ga)
+    if tied:
+        out["grad_q"] = -phi_l
+    else:
+        out["grad_q"] = np.zeros_like(q)
+        out["grad_qE"] = -phi_l
+    return out
