@@ -210,6 +210,26 @@ pfmm_status pfmm_backward(pfmm_handle* h, double g, double* grad_pos, double* gr
 pfmm_status pfmm_backward_qe(pfmm_handle* h, int64_t solve_id, double g, double* grad_pos, double* grad_q,
                              double* grad_qE, double* grad_alpha, void* stream);
 
+/* Gradients of a loss L that depends on the converged dipoles, given g_mu = dL/dmu (n x 3, device,
+   caller order), at the state of the named solve (solve_id as for pfmm_backward_qe; needs
+   PFMM_SAVE_FOR_BACKWARD).  The dipoles solve A mu = E^q with A = diag(1/alpha) - T~ (Sec. II.A,
+   dipole-moment equation); A is symmetric, so the adjoint lambda = A^-1 dL/dmu is a second solve with
+   the same operator, tree, orders and preconditioner (every evaluation at the full orders) and
+   dL = lambda . (dE^q + dT~ mu - d(diag(1/alpha)) mu):
+     grad_pos_i   = dL/dx_i = qE_i E^lambda_i + (lambda_i . grad)(E^q + E^mu_damped)_i
+                              + (mu_i . grad) E^lambda_damped,i      (qE = q without field charges)
+     grad_q_i     = dL/dq_i = -phi^lambda_i (0 after pfmm_solve_qe, where q does not polarise)
+     grad_qE_i    = dL/dqE_i = -phi^lambda_i (after pfmm_solve_qe only)
+     grad_alpha_i = dL/dalpha_i = (dL/dmu_i + E^lambda_damped,i) . E_i + sum_j [lambda_i . dT~_ij/ds mu_j
+                    + mu_i . dT~_ij/ds lambda_j] ds_ij/dalpha_i,   E = E^q + E^mu_damped
+   with phi^lambda, E^lambda the potential and fields of the point dipoles lambda.  No k_e scaling
+   (L is whatever the caller's loss is).  Each output n-sized (n x 3 for positions) or NULL.
+   Overwrites the outputs; the saved state stays valid for pfmm_backward.  Errors as pfmm_solve for
+   the adjoint solve (PFMM_ERR_NOT_CONVERGED, PFMM_ERR_NOT_SPD), PFMM_ERR_NONFINITE for non-finite
+   dL/dmu. */
+pfmm_status pfmm_backward_mu(pfmm_handle* h, int64_t solve_id, const double* g_mu, double* grad_pos,
+                             double* grad_q, double* grad_qE, double* grad_alpha, void* stream);
+
 /* Excluded pairs (the starred sums of Sec. II.A: bonded 1-2 and 1-3 pairs of a force field leave
    every sum: Coulomb energy, static field, dipole field, forces and gradients).  Host arrays in the
    caller's particle order, CSR form: the partners of particle i are xidx[xptr[i] .. xptr[i+1]-1];

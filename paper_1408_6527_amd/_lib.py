@@ -106,6 +106,8 @@ def _load():
     lib.pfmm_solve_qe.restype = ctypes.c_int
     lib.pfmm_backward_qe.argtypes = [vp, ctypes.c_int64, ctypes.c_double, vp, vp, vp, vp, vp]
     lib.pfmm_backward_qe.restype = ctypes.c_int
+    lib.pfmm_backward_mu.argtypes = [vp, ctypes.c_int64, vp, vp, vp, vp, vp, vp]
+    lib.pfmm_backward_mu.restype = ctypes.c_int
     lib.pfmm_set_exclusions.argtypes = [vp, ctypes.c_int64, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
     lib.pfmm_set_exclusions.restype = ctypes.c_int
     lib.pfmm_field.argtypes = [vp, ctypes.c_int64, vp, vp, vp, vp, vp, vp, vp, vp, vp]

@@ -15,7 +15,8 @@ import torch
 from . import _lib
 from ._lib import lib
 
-__all__ = ["PFMMError", "Solver", "SolveResult", "solve", "field_eval", "PolarizableEnergy", "config"]
+__all__ = ["PFMMError", "Solver", "SolveResult", "solve", "field_eval", "PolarizableEnergy", "PolarizableSolve",
+           "config"]
 
 
 class PFMMError(RuntimeError):
@@ -199,6 +200,22 @@ class Solver:
             self._raise(st)
         return (gp, gq, ga, ge) if want_qE else (gp, gq, ga)
 
+    def backward_mu(self, g_mu, want_pos=True, want_q=True, want_alpha=True, want_qE=False, solve_id=0):
+        """Gradients of a loss L through the converged dipoles, given g_mu = dL/dmu (n x 3): (grad_pos,
+        grad_q, grad_alpha), plus grad_qE last with want_qE.  One adjoint solve with the same operator."""
+        n = self._n_last
+        _check_tensor("g_mu", g_mu, (n, 3))
+        dev = g_mu.device
+        gp = torch.empty((n, 3), dtype=torch.float64, device=dev) if want_pos else None
+        gq = torch.empty((n,), dtype=torch.float64, device=dev) if want_q else None
+        ga = torch.empty((n,), dtype=torch.float64, device=dev) if want_alpha else None
+        ge = torch.empty((n,), dtype=torch.float64, device=dev) if want_qE else None
+        st = lib.pfmm_backward_mu(self._h, int(solve_id), _ptr(g_mu), _ptr(gp), _ptr(gq), _ptr(ge), _ptr(ga),
+                                  _stream())
+        if st != 0:
+            self._raise(st)
+        return (gp, gq, ga, ge) if want_qE else (gp, gq, ga)
+
     def field(self, pos, q=None, mu=None, alpha=None):
         """phi, E (undamped dipole part), E_damped and grad E_damped (n x 3 x 3) of the sources."""
         n = pos.shape[0]
@@ -264,3 +281,38 @@ class PolarizableEnergy(torch.autograd.Function):
         gp, gq, ga = ctx.solver.backward(g, ctx.needs_input_grad[0], ctx.needs_input_grad[1],
                                          ctx.needs_input_grad[2], n=ctx.n, solve_id=ctx.solve_id)
         return gp, gq, ga, None
+
+
+class PolarizableSolve(torch.autograd.Function):
+    """(U, mu): the energy U^{qq'} + U^pol and the converged dipoles, both differentiable in pos, q and
+    alpha.  The gradient through U uses the stationarity of U^pol in the dipoles (pfmm_backward); the
+    gradient through mu, for a loss that depends on the dipoles themselves, comes from the adjoint
+    solve with the same operator (pfmm_backward_mu).  Another solve on the same Solver before the
+    backward makes it raise (PFMM_ERR_NO_STATE).
+    """
+
+    @staticmethod
+    def forward(ctx, pos, q, alpha, solver: Solver):
+        ctx.set_materialize_grads(False)
+        pos_c, q_c, a_c = pos.detach().contiguous(), q.detach().contiguous(), alpha.detach().contiguous()
+        res = solver.solve(pos_c, q_c, a_c)
+        ctx.solver = solver
+        ctx.n = pos.shape[0]
+        ctx.solve_id = res.stats["solve_id"]
+        return torch.tensor(res.U, dtype=torch.float64, device=pos.device), res.mu
+
+    @staticmethod
+    def backward(ctx, gU, gmu):
+        need = ctx.needs_input_grad[:3]
+        out = [None, None, None]
+
+        def add(parts):
+            for k in range(3):
+                if parts[k] is not None:
+                    out[k] = parts[k] if out[k] is None else out[k] + parts[k]
+
+        if gU is not None:
+            add(ctx.solver.backward(float(gU.item()), need[0], need[1], need[2], n=ctx.n, solve_id=ctx.solve_id))
+        if gmu is not None:
+            add(ctx.solver.backward_mu(gmu.detach().contiguous(), need[0], need[1], need[2], solve_id=ctx.solve_id))
+        return out[0], out[1], out[2], None

@@ -220,6 +220,10 @@ struct pfmm_handle {
   bool saved_qE = false;  // the saved solve had separate field charges q^E
   int64_t solves = 0;     // successful solves on this handle; the saved state is that of solve saved_id
   int64_t saved_id = 0;
+  double saved_bn2 = 0.0;  // ||alpha E^q||^2 of the saved solve (scale of its dipoles)
+  // adjoint of the dipole equations (pfmm_backward_mu): dL/dmu sorted, the solution's dipoles, the
+  // adjoint dipoles, their fields, the dipole sets of the Thole polarisation identity
+  DevBuf a_G, a_mu4, a_lam4, a_phi, a_Eu, a_Ed, a_G6, a_pl4, a_mi4, a_dalp, a_dalm;
   // excluded pairs (rows in the caller's particle order) for systems of x_n particles; x_active:
   // they apply to the current tree, whose sorted position of each caller index is in w_inv
   DevBuf x_ptr, x_idx, w_inv;
@@ -563,6 +567,117 @@ void check_flag(pfmm_handle* h, int* dflag, hipStream_t s) {
   if (f) throw Error(PFMM_ERR_COINCIDENT, "two particles share the same position");
 }
 
+// Stage 2 of Sec. III on the current tree: conjugate gradients on (I - S T~ S) y = S Ee for the
+// right-hand-side field Ee (sorted order, 3n; the static field E^q for the dipoles, or any other
+// vector for the adjoint solve), preconditioned by the near field when configured, with relaxed
+// field evaluations from rp.start (0: none).  warm_now: start from the dipoles in h->w_mu4.  On
+// return h->cg_y holds y (mu = S y) and the host copy of the state is returned; *evals counts the
+// full-order field evaluations made outside the iterations.  st: two CGState (outer, inner).
+CGState dipole_cg(pfmm_handle* h, const double* Ee, bool warm_now, const RelaxParams& rp, CGState* st, int* err,
+                  hipStream_t s, int* evals) {
+  const pfmm_config& c = h->cfg;
+  const Particles& pa = h->pa;
+  const int n = pa.n;
+  double4* mu4 = h->w_mu4.as<double4>();
+  double* y = dev<double>(h->cg_y, 3 * (int64_t)n);
+  double* r = dev<double>(h->cg_r, 3 * (int64_t)n);
+  double* pv = dev<double>(h->cg_p, 3 * (int64_t)n);
+  double* Ap = dev<double>(h->cg_Ap, 3 * (int64_t)n);
+  double* E = dev<double>(h->f_E, 3 * (int64_t)n);
+  double* part = dev<double>(h->w_red, RED_BLOCKS * 8);
+  CGState* inner = st + 1;
+  const bool pc = c.precond_cutoff > 0.0;
+  double* z = pc ? dev<double>(h->pc_z, 3 * (int64_t)n) : nullptr;
+  double* ri = pc ? dev<double>(h->pc_r, 3 * (int64_t)n) : nullptr;
+  double* pi = pc ? dev<double>(h->pc_p, 3 * (int64_t)n) : nullptr;
+  double* Api = pc ? dev<double>(h->pc_Ap, 3 * (int64_t)n) : nullptr;
+  double* Epc = pc ? dev<double>(h->pc_E, 3 * (int64_t)n) : nullptr;
+  double4* mu4pc = pc ? dev<double4>(h->pc_mu4, n) : nullptr;
+  // z = inner CG approximation of (I - S T~_near S)^-1 r (the near field in float32)
+  auto precondition = [&](hipStream_t q) {
+    int ev = h->kt.begin();
+    launch_pc_init(3 * n, r, z, ri, pi, part, inner, st, q);
+    for (int k = 0; k < c.precond_iters; ++k) {
+      launch_make_dipoles(pa, pi, mu4pc, &inner->done, q);
+      launch_p2p(h->tv, pa, mu4pc, 3, 2, true, FieldOut{nullptr, nullptr, Epc, nullptr}, nullptr, err,
+                 &inner->done, q, c.precond_cutoff);
+      launch_cg_ap(pa, pi, Epc, Api, part, inner, q);
+      launch_cg_update(pa, z, ri, pi, Api, part, inner, -1.0, c.precond_iters, q);
+      launch_cg_direction(3 * n, ri, pi, inner, q);
+    }
+    h->kt.end(KC_SOLVER, ev);
+  };
+  FieldOut fo{nullptr, nullptr, E, nullptr};
+  const int* done = &st->done;
+  const bool timing = (c.flags & PFMM_TIMING) != 0;
+  // with timing, test convergence after every iteration so that no launch runs past it
+  const int chunk = timing ? 1 : (c.graph_iters > 0 ? c.graph_iters : 4);
+  const bool use_graph = c.graph_iters > 0 && !timing;
+  const bool relaxed = rp.start > 0.0;
+  const int* qcap = relaxed ? &st->qcap : nullptr;
+  if (pc && !warm_now) {
+    // the preconditioned solve starts from y0 = 0: r0 = S Ee costs no field evaluation, and
+    // p0 = z0 is a better first direction than the Jacobi guess alpha Ee
+    launch_cg_init_zero(pa, Ee, y, r, part, st, c.scf_tol, s);
+  } else {
+    launch_cg_init(pa, Ee, mu4, warm_now, y, pv, mu4, part, st, s);
+    fmm_pass(h, 2, 0, fo, err, nullptr, s);
+    ++*evals;
+    launch_cg_residual0(pa, Ee, E, y, r, pv, part, st, c.scf_tol, s);
+  }
+  if (pc) {
+    precondition(s);
+    launch_cg_direction(3 * n, z, pv, st, s);  // b = 0 here: p0 = z0
+  }
+  CGState hs{};
+  auto iteration = [&](hipStream_t q) {
+    int ev = h->kt.begin();
+    launch_make_dipoles(pa, pv, mu4, done, q);
+    h->kt.end(KC_SOLVER, ev);
+    // with timing the state is read back after every iteration, so the cap is known here
+    h->kt.tag = qcap ? hs.qcap : c.order_p;
+    fmm_pass(h, 2, 0, fo, err, done, q, qcap);
+    h->kt.tag = c.order_p;
+    if (pc) {
+      ev = h->kt.begin();
+      launch_pcg_ap(pa, pv, E, r, Ap, part, st, q);
+      launch_cg_update(pa, y, r, pv, Ap, part, st, c.scf_tol, c.scf_max_iter, q, rp);
+      h->kt.end(KC_SOLVER, ev);
+      precondition(q);
+      ev = h->kt.begin();
+      launch_pcg_zq(3 * n, z, Ap, part, st, q);
+      launch_cg_direction(3 * n, z, pv, st, q);
+      h->kt.end(KC_SOLVER, ev);
+      return;
+    }
+    ev = h->kt.begin();
+    launch_cg_ap(pa, pv, E, Ap, part, st, q);
+    launch_cg_update(pa, y, r, pv, Ap, part, st, c.scf_tol, c.scf_max_iter, q, rp);
+    launch_cg_direction(3 * n, r, pv, st, q);
+    h->kt.end(KC_SOLVER, ev);
+  };
+  sync_read(h, st, &hs, sizeof(hs), s);
+  int launched = 0;
+  if (use_graph && !hs.done) {
+    // chunk iterations captured as one HIP graph; every kernel in it returns at once when the
+    // device-side `done` flag is set, so replays past convergence are no-ops
+    h->graph.capture([&]() {
+      for (int k = 0; k < chunk; ++k) iteration(h->graph.cap);
+    });
+    while (!hs.done && launched < c.scf_max_iter) {
+      h->graph.launch(s);
+      launched += chunk;
+      sync_read(h, st, &hs, sizeof(hs), s);
+    }
+  } else {
+    while (!hs.done && launched < c.scf_max_iter) {
+      for (int k = 0; k < chunk && launched < c.scf_max_iter; ++k, ++launched) iteration(s);
+      sync_read(h, st, &hs, sizeof(hs), s);
+    }
+  }
+  return hs;
+}
+
 pfmm_status solve_impl(pfmm_handle* h, int64_t n64, const double* pos, const double* q, const double* qE,
                        const double* alpha, double* mu, double* forces, double* phi, double* phi_E,
                        pfmm_result* res, hipStream_t s) {
@@ -643,38 +758,9 @@ pfmm_status solve_impl(pfmm_handle* h, int64_t n64, const double* pos, const dou
   tm.mark();
 
   // stage 2: conjugate gradients
-  double* y = dev<double>(h->cg_y, 3 * (int64_t)n);
-  double* r = dev<double>(h->cg_r, 3 * (int64_t)n);
-  double* pv = dev<double>(h->cg_p, 3 * (int64_t)n);
-  double* Ap = dev<double>(h->cg_Ap, 3 * (int64_t)n);
-  double* E = dev<double>(h->f_E, 3 * (int64_t)n);
-  double* part = dev<double>(h->w_red, RED_BLOCKS * 8);
   CGState* st = static_cast<CGState*>(h->w_state.reserve(2 * sizeof(CGState)));
-  CGState* inner = st + 1;
-  const bool pc = c.precond_cutoff > 0.0;
-  double* z = pc ? dev<double>(h->pc_z, 3 * (int64_t)n) : nullptr;
-  double* ri = pc ? dev<double>(h->pc_r, 3 * (int64_t)n) : nullptr;
-  double* pi = pc ? dev<double>(h->pc_p, 3 * (int64_t)n) : nullptr;
-  double* Api = pc ? dev<double>(h->pc_Ap, 3 * (int64_t)n) : nullptr;
-  double* Epc = pc ? dev<double>(h->pc_E, 3 * (int64_t)n) : nullptr;
-  double4* mu4pc = pc ? dev<double4>(h->pc_mu4, n) : nullptr;
-  // z = inner CG approximation of (I - S T~_near S)^-1 r (the near field in float32)
-  auto precondition = [&](hipStream_t q) {
-    int ev = h->kt.begin();
-    launch_pc_init(3 * n, r, z, ri, pi, part, inner, st, q);
-    for (int k = 0; k < c.precond_iters; ++k) {
-      launch_make_dipoles(pa, pi, mu4pc, &inner->done, q);
-      launch_p2p(h->tv, pa, mu4pc, 3, 2, true, FieldOut{nullptr, nullptr, Epc, nullptr}, nullptr, err,
-                 &inner->done, q, c.precond_cutoff);
-      launch_cg_ap(pa, pi, Epc, Api, part, inner, q);
-      launch_cg_update(pa, z, ri, pi, Api, part, inner, -1.0, c.precond_iters, q);
-      launch_cg_direction(3 * n, ri, pi, inner, q);
-    }
-    h->kt.end(KC_SOLVER, ev);
-  };
   const bool warm = (c.flags & PFMM_WARM_START) != 0;
   if (warm) launch_permute_dipoles(h->w_perm.as<int>(), n, mu, pa.tau, mu4, s);
-  FieldOut fo{nullptr, nullptr, E, nullptr};
   // relaxed field evaluations: the update kernel of each iteration picks the order cap of the next
   RelaxParams rp;
   rp.p = c.order_p;
@@ -684,11 +770,6 @@ pfmm_status solve_impl(pfmm_handle* h, int64_t n64, const double* pos, const dou
   rp.lrho = 2.0 * std::log((c.ws + 1.0) / std::sqrt(3.0));
   launch_fill_int(&st->qcap, 1, c.order_p, s);
   launch_fill_int(st->ncap, 16, 0, s);
-  const int* done = &st->done;
-  const bool timing = (c.flags & PFMM_TIMING) != 0;
-  // with timing, test convergence after every iteration so that no launch runs past it
-  const int chunk = timing ? 1 : (c.graph_iters > 0 ? c.graph_iters : 4);
-  const bool use_graph = c.graph_iters > 0 && !timing;
   double* phim = dev<double>(h->f_phim, n);
   double* Eum = dev<double>(h->f_Eum, 3 * (int64_t)n);
   double* Edm = dev<double>(h->f_Edm, 3 * (int64_t)n);
@@ -704,67 +785,10 @@ pfmm_status solve_impl(pfmm_handle* h, int64_t n64, const double* pos, const dou
   bool warm_now = warm;
   for (;;) {
     const bool relaxed = rp.start > 0.0;
-    const int* qcap = relaxed ? &st->qcap : nullptr;
-    if (pc && !warm_now) {
-      // the preconditioned solve starts from y0 = 0: r0 = S E^q costs no field evaluation, and
-      // p0 = z0 is a better first direction than the Jacobi guess alpha E^q
-      launch_cg_init_zero(pa, Ee, y, r, part, st, c.scf_tol, s);
-    } else {
-      launch_cg_init(pa, Ee, mu4, warm_now, y, pv, mu4, part, st, s);
-      fmm_pass(h, 2, 0, fo, err, nullptr, s);
-      ++full_evals;
-      launch_cg_residual0(pa, Ee, E, y, r, pv, part, st, c.scf_tol, s);
-    }
-    if (pc) {
-      precondition(s);
-      launch_cg_direction(3 * n, z, pv, st, s);  // b = 0 here: p0 = z0
-    }
-    auto iteration = [&](hipStream_t q) {
-      int ev = h->kt.begin();
-      launch_make_dipoles(pa, pv, mu4, done, q);
-      h->kt.end(KC_SOLVER, ev);
-      // with timing the state is read back after every iteration, so the cap is known here
-      h->kt.tag = qcap ? hs.qcap : c.order_p;
-      fmm_pass(h, 2, 0, fo, err, done, q, qcap);
-      h->kt.tag = c.order_p;
-      if (pc) {
-        ev = h->kt.begin();
-        launch_pcg_ap(pa, pv, E, r, Ap, part, st, q);
-        launch_cg_update(pa, y, r, pv, Ap, part, st, c.scf_tol, c.scf_max_iter, q, rp);
-        h->kt.end(KC_SOLVER, ev);
-        precondition(q);
-        ev = h->kt.begin();
-        launch_pcg_zq(3 * n, z, Ap, part, st, q);
-        launch_cg_direction(3 * n, z, pv, st, q);
-        h->kt.end(KC_SOLVER, ev);
-        return;
-      }
-      ev = h->kt.begin();
-      launch_cg_ap(pa, pv, E, Ap, part, st, q);
-      launch_cg_update(pa, y, r, pv, Ap, part, st, c.scf_tol, c.scf_max_iter, q, rp);
-      launch_cg_direction(3 * n, r, pv, st, q);
-      h->kt.end(KC_SOLVER, ev);
-    };
-    sync_read(h, st, &hs, sizeof(hs), s);
-    int launched = 0;
-    if (use_graph && !hs.done) {
-      // chunk iterations captured as one HIP graph; every kernel in it returns at once when the
-      // device-side `done` flag is set, so replays past convergence are no-ops
-      h->graph.capture([&]() {
-        for (int k = 0; k < chunk; ++k) iteration(h->graph.cap);
-      });
-      while (!hs.done && launched < c.scf_max_iter) {
-        h->graph.launch(s);
-        launched += chunk;
-        sync_read(h, st, &hs, sizeof(hs), s);
-      }
-    } else {
-      while (!hs.done && launched < c.scf_max_iter) {
-        for (int k = 0; k < chunk && launched < c.scf_max_iter; ++k, ++launched) iteration(s);
-        sync_read(h, st, &hs, sizeof(hs), s);
-      }
-    }
+    hs = dipole_cg(h, Ee, warm_now, rp, st, err, s, &full_evals);
     total_iters += hs.iters;
+    const double* y = h->cg_y.as<double>();
+    double* part = h->w_red.as<double>();
     tm.mark();
 
     // stage 3: field of the converged dipoles (full orders), energy and forces
@@ -846,6 +870,7 @@ pfmm_status solve_impl(pfmm_handle* h, int64_t n64, const double* pos, const dou
   h->saved_n = n;
   h->saved_qE = qE != nullptr;
   h->saved_id = ++h->solves;
+  h->saved_bn2 = hs.bnorm2;
   res->solve_id = h->saved_id;
   return PFMM_OK;
 }
@@ -981,6 +1006,94 @@ pfmm_status pfmm_backward_qe(pfmm_handle* h, int64_t solve_id, double g, double*
     return PFMM_OK;
   } catch (const Error& e) {
     return fail(h, e);
+  }
+}
+
+pfmm_status pfmm_backward_mu(pfmm_handle* h, int64_t solve_id, const double* g_mu, double* grad_pos, double* grad_q,
+                             double* grad_qE, double* grad_alpha, void* stream) {
+  if (!h) return PFMM_ERR_INVALID_ARG;
+  h->err.clear();
+  try {
+    if (!h->saved || !(h->cfg.flags & PFMM_SAVE_FOR_BACKWARD))
+      throw Error(PFMM_ERR_NO_STATE, "pfmm_backward_mu needs a preceding successful pfmm_solve with PFMM_SAVE_FOR_BACKWARD");
+    if (solve_id != 0 && solve_id != h->saved_id)
+      throw Error(PFMM_ERR_NO_STATE, "the state of solve " + std::to_string(solve_id) +
+                                         " is gone: the handle holds that of solve " + std::to_string(h->saved_id));
+    if (grad_qE && !h->saved_qE)
+      throw Error(PFMM_ERR_INVALID_ARG, "grad_qE needs a preceding solve with field charges qE");
+    const int n = h->saved_n;
+    if (n == 0) return PFMM_OK;
+    if (!g_mu) throw Error(PFMM_ERR_INVALID_ARG, "dL/dmu is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    const pfmm_config& c = h->cfg;
+    const Particles& pa = h->pa;
+    const int* perm = h->w_perm.as<int>();
+    h->kt.reset(false, s);
+    int* err = dev<int>(h->w_flags, 4);
+    launch_fill_int(err, 4, 0, s);
+    launch_check_finite(g_mu, 3 * (int64_t)n, err + 1, s);
+    double* Gs = dev<double>(h->a_G, 3 * (int64_t)n);
+    launch_permute_vec3(perm, n, g_mu, Gs, s);
+    // the solution's dipoles: the adjoint solve uses the dipole buffer for its search directions
+    double4* mu4 = h->w_mu4.as<double4>();
+    double4* mus = dev<double4>(h->a_mu4, n);
+    PFMM_HIP(hipMemcpyAsync(mus, mu4, sizeof(double4) * (size_t)n, hipMemcpyDeviceToDevice, s));
+    // the adjoint lambda = A^-1 dL/dmu: the same symmetric operator (same tree, orders and
+    // preconditioner) with dL/dmu in place of the static field; every evaluation at the full orders
+    CGState* st = static_cast<CGState*>(h->w_state.reserve(2 * sizeof(CGState)));
+    RelaxParams rp;
+    rp.p = c.order_p;
+    rp.qmin = (c.order_p + 1) / 2;
+    rp.track = 0;
+    rp.start = 0.0;
+    rp.lrho = 2.0 * std::log((c.ws + 1.0) / std::sqrt(3.0));
+    launch_fill_int(&st->qcap, 1, c.order_p, s);
+    int evals = 0;
+    const CGState hs = dipole_cg(h, Gs, false, rp, st, err, s, &evals);
+    if (hs.notspd) throw Error(PFMM_ERR_NOT_SPD, "adjoint solve met p.Ap <= 0");
+    if (!hs.done || (hs.maxed && hs.res > c.scf_tol))
+      throw Error(PFMM_ERR_NOT_CONVERGED, "adjoint solve did not converge: residual " + std::to_string(hs.res));
+    double4* lam4 = dev<double4>(h->a_lam4, n);
+    launch_make_dipoles(pa, h->cg_y.as<double>(), lam4, nullptr, s);
+    // fields of the adjoint dipoles (potential, undamped and damped field, damped gradient)
+    PFMM_HIP(hipMemcpyAsync(mu4, lam4, sizeof(double4) * (size_t)n, hipMemcpyDeviceToDevice, s));
+    FieldOut lf{dev<double>(h->a_phi, n), dev<double>(h->a_Eu, 3 * (int64_t)n), dev<double>(h->a_Ed, 3 * (int64_t)n),
+                dev<double>(h->a_G6, 6 * (int64_t)n)};
+    fmm_pass(h, 2, 1, lf, err, nullptr, s);
+    // the bilinear Thole term from the quadratic one, with lambda scaled to the dipoles' size
+    double *dalp = nullptr, *dalm = nullptr;
+    double inv2c = 0.0;
+    if (grad_alpha && c.thole_a > 0.0) {
+      const double sc = hs.bnorm2 > 0.0 && h->saved_bn2 > 0.0 ? std::sqrt(h->saved_bn2 / hs.bnorm2) : 1.0;
+      double4* pl = dev<double4>(h->a_pl4, n);
+      double4* mi = dev<double4>(h->a_mi4, n);
+      launch_dipole_pm(n, mus, lam4, sc, pl, mi, s);
+      dalp = dev<double>(h->a_dalp, n);
+      dalm = dev<double>(h->a_dalm, n);
+      for (int k = 0; k < 2; ++k) {
+        double4* d4 = k == 0 ? pl : mi;
+        double* dd = k == 0 ? dalp : dalm;
+        launch_p2p(h->tv, pa, d4, 2, 2, false, FieldOut{}, dd, nullptr, nullptr, s);
+        if (h->x_active)
+          launch_exclusions(pa, perm, h->w_inv.as<int>(), h->x_ptr.as<int>(), h->x_idx.as<int>(), d4, 2, 2,
+                            FieldOut{}, dd, nullptr, s);
+      }
+      inv2c = 0.5 / sc;
+    }
+    PFMM_HIP(hipMemcpyAsync(mu4, mus, sizeof(double4) * (size_t)n, hipMemcpyDeviceToDevice, s));
+    const bool sep = h->saved_qE;
+    launch_backward_mu(pa, perm, mus, lam4, lf, sep ? h->f_GqE.as<double>() : h->f_Gq.as<double>(),
+                       h->f_Gm.as<double>(), h->s_Etot.as<double>(), Gs, sep ? h->w_qEs.as<double>() : nullptr,
+                       dalp, dalm, inv2c, grad_pos, grad_q, grad_qE, grad_alpha, s);
+    int flags[2];
+    sync_read(h, err, flags, sizeof(flags), s);
+    if (flags[1]) throw Error(PFMM_ERR_NONFINITE, "non-finite dL/dmu");
+    return PFMM_OK;
+  } catch (const Error& e) {
+    return fail(h, e);
+  } catch (const std::bad_alloc&) {
+    h->err = "host allocation failed";
+    return PFMM_ERR_OOM;
   }
 }
 

@@ -186,6 +186,13 @@ struct FieldCharges {
   const double* E = nullptr;
   const double* G = nullptr;
 };
+void launch_backward_mu(const Particles& pa, const int* perm, const double4* mu4, const double4* lam4,
+                        const FieldOut& lam, const double* Ge, const double* Gm, const double* Etot, const double* Gs,
+                        const double* qEs, const double* dalp, const double* dalm, double inv2c, double* gpos,
+                        double* gq, double* gqE, double* ga, hipStream_t s);
+void launch_permute_vec3(const int* perm, int n, const double* in, double* out, hipStream_t s);
+void launch_dipole_pm(int n, const double4* a, const double4* b, double c, double4* plus, double4* minus,
+                      hipStream_t s);
 void launch_assemble(const Particles& pa, const int* perm, const double4* mu4, const double* phiq,
                      const double* Eq, const FieldCharges& fc, const double* phim, const double* Eum,
                      const double* Edm, const double* Gm, double k_e, double* mu_out,

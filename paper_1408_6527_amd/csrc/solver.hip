@@ -456,6 +456,68 @@ __global__ __launch_bounds__(TPB) void k_backward(Particles pa, const int* __res
   }
 }
 
+// Gradients of a loss L(mu) through the dipoles (the adjoint of the dipole equations, from the
+// stationary problem of Sec. II.A): with lambda = A^-1 dL/dmu (A = diag(1/alpha) - T~),
+//   dL/dx_i     = qE_i E^lambda_u,i + (lambda_i . grad)(E^qE + E^mu_d)_i + (mu_i . grad) E^lambda_d,i
+//   dL/dqE_i    = -phi^lambda_i
+//   dL/dalpha_i = (G_i + E^lambda_d,i) . E_i + b_i,   E = E^qE + E^mu_d,
+// b_i the Thole term sum_j [lambda_i . dT~/ds mu_j + mu_i . dT~/ds lambda_j] ds_ij/dalpha_i, obtained
+// from the Thole term of dU/dalpha (P2P mode 2, dal(m) = -sum_j m_i . dT~/ds m_j ds/dalpha_i) by
+// polarisation: b = (dal(mu - c lambda) - dal(mu + c lambda)) / (2 c).  Gradients are written in the
+// caller's particle order; G6 arrays are symmetric gradients (xx, yy, zz, xy, xz, yz).
+__global__ __launch_bounds__(TPB) void k_backward_mu(
+    Particles pa, const int* __restrict__ perm, const double4* __restrict__ mu4, const double4* __restrict__ lam4,
+    const double* __restrict__ phil, const double* __restrict__ Eul, const double* __restrict__ Edl,
+    const double* __restrict__ Gl, const double* __restrict__ Ge, const double* __restrict__ Gm,
+    const double* __restrict__ Etot, const double* __restrict__ Gs, const double* __restrict__ qEs,
+    const double* __restrict__ dalp, const double* __restrict__ dalm, double inv2c, double* __restrict__ gpos,
+    double* __restrict__ gq, double* __restrict__ gqE, double* __restrict__ ga) {
+  GRID_STRIDE(i, pa.n) {
+    const int o = perm[i];
+    const double qe = qEs ? qEs[i] : pa.P[i].w;
+    if (gpos) {
+      const double4 l = lam4[i], m = mu4[i];
+      double A[6], B[6];
+      for (int k = 0; k < 6; ++k) {
+        A[k] = Ge[6 * i + k] + Gm[6 * i + k];
+        B[k] = Gl[6 * i + k];
+      }
+      const double la[3] = {l.x * A[0] + l.y * A[3] + l.z * A[4], l.x * A[3] + l.y * A[1] + l.z * A[5],
+                            l.x * A[4] + l.y * A[5] + l.z * A[2]};
+      const double mb[3] = {m.x * B[0] + m.y * B[3] + m.z * B[4], m.x * B[3] + m.y * B[1] + m.z * B[5],
+                            m.x * B[4] + m.y * B[5] + m.z * B[2]};
+      for (int c = 0; c < 3; ++c) gpos[3 * o + c] = qe * Eul[3 * i + c] + la[c] + mb[c];
+    }
+    if (gq) gq[o] = qEs ? 0.0 : -phil[i];
+    if (gqE) gqE[o] = -phil[i];
+    if (ga) {
+      double d = 0.0;
+      for (int c = 0; c < 3; ++c) d += (Gs[3 * i + c] + Edl[3 * i + c]) * Etot[3 * i + c];
+      if (dalp) d += (dalm[i] - dalp[i]) * inv2c;
+      ga[o] = d;
+    }
+  }
+}
+
+// out = a[perm] as a sorted 3-vector per particle (caller order in, sorted order out)
+__global__ __launch_bounds__(TPB) void k_permute_vec3(const int* __restrict__ perm, int n, const double* __restrict__ in,
+                                                      double* __restrict__ out) {
+  GRID_STRIDE(i, n) {
+    const int o = perm[i];
+    for (int c = 0; c < 3; ++c) out[3 * i + c] = in[3 * o + c];
+  }
+}
+
+// plus/minus = (a.xyz +/- c b.xyz, a.w): the two dipole sets of the polarisation identity
+__global__ __launch_bounds__(TPB) void k_dipole_pm(int n, const double4* __restrict__ a, const double4* __restrict__ b,
+                                                   double c, double4* __restrict__ plus, double4* __restrict__ minus) {
+  GRID_STRIDE(i, n) {
+    const double4 u = a[i], v = b[i];
+    plus[i] = make_double4(u.x + c * v.x, u.y + c * v.y, u.z + c * v.z, u.w);
+    minus[i] = make_double4(u.x - c * v.x, u.y - c * v.y, u.z - c * v.z, u.w);
+  }
+}
+
 __global__ __launch_bounds__(TPB) void k_unpermute_field(const int* __restrict__ perm, int n,
                                                          FieldOut src, double* __restrict__ phi,
                                                          double* __restrict__ E,
@@ -610,6 +672,29 @@ void launch_backward(const Particles& pa, const int* perm, const double4* mu4, c
                      hipStream_t s) {
   hipLaunchKernelGGL(k_backward, dim3(grid(pa.n)), dim3(TPB), 0, s, pa, perm, mu4, F_s, phi_s, Etot_s,
                      phiE_s, dal_thole, k_e, g, gpos, gq, gqE, galpha);
+  PFMM_LAUNCH_CHECK();
+}
+
+void launch_backward_mu(const Particles& pa, const int* perm, const double4* mu4, const double4* lam4,
+                        const FieldOut& lam, const double* Ge, const double* Gm, const double* Etot, const double* Gs,
+                        const double* qEs, const double* dalp, const double* dalm, double inv2c, double* gpos,
+                        double* gq, double* gqE, double* ga, hipStream_t s) {
+  if (pa.n <= 0) return;
+  hipLaunchKernelGGL(k_backward_mu, dim3(grid(pa.n)), dim3(TPB), 0, s, pa, perm, mu4, lam4, lam.phi, lam.Eu, lam.Ed,
+                     lam.G, Ge, Gm, Etot, Gs, qEs, dalp, dalm, inv2c, gpos, gq, gqE, ga);
+  PFMM_LAUNCH_CHECK();
+}
+
+void launch_permute_vec3(const int* perm, int n, const double* in, double* out, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_permute_vec3, dim3(grid(n)), dim3(TPB), 0, s, perm, n, in, out);
+  PFMM_LAUNCH_CHECK();
+}
+
+void launch_dipole_pm(int n, const double4* a, const double4* b, double c, double4* plus, double4* minus,
+                      hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_dipole_pm, dim3(grid(n)), dim3(TPB), 0, s, n, a, b, c, plus, minus);
   PFMM_LAUNCH_CHECK();
 }
 

@@ -775,6 +775,19 @@ def test_errors(api):
         api.Solver(order_p=11)
 
 
+def test_one_hip_runtime_is_mapped(api):
+    """The library binds to the HIP runtime PyTorch already loaded (same SONAME): after a solve the
+    process maps exactly one libamdhip64."""
+    import os
+    print_case("one hip runtime")
+    X, q, a, _ = cube(50, 6.0, 30)
+    api.Solver(order_p=4, ws=1).solve(T(X), T(q), T(a))
+    with open("/proc/self/maps") as f:
+        libs = {os.path.realpath(line.split()[-1]) for line in f if "libamdhip64" in line}
+    print(f"HIP runtimes mapped: {sorted(libs)}", flush=True)
+    assert len(libs) == 1
+
+
 def test_zero_polarizability_is_coulomb(api):
     print_case("alpha = 0")
     X, q, a, _ = cube(300, 12.0, 12)
