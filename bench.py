@@ -105,6 +105,11 @@ def parse():
                     help="polarise the dipoles with separate field charges (a seeded reshuffle of q)")
     ap.add_argument("--exclusions", type=int, default=0,
                     help="exclude the pairs (i, i + d), d = 1 .. K, of the generator's particle order")
+    ap.add_argument("--polarisable-fraction", type=float, default=1.0,
+                    help="keep the polarisability of a seeded fraction of the particles, zero for the rest "
+                         "(the paper's systems: about 1/3)")
+    ap.add_argument("--dipole-tree", action="store_true",
+                    help="run the dipole solve on a tree of the polarisable sites alone (T^mu)")
     ap.add_argument("--oracle-sample", type=int, default=0,
                     help="targets of the sampled oracle check (0: about 2e9 / n, between 64 and 4096)")
     ap.add_argument("--no-split", action="store_true",
@@ -135,6 +140,9 @@ def main():
             wl[k] = getattr(args, k)
     ps = inputs.make(wl["gen"])
     n = ps.n
+    if args.polarisable_fraction < 1.0:
+        keep = np.random.default_rng(13).permutation(n) < int(round(args.polarisable_fraction * n))
+        ps.alpha = np.where(keep, ps.alpha, 0.0)
     dev = torch.device("cuda", 0)
     variant = args.field_charges or args.exclusions > 0
     qE = None
@@ -158,7 +166,8 @@ def main():
     def make(prec, timing=False, tol=None):
         s = api.Solver(order_p=wl["p"], ws=wl["ws"], leaf_width=wl["leaf"], scf_tol=tol or wl["tol"],
                        m2l_order_slack=wl["slack"], precond_cutoff=wl["pc"], precond_iters=wl["pc_iters"],
-                       scf_relax=wl["relax"], dipole_pair_dl=args.pair_dl, precision=prec, timing=timing)
+                       scf_relax=wl["relax"], dipole_pair_dl=args.pair_dl, precision=prec, timing=timing,
+                       dipole_tree=int(args.dipole_tree))
         if pairs is not None:
             s.set_exclusions(n, pairs)
         return s
@@ -340,6 +349,8 @@ def main():
                    "precond_cutoff": wl["pc"], "precond_iters": wl["pc_iters"], "scf_relax": wl["relax"],
                    "dipole_pair_dl": args.pair_dl, "field_charges": bool(args.field_charges),
                    "excluded_pairs": 0 if pairs is None else int(len(pairs)),
+                   "polarisable_fraction": args.polarisable_fraction, "dipole_tree": bool(args.dipole_tree),
+                   "dipole_solve_sites": int(r0["res"].stats["n_sites"]),
                    "levels": r0["res"].stats["levels"],
                    "step": "solve (tree, charge field, dipole CG, energy, forces) + backward",
                    "parallelism": "single GPU"},

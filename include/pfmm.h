@@ -116,6 +116,15 @@ typedef struct pfmm_config {
                           finite dl this field is not additive in the dipoles, so the solve checks
                           its stopping rule on the final dipoles and continues from them if needed
                           (at most twice; PFMM_ERR_NOT_CONVERGED if the rule still fails).        */
+  int dipole_tree;     /* 0: the dipole solve uses the tree of all particles.  1: when the
+                          polarisable sites (alpha > 0) are a proper subset, the dipole solve runs on
+                          a tree of those sites alone (T^mu of Sec. III): its field evaluations
+                          involve the sites only, while the charge field, the final pass, energy and
+                          forces use the tree of all particles.  Same converged dipoles up to the
+                          FMM error of each tree; the stopping rule holds for the site tree's field,
+                          and pfmm_result.residual, measured with the full tree's, shows the two
+                          trees' difference.  Not combined with excluded pairs
+                          (PFMM_ERR_INVALID_ARG).                                                   */
 } pfmm_config;
 
 typedef struct pfmm_result {
@@ -152,6 +161,8 @@ typedef struct pfmm_result {
                                    orders [0] and of the order-capped launches of a relaxed solve [1] */
   int m2l_split_launches[2];    /* the launches counted in t_m2l_split_ms                          */
   int64_t m2l_split_flops[2];   /* their useful flops (2 C(q+6, 6) per cell pair at the order q used) */
+  int64_t n_sites;              /* particles in the tree of the dipole solve (n, or the polarisable
+                                   sites with dipole_tree)                                         */
 } pfmm_result;
 
 typedef struct pfmm_handle pfmm_handle;
@@ -159,7 +170,7 @@ typedef struct pfmm_handle pfmm_handle;
 /* Fill *cfg with the defaults: p = 6, ws = 2, leaf_width = 0, FP64, scf_tol = 1e-6,
    scf_max_iter = 200, graph_iters = 4, thole_a = 2.0, coulomb_k = 332.06371,
    flags = WANT_FORCES | WANT_POTENTIALS | SAVE_FOR_BACKWARD, m2l_order_slack = -1,
-   precond_cutoff = 0, precond_iters = 4, scf_relax = 0. */
+   precond_cutoff = 0, precond_iters = 4, scf_relax = 0, dipole_pair_dl = 0, dipole_tree = 0. */
 void pfmm_config_default(pfmm_config* cfg);
 
 /* Create a handle for a configuration.  Validates cfg, builds the constant operator tables of

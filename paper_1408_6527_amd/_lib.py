@@ -52,6 +52,7 @@ class Config(ctypes.Structure):
         ("precond_iters", ctypes.c_int),
         ("scf_relax", ctypes.c_double),
         ("dipole_pair_dl", ctypes.c_double),
+        ("dipole_tree", ctypes.c_int),
     ]
 
 
@@ -81,6 +82,7 @@ class Result(ctypes.Structure):
         ("t_m2l_split_ms", ctypes.c_double * 2),
         ("m2l_split_launches", ctypes.c_int * 2),
         ("m2l_split_flops", ctypes.c_int64 * 2),
+        ("n_sites", ctypes.c_int64),
     ]
 
 KERNEL_CLASSES = ["p2m", "m2m", "m2l", "l2l", "l2p", "p2p_scf", "p2p_full", "solver"]

@@ -31,7 +31,7 @@ def config(**kw) -> _lib.Config:
 
     Keywords: order_p, ws, leaf_width, precision ("fp64" | "mixed"), scf_tol, scf_max_iter,
     graph_iters, thole_a, coulomb_k, m2l_order_slack, precond_cutoff, precond_iters, scf_relax,
-    dipole_pair_dl,
+    dipole_pair_dl, dipole_tree (0 | 1),
     forces (bool), potentials (bool), save_for_backward (bool), warm_start (bool), timing (bool).
     """
     c = _lib.Config()
@@ -161,7 +161,7 @@ class Solver:
         stats = dict(levels=res.levels, leaf_width=res.leaf_width, n_leaves=res.n_leaves,
                      n_cells=res.n_cells, n_m2l=res.n_m2l, n_p2p=res.n_p2p, m2l_flops=res.m2l_flops, n_evals=res.n_evals,
                      m2l_flops_total=res.m2l_flops_total, m2l_order_cap_min=res.m2l_order_cap_min,
-                     scf_restarts=res.scf_restarts, solve_id=res.solve_id,
+                     scf_restarts=res.scf_restarts, solve_id=res.solve_id, n_sites=res.n_sites,
                      m2l_split=dict(ms=list(res.t_m2l_split_ms), launches=list(res.m2l_split_launches),
                                     flops=list(res.m2l_split_flops)),
                      t_phase_ms=list(res.t_phase_ms), status=_lib.STATUS[st],

@@ -224,6 +224,15 @@ struct pfmm_handle {
   // adjoint of the dipole equations (pfmm_backward_mu): dL/dmu sorted, the solution's dipoles, the
   // adjoint dipoles, their fields, the dipole sets of the Thole polarisation identity
   DevBuf a_G, a_mu4, a_lam4, a_phi, a_Eu, a_Ed, a_G6, a_pl4, a_mi4, a_dalp, a_dalm;
+  // the tree of the polarisable sites (dipole_tree, T^mu of Sec. III), held by an inner handle: flags
+  // and prefix sum of alpha > 0, the sites' caller indices, positions, polarisabilities and zero
+  // charges; for the sorted order of the site tree, each site's caller index (comp) and its index in
+  // this handle's sorted order (map); the right-hand side of the site tree's solves
+  pfmm_handle* sites = nullptr;
+  DevBuf t_flag, t_scan, t_scan_tmp, t_idx, t_pos, t_alpha, t_q, t_comp, t_map, t_rhs;
+  int n_sites = 0;
+  bool sites_active = false;
+  ~pfmm_handle() { delete sites; }
   // excluded pairs (rows in the caller's particle order) for systems of x_n particles; x_active:
   // they apply to the current tree, whose sorted position of each caller index is in w_inv
   DevBuf x_ptr, x_idx, w_inv;
@@ -296,6 +305,7 @@ void validate_config(const pfmm_config* c) {
     throw Error(PFMM_ERR_INVALID_ARG, "dipole_pair_dl must be in [0, 1] Angstrom");
   if (c->precond_cutoff > 0.0 && (c->precond_iters < 1 || c->precond_iters > 64))
     throw Error(PFMM_ERR_INVALID_ARG, "precond_iters must be in 1..64");
+  if (c->dipole_tree != 0 && c->dipole_tree != 1) throw Error(PFMM_ERR_INVALID_ARG, "dipole_tree must be 0 or 1");
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -567,6 +577,49 @@ void check_flag(pfmm_handle* h, int* dflag, hipStream_t s) {
   if (f) throw Error(PFMM_ERR_COINCIDENT, "two particles share the same position");
 }
 
+// The tree of the dipole solve.  With dipole_tree, when the polarisable sites (alpha > 0) are a
+// proper non-empty subset, they get a tree of their own (T^mu of Sec. III), held by the inner handle
+// h->sites: the solve's field evaluations then involve the sites only, while the charge field and the
+// final pass stay on the tree of all particles.  Returns the handle whose tree the solve runs on
+// (h itself otherwise).  pos and alpha are the caller's arrays; call after build_tree(h, ...).
+pfmm_handle* site_tree(pfmm_handle* h, int n, const double* pos, const double* alpha, hipStream_t s) {
+  h->sites_active = false;
+  if (!h->cfg.dipole_tree) return h;
+  if (h->x_active) throw Error(PFMM_ERR_INVALID_ARG, "dipole_tree does not apply excluded pairs");
+  int* flags = dev<int>(h->t_flag, n);
+  int* scan = dev<int>(h->t_scan, n);
+  launch_flag_polarisable(alpha, n, flags, s);
+  const size_t tb = scan_temp_bytes(n);
+  launch_inclusive_scan(raw(h->t_scan_tmp, tb), tb, flags, scan, n, s);
+  int m = 0;
+  sync_read(h, scan + (n - 1), &m, sizeof(int), s);
+  if (m == 0 || m == n) return h;
+  if (!h->sites) {
+    pfmm_config ci = h->cfg;
+    ci.dipole_tree = 0;
+    pfmm_handle* hi = nullptr;
+    const pfmm_status st = pfmm_create(&ci, &hi);
+    if (st != PFMM_OK) throw Error(st, "creating the handle of the polarisable sites' tree failed");
+    h->sites = hi;
+  }
+  pfmm_handle* hm = h->sites;
+  int* idx = dev<int>(h->t_idx, m);
+  double* spos = dev<double>(h->t_pos, 3 * (int64_t)m);
+  double* sal = dev<double>(h->t_alpha, m);
+  double* sq = dev<double>(h->t_q, m);
+  launch_compact_sites(scan, pos, alpha, n, idx, spos, sal, sq, s);
+  hm->kt.reset((h->cfg.flags & PFMM_TIMING) != 0, s);
+  hm->kt.tag = h->cfg.order_p;
+  build_tree(hm, m, spos, sq, sal, s);
+  hm->x_active = false;
+  int* inv = dev<int>(h->w_inv, n);
+  launch_inverse_perm(h->w_perm.as<int>(), n, inv, s);
+  launch_site_maps(hm->w_perm.as<int>(), idx, inv, m, dev<int>(h->t_comp, m), dev<int>(h->t_map, m), s);
+  h->n_sites = m;
+  h->sites_active = true;
+  return hm;
+}
+
 // Stage 2 of Sec. III on the current tree: conjugate gradients on (I - S T~ S) y = S Ee for the
 // right-hand-side field Ee (sorted order, 3n; the static field E^q for the dipoles, or any other
 // vector for the adjoint solve), preconditioned by the near field when configured, with relaxed
@@ -757,10 +810,25 @@ pfmm_status solve_impl(pfmm_handle* h, int64_t n64, const double* pos, const dou
   const double* Ee = fc.E;
   tm.mark();
 
-  // stage 2: conjugate gradients
-  CGState* st = static_cast<CGState*>(h->w_state.reserve(2 * sizeof(CGState)));
+  // stage 2: conjugate gradients, on the tree of all particles or on that of the polarisable sites
+  pfmm_handle* hm = site_tree(h, n, pos, alpha, s);
+  const bool on_sites = hm != h;
+  const int m = on_sites ? h->n_sites : n;
+  CGState* st = static_cast<CGState*>(hm->w_state.reserve(2 * sizeof(CGState)));
+  const double* Ecg = Ee;  // the right-hand side in the order of the solve's tree
+  double4* mu4cg = mu4;
+  int* errcg = err;
+  if (on_sites) {
+    double* rhs = dev<double>(h->t_rhs, 3 * (int64_t)m);
+    launch_permute_vec3(h->t_map.as<int>(), m, Ee, rhs, s);
+    Ecg = rhs;
+    mu4cg = dev<double4>(hm->w_mu4, m);
+    errcg = dev<int>(hm->w_flags, 4);
+    launch_fill_int(errcg, 4, 0, s);
+  }
   const bool warm = (c.flags & PFMM_WARM_START) != 0;
-  if (warm) launch_permute_dipoles(h->w_perm.as<int>(), n, mu, pa.tau, mu4, s);
+  if (warm)
+    launch_permute_dipoles(on_sites ? h->t_comp.as<int>() : h->w_perm.as<int>(), m, mu, hm->pa.tau, mu4cg, s);
   // relaxed field evaluations: the update kernel of each iteration picks the order cap of the next
   RelaxParams rp;
   rp.p = c.order_p;
@@ -781,18 +849,41 @@ pfmm_status solve_impl(pfmm_handle* h, int64_t n64, const double* pos, const dou
   EnergyParts* ep = static_cast<EnergyParts*>(h->w_ep.reserve(sizeof(EnergyParts)));
   CGState hs{};
   EnergyParts he{};
-  int total_iters = 0, restarts = 0, full_evals = 1;  // the charge pass
+  int total_iters = 0, restarts = 0, full_evals = qE ? 2 : 1, cg_evals = 0;  // the charge passes
   bool warm_now = warm;
+  double* part = dev<double>(h->w_red, RED_BLOCKS * 8);
+  const bool pair = c.dipole_pair_dl > 0.0;
   for (;;) {
     const bool relaxed = rp.start > 0.0;
-    hs = dipole_cg(h, Ee, warm_now, rp, st, err, s, &full_evals);
+    hs = dipole_cg(hm, Ecg, warm_now, rp, st, errcg, s, &cg_evals);
     total_iters += hs.iters;
-    const double* y = h->cg_y.as<double>();
-    double* part = h->w_red.as<double>();
+    if (on_sites && (relaxed || pair) && !hs.notspd && !hs.maxed) {
+      // On the site tree the stopping rule is checked with that tree's own field at the full orders
+      // (the full tree's field differs from it by the two trees' FMM errors): a warm-started solve
+      // without the cap from the final dipoles, which stops at once when the rule already holds
+      // (twice at most for charge-pair multipoles, whose field is not additive in the dipoles).
+      RelaxParams r0 = rp;
+      r0.start = 0.0;
+      for (int k = 0; k < (pair ? 2 : 1); ++k) {
+        launch_make_dipoles(hm->pa, hm->cg_y.as<double>(), mu4cg, nullptr, s);
+        launch_fill_int(&st->qcap, 1, c.order_p, s);
+        const CGState h2 = dipole_cg(hm, Ecg, true, r0, st, errcg, s, &cg_evals);
+        total_iters += h2.iters;
+        hs = h2;
+        if (h2.iters == 0 || h2.notspd || h2.maxed) break;
+        ++restarts;
+      }
+    }
+    const double* y = hm->cg_y.as<double>();
     tm.mark();
 
-    // stage 3: field of the converged dipoles (full orders), energy and forces
-    launch_make_dipoles(pa, y, mu4, nullptr, s);
+    // stage 3: field of the converged dipoles (full orders), energy and forces, on all particles
+    if (on_sites) {
+      launch_make_dipoles(hm->pa, y, mu4cg, nullptr, s);
+      launch_place_site_dipoles(h->t_map.as<int>(), m, mu4cg, n, pa.tau, mu4, s);
+    } else {
+      launch_make_dipoles(pa, y, mu4, nullptr, s);
+    }
     fmm_pass(h, 2, 1, FieldOut{phim, Eum, Edm, Gm}, err, nullptr, s);
     ++full_evals;
     tm.mark();
@@ -808,8 +899,8 @@ pfmm_status solve_impl(pfmm_handle* h, int64_t n64, const double* pos, const dou
     // a sum than for its terms), so the recursive residual of the conjugate gradients can converge
     // while the true one has not: continue the same way, each time on a correction that is smaller
     // by the residual's factor, so that the non-additive part shrinks with it.
-    const bool pair = c.dipole_pair_dl > 0.0;
-    if ((relaxed || pair) && !hs.notspd && !hs.maxed && true_res > c.scf_tol && restarts < (pair ? 2 : 1)) {
+    if (!on_sites && (relaxed || pair) && !hs.notspd && !hs.maxed && true_res > c.scf_tol &&
+        restarts < (pair ? 2 : 1)) {
       ++restarts;
       rp.start = 0.0;
       launch_fill_int(&st->qcap, 1, c.order_p, s);
@@ -818,7 +909,7 @@ pfmm_status solve_impl(pfmm_handle* h, int64_t n64, const double* pos, const dou
     }
     // after the continuations allowed, a relaxed or charge-pair solve whose final dipoles still miss
     // the stopping rule at the full orders has not converged
-    if ((relaxed || pair || restarts > 0) && true_res > c.scf_tol) {
+    if (!on_sites && (relaxed || pair || restarts > 0) && true_res > c.scf_tol) {
       hs.maxed = 1;
       hs.res = true_res;
     }
@@ -828,6 +919,12 @@ pfmm_status solve_impl(pfmm_handle* h, int64_t n64, const double* pos, const dou
   h->kt.collect(res->t_kernel_ms, res->kernel_launches);
   h->kt.collect_m2l(KC_M2L, c.order_p, h->m2l_flops, h->m2l_flops_cap, res->t_m2l_split_ms, res->m2l_split_launches,
                     res->m2l_split_flops);
+  if (on_sites) {
+    hm->kt.collect(res->t_kernel_ms, res->kernel_launches);
+    hm->kt.collect_m2l(KC_M2L, c.order_p, hm->m2l_flops, hm->m2l_flops_cap, res->t_m2l_split_ms,
+                       res->m2l_split_launches, res->m2l_split_flops);
+  }
+  res->n_sites = m;
 
   const double ke = c.coulomb_k;
   res->U_qq = ke * he.Uqq;
@@ -851,13 +948,13 @@ pfmm_status solve_impl(pfmm_handle* h, int64_t n64, const double* pos, const dou
     sync_read(h, st, &hc, sizeof(hc), s);
     std::memcpy(ncap, hc.ncap, sizeof(ncap));
   }
-  int64_t flops_total = (int64_t)full_evals * h->m2l_flops;
+  int64_t flops_total = (int64_t)full_evals * h->m2l_flops + (int64_t)cg_evals * hm->m2l_flops;
   int cap_min = c.order_p;
   for (int q = 0; q <= c.order_p; ++q) {
-    flops_total += (int64_t)ncap[q] * (q == c.order_p ? h->m2l_flops : h->m2l_flops_cap[q]);
+    flops_total += (int64_t)ncap[q] * (q == c.order_p ? hm->m2l_flops : hm->m2l_flops_cap[q]);
     if (ncap[q] > 0) cap_min = std::min(cap_min, q);
   }
-  res->n_evals = full_evals + total_iters;
+  res->n_evals = full_evals + cg_evals + total_iters;
   res->m2l_flops_total = flops_total;
   res->m2l_order_cap_min = cap_min;
   res->scf_restarts = restarts;
@@ -896,6 +993,7 @@ void pfmm_config_default(pfmm_config* c) {
   c->precond_iters = 4;
   c->scf_relax = 0.0;
   c->dipole_pair_dl = 0.0;
+  c->dipole_tree = 0;
 }
 
 pfmm_status pfmm_create(const pfmm_config* cfg, pfmm_handle** out) {
@@ -1040,7 +1138,21 @@ pfmm_status pfmm_backward_mu(pfmm_handle* h, int64_t solve_id, const double* g_m
     PFMM_HIP(hipMemcpyAsync(mus, mu4, sizeof(double4) * (size_t)n, hipMemcpyDeviceToDevice, s));
     // the adjoint lambda = A^-1 dL/dmu: the same symmetric operator (same tree, orders and
     // preconditioner) with dL/dmu in place of the static field; every evaluation at the full orders
-    CGState* st = static_cast<CGState*>(h->w_state.reserve(2 * sizeof(CGState)));
+    // on the tree the forward solve ran on (that of the polarisable sites with dipole_tree)
+    pfmm_handle* hm = h->sites_active ? h->sites : h;
+    const int m = h->sites_active ? h->n_sites : n;
+    const double* Gcg = Gs;
+    int* errcg = err;
+    if (h->sites_active) {
+      double* gm = dev<double>(h->t_rhs, 3 * (int64_t)m);
+      launch_permute_vec3(h->t_comp.as<int>(), m, g_mu, gm, s);
+      Gcg = gm;
+      dev<double4>(hm->w_mu4, m);
+      errcg = dev<int>(hm->w_flags, 4);
+      launch_fill_int(errcg, 4, 0, s);
+      hm->kt.reset(false, s);
+    }
+    CGState* st = static_cast<CGState*>(hm->w_state.reserve(2 * sizeof(CGState)));
     RelaxParams rp;
     rp.p = c.order_p;
     rp.qmin = (c.order_p + 1) / 2;
@@ -1049,12 +1161,18 @@ pfmm_status pfmm_backward_mu(pfmm_handle* h, int64_t solve_id, const double* g_m
     rp.lrho = 2.0 * std::log((c.ws + 1.0) / std::sqrt(3.0));
     launch_fill_int(&st->qcap, 1, c.order_p, s);
     int evals = 0;
-    const CGState hs = dipole_cg(h, Gs, false, rp, st, err, s, &evals);
+    const CGState hs = dipole_cg(hm, Gcg, false, rp, st, errcg, s, &evals);
     if (hs.notspd) throw Error(PFMM_ERR_NOT_SPD, "adjoint solve met p.Ap <= 0");
     if (!hs.done || (hs.maxed && hs.res > c.scf_tol))
       throw Error(PFMM_ERR_NOT_CONVERGED, "adjoint solve did not converge: residual " + std::to_string(hs.res));
     double4* lam4 = dev<double4>(h->a_lam4, n);
-    launch_make_dipoles(pa, h->cg_y.as<double>(), lam4, nullptr, s);
+    if (h->sites_active) {
+      double4* lm = hm->w_mu4.as<double4>();
+      launch_make_dipoles(hm->pa, hm->cg_y.as<double>(), lm, nullptr, s);
+      launch_place_site_dipoles(h->t_map.as<int>(), m, lm, n, pa.tau, lam4, s);
+    } else {
+      launch_make_dipoles(pa, h->cg_y.as<double>(), lam4, nullptr, s);
+    }
     // fields of the adjoint dipoles (potential, undamped and damped field, damped gradient)
     PFMM_HIP(hipMemcpyAsync(mu4, lam4, sizeof(double4) * (size_t)n, hipMemcpyDeviceToDevice, s));
     FieldOut lf{dev<double>(h->a_phi, n), dev<double>(h->a_Eu, 3 * (int64_t)n), dev<double>(h->a_Ed, 3 * (int64_t)n),

@@ -62,6 +62,7 @@ void launch_gather(const int* perm, const double* pos, const double* q, const do
                    double sqrt_a, double4* P, double* al, double* sqa, double* tau, double* itau,
                    hipStream_t s);
 size_t scan_temp_bytes(int n);
+void launch_inclusive_scan(void* tmp, size_t tmp_bytes, const int* in, int* out, int n, hipStream_t s);
 // cid[i] = 1 + index (within the level) of the cell holding sorted particle i (inclusive scan of
 // the cell-head flags); *count_out = cells on the level.
 void launch_level_scan(const uint64_t* keys, int n, int shift, int* flags, int* cid, int* count_out,
@@ -190,6 +191,12 @@ void launch_backward_mu(const Particles& pa, const int* perm, const double4* mu4
                         const FieldOut& lam, const double* Ge, const double* Gm, const double* Etot, const double* Gs,
                         const double* qEs, const double* dalp, const double* dalm, double inv2c, double* gpos,
                         double* gq, double* gqE, double* ga, hipStream_t s);
+void launch_flag_polarisable(const double* alpha, int n, int* flags, hipStream_t s);
+void launch_compact_sites(const int* scan, const double* pos, const double* alpha, int n, int* idx, double* spos,
+                          double* salpha, double* sq, hipStream_t s);
+void launch_site_maps(const int* perm_mu, const int* idx, const int* inv, int m, int* comp, int* map, hipStream_t s);
+void launch_place_site_dipoles(const int* map, int m, const double4* src, int n, const double* tau, double4* dst,
+                               hipStream_t s);
 void launch_permute_vec3(const int* perm, int n, const double* in, double* out, hipStream_t s);
 void launch_dipole_pm(int n, const double4* a, const double4* b, double c, double4* plus, double4* minus,
                       hipStream_t s);

@@ -518,6 +518,50 @@ __global__ __launch_bounds__(TPB) void k_dipole_pm(int n, const double4* __restr
   }
 }
 
+// The tree of the polarisable sites (T^mu of Sec. III): the sites with alpha > 0 in the caller's
+// order, compacted through an inclusive prefix sum of their flags, with zero charges (the dipole solve
+// uses dipole sources only).
+__global__ __launch_bounds__(TPB) void k_flag_polarisable(const double* __restrict__ alpha, int n, int* __restrict__ f) {
+  GRID_STRIDE(i, n) { f[i] = alpha[i] > 0.0 ? 1 : 0; }
+}
+__global__ __launch_bounds__(TPB) void k_compact_sites(const int* __restrict__ scan, const double* __restrict__ pos,
+                                                       const double* __restrict__ alpha, int n, int* __restrict__ idx,
+                                                       double* __restrict__ spos, double* __restrict__ salpha,
+                                                       double* __restrict__ sq) {
+  GRID_STRIDE(i, n) {
+    if (alpha[i] > 0.0) {
+      const int k = scan[i] - 1;
+      idx[k] = i;
+      for (int c = 0; c < 3; ++c) spos[3 * k + c] = pos[3 * i + c];
+      salpha[k] = alpha[i];
+      sq[k] = 0.0;
+    }
+  }
+}
+// For the j-th particle of the site tree (sorted): its caller index comp[j] and its index in the
+// sorted order of the full tree map[j] (inv = inverse permutation of the full tree).
+__global__ __launch_bounds__(TPB) void k_site_maps(const int* __restrict__ perm_mu, const int* __restrict__ idx,
+                                                   const int* __restrict__ inv, int m, int* __restrict__ comp,
+                                                   int* __restrict__ map) {
+  GRID_STRIDE(j, m) {
+    const int o = idx[perm_mu[j]];
+    comp[j] = o;
+    map[j] = inv[o];
+  }
+}
+// dst = (0, 0, 0, tau) everywhere, then the site tree's dipoles at their places in the full tree
+__global__ __launch_bounds__(TPB) void k_zero_dipoles(int n, const double* __restrict__ tau, double4* __restrict__ dst) {
+  GRID_STRIDE(i, n) { dst[i] = make_double4(0.0, 0.0, 0.0, tau[i]); }
+}
+__global__ __launch_bounds__(TPB) void k_scatter_dipoles(const int* __restrict__ map, int m, const double4* __restrict__ src,
+                                                         double4* __restrict__ dst) {
+  GRID_STRIDE(j, m) {
+    const double4 u = src[j];
+    const int i = map[j];
+    dst[i] = make_double4(u.x, u.y, u.z, dst[i].w);
+  }
+}
+
 __global__ __launch_bounds__(TPB) void k_unpermute_field(const int* __restrict__ perm, int n,
                                                          FieldOut src, double* __restrict__ phi,
                                                          double* __restrict__ E,
@@ -695,6 +739,32 @@ void launch_dipole_pm(int n, const double4* a, const double4* b, double c, doubl
                       hipStream_t s) {
   if (n <= 0) return;
   hipLaunchKernelGGL(k_dipole_pm, dim3(grid(n)), dim3(TPB), 0, s, n, a, b, c, plus, minus);
+  PFMM_LAUNCH_CHECK();
+}
+
+void launch_flag_polarisable(const double* alpha, int n, int* flags, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_flag_polarisable, dim3(grid(n)), dim3(TPB), 0, s, alpha, n, flags);
+  PFMM_LAUNCH_CHECK();
+}
+void launch_compact_sites(const int* scan, const double* pos, const double* alpha, int n, int* idx, double* spos,
+                          double* salpha, double* sq, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_compact_sites, dim3(grid(n)), dim3(TPB), 0, s, scan, pos, alpha, n, idx, spos, salpha, sq);
+  PFMM_LAUNCH_CHECK();
+}
+void launch_site_maps(const int* perm_mu, const int* idx, const int* inv, int m, int* comp, int* map, hipStream_t s) {
+  if (m <= 0) return;
+  hipLaunchKernelGGL(k_site_maps, dim3(grid(m)), dim3(TPB), 0, s, perm_mu, idx, inv, m, comp, map);
+  PFMM_LAUNCH_CHECK();
+}
+void launch_place_site_dipoles(const int* map, int m, const double4* src, int n, const double* tau, double4* dst,
+                               hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_zero_dipoles, dim3(grid(n)), dim3(TPB), 0, s, n, tau, dst);
+  PFMM_LAUNCH_CHECK();
+  if (m <= 0) return;
+  hipLaunchKernelGGL(k_scatter_dipoles, dim3(grid(m)), dim3(TPB), 0, s, map, m, src, dst);
   PFMM_LAUNCH_CHECK();
 }
 

@@ -286,6 +286,10 @@ size_t scan_temp_bytes(int n) {
   return bytes;
 }
 
+void launch_inclusive_scan(void* tmp, size_t tmp_bytes, const int* in, int* out, int n, hipStream_t s) {
+  PFMM_HIP(hipcub::DeviceScan::InclusiveSum(tmp, tmp_bytes, in, out, n, s));
+}
+
 void launch_level_scan(const uint64_t* keys, int n, int shift, int* flags, int* cid, int* count_out,
                        void* tmp, size_t tmp_bytes, hipStream_t s) {
   hipLaunchKernelGGL(k_level_flags, dim3(grid_for(n)), dim3(TPB), 0, s, keys, n, shift, flags);
