@@ -110,6 +110,13 @@ def parse():
                          "(the paper's systems: about 1/3)")
     ap.add_argument("--dipole-tree", action="store_true",
                     help="run the dipole solve on a tree of the polarisable sites alone (T^mu)")
+    ap.add_argument("--theta", type=float, default=0.0,
+                    help="interaction lists of the acceptance criterion with this theta (0: the ws lists); every "
+                         "M2L at order p (the order slack is dropped)")
+    ap.add_argument("--ndirect", type=int, default=64,
+                    help="with --theta: cell pairs holding fewer particles together are summed directly")
+    ap.add_argument("--leaf-direct", type=int, default=1, choices=[0, 1],
+                    help="with --theta: leaf pairs are always summed directly")
     ap.add_argument("--oracle-sample", type=int, default=0,
                     help="targets of the sampled oracle check (0: about 2e9 / n, between 64 and 4096)")
     ap.add_argument("--no-split", action="store_true",
@@ -138,6 +145,8 @@ def main():
     for k in ("p", "ws", "leaf", "tol", "slack", "pc", "pc_iters", "relax"):
         if getattr(args, k) is not None:
             wl[k] = getattr(args, k)
+    if args.theta > 0.0:
+        wl["slack"] = -1
     ps = inputs.make(wl["gen"])
     n = ps.n
     if args.polarisable_fraction < 1.0:
@@ -167,7 +176,8 @@ def main():
         s = api.Solver(order_p=wl["p"], ws=wl["ws"], leaf_width=wl["leaf"], scf_tol=tol or wl["tol"],
                        m2l_order_slack=wl["slack"], precond_cutoff=wl["pc"], precond_iters=wl["pc_iters"],
                        scf_relax=wl["relax"], dipole_pair_dl=args.pair_dl, precision=prec, timing=timing,
-                       dipole_tree=int(args.dipole_tree))
+                       dipole_tree=int(args.dipole_tree), mac_theta=args.theta, mac_ndirect=args.ndirect,
+                       mac_leaf_direct=args.leaf_direct)
         if pairs is not None:
             s.set_exclusions(n, pairs)
         return s
@@ -286,7 +296,13 @@ def main():
                 "avg_launch_ms": round(ms / nl, 4), "work_per_launch": work, "pairs": stats["n_p2p"],
                 "flops_per_pair": P2P_SCF_FLOPS_PER_PAIR}
 
-    if dominant == "m2l":
+    if dominant == "m2l" and args.theta > 0.0:
+        # the M2L of the acceptance-criterion lists runs on the float64 vector units on both paths
+        mr = m2l_roof(kst, PEAK["fp64_vector"])
+        roofline = {"bound": "alu", "kernel": "m2l_list", "achieved": mr["achieved"], "peak": PEAK["fp64_vector"],
+                    "unit": "TFLOP/s", "frac": mr["frac"], "traffic": None,
+                    "avg_launch_ms": mr["avg_launch_ms"], "work_per_launch": mr["work_per_launch"]}
+    elif dominant == "m2l":
         peak = PEAK["fp32_mfma"] if prim == "mixed" else PEAK["fp64_mfma"]
         mr = m2l_roof(kst, peak)
         roofline = {"bound": "mfma", "kernel": "m2l", "achieved": mr["achieved"], "peak": peak, "unit": "TFLOP/s",
@@ -351,6 +367,9 @@ def main():
                    "excluded_pairs": 0 if pairs is None else int(len(pairs)),
                    "polarisable_fraction": args.polarisable_fraction, "dipole_tree": bool(args.dipole_tree),
                    "dipole_solve_sites": int(r0["res"].stats["n_sites"]),
+                   "mac_theta": args.theta, "mac_ndirect": args.ndirect if args.theta > 0 else None,
+                   "mac_leaf_direct": args.leaf_direct if args.theta > 0 else None,
+                   "m2l_pairs": int(r0["res"].stats["n_m2l"]), "near_pairs": int(r0["res"].stats["n_p2p"]),
                    "levels": r0["res"].stats["levels"],
                    "step": "solve (tree, charge field, dipole CG, energy, forces) + backward",
                    "parallelism": "single GPU"},

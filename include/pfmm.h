@@ -125,6 +125,22 @@ typedef struct pfmm_config {
                           and pfmm_result.residual, measured with the full tree's, shows the two
                           trees' difference.  Not combined with excluded pairs
                           (PFMM_ERR_INVALID_ARG).                                                   */
+  double mac_theta;    /* 0: interaction lists by the well-separation rule ws (the default).  In
+                          [0.3, 1): the multipole acceptance criterion and dual tree walk of Sec. III
+                          (eq. mac): two cells of one level that are not adjacent interact through
+                          one M2L when theta |z_A - z_B| > r_A + r_B, with z the cell centres and r
+                          the largest distance from a cell's centre to one of its particles;
+                          otherwise the pairs of their children are examined, down to the leaves,
+                          whose pairs that are not accepted are summed directly.  Every M2L is at
+                          order p (m2l_order_slack must be -1) and runs in float64 on both precision
+                          paths; ws no longer shapes the lists.  The Thole damping radius must not
+                          exceed the leaf edge.  Below 0.3 the offsets of accepted pairs outgrow the
+                          operator table (PFMM_ERR_INVALID_ARG).                                   */
+  int mac_ndirect;     /* with mac_theta: a pair of cells holding fewer than this many particles
+                          together is summed directly, whatever the criterion says (the paper's
+                          direct interaction of small node pairs, about 64); 0 = no such rule      */
+  int mac_leaf_direct; /* with mac_theta: 1 = pairs of leaves are always summed directly (the paper's
+                          rule for two leaves), 0 = leaf pairs are accepted by the criterion too    */
 } pfmm_config;
 
 typedef struct pfmm_result {
@@ -170,7 +186,8 @@ typedef struct pfmm_handle pfmm_handle;
 /* Fill *cfg with the defaults: p = 6, ws = 2, leaf_width = 0, FP64, scf_tol = 1e-6,
    scf_max_iter = 200, graph_iters = 4, thole_a = 2.0, coulomb_k = 332.06371,
    flags = WANT_FORCES | WANT_POTENTIALS | SAVE_FOR_BACKWARD, m2l_order_slack = -1,
-   precond_cutoff = 0, precond_iters = 4, scf_relax = 0, dipole_pair_dl = 0, dipole_tree = 0. */
+   precond_cutoff = 0, precond_iters = 4, scf_relax = 0, dipole_pair_dl = 0, dipole_tree = 0,
+   mac_theta = 0, mac_ndirect = 64, mac_leaf_direct = 1. */
 void pfmm_config_default(pfmm_config* cfg);
 
 /* Create a handle for a configuration.  Validates cfg, builds the constant operator tables of

@@ -318,19 +318,88 @@ class Octree:
         leaves = self.cells[self.L]
         return [(B, A) for B in leaves for A in leaves if self.cheb(A, B) <= self.ws]
 
+    @staticmethod
+    def _length(d):
+        """|d| of the rows of d, summed in the order x, y, z in float64 (np.sqrt is correctly
+        rounded): the acceptance decisions below are integer results decided in floating point, so
+        the arithmetic is spelled out."""
+        d = np.atleast_2d(np.asarray(d, np.float64))
+        return np.sqrt(d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1] + d[:, 2] * d[:, 2])
+
+    def enclosing_radii(self, X):
+        """r_enc of every cell: the largest distance from the cell's centre (its expansion centre) to
+        one of its particles (Sec. III, the cell record's enclosing radius)."""
+        X = np.asarray(X, np.float64)
+        renc = [dict() for _ in range(self.L + 1)]
+        for cc, idx in self.leaves.items():
+            for l in range(self.L + 1):
+                sh = self.L - l
+                c = (cc[0] >> sh, cc[1] >> sh, cc[2] >> sh)
+                r = float(np.max(self._length(X[idx] - self.centre(l, c)[None, :])))
+                renc[l][c] = max(renc[l].get(c, 0.0), r)
+        return renc
+
+    def mac_lists(self, X, theta, ndirect=0, leaf_direct=False):
+        """Interaction lists of the paper's dual tree walk (Sec. III) on this octree, with its
+        multipole acceptance criterion (eq:mac): a pair of cells of one level, A != B, is accepted for
+        M2L when theta |z_A - z_B| > r_A + r_B (z the cell centres, r the enclosing radii), the two
+        cells are not adjacent (Chebyshev distance >= 2: Thole-damped pairs, closer than a leaf edge,
+        stay in the direct part), they hold at least ndirect particles together and, with
+        leaf_direct, they are not leaves (the paper's direct interaction of small or leaf pairs);
+        otherwise the pair is split into the pairs of their children, and a pair of leaves that is
+        not accepted goes to the direct part.  The children of a pair below ndirect hold fewer
+        particles still, so all of its descendants are direct.  The walk starts from the root paired
+        with itself, so every ordered pair of particles is counted once.
+        Returns (m2l, near): m2l[l] the (B, A) pairs accepted at level l, near the (B, A) leaf pairs."""
+        renc = self.enclosing_radii(X)
+        count = [dict() for _ in range(self.L + 1)]
+        for cc, idx in self.leaves.items():
+            for l in range(self.L + 1):
+                sh = self.L - l
+                c = (cc[0] >> sh, cc[1] >> sh, cc[2] >> sh)
+                count[l][c] = count[l].get(c, 0) + len(idx)
+        kids = [dict() for _ in range(self.L + 1)]
+        for l in range(1, self.L + 1):
+            for c in self.cells[l]:
+                kids[l - 1].setdefault((c[0] >> 1, c[1] >> 1, c[2] >> 1), []).append(c)
+        m2l = [[] for _ in range(self.L + 1)]
+        near = []
+        stack = [(0, (0, 0, 0), (0, 0, 0))]
+        while stack:
+            l, B, A = stack.pop()
+            if (A != B and self.cheb(A, B) >= 2 and count[l][B] + count[l][A] >= ndirect
+                    and not (leaf_direct and l == self.L)):
+                dist = float(self._length((np.asarray(B, np.float64) - np.asarray(A, np.float64)) * self.width(l))[0])
+                if theta * dist > renc[l][B] + renc[l][A]:
+                    m2l[l].append((B, A))
+                    continue
+            if l == self.L:
+                near.append((B, A))
+                continue
+            for b in kids[l][B]:
+                for a in kids[l][A]:
+                    stack.append((l + 1, b, a))
+        for lst in m2l:
+            lst.sort()
+        near.sort()
+        return m2l, near
+
 
 # ----------------------------------------------------------------------------------------------
 # Field evaluation.
 # ----------------------------------------------------------------------------------------------
 
 def fmm_fields(X, q, mu, alpha, thole_a, p, leaf_width, ws=1, want_grad=True, order_slack=-1,
-               pair_dl=0.0, excl=None):
+               pair_dl=0.0, excl=None, theta=None, ndirect=0, leaf_direct=False):
     """FMM fields of charges q and point dipoles mu at every particle.
 
     pair_dl > 0 builds the multipoles of the dipoles from their +/- q^mu pairs (Sec. II.C, p2m_pair)
     instead of the point-dipole limit; the near field keeps the point dipoles.
     excl: excluded pairs (direct.exclusion_matrix); the exact terms of each excluded pair are taken
     off the result, wherever the pair was counted (near field, or M2L to within its truncation).
+    theta: the interaction lists of the paper's dual tree walk with its acceptance criterion
+    (Octree.mac_lists, with ndirect and leaf_direct) instead of the well-separation lists; the M2L
+    then runs at order p.
 
     Returns a dict with
       phi  total potential (undamped),
@@ -366,8 +435,9 @@ def fmm_fields(X, q, mu, alpha, thole_a, p, leaf_width, ws=1, want_grad=True, or
     # transfer
     nm = m2l_matrix(p)
     F = [dict() for _ in range(L + 1)]
+    mac = tree.mac_lists(X, theta, ndirect, leaf_direct) if theta is not None else None
     for l in range(1, L + 1):
-        pairs = tree.m2l_pairs(l)
+        pairs = mac[0][l] if mac is not None else tree.m2l_pairs(l)
         for s in range(0, len(pairs), 256):
             chunk = pairs[s:s + 256]
             R = np.array([tree.centre(l, B) - tree.centre(l, A) for B, A in chunk])
@@ -396,7 +466,7 @@ def fmm_fields(X, q, mu, alpha, thole_a, p, leaf_width, ws=1, want_grad=True, or
 
     # near field, direct with point dipoles
     E_u = E_far.copy(); E_d = E_far.copy(); G_d = G_far.copy()
-    for B, A in tree.near_pairs():
+    for B, A in (mac[1] if mac is not None else tree.near_pairs()):
         ib = tree.leaves[B]; ia = tree.leaves[A]
         for i in ib:
             src = [j for j in ia if j != i]

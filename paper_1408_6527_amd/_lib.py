@@ -53,6 +53,9 @@ class Config(ctypes.Structure):
         ("scf_relax", ctypes.c_double),
         ("dipole_pair_dl", ctypes.c_double),
         ("dipole_tree", ctypes.c_int),
+        ("mac_theta", ctypes.c_double),
+        ("mac_ndirect", ctypes.c_int),
+        ("mac_leaf_direct", ctypes.c_int),
     ]
 
 

@@ -21,7 +21,7 @@ BUILD = os.path.join(ROOT, "_build", "pfmm")
 LIB = os.path.join(HERE, "libpfmm.so")
 ARCH = os.environ.get("PFMM_ARCH", "gfx950")
 
-SOURCES = ["tables.cpp", "tree.hip", "expansions.hip", "m2l.hip", "p2p.hip", "solver.hip", "api.hip"]
+SOURCES = ["tables.cpp", "tree.hip", "expansions.hip", "m2l.hip", "mac.hip", "p2p.hip", "solver.hip", "api.hip"]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-result", "-Wno-unused-function"]

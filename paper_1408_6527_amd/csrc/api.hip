@@ -6,8 +6,10 @@
 //   stage 2   conjugate gradients on (I - S T~ S) y = S E^q, one FMM pass of the
 //             dipoles per iteration                                             (solver.hip)
 //   stage 3   field of the converged dipoles, energy, forces, un-permutation
-// An FMM pass is P2M -> M2M (up) -> M2L -> L2L (down) -> L2P, plus P2P over colleague leaves.
+// An FMM pass is P2M -> M2M (up) -> M2L -> L2L (down) -> L2P, plus P2P over colleague leaves; with
+// mac_theta the M2L and P2P run from the lists of the acceptance-criterion walk (mac.hip).
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <climits>
 #include <cmath>
@@ -18,6 +20,7 @@
 #include <vector>
 
 #include "kernels.hpp"
+#include "schedule.hpp"
 #include "tables.hpp"
 
 using namespace pfmm;
@@ -249,6 +252,16 @@ struct pfmm_handle {
   int64_t n_m2l = 0, n_p2p = 0, m2l_flops = 0;
   int64_t m2l_flops_cap[11] = {};  // useful M2L flops per evaluation with every order capped at c
   int n_evals = 0;
+  // acceptance-criterion lists (mac_theta > 0): operator rows of the offsets in [-mac_R, mac_R]^3,
+  // enclosing radii, the frontier pairs of the walk and their prefix sums, the accepted pairs of
+  // each level, the near pairs, and the rows sorted by target
+  bool mac = false;
+  int mac_R = 0;
+  MacView mv;
+  DevBuf t_mdvec, m_renc, m_bad, m_acc, m_kid, m_accs, m_kids, m_stmp, m_nt, m_ns, m_kin, m_vin, m_kout, m_vout,
+      m_sort_tmp, m_cnt, m_mptr, m_nkout, m_nvout, m_nptr;
+  DevBuf m_fr[2];
+  std::array<DevBuf, MAX_LEVELS + 1> m_lt, m_lv;
 };
 
 namespace {
@@ -306,11 +319,22 @@ void validate_config(const pfmm_config* c) {
   if (c->precond_cutoff > 0.0 && (c->precond_iters < 1 || c->precond_iters > 64))
     throw Error(PFMM_ERR_INVALID_ARG, "precond_iters must be in 1..64");
   if (c->dipole_tree != 0 && c->dipole_tree != 1) throw Error(PFMM_ERR_INVALID_ARG, "dipole_tree must be 0 or 1");
+  if (!(c->mac_theta == 0.0 || (c->mac_theta >= 0.3 && c->mac_theta < 1.0)))
+    throw Error(PFMM_ERR_INVALID_ARG, "mac_theta must be 0 or in [0.3, 1)");
+  if (c->mac_ndirect < 0) throw Error(PFMM_ERR_INVALID_ARG, "mac_ndirect must be >= 0");
+  if (c->mac_leaf_direct != 0 && c->mac_leaf_direct != 1)
+    throw Error(PFMM_ERR_INVALID_ARG, "mac_leaf_direct must be 0 or 1");
+  if (c->mac_theta > 0.0 && c->m2l_order_slack >= 0)
+    throw Error(PFMM_ERR_INVALID_ARG, "mac_theta runs every M2L at order p: m2l_order_slack must be -1");
 }
 
 // ------------------------------------------------------------------------------------------------
 // Tree build.  Leaves h->tv / h->pa describing the sorted particles and the octree.
 // ------------------------------------------------------------------------------------------------
+void build_mac_lists(pfmm_handle* h, hipStream_t s);
+void build_tree_stats(pfmm_handle* h, hipStream_t s);
+void set_m2l_split(pfmm_handle* h);
+
 void build_tree(pfmm_handle* h, int n, const double* pos, const double* q, const double* alpha,
                 hipStream_t s) {
   const pfmm_config& c = h->cfg;
@@ -342,6 +366,9 @@ void build_tree(pfmm_handle* h, int n, const double* pos, const double* q, const
     extent = std::max(extent, hi[a] - lo[a]);
   }
   const double alpha_max = hb.bb[6];
+  // leaves whose pairs are always summed directly: within ws, or the adjacent ones of the
+  // acceptance-criterion walk
+  const int reach = h->mac ? 1 : c.ws;
   const double s_max = c.thole_a * std::cbrt(alpha_max);  // a (alpha_max^2)^(1/6)
   double w = c.leaf_width;
   if (w == 0.0) {
@@ -349,13 +376,14 @@ void build_tree(pfmm_handle* h, int n, const double* pos, const double* q, const
     for (int a = 0; a < 3; ++a) vol *= std::max(hi[a] - lo[a], 1.0);
     const double occ = c.ws == 1 ? 24.0 : 12.0;
     w = std::cbrt(occ * vol / std::max(n, 1));
-    w = std::max(w, 1.0001 * s_max / c.ws);
+    w = std::max(w, 1.0001 * s_max / reach);
     w = std::max(w, 1e-3);
   }
-  if (s_max > c.ws * w)
+  if (s_max > reach * w)
     throw Error(PFMM_ERR_INVALID_ARG,
-                "Thole damping radius " + std::to_string(s_max) + " exceeds the near-field range ws * leaf_width = " +
-                    std::to_string(c.ws * w) + "; increase leaf_width or ws");
+                "Thole damping radius " + std::to_string(s_max) + " exceeds the near-field range " +
+                    (h->mac ? std::string("leaf_width = ") : std::string("ws * leaf_width = ")) +
+                    std::to_string(reach * w) + "; increase leaf_width" + (h->mac ? "" : " or ws"));
   int L = 0;
   while (w * std::ldexp(1.0, L) < extent * (1.0 + std::ldexp(1.0, -20))) {
     ++L;
@@ -426,6 +454,31 @@ void build_tree(pfmm_handle* h, int n, const double* pos, const double* q, const
   Particles& pa = h->pa;
   pa.n = n; pa.P = P; pa.alpha = al; pa.sqa = sqa; pa.tau = tau; pa.itau = itau;
 
+  if (h->mac) {
+    build_mac_lists(h, s);
+  } else {
+    build_tree_stats(h, s);
+  }
+  if (h->mac) {
+    h->m2l_tiles = 0;
+    h->nsplit = 1;
+  } else {
+    set_m2l_split(h);
+  }
+  // expansions (one extra zero row serves empty M2L sources); F holds nsplit partial copies
+  const int64_t rows = (int64_t)ncell + 1;
+  h->split_stride = rows * h->op.stride;
+  double* M = dev<double>(h->w_M, rows * h->op.stride);
+  dev<double>(h->w_F, rows * h->op.stride * h->nsplit);
+  if (c.precision == PFMM_MIXED && !h->mac) dev<float>(h->w_M32, rows * h->op.stride);
+  launch_fill_double(M + (int64_t)ncell * h->op.stride, h->op.stride, 0.0, s);
+  h->n_evals = 0;
+}
+
+// Pair statistics of the well-separation lists: M2L pairs, near particle pairs, useful M2L flops
+// (also with every order capped at c).
+void build_tree_stats(pfmm_handle* h, hipStream_t s) {
+  const TreeView& t = h->tv;
   unsigned long long* stats = dev<unsigned long long>(h->w_stats, 14);
   PFMM_HIP(hipMemsetAsync(stats, 0, 14 * sizeof(unsigned long long), s));
   launch_tree_stats(t, h->op.m2l_code, h->op.dorder, h->op.noff, h->op.p, stats, s);
@@ -440,6 +493,12 @@ void build_tree(pfmm_handle* h, int n, const double* pos, const double* q, const
   h->n_p2p = (int64_t)st[1];
   h->m2l_flops = (int64_t)st[2];
   for (int c = 0; c <= 10; ++c) h->m2l_flops_cap[c] = c <= h->op.p ? (int64_t)st[3 + c] : 0;
+}
+
+void set_m2l_split(pfmm_handle* h) {
+  const pfmm_config& c = h->cfg;
+  const TreeView& t = h->tv;
+  const int L = t.L;
   // Split each parent tile's colleague offsets over nsplit workgroups (one per CU at a time).  The
   // launch takes ceil(tiles * nsplit / CUs) rounds of workgroups, each 1/nsplit of a tile's work,
   // plus a fixed cost per round (staging the index table, the first offset's loads), and L2L reads
@@ -462,14 +521,132 @@ void build_tree(pfmm_handle* h, int n, const double* pos, const double* q, const
       }
     }
   }
-  // expansions (one extra zero row serves empty M2L sources); F holds nsplit partial copies
-  const int64_t rows = (int64_t)ncell + 1;
-  h->split_stride = rows * h->op.stride;
-  double* M = dev<double>(h->w_M, rows * h->op.stride);
-  dev<double>(h->w_F, rows * h->op.stride * h->nsplit);
-  if (c.precision == PFMM_MIXED) dev<float>(h->w_M32, rows * h->op.stride);
-  launch_fill_double(M + (int64_t)ncell * h->op.stride, h->op.stride, 0.0, s);
-  h->n_evals = 0;
+}
+
+// The lists of the acceptance-criterion walk (mac.hip) for the tree in h->tv: each cell's M2L row
+// (h->mv), each leaf's near row (h->tv.nptr / nidx) and the pair statistics.  One synchronisation
+// per level reads the sizes of the next frontier and of the accepted pairs.
+void build_mac_lists(pfmm_handle* h, hipStream_t s) {
+  TreeView& t = h->tv;
+  const int L = t.L, ncell = t.ncell;
+  double* renc = dev<double>(h->m_renc, ncell);
+  for (int l = 0; l <= L; ++l) launch_mac_radii(t, h->pa.P, l, renc, s);
+  int* bad = dev<int>(h->m_bad, 1);
+  launch_fill_int(bad, 1, 0, s);
+  int cur = 0;
+  int2* fr = dev<int2>(h->m_fr[cur], 1);
+  launch_fill_int(reinterpret_cast<int*>(fr), 2, 0, s);  // (root, root)
+  int64_t nfr = 1;
+  std::vector<int> macc(L + 1, 0);
+  int nnear = 0;
+  int* near_t = nullptr;
+  int* near_s = nullptr;
+  for (int l = 0; l <= L; ++l) {
+    // the child pairs of a split pair are at most 64; the prefix sums are 32-bit
+    if (l < L && nfr * 64 > INT_MAX)
+      throw Error(PFMM_ERR_INVALID_ARG, "acceptance-criterion lists too large (" + std::to_string(nfr) +
+                                            " cell pairs at level " + std::to_string(l) +
+                                            "); raise leaf_width or mac_theta");
+    const int nf = (int)nfr;
+    int* acc = dev<int>(h->m_acc, nf);
+    int* kid = dev<int>(h->m_kid, nf);
+    int* accs = dev<int>(h->m_accs, nf);
+    int* kids = dev<int>(h->m_kids, nf);
+    launch_mac_classify(t, renc, h->cfg.mac_theta, h->cfg.mac_ndirect, h->cfg.mac_leaf_direct != 0, l, fr, nf, acc,
+                        kid, s);
+    const size_t tb = scan_temp_bytes(nf);
+    void* tmp = raw(h->m_stmp, tb);
+    launch_inclusive_scan(tmp, tb, acc, accs, nf, s);
+    launch_inclusive_scan(tmp, tb, kid, kids, nf, s);
+    int tot[2];
+    void* pin = h->pinned.get(sizeof(tot));
+    PFMM_HIP(hipMemcpyAsync(pin, accs + (nf - 1), sizeof(int), hipMemcpyDeviceToHost, s));
+    PFMM_HIP(hipMemcpyAsync((char*)pin + sizeof(int), kids + (nf - 1), sizeof(int), hipMemcpyDeviceToHost, s));
+    PFMM_HIP(hipStreamSynchronize(s));
+    std::memcpy(tot, pin, sizeof(tot));
+    macc[l] = tot[0];
+    int* mt = tot[0] > 0 ? dev<int>(h->m_lt[l], tot[0]) : nullptr;
+    unsigned long long* mvv = tot[0] > 0 ? dev<unsigned long long>(h->m_lv[l], tot[0]) : nullptr;
+    int2* next = nullptr;
+    if (l == L) {
+      nnear = tot[1];
+      near_t = dev<int>(h->m_nt, nnear);
+      near_s = dev<int>(h->m_ns, nnear);
+    } else {
+      next = dev<int2>(h->m_fr[cur ^ 1], tot[1]);
+    }
+    launch_mac_emit(t, h->mac_R, l, fr, nf, accs, kids, mt, mvv, next, near_t, near_s, bad, s);
+    if (l < L) {
+      fr = next;
+      nfr = tot[1];
+      cur ^= 1;
+    }
+  }
+  int badh = 0;
+  sync_read(h, bad, &badh, sizeof(int), s);
+  if (badh) throw Error(PFMM_ERR_INVALID_ARG, "internal: an accepted cell offset exceeds the operator table");
+
+  int bits = 1;
+  while ((1LL << bits) <= (int64_t)ncell) ++bits;
+  // M2L rows of the cells of levels >= 2 (levels 0 and 1 never accept: their cells are adjacent)
+  int64_t nm = 0;
+  for (int l = 0; l <= L; ++l) nm += macc[l];
+  if (nm > INT_MAX) throw Error(PFMM_ERR_INVALID_ARG, "acceptance-criterion lists too large; raise leaf_width");
+  const int rows = L >= 2 ? ncell - t.off[2] : 0;
+  const int nleaf = t.off[L + 1] - t.off[L];
+  // one sort workspace, count array and scan workspace serve both sorts
+  const size_t sortb = std::max(nm > 0 ? mac_sort_temp_bytes((int)nm, bits, true) : 0,
+                                mac_sort_temp_bytes(nnear, bits, false));
+  void* sort_tmp = raw(h->m_sort_tmp, sortb);
+  int* cnt = dev<int>(h->m_cnt, std::max(rows, nleaf));
+  const size_t scanb = scan_temp_bytes(std::max(rows, nleaf));
+  void* scan_tmp = raw(h->m_stmp, scanb);
+  int* mptr = dev<int>(h->m_mptr, (int64_t)rows + 1);
+  launch_fill_int(mptr, (int64_t)rows + 1, 0, s);
+  unsigned long long* mval = nullptr;
+  if (nm > 0) {
+    int* kin = dev<int>(h->m_kin, nm);
+    unsigned long long* vin = dev<unsigned long long>(h->m_vin, nm);
+    int64_t o = 0;
+    for (int l = 0; l <= L; ++l) {
+      if (!macc[l]) continue;
+      PFMM_HIP(hipMemcpyAsync(kin + o, h->m_lt[l].ptr, (size_t)macc[l] * sizeof(int), hipMemcpyDeviceToDevice, s));
+      PFMM_HIP(hipMemcpyAsync(vin + o, h->m_lv[l].ptr, (size_t)macc[l] * sizeof(unsigned long long),
+                              hipMemcpyDeviceToDevice, s));
+      o += macc[l];
+    }
+    int* kout = dev<int>(h->m_kout, nm);
+    mval = dev<unsigned long long>(h->m_vout, nm);
+    launch_mac_sort(sort_tmp, sortb, kin, kout, vin, mval, (int)nm, bits, true, s);
+    launch_fill_int(cnt, rows, 0, s);
+    launch_mac_count(kout, (int)nm, t.off[2], cnt, s);
+    launch_inclusive_scan(scan_tmp, scanb, cnt, mptr + 1, rows, s);
+  }
+  h->mv.mptr = mptr;
+  h->mv.mval = mval;
+
+  // near rows of the leaves
+  int* nkey = dev<int>(h->m_nkout, nnear);
+  int* nsrc = dev<int>(h->m_nvout, nnear);
+  launch_mac_sort(sort_tmp, sortb, near_t, nkey, near_s, nsrc, nnear, bits, false, s);
+  int* nptr = dev<int>(h->m_nptr, (int64_t)nleaf + 1);
+  launch_fill_int(nptr, (int64_t)nleaf + 1, 0, s);
+  launch_fill_int(cnt, nleaf, 0, s);
+  launch_mac_count(nkey, nnear, t.off[L], cnt, s);
+  launch_inclusive_scan(scan_tmp, scanb, cnt, nptr + 1, nleaf, s);
+  t.nptr = nptr;
+  t.nidx = nsrc;
+
+  unsigned long long* pairs = dev<unsigned long long>(h->w_stats, 1);
+  launch_fill_int(reinterpret_cast<int*>(pairs), 2, 0, s);
+  launch_mac_near_pairs(t, nkey, nsrc, nnear, pairs, s);
+  unsigned long long np = 0;
+  sync_read(h, pairs, &np, sizeof(np), s);
+  h->n_m2l = nm;
+  h->n_p2p = (int64_t)np;
+  auto flops = [](int q) { return 2 * (int64_t)mi_count(q) * (q + 4) * (q + 5) * (q + 6) / 120; };
+  h->m2l_flops = nm * flops(h->op.p);
+  for (int c = 0; c <= 10; ++c) h->m2l_flops_cap[c] = c <= h->op.p ? nm * flops(c) : 0;
 }
 
 // One FMM evaluation: sources 1 = charges, 2 = dipoles (mu4), 3 = both.
@@ -495,12 +672,16 @@ void fmm_pass(pfmm_handle* h, int sources, int mode, FieldOut out, int* err, con
     for (int lp = t.L - 1; lp >= 2; --lp) launch_m2m(t, op, lp, M, done, s);
     kt.end(KC_M2M, e);
     e = kt.begin();
-    float* M32 = nullptr;
-    if (fp32) {
-      M32 = h->w_M32.as<float>();
-      launch_to_float(M, M32, ((int64_t)t.ncell + 1) * op.stride, done, s);
+    if (h->mac) {
+      launch_m2l_list(t, op, h->mv, M, F, done, qcap, s);
+    } else {
+      float* M32 = nullptr;
+      if (fp32) {
+        M32 = h->w_M32.as<float>();
+        launch_to_float(M, M32, ((int64_t)t.ncell + 1) * op.stride, done, s);
+      }
+      launch_m2l(t, op, h->nsplit, M, M32, F, h->split_stride, fp32, 3, done, qcap, s);
     }
-    launch_m2l(t, op, h->nsplit, M, M32, F, h->split_stride, fp32, 3, done, qcap, s);
     kt.end(KC_M2L, e);
     e = kt.begin();
     for (int lc = 2; lc <= t.L; ++lc) launch_l2l(t, op, lc, F, h->nsplit, h->split_stride, done, s);
@@ -994,6 +1175,9 @@ void pfmm_config_default(pfmm_config* c) {
   c->scf_relax = 0.0;
   c->dipole_pair_dl = 0.0;
   c->dipole_tree = 0;
+  c->mac_theta = 0.0;
+  c->mac_ndirect = 64;
+  c->mac_leaf_direct = 1;
 }
 
 pfmm_status pfmm_create(const pfmm_config* cfg, pfmm_handle** out) {
@@ -1031,6 +1215,16 @@ pfmm_status pfmm_create(const pfmm_config* cfg, pfmm_handle** out) {
     op.hidx = h->t_hidx.as<unsigned short>();
     op.dorder = h->t_dorder.as<unsigned char>();
     op.nblocks = T.nblocks;
+    if (cfg->mac_theta > 0.0) {
+      // offsets of accepted pairs: the parents of a pair at level l + 1 were not accepted, so their
+      // offset D has |D| <= (r_A + r_B) / (theta w_l) <= sqrt(3) / theta (or they were adjacent), and
+      // the child offset 2 D + (o_B - o_A) has components of at most 2 sqrt(3) / theta + 1
+      h->mac = true;
+      h->mac_R = std::max(3, (int)std::floor(2.0 * std::sqrt(3.0) / cfg->mac_theta + 1.0) + 1);
+      upload(h->t_mdvec, mac_operator_rows(T, h->mac_R));
+      h->mv.R = h->mac_R;
+      h->mv.dvec = h->t_mdvec.as<double>();
+    }
     PFMM_HIP(hipGetDevice(&h->device));
     // host staging for the small read-backs, so that later calls need not allocate it
     h->pinned.get(4096);

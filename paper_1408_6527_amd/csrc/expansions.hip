@@ -126,10 +126,6 @@ __global__ __launch_bounds__(P2M_TPB) void k_p2m(TreeView t, OpTables op, Partic
 constexpr int SH_TPB = 256;
 constexpr int MAX_STRIDE = 288;  // row stride of an expansion at p = 10
 
-__host__ __device__ constexpr int mi_index(int nx, int ny, int nz) {
-  // position of n = (nx, ny, nz) in the degree-major order (descending nx, then descending ny)
-  return mi_count(nx + ny + nz - 1) + (ny + nz) * (ny + nz + 1) / 2 + nz;
-}
 
 // (h/4)^e / e! and (-h/4)^e / e! for e = 0..p: per-axis factors of the shift coefficients x^k / k!
 // for a child centre offset of a quarter of the parent edge, times 2^e when h = 2

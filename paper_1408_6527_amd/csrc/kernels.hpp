@@ -29,6 +29,10 @@ struct TreeView {
   const int* parent = nullptr;     // global index of the parent, -1 at the root
   const int* child8 = nullptr;     // 8 global child indices per cell (octant order), -1 if empty
   const int* coll = nullptr;       // nnear colleagues per cell (offset order), -1 if empty
+  // near field from the acceptance-criterion walk (mac.hip) instead of the colleagues: for leaf
+  // g - off[L], the source leaves nidx[nptr[g - off[L]] .. nptr[g - off[L] + 1]); null otherwise
+  const int* nptr = nullptr;
+  const int* nidx = nullptr;
 };
 
 // Particle arrays in sorted (Morton) order.
@@ -140,6 +144,44 @@ void launch_exclusions(const Particles& pa, const int* perm, const int* inv, con
                        const double4* mu4, int mode, int sources, FieldOut out, double* dal, const int* done,
                        hipStream_t s);
 void launch_inverse_perm(const int* perm, int n, int* inv, hipStream_t s);
+
+// ---------------------------------------------------------------- mac.hip
+// M2L lists of the acceptance-criterion walk: for target cell g of levels >= 2, entries
+// mptr[g - off[2]] .. mptr[g - off[2] + 1] of mval, each (source cell << 32) | offset slot, the slot
+// of d = B - A being ((dx + R) (2R + 1) + dy + R) (2R + 1) + dz + R; dvec holds D_k(d) at unit cell
+// width for every slot, nc values per row.
+struct MacView {
+  int R = 0;
+  const double* dvec = nullptr;
+  const int* mptr = nullptr;
+  const unsigned long long* mval = nullptr;
+};
+// enclosing radius of every cell of a level: the largest distance from its centre to its particles
+void launch_mac_radii(const TreeView& t, const double4* P, int level, double* renc, hipStream_t s);
+// one level of the walk over the frontier pairs fr (target, source) of level l:
+// classify: acc[i] = 1 if the pair is accepted for M2L (never below ndirect particles together,
+// nor at the leaf level with leaf_direct); kid[i] = its child pairs (l < L) or 1 if it
+// goes to the near list (l = L), 0 otherwise;
+// emit (from the inclusive prefix sums of acc and kid): accepted pairs to m_tgt / m_val, child pairs
+// to next (l < L) or near pairs to near_tgt / near_src (l = L); *bad |= 1 for an accepted offset
+// outside the operator table
+void launch_mac_classify(const TreeView& t, const double* renc, double theta, int ndirect, bool leaf_direct,
+                         int level, const int2* fr, int nfr, int* acc, int* kid, hipStream_t s);
+void launch_mac_emit(const TreeView& t, int R, int level, const int2* fr, int nfr, const int* acc_scan,
+                     const int* kid_scan, int* m_tgt, unsigned long long* m_val, int2* next, int* near_tgt,
+                     int* near_src, int* bad, hipStream_t s);
+// stable sort of (key, value) by key over the low end_bit bits
+size_t mac_sort_temp_bytes(int n, int end_bit, bool wide);
+void launch_mac_sort(void* tmp, size_t tmp_bytes, const int* kin, int* kout, const void* vin, void* vout, int n,
+                     int end_bit, bool wide, hipStream_t s);
+// counts per key (keys - key0 in [0, nkey)), added to cnt; then ptr = exclusive prefix (ptr[0] = 0)
+void launch_mac_count(const int* keys, int n, int key0, int* cnt, hipStream_t s);
+// ordered near-field particle pairs of the near list (i != j), added to *pairs
+void launch_mac_near_pairs(const TreeView& t, const int* near_tgt, const int* near_src, int n,
+                           unsigned long long* pairs, hipStream_t s);
+// F~ of every cell of levels >= 2 from its M2L row, in float64, at order min(p, *qcap)
+void launch_m2l_list(const TreeView& t, const OpTables& op, const MacView& mv, const double* M, double* F,
+                     const int* done, const int* qcap, hipStream_t s);
 
 // ---------------------------------------------------------------- solver.hip
 struct CGState {

@@ -1,8 +1,9 @@
 // Near field by direct summation over neighbouring leaves (the direct component of Sec. III),
 // with true point dipoles and Thole damping of dipole-dipole pairs.
 //
-// One wavefront per target leaf.  The sources of all colleague leaves (Chebyshev distance <= ws)
-// are walked as one concatenated sequence and staged in LDS 64 at a time, densely, whatever the
+// One wavefront per target leaf.  The sources of all colleague leaves (Chebyshev distance <= ws),
+// or of the leaf's row of the near list of the acceptance-criterion walk (mac.hip, LIST), are walked
+// as one concatenated sequence and staged in LDS 64 at a time, densely, whatever the
 // leaf occupancy.  A leaf holds only a few particles at protein density, so each of its T targets
 // is served by G = floor(64 / T) lanes (lanes t, t + T, t + 2T, ...); every lane sweeps a 1/G slice
 // of each staged chunk, and the G partial sums of a target are combined at the end through LDS in
@@ -31,12 +32,12 @@ namespace pfmm {
 namespace {
 
 constexpr int TPB = 64;
-constexpr int MAXNN = 125;  // colleagues per leaf at ws = 2
+constexpr int CHUNK = 2 * TPB;  // source leaves per prefix pass (the 125 colleagues at ws = 2 in one)
 
 __device__ inline double rsqrt_t(double x) { return rsqrt(x); }
 __device__ inline float rsqrt_t(float x) { return rsqrtf(x); }
 
-template <typename T, int MODE, int SRC>
+template <typename T, int MODE, int SRC, bool LIST>
 __global__ __launch_bounds__(TPB) void k_p2p(TreeView t, Particles pa, const double4* __restrict__ mu4,
                                              FieldOut out, double* __restrict__ dal,
                                              int* __restrict__ err, const int* done, T rc2) {
@@ -44,16 +45,27 @@ __global__ __launch_bounds__(TPB) void k_p2p(TreeView t, Particles pa, const dou
   constexpr bool HQ = (SRC & 1) != 0;
   constexpr bool HM = (SRC & 2) != 0;
   constexpr bool STAGE_MU = HM || MODE == 2;
-  __shared__ int s_pref[MAXNN + 1], s_first[MAXNN];
+  static_assert(!LIST || MODE != 3, "the preconditioner takes the colleagues");
+  __shared__ int s_pref[CHUNK + 1], s_first[CHUNK];
   __shared__ T sx[TPB], sy[TPB], sz[TPB], sq[TPB], smx[TPB], smy[TPB], smz[TPB], sit[TPB];
   __shared__ int sidx[TPB];
   const int g = t.off[t.L] + blockIdx.x;
   const int first = t.first[g], cnt = t.count[g];
   const int lane = threadIdx.x;
-  const int nn = t.nnear;
+  // the source leaves: the colleague row (nnear <= 125 entries in offset order, -1 where empty), or
+  // the leaf's row of the near list, taken in chunks of CHUNK
+  const int* ent = t.coll + (int64_t)g * t.nnear;
+  int ne = t.nnear;
+  if constexpr (LIST) {
+    const int lg = g - t.off[t.L];
+    ent = t.nidx + t.nptr[lg];
+    ne = t.nptr[lg + 1] - t.nptr[lg];
+  }
 
-  // exclusive prefix of the colleague occupancies (up to 125 entries, two per lane)
-  {
+  // exclusive prefix of the occupancies of the source leaves E0 .. E0 + nn - 1 (two per lane) into
+  // s_pref[0 .. nn], their first particles into s_first; returns nn
+  auto prefix = [&](int E0) {
+    const int nn = min(CHUNK, ne - E0);
     int c0 = 0, c1 = 0, f0 = 0, f1 = 0;
     // mode 3 walks only the adjacent leaves (colleague offsets with every component in [-1, 1])
     const int side = 2 * t.ws + 1;
@@ -61,12 +73,12 @@ __global__ __launch_bounds__(TPB) void k_p2p(TreeView t, Particles pa, const dou
       return MODE != 3 || (abs(ci / (side * side) - t.ws) <= 1 && abs((ci / side) % side - t.ws) <= 1 &&
                            abs(ci % side - t.ws) <= 1);
     };
-    if (lane < nn && adjacent(lane)) {
-      const int A = t.coll[(int64_t)g * nn + lane];
+    if (lane < nn && adjacent(E0 + lane)) {
+      const int A = ent[E0 + lane];
       if (A >= 0) { c0 = t.count[A]; f0 = t.first[A]; }
     }
-    if (lane + TPB < nn && adjacent(lane + TPB)) {
-      const int A = t.coll[(int64_t)g * nn + lane + TPB];
+    if (lane + TPB < nn && adjacent(E0 + lane + TPB)) {
+      const int A = ent[E0 + lane + TPB];
       if (A >= 0) { c1 = t.count[A]; f1 = t.first[A]; }
     }
     int i0 = c0, i1 = c1;
@@ -79,9 +91,13 @@ __global__ __launch_bounds__(TPB) void k_p2p(TreeView t, Particles pa, const dou
     if (lane + TPB < nn) { s_pref[lane + TPB] = tot0 + i1 - c1; s_first[lane + TPB] = f1; }
     const int tot = tot0 + __shfl(i1, TPB - 1);
     if (lane == 0) s_pref[nn] = tot;
+    return nn;
+  };
+  int nn = 0;
+  if constexpr (!LIST) {
+    nn = prefix(0);
+    __syncthreads();
   }
-  __syncthreads();
-  const int total = s_pref[nn];
 
   double cen[3];
   {
@@ -108,93 +124,101 @@ __global__ __launch_bounds__(TPB) void k_p2p(TreeView t, Particles pa, const dou
     T gxx = 0, gyy = 0, gzz = 0, gxy = 0, gxz = 0, gyz = 0;
     double dsum = 0.0;
     int bad = 0;
-    for (int S0 = 0; S0 < total; S0 += TPB) {
-      const int m = min(TPB, total - S0);
-      __syncthreads();
-      if (lane < m) {
-        const int idx = S0 + lane;
-        int lo = 0, hi = nn - 1;  // last colleague k with s_pref[k] <= idx
-        while (lo < hi) {
-          const int mid = (lo + hi + 1) >> 1;
-          if (s_pref[mid] <= idx) lo = mid; else hi = mid - 1;
-        }
-        const int j = s_first[lo] + idx - s_pref[lo];
-        const double4 Pj = pa.P[j];
-        sx[lane] = (T)(Pj.x - cen[0]);
-        sy[lane] = (T)(Pj.y - cen[1]);
-        sz[lane] = (T)(Pj.z - cen[2]);
-        sq[lane] = (T)Pj.w;
-        if (STAGE_MU) {
-          const double4 u = mu4[j];
-          smx[lane] = (T)u.x; smy[lane] = (T)u.y; smz[lane] = (T)u.z;
-        }
-        sit[lane] = (T)pa.itau[j];
-        sidx[lane] = j;
+    for (int E0 = 0; LIST ? E0 < ne : E0 == 0; E0 += CHUNK) {
+      if constexpr (LIST) {
+        __syncthreads();  // the previous chunk's prefix is no longer read
+        nn = prefix(E0);
+        __syncthreads();
       }
-      __syncthreads();
-      if (!active) continue;
-#pragma unroll 4
-      for (int jj = slice; jj < m; jj += G) {
-        const T rx = xi - sx[jj], ry = yi - sy[jj], rz = zi - sz[jj];
-        const T r2 = rx * rx + ry * ry + rz * rz;
-        const bool valid = r2 > T(0) && (MODE != 3 || r2 < rc2);
-        if (MODE == 1 && !valid && sidx[jj] != i) bad = 1;
-        const T rinv = valid ? rsqrt_t(valid ? r2 : T(1)) : T(0);
-        const T rinv2 = rinv * rinv;
-        const T rinv3 = rinv * rinv2;
-        if (MODE == 1 && HQ) {
-          const T qj = sq[jj];
-          const T qr3 = qj * rinv3;
-          phi += qj * rinv;
-          const T ex = qr3 * rx, ey = qr3 * ry, ez = qr3 * rz;
-          eux += ex; euy += ey; euz += ez;
-          edx += ex; edy += ey; edz += ez;
-          const T c5 = T(3) * qr3 * rinv2;
-          gxx += qr3 - c5 * rx * rx; gyy += qr3 - c5 * ry * ry; gzz += qr3 - c5 * rz * rz;
-          gxy -= c5 * rx * ry; gxz -= c5 * rx * rz; gyz -= c5 * ry * rz;
-        }
-        if (MODE == 2) {
-          // Thole term of dU/dalpha_i: (2 v^4 (mu_i.u)(mu_j.u) - 2 (v^3 - v^4) mu_i.mu_j) / (alpha_i r^3)
-          const T ii = iti * sit[jj];
-          const T rr = r2 * rinv;
-          const T v = ii > T(0) ? fmin(rr * ii, T(1)) : T(1);
-          if (valid && v < T(1)) {
-            const T v3 = v * v * v, v4 = v3 * v;
-            const T miu = (T(mui.x) * rx + T(mui.y) * ry + T(mui.z) * rz) * rinv;
-            const T mju = (smx[jj] * rx + smy[jj] * ry + smz[jj] * rz) * rinv;
-            const T mm = T(mui.x) * smx[jj] + T(mui.y) * smy[jj] + T(mui.z) * smz[jj];
-            dsum += (double)((T(2) * v4 * miu * mju - T(2) * (v3 - v4) * mm) * rinv3);
+      const int total = s_pref[nn];
+      for (int S0 = 0; S0 < total; S0 += TPB) {
+        const int m = min(TPB, total - S0);
+        __syncthreads();
+        if (lane < m) {
+          const int idx = S0 + lane;
+          int lo = 0, hi = nn - 1;  // last colleague k with s_pref[k] <= idx
+          while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_pref[mid] <= idx) lo = mid; else hi = mid - 1;
           }
+          const int j = s_first[lo] + idx - s_pref[lo];
+          const double4 Pj = pa.P[j];
+          sx[lane] = (T)(Pj.x - cen[0]);
+          sy[lane] = (T)(Pj.y - cen[1]);
+          sz[lane] = (T)(Pj.z - cen[2]);
+          sq[lane] = (T)Pj.w;
+          if (STAGE_MU) {
+            const double4 u = mu4[j];
+            smx[lane] = (T)u.x; smy[lane] = (T)u.y; smz[lane] = (T)u.z;
+          }
+          sit[lane] = (T)pa.itau[j];
+          sidx[lane] = j;
         }
-        if ((MODE == 0 || MODE == 1 || MODE == 3) && HM) {
-          const T mx = smx[jj], my = smy[jj], mz = smz[jj];
-          const T rmu = rx * mx + ry * my + rz * mz;
-          const T ii = iti * sit[jj];
-          const T rr = r2 * rinv;
-          const T v = ii > T(0) ? fmin(rr * ii, T(1)) : T(1);
-          const T v3 = v * v * v, v4 = v3 * v;
-          const T ft = v4, fe = v3 * (T(4) - T(3) * v);
-          const T c3 = T(3) * ft * rmu * rinv2;
-          edx += (c3 * rx - fe * mx) * rinv3;
-          edy += (c3 * ry - fe * my) * rinv3;
-          edz += (c3 * rz - fe * mz) * rinv3;
-          if (MODE == 1) {
-            phi += rmu * rinv3;
-            const T cu = T(3) * rmu * rinv2;
-            eux += (cu * rx - mx) * rinv3;
-            euy += (cu * ry - my) * rinv3;
-            euz += (cu * rz - mz) * rinv3;
-            const T Ac = (v < T(1)) ? T(-3) * v4 : T(-15);
-            const T Bc = T(3) * v4;
-            const T rinv5 = rinv3 * rinv2;
-            const T a7 = Ac * rmu * rinv5 * rinv2;  // A (u.mu) u_a u_b / r^4 = A rmu r_a r_b / r^7
-            const T b5 = Bc * rinv5;
-            gxx += a7 * rx * rx + b5 * (rmu + T(2) * rx * mx);
-            gyy += a7 * ry * ry + b5 * (rmu + T(2) * ry * my);
-            gzz += a7 * rz * rz + b5 * (rmu + T(2) * rz * mz);
-            gxy += a7 * rx * ry + b5 * (rx * my + ry * mx);
-            gxz += a7 * rx * rz + b5 * (rx * mz + rz * mx);
-            gyz += a7 * ry * rz + b5 * (ry * mz + rz * my);
+        __syncthreads();
+        if (!active) continue;
+  #pragma unroll 4
+        for (int jj = slice; jj < m; jj += G) {
+          const T rx = xi - sx[jj], ry = yi - sy[jj], rz = zi - sz[jj];
+          const T r2 = rx * rx + ry * ry + rz * rz;
+          const bool valid = r2 > T(0) && (MODE != 3 || r2 < rc2);
+          if (MODE == 1 && !valid && sidx[jj] != i) bad = 1;
+          const T rinv = valid ? rsqrt_t(valid ? r2 : T(1)) : T(0);
+          const T rinv2 = rinv * rinv;
+          const T rinv3 = rinv * rinv2;
+          if (MODE == 1 && HQ) {
+            const T qj = sq[jj];
+            const T qr3 = qj * rinv3;
+            phi += qj * rinv;
+            const T ex = qr3 * rx, ey = qr3 * ry, ez = qr3 * rz;
+            eux += ex; euy += ey; euz += ez;
+            edx += ex; edy += ey; edz += ez;
+            const T c5 = T(3) * qr3 * rinv2;
+            gxx += qr3 - c5 * rx * rx; gyy += qr3 - c5 * ry * ry; gzz += qr3 - c5 * rz * rz;
+            gxy -= c5 * rx * ry; gxz -= c5 * rx * rz; gyz -= c5 * ry * rz;
+          }
+          if (MODE == 2) {
+            // Thole term of dU/dalpha_i: (2 v^4 (mu_i.u)(mu_j.u) - 2 (v^3 - v^4) mu_i.mu_j) / (alpha_i r^3)
+            const T ii = iti * sit[jj];
+            const T rr = r2 * rinv;
+            const T v = ii > T(0) ? fmin(rr * ii, T(1)) : T(1);
+            if (valid && v < T(1)) {
+              const T v3 = v * v * v, v4 = v3 * v;
+              const T miu = (T(mui.x) * rx + T(mui.y) * ry + T(mui.z) * rz) * rinv;
+              const T mju = (smx[jj] * rx + smy[jj] * ry + smz[jj] * rz) * rinv;
+              const T mm = T(mui.x) * smx[jj] + T(mui.y) * smy[jj] + T(mui.z) * smz[jj];
+              dsum += (double)((T(2) * v4 * miu * mju - T(2) * (v3 - v4) * mm) * rinv3);
+            }
+          }
+          if ((MODE == 0 || MODE == 1 || MODE == 3) && HM) {
+            const T mx = smx[jj], my = smy[jj], mz = smz[jj];
+            const T rmu = rx * mx + ry * my + rz * mz;
+            const T ii = iti * sit[jj];
+            const T rr = r2 * rinv;
+            const T v = ii > T(0) ? fmin(rr * ii, T(1)) : T(1);
+            const T v3 = v * v * v, v4 = v3 * v;
+            const T ft = v4, fe = v3 * (T(4) - T(3) * v);
+            const T c3 = T(3) * ft * rmu * rinv2;
+            edx += (c3 * rx - fe * mx) * rinv3;
+            edy += (c3 * ry - fe * my) * rinv3;
+            edz += (c3 * rz - fe * mz) * rinv3;
+            if (MODE == 1) {
+              phi += rmu * rinv3;
+              const T cu = T(3) * rmu * rinv2;
+              eux += (cu * rx - mx) * rinv3;
+              euy += (cu * ry - my) * rinv3;
+              euz += (cu * rz - mz) * rinv3;
+              const T Ac = (v < T(1)) ? T(-3) * v4 : T(-15);
+              const T Bc = T(3) * v4;
+              const T rinv5 = rinv3 * rinv2;
+              const T a7 = Ac * rmu * rinv5 * rinv2;  // A (u.mu) u_a u_b / r^4 = A rmu r_a r_b / r^7
+              const T b5 = Bc * rinv5;
+              gxx += a7 * rx * rx + b5 * (rmu + T(2) * rx * mx);
+              gyy += a7 * ry * ry + b5 * (rmu + T(2) * ry * my);
+              gzz += a7 * rz * rz + b5 * (rmu + T(2) * rz * mz);
+              gxy += a7 * rx * ry + b5 * (rx * my + ry * mx);
+              gxz += a7 * rx * rz + b5 * (rx * mz + rz * mx);
+              gyz += a7 * ry * rz + b5 * (ry * mz + rz * my);
+            }
           }
         }
       }
@@ -254,24 +278,26 @@ __global__ __launch_bounds__(TPB) void k_p2p(TreeView t, Particles pa, const dou
   }
 }
 
-template <typename T>
+template <typename T, bool LIST>
 void p2p_dispatch(const TreeView& t, const Particles& pa, const double4* mu4, int mode, int sources,
                   FieldOut out, double* dal, int* err, const int* done, hipStream_t s, int nleaf,
                   double rc2) {
   const T r2 = (T)rc2;
   if (mode == 0)
-    hipLaunchKernelGGL((k_p2p<T, 0, 2>), dim3(nleaf), dim3(TPB), 0, s, t, pa, mu4, out, dal, err, done, r2);
+    hipLaunchKernelGGL((k_p2p<T, 0, 2, LIST>), dim3(nleaf), dim3(TPB), 0, s, t, pa, mu4, out, dal, err, done, r2);
   else if (mode == 1 && sources == 1)
-    hipLaunchKernelGGL((k_p2p<T, 1, 1>), dim3(nleaf), dim3(TPB), 0, s, t, pa, mu4, out, dal, err, done, r2);
+    hipLaunchKernelGGL((k_p2p<T, 1, 1, LIST>), dim3(nleaf), dim3(TPB), 0, s, t, pa, mu4, out, dal, err, done, r2);
   else if (mode == 1 && sources == 2)
-    hipLaunchKernelGGL((k_p2p<T, 1, 2>), dim3(nleaf), dim3(TPB), 0, s, t, pa, mu4, out, dal, err, done, r2);
+    hipLaunchKernelGGL((k_p2p<T, 1, 2, LIST>), dim3(nleaf), dim3(TPB), 0, s, t, pa, mu4, out, dal, err, done, r2);
   else if (mode == 1 && sources == 3)
-    hipLaunchKernelGGL((k_p2p<T, 1, 3>), dim3(nleaf), dim3(TPB), 0, s, t, pa, mu4, out, dal, err, done, r2);
-  else if (mode == 3)
-    hipLaunchKernelGGL((k_p2p<T, 3, 2>), dim3(nleaf), dim3(TPB), 0, s, t, pa, mu4, out, dal, err, done, r2);
+    hipLaunchKernelGGL((k_p2p<T, 1, 3, LIST>), dim3(nleaf), dim3(TPB), 0, s, t, pa, mu4, out, dal, err, done, r2);
+  else if (mode == 2)
+    hipLaunchKernelGGL((k_p2p<double, 2, 2, LIST>), dim3(nleaf), dim3(TPB), 0, s, t, pa, mu4, out, dal, err, done,
+                       0.0);
   else
     throw Error(PFMM_ERR_INVALID_ARG, "internal: bad P2P mode");
 }
+
 
 // Excluded pairs (the starred sums of Sec. II.A): one thread per sorted target i takes the exact
 // terms of each of its excluded partners off what the evaluation summed (the same pair kernels as
@@ -384,13 +410,25 @@ void launch_p2p(const TreeView& t, const Particles& pa, const double4* mu4, int 
                 double rc) {
   const int nleaf = t.off[t.L + 1] - t.off[t.L];
   if (nleaf <= 0) return;
-  if (mode == 2)
-    hipLaunchKernelGGL((k_p2p<double, 2, 2>), dim3(nleaf), dim3(TPB), 0, s, t, pa, mu4, out, dal, err,
-                       done, 0.0);
-  else if (fp32)
-    p2p_dispatch<float>(t, pa, mu4, mode, sources, out, dal, err, done, s, nleaf, rc * rc);
-  else
-    p2p_dispatch<double>(t, pa, mu4, mode, sources, out, dal, err, done, s, nleaf, rc * rc);
+  // mode 3 (the preconditioner) takes the colleagues; mode 2 is float64 on both paths
+  if (mode == 3) {
+    if (fp32)
+      hipLaunchKernelGGL((k_p2p<float, 3, 2, false>), dim3(nleaf), dim3(TPB), 0, s, t, pa, mu4, out, dal, err, done,
+                         (float)(rc * rc));
+    else
+      hipLaunchKernelGGL((k_p2p<double, 3, 2, false>), dim3(nleaf), dim3(TPB), 0, s, t, pa, mu4, out, dal, err, done,
+                         rc * rc);
+  } else if (t.nptr) {
+    if (fp32 && mode != 2)
+      p2p_dispatch<float, true>(t, pa, mu4, mode, sources, out, dal, err, done, s, nleaf, rc * rc);
+    else
+      p2p_dispatch<double, true>(t, pa, mu4, mode, sources, out, dal, err, done, s, nleaf, rc * rc);
+  } else {
+    if (fp32 && mode != 2)
+      p2p_dispatch<float, false>(t, pa, mu4, mode, sources, out, dal, err, done, s, nleaf, rc * rc);
+    else
+      p2p_dispatch<double, false>(t, pa, mu4, mode, sources, out, dal, err, done, s, nleaf, rc * rc);
+  }
   PFMM_LAUNCH_CHECK();
 }
 

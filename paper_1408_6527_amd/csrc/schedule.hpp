@@ -20,6 +20,10 @@ namespace pfmm {
 
 // number of multi-indices of degree <= d in 3D: C(d + 3, 3)
 __host__ __device__ constexpr int mi_count(int d) { return d < 0 ? 0 : (d + 1) * (d + 2) * (d + 3) / 6; }
+// position of n = (nx, ny, nz) in the degree-major order (descending nx, then descending ny)
+__host__ __device__ constexpr int mi_index(int nx, int ny, int nz) {
+  return mi_count(nx + ny + nz - 1) + (ny + nz) * (ny + nz + 1) / 2 + nz;
+}
 __host__ __device__ constexpr int sched_nc(int p) { return mi_count(p); }
 __host__ __device__ constexpr int sched_stride(int p) { return (mi_count(p) + 7) / 8 * 8; }
 // length of a stored derivative vector D_k(d): the C(p + 3, 3) values, then at least one zero (the

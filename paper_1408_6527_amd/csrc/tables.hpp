@@ -50,4 +50,9 @@ int offset_order(const int d[3], int p, int ws, int slack);
 // |n| r^2 a_n = -(2|n| - 1) sum_i d_i a_{n - e_i} - (|n| - 1) sum_i a_{n - 2 e_i},  D_n = n! a_n.
 void derivative_tensor_unit(int p, const int* mi, int nc, const int d[3], double* out);
 
+// The operators of the acceptance-criterion lists: D_k(d), |k| <= p, at unit cell width for every
+// offset d in [-R, R]^3 of Chebyshev norm >= 2, one row of nc values per slot
+// ((dx + R)(2R + 1) + dy + R)(2R + 1) + dz + R (zero rows for the other slots).
+std::vector<double> mac_operator_rows(const HostTables& t, int R);
+
 }  // namespace pfmm
