@@ -297,9 +297,9 @@ def main():
                 "flops_per_pair": P2P_SCF_FLOPS_PER_PAIR}
 
     if dominant == "m2l" and args.theta > 0.0:
-        # the M2L of the acceptance-criterion lists runs on the float64 vector units on both paths
-        mr = m2l_roof(kst, PEAK["fp64_vector"])
-        roofline = {"bound": "alu", "kernel": "m2l_list", "achieved": mr["achieved"], "peak": PEAK["fp64_vector"],
+        # the M2L of the acceptance-criterion lists runs on the float64 matrix cores on both paths
+        mr = m2l_roof(kst, PEAK["fp64_mfma"])
+        roofline = {"bound": "mfma", "kernel": "m2l_mac", "achieved": mr["achieved"], "peak": PEAK["fp64_mfma"],
                     "unit": "TFLOP/s", "frac": mr["frac"], "traffic": None,
                     "avg_launch_ms": mr["avg_launch_ms"], "work_per_launch": mr["work_per_launch"]}
     elif dominant == "m2l":

@@ -132,8 +132,8 @@ typedef struct pfmm_config {
                           the largest distance from a cell's centre to one of its particles;
                           otherwise the pairs of their children are examined, down to the leaves,
                           whose pairs that are not accepted are summed directly.  Every M2L is at
-                          order p (m2l_order_slack must be -1) and runs in float64 on both precision
-                          paths; ws no longer shapes the lists.  The Thole damping radius must not
+                          order p (m2l_order_slack must be -1; order_p at most 9) and runs in float64
+                          on both precision paths; ws no longer shapes the lists.  The Thole damping radius must not
                           exceed the leaf edge.  Below 0.3 the offsets of accepted pairs outgrow the
                           operator table (PFMM_ERR_INVALID_ARG).                                   */
   int mac_ndirect;     /* with mac_theta: a pair of cells holding fewer than this many particles

@@ -252,16 +252,14 @@ struct pfmm_handle {
   int64_t n_m2l = 0, n_p2p = 0, m2l_flops = 0;
   int64_t m2l_flops_cap[11] = {};  // useful M2L flops per evaluation with every order capped at c
   int n_evals = 0;
-  // acceptance-criterion lists (mac_theta > 0): operator rows of the offsets in [-mac_R, mac_R]^3,
-  // enclosing radii, the frontier pairs of the walk and their prefix sums, the accepted pairs of
-  // each level, the near pairs, and the rows sorted by target
+  // acceptance-criterion lists (mac_theta > 0): operator rows of the offsets in
+  // [-(2 Rp + 1), 2 Rp + 1]^3, enclosing radii, split partners, the frontier pairs of the walk and
+  // their prefix sums, the near pairs and their rows sorted by target
   bool mac = false;
-  int mac_R = 0;
   MacView mv;
-  DevBuf t_mdvec, m_renc, m_bad, m_acc, m_kid, m_accs, m_kids, m_stmp, m_nt, m_ns, m_kin, m_vin, m_kout, m_vout,
-      m_sort_tmp, m_cnt, m_mptr, m_nkout, m_nvout, m_nptr;
+  DevBuf t_mdvec, m_renc, m_split, m_bad, m_acc, m_kid, m_accs, m_kids, m_stmp, m_stmp2, m_nt, m_ns, m_sort_tmp,
+      m_cnt, m_nkout, m_nvout, m_nptr;
   DevBuf m_fr[2];
-  std::array<DevBuf, MAX_LEVELS + 1> m_lt, m_lv;
 };
 
 namespace {
@@ -324,6 +322,8 @@ void validate_config(const pfmm_config* c) {
   if (c->mac_ndirect < 0) throw Error(PFMM_ERR_INVALID_ARG, "mac_ndirect must be >= 0");
   if (c->mac_leaf_direct != 0 && c->mac_leaf_direct != 1)
     throw Error(PFMM_ERR_INVALID_ARG, "mac_leaf_direct must be 0 or 1");
+  if (c->mac_theta > 0.0 && c->order_p > MAX_P_MAC)
+    throw Error(PFMM_ERR_INVALID_ARG, "mac_theta supports order_p up to " + std::to_string(MAX_P_MAC));
   if (c->mac_theta > 0.0 && c->m2l_order_slack >= 0)
     throw Error(PFMM_ERR_INVALID_ARG, "mac_theta runs every M2L at order p: m2l_order_slack must be -1");
 }
@@ -459,12 +459,7 @@ void build_tree(pfmm_handle* h, int n, const double* pos, const double* q, const
   } else {
     build_tree_stats(h, s);
   }
-  if (h->mac) {
-    h->m2l_tiles = 0;
-    h->nsplit = 1;
-  } else {
-    set_m2l_split(h);
-  }
+  set_m2l_split(h);
   // expansions (one extra zero row serves empty M2L sources); F holds nsplit partial copies
   const int64_t rows = (int64_t)ncell + 1;
   h->split_stride = rows * h->op.stride;
@@ -505,11 +500,16 @@ void set_m2l_split(pfmm_handle* h) {
   // one partial copy of F~ per split: choose the nsplit that minimises
   // rounds / nsplit + 0.004 rounds + 0.006 nsplit (in units of one round of whole tiles), with at
   // least one round of workgroups and at least 4 offsets per split.
-  h->m2l_tiles = L >= 2 ? m2l_tiles(t, 1, L - 1, m2l_tile_ncb(c.order_p, c.precision == PFMM_MIXED)) : 0;
+  // the acceptance-criterion M2L: float64 tiles, over the split partners instead of the colleagues
+  const bool mac = h->mac;
+  const int side = 2 * h->mv.Rp + 1;
+  const int nn = mac ? side * side * side : t.nnear;
+  const int lp_hi = L - 1 - (mac && h->mv.leaf_direct ? 1 : 0);
+  h->m2l_tiles = L >= 2 ? m2l_tiles(t, 1, lp_hi, mac ? 1 : m2l_tile_ncb(c.order_p, c.precision == PFMM_MIXED)) : 0;
   h->nsplit = 1;
   if (h->m2l_tiles > 0) {
     const int64_t T = h->m2l_tiles, C = std::max(1, h->n_cu);
-    const int hi = std::max(1, std::min(32, t.nnear / 4));
+    const int hi = std::max(1, std::min(32, nn / 4));
     const int lo = (int)std::min<int64_t>(hi, std::max<int64_t>(1, (C + T - 1) / T));
     double best = 0.0;
     for (int ns = lo; ns <= hi; ++ns) {
@@ -523,21 +523,26 @@ void set_m2l_split(pfmm_handle* h) {
   }
 }
 
-// The lists of the acceptance-criterion walk (mac.hip) for the tree in h->tv: each cell's M2L row
-// (h->mv), each leaf's near row (h->tv.nptr / nidx) and the pair statistics.  One synchronisation
-// per level reads the sizes of the next frontier and of the accepted pairs.
+// The acceptance-criterion walk (mac.hip) for the tree in h->tv: the split partners of every cell of
+// levels < L (h->mv.split, read by the M2L), each leaf's near row (h->tv.nptr / nidx) and the pair
+// statistics.  One synchronisation per level reads the sizes of the next frontier.
 void build_mac_lists(pfmm_handle* h, hipStream_t s) {
   TreeView& t = h->tv;
+  MacView& mv = h->mv;
   const int L = t.L, ncell = t.ncell;
   double* renc = dev<double>(h->m_renc, ncell);
   for (int l = 0; l <= L; ++l) launch_mac_radii(t, h->pa.P, l, renc, s);
+  mv.renc = renc;
+  const int side = 2 * mv.Rp + 1, nn = side * side * side;
+  int* split = dev<int>(h->m_split, (int64_t)std::max(t.off[L], 1) * nn);
+  launch_fill_int(split, (int64_t)std::max(t.off[L], 1) * nn, -1, s);
+  mv.split = split;
   int* bad = dev<int>(h->m_bad, 1);
   launch_fill_int(bad, 1, 0, s);
   int cur = 0;
   int2* fr = dev<int2>(h->m_fr[cur], 1);
   launch_fill_int(reinterpret_cast<int*>(fr), 2, 0, s);  // (root, root)
-  int64_t nfr = 1;
-  std::vector<int> macc(L + 1, 0);
+  int64_t nfr = 1, nm = 0;
   int nnear = 0;
   int* near_t = nullptr;
   int* near_s = nullptr;
@@ -552,8 +557,7 @@ void build_mac_lists(pfmm_handle* h, hipStream_t s) {
     int* kid = dev<int>(h->m_kid, nf);
     int* accs = dev<int>(h->m_accs, nf);
     int* kids = dev<int>(h->m_kids, nf);
-    launch_mac_classify(t, renc, h->cfg.mac_theta, h->cfg.mac_ndirect, h->cfg.mac_leaf_direct != 0, l, fr, nf, acc,
-                        kid, s);
+    launch_mac_classify(t, mv, l, fr, nf, acc, kid, s);
     const size_t tb = scan_temp_bytes(nf);
     void* tmp = raw(h->m_stmp, tb);
     launch_inclusive_scan(tmp, tb, acc, accs, nf, s);
@@ -564,9 +568,7 @@ void build_mac_lists(pfmm_handle* h, hipStream_t s) {
     PFMM_HIP(hipMemcpyAsync((char*)pin + sizeof(int), kids + (nf - 1), sizeof(int), hipMemcpyDeviceToHost, s));
     PFMM_HIP(hipStreamSynchronize(s));
     std::memcpy(tot, pin, sizeof(tot));
-    macc[l] = tot[0];
-    int* mt = tot[0] > 0 ? dev<int>(h->m_lt[l], tot[0]) : nullptr;
-    unsigned long long* mvv = tot[0] > 0 ? dev<unsigned long long>(h->m_lv[l], tot[0]) : nullptr;
+    nm += tot[0];
     int2* next = nullptr;
     if (l == L) {
       nnear = tot[1];
@@ -575,7 +577,7 @@ void build_mac_lists(pfmm_handle* h, hipStream_t s) {
     } else {
       next = dev<int2>(h->m_fr[cur ^ 1], tot[1]);
     }
-    launch_mac_emit(t, h->mac_R, l, fr, nf, accs, kids, mt, mvv, next, near_t, near_s, bad, s);
+    launch_mac_emit(t, mv, l, fr, nf, accs, kids, next, split, near_t, near_s, bad, s);
     if (l < L) {
       fr = next;
       nfr = tot[1];
@@ -584,56 +586,23 @@ void build_mac_lists(pfmm_handle* h, hipStream_t s) {
   }
   int badh = 0;
   sync_read(h, bad, &badh, sizeof(int), s);
-  if (badh) throw Error(PFMM_ERR_INVALID_ARG, "internal: an accepted cell offset exceeds the operator table");
+  if (badh) throw Error(PFMM_ERR_INVALID_ARG, "internal: a split cell pair lies beyond the partner table");
 
+  // near rows of the leaves, sorted by target (stable)
   int bits = 1;
   while ((1LL << bits) <= (int64_t)ncell) ++bits;
-  // M2L rows of the cells of levels >= 2 (levels 0 and 1 never accept: their cells are adjacent)
-  int64_t nm = 0;
-  for (int l = 0; l <= L; ++l) nm += macc[l];
-  if (nm > INT_MAX) throw Error(PFMM_ERR_INVALID_ARG, "acceptance-criterion lists too large; raise leaf_width");
-  const int rows = L >= 2 ? ncell - t.off[2] : 0;
   const int nleaf = t.off[L + 1] - t.off[L];
-  // one sort workspace, count array and scan workspace serve both sorts
-  const size_t sortb = std::max(nm > 0 ? mac_sort_temp_bytes((int)nm, bits, true) : 0,
-                                mac_sort_temp_bytes(nnear, bits, false));
-  void* sort_tmp = raw(h->m_sort_tmp, sortb);
-  int* cnt = dev<int>(h->m_cnt, std::max(rows, nleaf));
-  const size_t scanb = scan_temp_bytes(std::max(rows, nleaf));
-  void* scan_tmp = raw(h->m_stmp, scanb);
-  int* mptr = dev<int>(h->m_mptr, (int64_t)rows + 1);
-  launch_fill_int(mptr, (int64_t)rows + 1, 0, s);
-  unsigned long long* mval = nullptr;
-  if (nm > 0) {
-    int* kin = dev<int>(h->m_kin, nm);
-    unsigned long long* vin = dev<unsigned long long>(h->m_vin, nm);
-    int64_t o = 0;
-    for (int l = 0; l <= L; ++l) {
-      if (!macc[l]) continue;
-      PFMM_HIP(hipMemcpyAsync(kin + o, h->m_lt[l].ptr, (size_t)macc[l] * sizeof(int), hipMemcpyDeviceToDevice, s));
-      PFMM_HIP(hipMemcpyAsync(vin + o, h->m_lv[l].ptr, (size_t)macc[l] * sizeof(unsigned long long),
-                              hipMemcpyDeviceToDevice, s));
-      o += macc[l];
-    }
-    int* kout = dev<int>(h->m_kout, nm);
-    mval = dev<unsigned long long>(h->m_vout, nm);
-    launch_mac_sort(sort_tmp, sortb, kin, kout, vin, mval, (int)nm, bits, true, s);
-    launch_fill_int(cnt, rows, 0, s);
-    launch_mac_count(kout, (int)nm, t.off[2], cnt, s);
-    launch_inclusive_scan(scan_tmp, scanb, cnt, mptr + 1, rows, s);
-  }
-  h->mv.mptr = mptr;
-  h->mv.mval = mval;
-
-  // near rows of the leaves
   int* nkey = dev<int>(h->m_nkout, nnear);
   int* nsrc = dev<int>(h->m_nvout, nnear);
-  launch_mac_sort(sort_tmp, sortb, near_t, nkey, near_s, nsrc, nnear, bits, false, s);
+  const size_t sortb = mac_sort_temp_bytes(nnear, bits);
+  launch_mac_sort(raw(h->m_sort_tmp, sortb), sortb, near_t, nkey, near_s, nsrc, nnear, bits, s);
   int* nptr = dev<int>(h->m_nptr, (int64_t)nleaf + 1);
   launch_fill_int(nptr, (int64_t)nleaf + 1, 0, s);
+  int* cnt = dev<int>(h->m_cnt, nleaf);
   launch_fill_int(cnt, nleaf, 0, s);
   launch_mac_count(nkey, nnear, t.off[L], cnt, s);
-  launch_inclusive_scan(scan_tmp, scanb, cnt, nptr + 1, nleaf, s);
+  const size_t scanb = scan_temp_bytes(nleaf);
+  launch_inclusive_scan(raw(h->m_stmp2, scanb), scanb, cnt, nptr + 1, nleaf, s);
   t.nptr = nptr;
   t.nidx = nsrc;
 
@@ -673,7 +642,10 @@ void fmm_pass(pfmm_handle* h, int sources, int mode, FieldOut out, int* err, con
     kt.end(KC_M2M, e);
     e = kt.begin();
     if (h->mac) {
-      launch_m2l_list(t, op, h->mv, M, F, done, qcap, s);
+      // with leaf pairs direct no M2L runs for the leaves: their F~ starts from zero for the L2L
+      if (h->mv.leaf_direct)
+        launch_fill_double(F + (int64_t)t.off[t.L] * op.stride, (int64_t)(t.ncell - t.off[t.L]) * op.stride, 0.0, s);
+      launch_m2l(t, op, h->nsplit, M, nullptr, F, h->split_stride, false, 0, done, qcap, s, &h->mv);
     } else {
       float* M32 = nullptr;
       if (fp32) {
@@ -1216,14 +1188,18 @@ pfmm_status pfmm_create(const pfmm_config* cfg, pfmm_handle** out) {
     op.dorder = h->t_dorder.as<unsigned char>();
     op.nblocks = T.nblocks;
     if (cfg->mac_theta > 0.0) {
-      // offsets of accepted pairs: the parents of a pair at level l + 1 were not accepted, so their
-      // offset D has |D| <= (r_A + r_B) / (theta w_l) <= sqrt(3) / theta (or they were adjacent), and
-      // the child offset 2 D + (o_B - o_A) has components of at most 2 sqrt(3) / theta + 1
+      // a split pair whose children can be accepted failed the criterion (or was adjacent): its
+      // offset D has |D| <= (r_A + r_B) / (theta w) <= sqrt(3) / theta, as every particle of a cell
+      // lies within sqrt(3) w / 2 of its centre; the child offsets 2 D + (o_B - o_A) then lie within
+      // 2 Rp + 1, the radius of the operator table
       h->mac = true;
-      h->mac_R = std::max(3, (int)std::floor(2.0 * std::sqrt(3.0) / cfg->mac_theta + 1.0) + 1);
-      upload(h->t_mdvec, mac_operator_rows(T, h->mac_R));
-      h->mv.R = h->mac_R;
-      h->mv.dvec = h->t_mdvec.as<double>();
+      MacView& mv = h->mv;
+      mv.theta = cfg->mac_theta;
+      mv.ndirect = cfg->mac_ndirect;
+      mv.leaf_direct = cfg->mac_leaf_direct;
+      mv.Rp = std::max(1, (int)std::floor(std::sqrt(3.0) / cfg->mac_theta * (1.0 + 1e-9)));
+      upload(h->t_mdvec, mac_operator_rows(T, 2 * mv.Rp + 1));
+      mv.dvec = h->t_mdvec.as<double>();
     }
     PFMM_HIP(hipGetDevice(&h->device));
     // host staging for the small read-backs, so that later calls need not allocate it

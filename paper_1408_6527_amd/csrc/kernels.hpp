@@ -12,6 +12,7 @@ namespace pfmm {
 
 constexpr int MAX_LEVELS = 21;  // 63-bit Morton keys
 constexpr int MAX_P = 10;
+constexpr int MAX_P_MAC = 9;  // highest order of the acceptance-criterion M2L
 
 // Device view of the octree.  Cells of all levels live in one array, level by level; inside a
 // level they are in Morton order, so each cell's particles are a contiguous range of the sorted
@@ -125,9 +126,13 @@ int m2l_tile_ncb(int p, bool fp32);
 // targets at levels <= fp64_max_level still run in float64.
 // qcap (device, may be NULL): every offset's order is capped at *qcap.  M32: float32 copy of M,
 // read by the float32 launches of the mixed path (launch_to_float).
+struct MacView;
+// mac (may be NULL): the acceptance-criterion lists instead of the ws lists: the split partners of
+// each parent take the place of its colleagues and every child pair is tested with the criterion;
+// float64 on both paths, every M2L at order p (or the cap).
 void launch_m2l(const TreeView& t, const OpTables& op, int nsplit, const double* M, const float* M32,
                 double* F, int64_t split_stride, bool fp32, int fp64_max_level, const int* done,
-                const int* qcap, hipStream_t s);
+                const int* qcap, hipStream_t s, const MacView* mac = nullptr);
 void launch_to_float(const double* in, float* out, int64_t count, const int* done, hipStream_t s);
 
 // ---------------------------------------------------------------- p2p.hip
@@ -146,42 +151,42 @@ void launch_exclusions(const Particles& pa, const int* perm, const int* inv, con
 void launch_inverse_perm(const int* perm, int n, int* inv, hipStream_t s);
 
 // ---------------------------------------------------------------- mac.hip
-// M2L lists of the acceptance-criterion walk: for target cell g of levels >= 2, entries
-// mptr[g - off[2]] .. mptr[g - off[2] + 1] of mval, each (source cell << 32) | offset slot, the slot
-// of d = B - A being ((dx + R) (2R + 1) + dy + R) (2R + 1) + dz + R; dvec holds D_k(d) at unit cell
-// width for every slot, nc values per row.
+// The acceptance-criterion walk: the criterion's parameters, the cells' enclosing radii, and for every
+// cell of levels < L the partners of its split pairs (the pairs whose children the walk examined):
+// split[B (2 Rp + 1)^3 + slot(A - B)] = A, -1 elsewhere, the offsets of split pairs that can have
+// accepted children lying in [-Rp, Rp]^3.  The M2L kernel runs over these like the colleagues of the
+// ws lists and applies the criterion to the children (mac.hpp); dvec holds D_k(d) at unit cell width
+// for every offset in [-(2 Rp + 1), 2 Rp + 1]^3 at the row pitch of the M2L tables.
 struct MacView {
-  int R = 0;
+  double theta = 0.0;
+  int ndirect = 0, leaf_direct = 0, Rp = 0;
+  const double* renc = nullptr;
+  const int* split = nullptr;
   const double* dvec = nullptr;
-  const int* mptr = nullptr;
-  const unsigned long long* mval = nullptr;
 };
 // enclosing radius of every cell of a level: the largest distance from its centre to its particles
 void launch_mac_radii(const TreeView& t, const double4* P, int level, double* renc, hipStream_t s);
 // one level of the walk over the frontier pairs fr (target, source) of level l:
-// classify: acc[i] = 1 if the pair is accepted for M2L (never below ndirect particles together,
-// nor at the leaf level with leaf_direct); kid[i] = its child pairs (l < L) or 1 if it
-// goes to the near list (l = L), 0 otherwise;
-// emit (from the inclusive prefix sums of acc and kid): accepted pairs to m_tgt / m_val, child pairs
-// to next (l < L) or near pairs to near_tgt / near_src (l = L); *bad |= 1 for an accepted offset
-// outside the operator table
-void launch_mac_classify(const TreeView& t, const double* renc, double theta, int ndirect, bool leaf_direct,
-                         int level, const int2* fr, int nfr, int* acc, int* kid, hipStream_t s);
-void launch_mac_emit(const TreeView& t, int R, int level, const int2* fr, int nfr, const int* acc_scan,
-                     const int* kid_scan, int* m_tgt, unsigned long long* m_val, int2* next, int* near_tgt,
-                     int* near_src, int* bad, hipStream_t s);
-// stable sort of (key, value) by key over the low end_bit bits
-size_t mac_sort_temp_bytes(int n, int end_bit, bool wide);
-void launch_mac_sort(void* tmp, size_t tmp_bytes, const int* kin, int* kout, const void* vin, void* vout, int n,
-                     int end_bit, bool wide, hipStream_t s);
-// counts per key (keys - key0 in [0, nkey)), added to cnt; then ptr = exclusive prefix (ptr[0] = 0)
+// classify: acc[i] = 1 if the pair is accepted for M2L (never below ndirect particles together, nor
+// at the leaf level with leaf_direct); kid[i] = its child pairs (l < L) or 1 if it goes to the near
+// list (l = L), 0 otherwise;
+// emit (from the inclusive prefix sums of acc and kid): child pairs to next and the split table's
+// entries (l < L), or near pairs to near_tgt / near_src (l = L); *bad |= 1 for a split pair whose
+// children could be accepted outside [-Rp, Rp]^3 (which the bound on the radii rules out)
+void launch_mac_classify(const TreeView& t, const MacView& mv, int level, const int2* fr, int nfr, int* acc, int* kid,
+                         hipStream_t s);
+void launch_mac_emit(const TreeView& t, const MacView& mv, int level, const int2* fr, int nfr, const int* acc_scan,
+                     const int* kid_scan, int2* next, int* split, int* near_tgt, int* near_src, int* bad,
+                     hipStream_t s);
+// stable sort of (key, value) int pairs by key over the low end_bit bits
+size_t mac_sort_temp_bytes(int n, int end_bit);
+void launch_mac_sort(void* tmp, size_t tmp_bytes, const int* kin, int* kout, const int* vin, int* vout, int n,
+                     int end_bit, hipStream_t s);
+// counts per key (keys - key0 in [0, nkey)), added to cnt
 void launch_mac_count(const int* keys, int n, int key0, int* cnt, hipStream_t s);
 // ordered near-field particle pairs of the near list (i != j), added to *pairs
 void launch_mac_near_pairs(const TreeView& t, const int* near_tgt, const int* near_src, int n,
                            unsigned long long* pairs, hipStream_t s);
-// F~ of every cell of levels >= 2 from its M2L row, in float64, at order min(p, *qcap)
-void launch_m2l_list(const TreeView& t, const OpTables& op, const MacView& mv, const double* M, double* F,
-                     const int* done, const int* qcap, hipStream_t s);
 
 // ---------------------------------------------------------------- solver.hip
 struct CGState {

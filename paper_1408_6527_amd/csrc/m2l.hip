@@ -29,6 +29,7 @@
 #include <utility>
 
 #include "kernels.hpp"
+#include "mac.hpp"
 #include "schedule.hpp"
 
 namespace pfmm {
@@ -98,13 +99,15 @@ constexpr int m2l_dg() { return F32 ? (P >= 9 ? 3 : 6) : (P == 9 ? 2 : (P >= 10 
 // One slot of one wave at truncation order Q: A = K_d entries gathered from the staged D(d) at Dv
 // through the index table sH, B = the staged source coefficients at Bp.  The staged D(d) holds zeros
 // above degree Q, so the blocks of the order-Q subset read the truncated operator unmasked.
-template <int P, bool F32, int NCB, int Q, int H, typename kt, typename kt2, typename acc_t>
+template <int P, bool F32, int NCB, int Q, int H, bool MASK, typename kt, typename kt2, typename acc_t>
 __device__ __forceinline__ void m2l_mfma(const kt* Dv, const kt* Bp, const unsigned short* sH, int lane,
-                                         acc_t (&acc)[NCB][SchedHalvesOf<P>::value.nloc]) {
+                                         acc_t (&acc)[NCB][SchedHalvesOf<P>::value.nloc], const bool (&bm)[NCB]) {
   constexpr BlockOrder<P, Q, H> order{};
   constexpr int NB = order.n;
   constexpr int BP = sched_stride(P) + 2;
-  constexpr int DG = m2l_dg<P, F32>(), DI = 2 * DG;
+  // (one block less of look-ahead with column masks, whose test needs registers of its own)
+  constexpr int DG = MASK ? (m2l_dg<P, F32>() > 2 ? m2l_dg<P, F32>() - 1 : m2l_dg<P, F32>()) : m2l_dg<P, F32>();
+  constexpr int DI = 2 * DG;
   constexpr int RA = DG + 1, RI = DI - DG + 1;  // live K entries and indices
   constexpr int RB = order.pair_span(DG + 1);   // live step pairs of source coefficients
   unsigned ix[RI];
@@ -120,8 +123,13 @@ __device__ __forceinline__ void m2l_mfma(const kt* Dv, const kt* Bp, const unsig
       if (kg == 0 || order.s[kg - 1] / 2 != sg / 2) {
         // steps 2j and 2j + 1 read coefficients m(2j, q) and m(2j, q) + 1 of the lane's column
 #pragma unroll
-        for (int cb = 0; cb < NCB; ++cb)
-          bb[(sg / 2) % RB][cb] = *reinterpret_cast<const kt2*>(Bp + cb * 16 * BP + 8 * (sg / 2));
+        for (int cb = 0; cb < NCB; ++cb) {
+          kt2 v = *reinterpret_cast<const kt2*>(Bp + cb * 16 * BP + 8 * (sg / 2));
+          if constexpr (MASK) {
+            if (!bm[cb]) v = kt2{(kt)0, (kt)0};  // the lane's column holds a pair that is not accepted
+          }
+          bb[(sg / 2) % RB][cb] = v;
+        }
       }
     }
     if (k >= 0) {
@@ -141,37 +149,46 @@ __device__ __forceinline__ void m2l_mfma(const kt* Dv, const kt* Bp, const unsig
   }
 }
 
-// Run the slot of half H at a runtime order q <= P (one unrolled schedule per order).
-template <int P, bool F32, int NCB, int H, typename kt, typename kt2, typename acc_t, int... Qs>
+// Run the slot of half H at a runtime order q <= P (one unrolled schedule per order).  MASK: the
+// source coefficients of column cb are taken as 0 where bm[cb] is false.
+template <int P, bool F32, int NCB, int H, bool MASK, typename kt, typename kt2, typename acc_t, int... Qs>
 __device__ __forceinline__ void m2l_mfma_order(int q, std::integer_sequence<int, Qs...>, const kt* Dv,
                                                const kt* Bp, const unsigned short* sH, int lane,
-                                               acc_t (&acc)[NCB][SchedHalvesOf<P>::value.nloc]) {
-  (void)((q == Qs ? (m2l_mfma<P, F32, NCB, Qs, H, kt, kt2, acc_t>(Dv, Bp, sH, lane, acc), true) : false) || ...);
+                                               acc_t (&acc)[NCB][SchedHalvesOf<P>::value.nloc], const bool (&bm)[NCB]) {
+  (void)((q == Qs ? (m2l_mfma<P, F32, NCB, Qs, H, MASK, kt, kt2, acc_t>(Dv, Bp, sH, lane, acc, bm), true) : false) ||
+         ...);
 }
-template <int P, bool F32, int NCB, int H, typename kt, typename kt2, typename acc_t>
+template <int P, bool F32, int NCB, int H, bool MASK, typename kt, typename kt2, typename acc_t>
 __device__ __forceinline__ void m2l_slot(int q, const kt* Dv, const kt* Bp, const unsigned short* sH, int lane,
-                                         acc_t (&acc)[NCB][SchedHalvesOf<P>::value.nloc]) {
+                                         acc_t (&acc)[NCB][SchedHalvesOf<P>::value.nloc], const bool (&bm)[NCB]) {
   if (q >= P)
-    m2l_mfma<P, F32, NCB, P, H, kt, kt2, acc_t>(Dv, Bp, sH, lane, acc);
+    m2l_mfma<P, F32, NCB, P, H, MASK, kt, kt2, acc_t>(Dv, Bp, sH, lane, acc, bm);
   else
-    m2l_mfma_order<P, F32, NCB, H, kt, kt2, acc_t>(q, std::make_integer_sequence<int, P>{}, Dv, Bp, sH, lane, acc);
+    m2l_mfma_order<P, F32, NCB, H, MASK, kt, kt2, acc_t>(q, std::make_integer_sequence<int, P>{}, Dv, Bp, sH, lane,
+                                                         acc, bm);
 }
 
 // registers per lane: 2 waves per SIMD, one workgroup per CU
 template <int P, bool F32>
 constexpr int m2l_waves_per_eu() { return 2; }
 
-template <int P, bool F32>
-__global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(m2l_waves_per_eu<P, F32>()))) void k_m2l(TreeView t, OpTables op, int lp_lo, int lp_hi, int nsplit,
+// MAC: the lists of the acceptance-criterion walk.  The split partners of each parent (mv.split, at
+// offsets e in [-Rp, Rp]^3) take the place of its colleagues, the operator rows come from mv.dvec,
+// and every (target, source) column of a slot is tested with the criterion (mac.hpp); the columns
+// of pairs that are not accepted multiply zero source coefficients.  Every M2L at order P or the cap.
+template <int P, bool F32, bool MAC>
+__global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(m2l_waves_per_eu<P, F32>()))) void k_m2l(TreeView t, OpTables op, MacView mv, int lp_lo, int lp_hi, int nsplit,
                                              const double* __restrict__ M, const float* __restrict__ M32,
                                              double* __restrict__ F,
                                              int64_t split_stride, const int* done, const int* qcap) {
   if (done && *done) return;
+  static_assert(!(MAC && F32), "the acceptance-criterion M2L runs in float64");
   const int qc = qcap ? *qcap : P;  // order cap of a relaxed evaluation
   using kt = typename std::conditional<F32, float, double>::type;
   using kt2 = typename std::conditional<F32, float2, double2>::type;
   using acc_t = typename std::conditional<F32, f4, d4>::type;
-  constexpr int NCB = m2l_ncb<P, F32>();
+  // (one column block with the criterion: its masks leave no registers for a second)
+  constexpr int NCB = MAC ? 1 : m2l_ncb<P, F32>();
   constexpr int NRB = sched_nrb(P);
   constexpr int NC = mi_count(P);
   constexpr int STRIDE = sched_stride(P);
@@ -191,6 +208,7 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(m2l_waves_p
   // source rows of two slots: the rows of the next slot are stored while the current one is read
   __shared__ __attribute__((aligned(16))) kt sB[2][ROWS * BP];
   __shared__ int sSrc[8][ROWS];
+  __shared__ unsigned char sMask[MAC ? 8 : 1][MAC ? ROWS : 1];  // MAC: accepted source octants per target
   constexpr int NXCH = 2 * 4 * NCB * 64;  // row-block-0 partial sums handed between the halves
   constexpr bool XCH_IN_SB = NXCH * sizeof(acc_t) <= 2 * ROWS * BP * sizeof(kt);
   __shared__ acc_t sX[XCH_IN_SB ? 1 : NXCH];
@@ -233,10 +251,14 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(m2l_waves_p
   for (int e = threadIdx.x; e < NBLK * 8; e += TPB) sHv[e] = reinterpret_cast<const uint4*>(op.hidx)[e];
   const unsigned short* sH = reinterpret_cast<const unsigned short*>(sHv);
 
-  const int ws = t.ws, side = 2 * ws + 1, nn = t.nnear;
+  // ws lists: colleagues within ws; MAC: split partners within Rp.  Offsets d = u - 2 e of a slot
+  // then lie within R = 2 ws + 1 (or 2 Rp + 1), the radius of the operator table.
+  const int ws = MAC ? mv.Rp : t.ws, side = 2 * ws + 1, nn = MAC ? side * side * side : t.nnear;
+  const int* colls = MAC ? mv.split : t.coll;
   const int R = 2 * ws + 1, cube = 2 * R + 1;
   const kt* dtab;
-  if constexpr (F32) dtab = op.dvec32; else dtab = op.dvec;
+  if constexpr (F32) dtab = op.dvec32; else dtab = MAC ? mv.dvec : op.dvec;
+  const double wt = ldexp(t.w, t.L - (lp + 1));  // cell edge of the targets (MAC)
 
   constexpr const SchedHalves& HS = SchedHalvesOf<P>::value;
   constexpr int NLOC = HS.nloc;
@@ -321,7 +343,7 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(m2l_waves_p
       const int c = e % ROWS, r = e / ROWS;
       int src = -1;
       if (pbeg + c < pend) {
-        const int S = t.coll[(int64_t)(pbeg + c) * nn + ci];
+        const int S = colls[(int64_t)(pbeg + c) * nn + ci];
         if (S >= 0) src = t.child8[8 * S + r];
       }
       sSrc[r][c] = src;
@@ -334,15 +356,34 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(m2l_waves_p
       live |= (unsigned)any << r;
     }
     if (!live) continue;
+    if constexpr (MAC) {
+      // the criterion for every (target octant, column): bit r set when the pair with the column's
+      // source of octant r is accepted (read after the barrier that opens the first slot)
+      for (int e = threadIdx.x; e < 8 * ROWS; e += TPB) {
+        const int o = e / ROWS, c = e - o * ROWS;
+        const int tg = pbeg + c < pend ? t.child8[8 * (pbeg + c) + o] : -1;
+        unsigned bits = 0u;
+        if (tg >= 0) {
+          for (int rr = 0; rr < 8; ++rr) {
+            const int src = sSrc[rr][c];
+            if (src < 0) continue;
+            const int d0 = ((o >> 2) & 1) - ((rr >> 2) & 1) - 2 * e0, d1 = ((o >> 1) & 1) - ((rr >> 1) & 1) - 2 * e1,
+                      d2 = (o & 1) - (rr & 1) - 2 * e2;
+            if (mac_accept(t, mv.renc, mv.theta, mv.ndirect, wt, tg, src, d0, d1, d2)) bits |= 1u << rr;
+          }
+        }
+        sMask[o][c] = (unsigned char)bits;
+      }
+    }
     int r = __ffs(live) - 1;
     prefetch(r);
     for (int e = threadIdx.x; e < NU * DP; e += TPB) {
       const int v = e / DP, k = e - v * DP;
       const int d0 = v / 9 - 1 - 2 * e0, d1 = (v / 3) % 3 - 1 - 2 * e1, d2 = v % 3 - 1 - 2 * e2;
-      if (max(abs(d0), max(abs(d1), abs(d2))) > ws) {
+      if (max(abs(d0), max(abs(d1), abs(d2))) > (MAC ? 1 : ws)) {
         // D_k(d) for |k| <= q(d), zero above: the M2L truncated at order q(d)
         const int slot = ((d0 + R) * cube + (d1 + R)) * cube + (d2 + R);
-        const int q = min((int)op.dorder[slot], qc);
+        const int q = MAC ? min(P, qc) : min((int)op.dorder[slot], qc);
         sD[e] = k < mi_count(q) ? dtab[(int64_t)slot * DP + k] : (kt)0;
         if (k == 0) sQ[v] = q;
       }
@@ -365,15 +406,31 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(m2l_waves_p
       auto octant_slot = [&](acc_t(&acc)[NCB][NLOC], int o, bool act) {
         const int u0 = ((o >> 2) & 1) - ((r >> 2) & 1), u1 = ((o >> 1) & 1) - ((r >> 1) & 1), u2 = (o & 1) - (r & 1);
         const int d0 = u0 - 2 * e0, d1 = u1 - 2 * e1, d2 = u2 - 2 * e2;
-        if (act && max(abs(d0), max(abs(d1), abs(d2))) > ws) {  // wave-uniform
-          const int v = (u0 + 1) * 9 + (u1 + 1) * 3 + (u2 + 1);
-          const kt* Dv = sD + v * DP;
-          const kt* Bp = sB[buf] + col * BP + 2 * kq;
-          const int q = sQ[v];
-          if (half == 0)
-            m2l_slot<P, F32, NCB, 0, kt, kt2, acc_t>(q, Dv, Bp, sH, lane, acc);
-          else
-            m2l_slot<P, F32, NCB, 1, kt, kt2, acc_t>(q, Dv, Bp, sH, lane, acc);
+        if (act && max(abs(d0), max(abs(d1), abs(d2))) > (MAC ? 1 : ws)) {  // wave-uniform
+          bool bm[NCB];
+          bool run = true;
+          if constexpr (MAC) {
+            bool any = false;
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) {
+              bm[cb] = (sMask[o][16 * cb + col] >> r) & 1u;
+              any |= bm[cb];
+            }
+            run = __ballot(any) != 0;
+          } else {
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) bm[cb] = true;
+          }
+          if (run) {
+            const int v = (u0 + 1) * 9 + (u1 + 1) * 3 + (u2 + 1);
+            const kt* Dv = sD + v * DP;
+            const kt* Bp = sB[buf] + col * BP + 2 * kq;
+            const int q = sQ[v];
+            if (half == 0)
+              m2l_slot<P, F32, NCB, 0, MAC, kt, kt2, acc_t>(q, Dv, Bp, sH, lane, acc, bm);
+            else
+              m2l_slot<P, F32, NCB, 1, MAC, kt, kt2, acc_t>(q, Dv, Bp, sH, lane, acc, bm);
+          }
         }
       };
       octant_slot(accA, oc[0], activeA);
@@ -435,23 +492,37 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(m2l_waves_p
 template <int P>
 void m2l_dispatch(const TreeView& t, const OpTables& op, int nsplit, const double* M, const float* M32,
                   double* F, int64_t split_stride, bool fp32, int fp64_max_level, const int* done,
-                  const int* qcap, hipStream_t s) {
+                  const int* qcap, hipStream_t s, const MacView* mac) {
+  if (mac) {
+    // parents of levels [1, L - 1] (L - 2 when leaf pairs are direct), float64 on both paths.  At
+    // order 10 the accumulators of a tile leave no registers for the criterion's masks.
+    if constexpr (P <= MAX_P_MAC) {
+      const int hi = t.L - 1 - (mac->leaf_direct ? 1 : 0);
+      const int nt = m2l_tiles(t, 1, hi, 1);
+      if (nt > 0)
+        hipLaunchKernelGGL((k_m2l<P, false, true>), dim3(nt * nsplit), dim3(TPB), 0, s, t, op, *mac, 1, hi, nsplit,
+                           M, M32, F, split_stride, done, qcap);
+    } else {
+      throw Error(PFMM_ERR_INVALID_ARG, "mac_theta supports order_p up to 9");
+    }
+    return;
+  }
   // parents of levels [1, L - 1]; float64 for targets at levels <= fp64_max_level on the mixed path
   const int lo = 1, hi = t.L - 1;
   const int hi64 = fp32 ? std::min(hi, fp64_max_level - 1) : hi;
   if (hi64 >= lo) {
     const int nt = m2l_tiles(t, lo, hi64, m2l_ncb<P, false>());
     if (nt > 0)
-      hipLaunchKernelGGL((k_m2l<P, false>), dim3(nt * nsplit), dim3(TPB), 0, s, t, op, lo, hi64, nsplit,
-                         M, M32, F, split_stride, done, qcap);
+      hipLaunchKernelGGL((k_m2l<P, false, false>), dim3(nt * nsplit), dim3(TPB), 0, s, t, op, MacView(), lo, hi64,
+                         nsplit, M, M32, F, split_stride, done, qcap);
   }
   if (fp32) {
     const int lo32 = std::max(lo, hi64 + 1);
     if (hi >= lo32) {
       const int nt = m2l_tiles(t, lo32, hi, m2l_ncb<P, true>());
       if (nt > 0)
-        hipLaunchKernelGGL((k_m2l<P, true>), dim3(nt * nsplit), dim3(TPB), 0, s, t, op, lo32, hi, nsplit,
-                           M, M32, F, split_stride, done, qcap);
+        hipLaunchKernelGGL((k_m2l<P, true, false>), dim3(nt * nsplit), dim3(TPB), 0, s, t, op, MacView(), lo32, hi,
+                           nsplit, M, M32, F, split_stride, done, qcap);
     }
   }
 }
@@ -492,14 +563,18 @@ int m2l_tiles(const TreeView& t, int lp_lo, int lp_hi, int ncb) {
 
 void launch_m2l(const TreeView& t, const OpTables& op, int nsplit, const double* M, const float* M32,
                 double* F, int64_t split_stride, bool fp32, int fp64_max_level, const int* done,
-                const int* qcap, hipStream_t s) {
+                const int* qcap, hipStream_t s, const MacView* mac) {
   if (t.L < 2) return;
-  if (nsplit < 1 || nsplit > t.nnear) throw Error(PFMM_ERR_INVALID_ARG, "internal: M2L split out of range");
-  if (fp32 && (!op.dvec32 || !M32)) throw Error(PFMM_ERR_INVALID_ARG, "internal: float32 M2L inputs missing");
+  const int side = mac ? 2 * mac->Rp + 1 : 0;
+  if (nsplit < 1 || nsplit > (mac ? side * side * side : t.nnear))
+    throw Error(PFMM_ERR_INVALID_ARG, "internal: M2L split out of range");
+  if (mac && (!mac->split || !mac->dvec || !mac->renc || mac->Rp < 1))
+    throw Error(PFMM_ERR_INVALID_ARG, "internal: acceptance-criterion M2L inputs missing");
+  if (!mac && fp32 && (!op.dvec32 || !M32)) throw Error(PFMM_ERR_INVALID_ARG, "internal: float32 M2L inputs missing");
   switch (op.p) {
-#define PFMM_M2L_CASE(PP)                                                                          \
-  case PP:                                                                                         \
-    m2l_dispatch<PP>(t, op, nsplit, M, M32, F, split_stride, fp32, fp64_max_level, done, qcap, s); \
+#define PFMM_M2L_CASE(PP)                                                                               \
+  case PP:                                                                                              \
+    m2l_dispatch<PP>(t, op, nsplit, M, M32, F, split_stride, fp32, fp64_max_level, done, qcap, s, mac); \
     break;
     PFMM_M2L_CASE(1) PFMM_M2L_CASE(2) PFMM_M2L_CASE(3) PFMM_M2L_CASE(4) PFMM_M2L_CASE(5)
     PFMM_M2L_CASE(6) PFMM_M2L_CASE(7) PFMM_M2L_CASE(8) PFMM_M2L_CASE(9) PFMM_M2L_CASE(10)

@@ -208,15 +208,15 @@ void HostTables::build(int p_, int ws_, int order_slack) {
 }
 
 std::vector<double> mac_operator_rows(const HostTables& t, int R) {
-  const int cube = 2 * R + 1, nc = t.nc;
-  std::vector<double> rows((size_t)cube * cube * cube * nc, 0.0);
+  const int cube = 2 * R + 1, nc = t.nc, dp = t.dpitch;
+  std::vector<double> rows((size_t)cube * cube * cube * dp, 0.0);
   for (int dx = -R; dx <= R; ++dx)
     for (int dy = -R; dy <= R; ++dy)
       for (int dz = -R; dz <= R; ++dz) {
         if (std::max(std::abs(dx), std::max(std::abs(dy), std::abs(dz))) < 2) continue;
         const int slot = ((dx + R) * cube + (dy + R)) * cube + (dz + R);
         const int d[3] = {dx, dy, dz};
-        derivative_tensor_unit(t.p, t.mi.data(), nc, d, rows.data() + (size_t)slot * nc);
+        derivative_tensor_unit(t.p, t.mi.data(), nc, d, rows.data() + (size_t)slot * dp);
       }
   return rows;
 }

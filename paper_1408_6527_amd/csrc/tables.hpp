@@ -51,8 +51,8 @@ int offset_order(const int d[3], int p, int ws, int slack);
 void derivative_tensor_unit(int p, const int* mi, int nc, const int d[3], double* out);
 
 // The operators of the acceptance-criterion lists: D_k(d), |k| <= p, at unit cell width for every
-// offset d in [-R, R]^3 of Chebyshev norm >= 2, one row of nc values per slot
-// ((dx + R)(2R + 1) + dy + R)(2R + 1) + dz + R (zero rows for the other slots).
+// offset d in [-R, R]^3 of Chebyshev norm >= 2, one row per slot ((dx + R)(2R + 1) + dy + R)(2R + 1)
+// + dz + R at the pitch dpitch of dvec, zero-padded (zero rows for the other slots).
 std::vector<double> mac_operator_rows(const HostTables& t, int R);
 
 }  // namespace pfmm
