@@ -207,7 +207,20 @@ __global__ __launch_bounds__(TPB) void k_p2p(TreeView t, Particles pa, const dou
               eux += (cu * rx - mx) * rinv3;
               euy += (cu * ry - my) * rinv3;
               euz += (cu * rz - mz) * rinv3;
-              const T Ac = (v < T(1)) ? T(-3) * v4 : T(-15);
+              // The coefficient of u_a u_b u_c jumps at the edge of the damping cone (-3 inside, -15
+              // outside: the linear model's third derivative is discontinuous at r = s).  Which
+              // side a pair falls on is decided in float64 on both paths: near the edge the float32
+              // ratio can round across it.
+              bool inside = v < T(1);
+              if constexpr (std::is_same<T, float>::value) {
+                if (ii > T(0) && fabsf(v - 1.0f) < 1e-4f) {
+                  const int j = sidx[jj];
+                  const double4 Pj = pa.P[j];
+                  const double dx = Pi.x - Pj.x, dy = Pi.y - Pj.y, dz = Pi.z - Pj.z;
+                  inside = sqrt(dx * dx + dy * dy + dz * dz) * (pa.itau[i] * pa.itau[j]) < 1.0;
+                }
+              }
+              const T Ac = inside ? T(-3) * v4 : T(-15);
               const T Bc = T(3) * v4;
               const T rinv5 = rinv3 * rinv2;
               const T a7 = Ac * rmu * rinv5 * rinv2;  // A (u.mu) u_a u_b / r^4 = A rmu r_a r_b / r^7
