@@ -435,6 +435,7 @@ void build_tree(pfmm_handle* h, int n, const double* pos, const double* q, const
   t.w = w;
   t.ws = c.ws;
   t.nnear = h->tab.nnear;
+  t.damp_adjacent = s_max * (1.0 + 1e-9) <= w ? 1 : 0;
   const int ncell = t.ncell;
   uint64_t* ckey = dev<uint64_t>(h->w_ckey, ncell);
   int* cfirst = dev<int>(h->w_cfirst, ncell);
@@ -642,9 +643,12 @@ void fmm_pass(pfmm_handle* h, int sources, int mode, FieldOut out, int* err, con
     kt.end(KC_M2M, e);
     e = kt.begin();
     if (h->mac) {
-      // with leaf pairs direct no M2L runs for the leaves: their F~ starts from zero for the L2L
+      // with leaf pairs direct no M2L runs for the leaves: their F~ (and its partial sums of the
+      // offset splits, which the L2L adds) start from zero
       if (h->mv.leaf_direct)
-        launch_fill_double(F + (int64_t)t.off[t.L] * op.stride, (int64_t)(t.ncell - t.off[t.L]) * op.stride, 0.0, s);
+        for (int sp = 0; sp < h->nsplit; ++sp)
+          launch_fill_double(F + sp * h->split_stride + (int64_t)t.off[t.L] * op.stride,
+                             (int64_t)(t.ncell - t.off[t.L]) * op.stride, 0.0, s);
       launch_m2l(t, op, h->nsplit, M, nullptr, F, h->split_stride, false, 0, done, qcap, s, &h->mv);
     } else {
       float* M32 = nullptr;

@@ -24,6 +24,8 @@ struct TreeView {
   double origin[3] = {0, 0, 0};
   double w = 1.0;                  // leaf edge
   int ws = 1, nnear = 1;
+  int damp_adjacent = 0;           // 1: the Thole damping radius is at most the leaf edge, so only
+                                   // adjacent leaves hold damped pairs
   const uint64_t* key = nullptr;   // cell key at its own level (3 bits per level)
   const int* first = nullptr;      // first sorted particle
   const int* count = nullptr;      // particles in the cell

@@ -22,6 +22,7 @@
 // sources within a cutoff radius rc (rc <= leaf edge, so the 27 adjacent leaves hold them all),
 // written rather than added.
 #include <algorithm>
+#include <climits>
 #include <type_traits>
 
 #include "kernels.hpp"
@@ -62,23 +63,53 @@ __global__ __launch_bounds__(TPB) void k_p2p(TreeView t, Particles pa, const dou
     ne = t.nptr[lg + 1] - t.nptr[lg];
   }
 
+  // The colleagues are taken adjacent ones first (offsets with every component in [-1, 1]).  When the
+  // damping radius is at most the leaf edge (t.damp_adjacent) only they can hold Thole-damped pairs,
+  // so the staged chunks past their particles run the undamped pair kernel; mode 3 (the
+  // preconditioner, cutoff below the leaf edge) takes the adjacent ones alone.  s_ord[k]: colleague
+  // index of position k.
+  __shared__ int s_ord[LIST ? 1 : CHUNK];
+  if constexpr (!LIST) {
+    const int side = 2 * t.ws + 1;
+    auto is_adj = [&](int ci) {
+      return abs(ci / (side * side) - t.ws) <= 1 && abs((ci / side) % side - t.ws) <= 1 && abs(ci % side - t.ws) <= 1;
+    };
+    const bool a0 = lane < ne && is_adj(lane), a1 = lane + TPB < ne && is_adj(lane + TPB);
+    const unsigned long long b0 = __ballot(a0), b1 = __ballot(a1);
+    const unsigned long long below = lane == 0 ? 0ULL : (~0ULL >> (64 - lane));
+    const int n0 = __popcll(b0), na = n0 + __popcll(b1);
+    if (lane < ne) {
+      const int ra = __popcll(b0 & below);
+      s_ord[a0 ? ra : na + (lane - ra)] = lane;
+    }
+    if (lane + TPB < ne) {
+      const int ra = n0 + __popcll(b1 & below), k = lane + TPB;
+      s_ord[a1 ? ra : na + (k - ra)] = k;
+    }
+    if (MODE == 3) ne = na;
+    __syncthreads();
+  }
+  const int nadj = [&] {
+    if constexpr (LIST) return ne;
+    const int side = 2 * t.ws + 1;
+    return min(ne, side >= 3 ? 27 : ne);
+  }();
+
   // exclusive prefix of the occupancies of the source leaves E0 .. E0 + nn - 1 (two per lane) into
   // s_pref[0 .. nn], their first particles into s_first; returns nn
+  auto entry = [&](int k) {
+    if constexpr (LIST) return ent[k];
+    else return ent[s_ord[k]];
+  };
   auto prefix = [&](int E0) {
     const int nn = min(CHUNK, ne - E0);
     int c0 = 0, c1 = 0, f0 = 0, f1 = 0;
-    // mode 3 walks only the adjacent leaves (colleague offsets with every component in [-1, 1])
-    const int side = 2 * t.ws + 1;
-    auto adjacent = [&](int ci) {
-      return MODE != 3 || (abs(ci / (side * side) - t.ws) <= 1 && abs((ci / side) % side - t.ws) <= 1 &&
-                           abs(ci % side - t.ws) <= 1);
-    };
-    if (lane < nn && adjacent(E0 + lane)) {
-      const int A = ent[E0 + lane];
+    if (lane < nn) {
+      const int A = entry(E0 + lane);
       if (A >= 0) { c0 = t.count[A]; f0 = t.first[A]; }
     }
-    if (lane + TPB < nn && adjacent(E0 + lane + TPB)) {
-      const int A = ent[E0 + lane + TPB];
+    if (lane + TPB < nn) {
+      const int A = entry(E0 + lane + TPB);
       if (A >= 0) { c1 = t.count[A]; f1 = t.first[A]; }
     }
     int i0 = c0, i1 = c1;
@@ -94,9 +125,11 @@ __global__ __launch_bounds__(TPB) void k_p2p(TreeView t, Particles pa, const dou
     return nn;
   };
   int nn = 0;
+  int adj_src = INT_MAX;  // staged sources below this index may form damped pairs
   if constexpr (!LIST) {
     nn = prefix(0);
     __syncthreads();
+    if (t.damp_adjacent) adj_src = s_pref[min(nadj, nn)];
   }
 
   double cen[3];
@@ -132,6 +165,7 @@ __global__ __launch_bounds__(TPB) void k_p2p(TreeView t, Particles pa, const dou
       }
       const int total = s_pref[nn];
       for (int S0 = 0; S0 < total; S0 += TPB) {
+        if (MODE == 2 && S0 >= adj_src) break;  // the Thole term needs damped pairs only
         const int m = min(TPB, total - S0);
         __syncthreads();
         if (lane < m) {
@@ -156,84 +190,95 @@ __global__ __launch_bounds__(TPB) void k_p2p(TreeView t, Particles pa, const dou
         }
         __syncthreads();
         if (!active) continue;
+        // DAMP: the chunk may hold pairs inside a damping cone; otherwise v = 1 for every pair
+        auto chunk = [&](auto dampc) {
+          constexpr bool DAMP = decltype(dampc)::value;
   #pragma unroll 4
-        for (int jj = slice; jj < m; jj += G) {
-          const T rx = xi - sx[jj], ry = yi - sy[jj], rz = zi - sz[jj];
-          const T r2 = rx * rx + ry * ry + rz * rz;
-          const bool valid = r2 > T(0) && (MODE != 3 || r2 < rc2);
-          if (MODE == 1 && !valid && sidx[jj] != i) bad = 1;
-          const T rinv = valid ? rsqrt_t(valid ? r2 : T(1)) : T(0);
-          const T rinv2 = rinv * rinv;
-          const T rinv3 = rinv * rinv2;
-          if (MODE == 1 && HQ) {
-            const T qj = sq[jj];
-            const T qr3 = qj * rinv3;
-            phi += qj * rinv;
-            const T ex = qr3 * rx, ey = qr3 * ry, ez = qr3 * rz;
-            eux += ex; euy += ey; euz += ez;
-            edx += ex; edy += ey; edz += ez;
-            const T c5 = T(3) * qr3 * rinv2;
-            gxx += qr3 - c5 * rx * rx; gyy += qr3 - c5 * ry * ry; gzz += qr3 - c5 * rz * rz;
-            gxy -= c5 * rx * ry; gxz -= c5 * rx * rz; gyz -= c5 * ry * rz;
-          }
-          if (MODE == 2) {
-            // Thole term of dU/dalpha_i: (2 v^4 (mu_i.u)(mu_j.u) - 2 (v^3 - v^4) mu_i.mu_j) / (alpha_i r^3)
-            const T ii = iti * sit[jj];
-            const T rr = r2 * rinv;
-            const T v = ii > T(0) ? fmin(rr * ii, T(1)) : T(1);
-            if (valid && v < T(1)) {
-              const T v3 = v * v * v, v4 = v3 * v;
-              const T miu = (T(mui.x) * rx + T(mui.y) * ry + T(mui.z) * rz) * rinv;
-              const T mju = (smx[jj] * rx + smy[jj] * ry + smz[jj] * rz) * rinv;
-              const T mm = T(mui.x) * smx[jj] + T(mui.y) * smy[jj] + T(mui.z) * smz[jj];
-              dsum += (double)((T(2) * v4 * miu * mju - T(2) * (v3 - v4) * mm) * rinv3);
+          for (int jj = slice; jj < m; jj += G) {
+            const T rx = xi - sx[jj], ry = yi - sy[jj], rz = zi - sz[jj];
+            const T r2 = rx * rx + ry * ry + rz * rz;
+            const bool valid = r2 > T(0) && (MODE != 3 || r2 < rc2);
+            if (MODE == 1 && !valid && sidx[jj] != i) bad = 1;
+            const T rinv = valid ? rsqrt_t(valid ? r2 : T(1)) : T(0);
+            const T rinv2 = rinv * rinv;
+            const T rinv3 = rinv * rinv2;
+            if (MODE == 1 && HQ) {
+              const T qj = sq[jj];
+              const T qr3 = qj * rinv3;
+              phi += qj * rinv;
+              const T ex = qr3 * rx, ey = qr3 * ry, ez = qr3 * rz;
+              eux += ex; euy += ey; euz += ez;
+              edx += ex; edy += ey; edz += ez;
+              const T c5 = T(3) * qr3 * rinv2;
+              gxx += qr3 - c5 * rx * rx; gyy += qr3 - c5 * ry * ry; gzz += qr3 - c5 * rz * rz;
+              gxy -= c5 * rx * ry; gxz -= c5 * rx * rz; gyz -= c5 * ry * rz;
             }
-          }
-          if ((MODE == 0 || MODE == 1 || MODE == 3) && HM) {
-            const T mx = smx[jj], my = smy[jj], mz = smz[jj];
-            const T rmu = rx * mx + ry * my + rz * mz;
-            const T ii = iti * sit[jj];
-            const T rr = r2 * rinv;
-            const T v = ii > T(0) ? fmin(rr * ii, T(1)) : T(1);
-            const T v3 = v * v * v, v4 = v3 * v;
-            const T ft = v4, fe = v3 * (T(4) - T(3) * v);
-            const T c3 = T(3) * ft * rmu * rinv2;
-            edx += (c3 * rx - fe * mx) * rinv3;
-            edy += (c3 * ry - fe * my) * rinv3;
-            edz += (c3 * rz - fe * mz) * rinv3;
-            if (MODE == 1) {
-              phi += rmu * rinv3;
-              const T cu = T(3) * rmu * rinv2;
-              eux += (cu * rx - mx) * rinv3;
-              euy += (cu * ry - my) * rinv3;
-              euz += (cu * rz - mz) * rinv3;
-              // The coefficient of u_a u_b u_c jumps at the edge of the damping cone (-3 inside, -15
-              // outside: the linear model's third derivative is discontinuous at r = s).  Which
-              // side a pair falls on is decided in float64 on both paths: near the edge the float32
-              // ratio can round across it.
-              bool inside = v < T(1);
-              if constexpr (std::is_same<T, float>::value) {
-                if (ii > T(0) && fabsf(v - 1.0f) < 1e-4f) {
-                  const int j = sidx[jj];
-                  const double4 Pj = pa.P[j];
-                  const double dx = Pi.x - Pj.x, dy = Pi.y - Pj.y, dz = Pi.z - Pj.z;
-                  inside = sqrt(dx * dx + dy * dy + dz * dz) * (pa.itau[i] * pa.itau[j]) < 1.0;
-                }
+            if (MODE == 2 && DAMP) {
+              // Thole term of dU/dalpha_i: (2 v^4 (mu_i.u)(mu_j.u) - 2 (v^3 - v^4) mu_i.mu_j) / (alpha_i r^3)
+              const T ii = iti * sit[jj];
+              const T rr = r2 * rinv;
+              const T v = ii > T(0) ? fmin(rr * ii, T(1)) : T(1);
+              if (valid && v < T(1)) {
+                const T v3 = v * v * v, v4 = v3 * v;
+                const T miu = (T(mui.x) * rx + T(mui.y) * ry + T(mui.z) * rz) * rinv;
+                const T mju = (smx[jj] * rx + smy[jj] * ry + smz[jj] * rz) * rinv;
+                const T mm = T(mui.x) * smx[jj] + T(mui.y) * smy[jj] + T(mui.z) * smz[jj];
+                dsum += (double)((T(2) * v4 * miu * mju - T(2) * (v3 - v4) * mm) * rinv3);
               }
-              const T Ac = inside ? T(-3) * v4 : T(-15);
-              const T Bc = T(3) * v4;
-              const T rinv5 = rinv3 * rinv2;
-              const T a7 = Ac * rmu * rinv5 * rinv2;  // A (u.mu) u_a u_b / r^4 = A rmu r_a r_b / r^7
-              const T b5 = Bc * rinv5;
-              gxx += a7 * rx * rx + b5 * (rmu + T(2) * rx * mx);
-              gyy += a7 * ry * ry + b5 * (rmu + T(2) * ry * my);
-              gzz += a7 * rz * rz + b5 * (rmu + T(2) * rz * mz);
-              gxy += a7 * rx * ry + b5 * (rx * my + ry * mx);
-              gxz += a7 * rx * rz + b5 * (rx * mz + rz * mx);
-              gyz += a7 * ry * rz + b5 * (ry * mz + rz * my);
+            }
+            if ((MODE == 0 || MODE == 1 || MODE == 3) && HM) {
+              const T mx = smx[jj], my = smy[jj], mz = smz[jj];
+              const T rmu = rx * mx + ry * my + rz * mz;
+              T v = T(1), v4 = T(1), ii = T(0);
+              if constexpr (DAMP) {
+                ii = iti * sit[jj];
+                const T rr = r2 * rinv;
+                v = ii > T(0) ? fmin(rr * ii, T(1)) : T(1);
+                v4 = v * v * v * v;
+              }
+              const T ft = v4, fe = DAMP ? v * v * v * (T(4) - T(3) * v) : T(1);
+              const T c3 = T(3) * ft * rmu * rinv2;
+              edx += (c3 * rx - fe * mx) * rinv3;
+              edy += (c3 * ry - fe * my) * rinv3;
+              edz += (c3 * rz - fe * mz) * rinv3;
+              if (MODE == 1) {
+                phi += rmu * rinv3;
+                const T cu = T(3) * rmu * rinv2;
+                eux += (cu * rx - mx) * rinv3;
+                euy += (cu * ry - my) * rinv3;
+                euz += (cu * rz - mz) * rinv3;
+                // The coefficient of u_a u_b u_c jumps at the edge of the damping cone (-3 inside, -15
+                // outside: the linear model's third derivative is discontinuous at r = s).  Which
+                // side a pair falls on is decided in float64 on both paths: near the edge the float32
+                // ratio can round across it.
+                bool inside = DAMP && v < T(1);
+                if constexpr (DAMP && std::is_same<T, float>::value) {
+                  if (ii > T(0) && fabs(v - T(1)) < T(1e-4)) {
+                    const int j = sidx[jj];
+                    const double4 Pj = pa.P[j];
+                    const double dx = Pi.x - Pj.x, dy = Pi.y - Pj.y, dz = Pi.z - Pj.z;
+                    inside = sqrt(dx * dx + dy * dy + dz * dz) * (pa.itau[i] * pa.itau[j]) < 1.0;
+                  }
+                }
+                const T Ac = inside ? T(-3) * v4 : T(-15);
+                const T Bc = T(3) * v4;
+                const T rinv5 = rinv3 * rinv2;
+                const T a7 = Ac * rmu * rinv5 * rinv2;  // A (u.mu) u_a u_b / r^4 = A rmu r_a r_b / r^7
+                const T b5 = Bc * rinv5;
+                gxx += a7 * rx * rx + b5 * (rmu + T(2) * rx * mx);
+                gyy += a7 * ry * ry + b5 * (rmu + T(2) * ry * my);
+                gzz += a7 * rz * rz + b5 * (rmu + T(2) * rz * mz);
+                gxy += a7 * rx * ry + b5 * (rx * my + ry * mx);
+                gxz += a7 * rx * rz + b5 * (rx * mz + rz * mx);
+                gyz += a7 * ry * rz + b5 * (ry * mz + rz * my);
+              }
             }
           }
-        }
+        };
+        if (S0 < adj_src)
+          chunk(std::true_type{});
+        else
+          chunk(std::false_type{});
       }
     }
     // combine the G slices of every target (lanes slot, slot + T, slot + 2T, ...) in slice order

@@ -64,6 +64,16 @@ def _cube(n, side, seed, r_min=1.0):
     return pts, q, a, mu
 
 
+def _dirty_device_memory():
+    """Hand NaN-filled memory back to the HIP allocator, so that workspace the library allocates next
+    is likely to start out as garbage rather than zeros (a buffer read before it is written shows)."""
+    import torch
+    junk = torch.full((64 << 20,), float("nan"), dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    del junk
+    torch.cuda.empty_cache()
+
+
 def _oracle_counts(X, lw, theta, nd, ld):
     tree = FM.Octree(X, lw, 1)
     m2l, near = tree.mac_lists(X, theta, nd, bool(ld))
@@ -87,6 +97,7 @@ def test_mac_fields_and_lists_match_oracle(api, n, side, lw, thole, theta, p, nd
     print(f"[case] mac fields n={n} theta={theta} p={p} ndirect={nd} leaf_direct={ld}", flush=True)
     X, q, a, mu = _cube(n, side, 2)
     kw = dict(order_p=p, ws=1, leaf_width=lw, thole_a=thole, mac_theta=theta, mac_ndirect=nd, mac_leaf_direct=ld)
+    _dirty_device_memory()
     s = api.Solver(scf_tol=1e-10, **kw)
     # a first evaluation of other sources on the same handle: nothing of it may leak into the next
     s.field(T(X), T(3.0 * q[::-1].copy()), T(-2.0 * mu), T(a))
