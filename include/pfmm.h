@@ -107,7 +107,9 @@ typedef struct pfmm_config {
                           products in a Krylov solve, whose late corrections are small).  The
                           stopping rule is checked again on the final dipoles with the full orders;
                           if it fails, the solve continues once from them without the cap, and
-                          returns PFMM_ERR_NOT_CONVERGED if it still fails.                       */
+                          returns PFMM_ERR_NOT_CONVERGED if it still fails.  On the mixed path the
+                          relaxed iterations stop at scf_tol / 2, leaving room for the float32
+                          rounding of their products in that final check.                         */
   double dipole_pair_dl; /* 0: the multipoles of the induced dipoles are those of point dipoles (the
                           limit of Sec. II.C).  > 0 (Angstrom, at most 1): each dipole's multipole
                           expansion is that of the pair of charges +/- |mu| / (2 dl) at x +/- dl mu/|mu|

@@ -825,15 +825,16 @@ CGState dipole_cg(pfmm_handle* h, const double* Ee, bool warm_now, const RelaxPa
   const bool use_graph = c.graph_iters > 0 && !timing;
   const bool relaxed = rp.start > 0.0;
   const int* qcap = relaxed ? &st->qcap : nullptr;
+  const double tol = c.scf_tol * (relaxed ? rp.tol_scale : 1.0);
   if (pc && !warm_now) {
     // the preconditioned solve starts from y0 = 0: r0 = S Ee costs no field evaluation, and
     // p0 = z0 is a better first direction than the Jacobi guess alpha Ee
-    launch_cg_init_zero(pa, Ee, y, r, part, st, c.scf_tol, s);
+    launch_cg_init_zero(pa, Ee, y, r, part, st, tol, s);
   } else {
     launch_cg_init(pa, Ee, mu4, warm_now, y, pv, mu4, part, st, s);
     fmm_pass(h, 2, 0, fo, err, nullptr, s);
     ++*evals;
-    launch_cg_residual0(pa, Ee, E, y, r, pv, part, st, c.scf_tol, s);
+    launch_cg_residual0(pa, Ee, E, y, r, pv, part, st, tol, s);
   }
   if (pc) {
     precondition(s);
@@ -851,7 +852,7 @@ CGState dipole_cg(pfmm_handle* h, const double* Ee, bool warm_now, const RelaxPa
     if (pc) {
       ev = h->kt.begin();
       launch_pcg_ap(pa, pv, E, r, Ap, part, st, q);
-      launch_cg_update(pa, y, r, pv, Ap, part, st, c.scf_tol, c.scf_max_iter, q, rp);
+      launch_cg_update(pa, y, r, pv, Ap, part, st, tol, c.scf_max_iter, q, rp);
       h->kt.end(KC_SOLVER, ev);
       precondition(q);
       ev = h->kt.begin();
@@ -862,7 +863,7 @@ CGState dipole_cg(pfmm_handle* h, const double* Ee, bool warm_now, const RelaxPa
     }
     ev = h->kt.begin();
     launch_cg_ap(pa, pv, E, Ap, part, st, q);
-    launch_cg_update(pa, y, r, pv, Ap, part, st, c.scf_tol, c.scf_max_iter, q, rp);
+    launch_cg_update(pa, y, r, pv, Ap, part, st, tol, c.scf_max_iter, q, rp);
     launch_cg_direction(3 * n, r, pv, st, q);
     h->kt.end(KC_SOLVER, ev);
   };
@@ -993,6 +994,9 @@ pfmm_status solve_impl(pfmm_handle* h, int64_t n64, const double* pos, const dou
   rp.track = 1;
   rp.start = c.scf_relax;
   rp.lrho = 2.0 * std::log((c.ws + 1.0) / std::sqrt(3.0));
+  // the float32 products of the mixed path add their rounding to every relaxed product: the relaxed
+  // phase stops at half the tolerance, leaving room for it in the final check at the full orders
+  rp.tol_scale = c.precision == PFMM_MIXED ? 0.5 : 1.0;
   launch_fill_int(&st->qcap, 1, c.order_p, s);
   launch_fill_int(st->ncap, 16, 0, s);
   double* phim = dev<double>(h->f_phim, n);
@@ -1333,6 +1337,9 @@ pfmm_status pfmm_backward_mu(pfmm_handle* h, int64_t solve_id, const double* g_m
     rp.track = 0;
     rp.start = 0.0;
     rp.lrho = 2.0 * std::log((c.ws + 1.0) / std::sqrt(3.0));
+  // the float32 products of the mixed path add their rounding to every relaxed product: the relaxed
+  // phase stops at half the tolerance, leaving room for it in the final check at the full orders
+  rp.tol_scale = c.precision == PFMM_MIXED ? 0.5 : 1.0;
     launch_fill_int(&st->qcap, 1, c.order_p, s);
     int evals = 0;
     const CGState hs = dipole_cg(hm, Gcg, false, rp, st, errcg, s, &evals);

@@ -203,6 +203,7 @@ struct CGState {
 struct RelaxParams {
   int p = 0, qmin = 0, track = 0;
   double start = 0.0, lrho = 1.0;
+  double tol_scale = 1.0;  // a relaxed solve stops at tol_scale * scf_tol (its final check: scf_tol)
 };
 constexpr int RED_BLOCKS = 512;   // partial sums per reduction
 void launch_cg_init(const Particles& pa, const double* Eq, const double4* mu_warm, bool warm,
