@@ -50,7 +50,8 @@ WORKLOADS = {
 
 # HBM traffic of the dominant kernel from rocprofv3 counters (profiles/), valid only while the
 # kernel sources hash to the value recorded with the counters
-TRAFFIC_SOURCES = ["paper_1408_6527_amd/csrc/m2l.hip", "paper_1408_6527_amd/csrc/schedule.hpp"]
+TRAFFIC_SOURCES = ["paper_1408_6527_amd/csrc/m2l.hip", "paper_1408_6527_amd/csrc/schedule.hpp",
+                   "paper_1408_6527_amd/csrc/mac.hpp"]
 
 
 def kernel_source_hash() -> str:
