@@ -35,7 +35,9 @@ Tree geometry (the same rule is implemented by the library):
     level l - 1 and A, B themselves are farther apart than ws.
 These lists reproduce the classical well-separation criterion of Greengard and Rokhlin (Sec. III
 mentions it beside the paper's own MAC); every particle pair is counted exactly once, either in
-the near field or in exactly one M2L.
+the near field or in exactly one M2L.  Octree.walk_lists gives the lists of a dual tree walk instead:
+the paper's acceptance criterion, and the adaptive octree, whose leaves stop splitting at leaf_max
+particles (Sec. III) and whose walk sums the particles of two terminal cells directly.
 """
 from __future__ import annotations
 
@@ -289,6 +291,17 @@ class Octree:
         for l in range(L + 1):
             sh = L - l
             self.cells.append(sorted({(a >> sh, b >> sh, d >> sh) for (a, b, d) in self.leaves}))
+        # particles of every cell of every level (the leaves' lists at level L)
+        self._mem = [dict() for _ in range(L + 1)]
+        self._mem[L] = self.leaves
+        for cc, idx in self.leaves.items():
+            for l in range(L):
+                sh = L - l
+                self._mem[l].setdefault((cc[0] >> sh, cc[1] >> sh, cc[2] >> sh), []).extend(idx)
+
+    def members(self, l, c):
+        """Indices of the particles in cell c of level l."""
+        return self._mem[l][c]
 
     def width(self, l):
         return self.w * 2.0 ** (self.L - l)
@@ -339,25 +352,62 @@ class Octree:
                 renc[l][c] = max(renc[l].get(c, 0.0), r)
         return renc
 
-    def mac_lists(self, X, theta, ndirect=0, leaf_direct=False):
-        """Interaction lists of the paper's dual tree walk (Sec. III) on this octree, with its
-        multipole acceptance criterion (eq:mac): a pair of cells of one level, A != B, is accepted for
-        M2L when theta |z_A - z_B| > r_A + r_B (z the cell centres, r the enclosing radii), the two
-        cells are not adjacent (Chebyshev distance >= 2: Thole-damped pairs, closer than a leaf edge,
-        stay in the direct part), they hold at least ndirect particles together and, with
-        leaf_direct, they are not leaves (the paper's direct interaction of small or leaf pairs);
-        otherwise the pair is split into the pairs of their children, and a pair of leaves that is
-        not accepted goes to the direct part.  The children of a pair below ndirect hold fewer
-        particles still, so all of its descendants are direct.  The walk starts from the root paired
-        with itself, so every ordered pair of particles is counted once.
-        Returns (m2l, near): m2l[l] the (B, A) pairs accepted at level l, near the (B, A) leaf pairs."""
-        renc = self.enclosing_radii(X)
-        count = [dict() for _ in range(self.L + 1)]
-        for cc, idx in self.leaves.items():
-            for l in range(self.L + 1):
-                sh = self.L - l
-                c = (cc[0] >> sh, cc[1] >> sh, cc[2] >> sh)
-                count[l][c] = count[l].get(c, 0) + len(idx)
+    def refined_cells(self, leaf_max):
+        """The split cells of the adaptive octree, per level: the octree form of the paper's adaptive
+        tree, whose recursion stops once a cell holds no more than N_bucket particles (Sec. III).
+
+        A cell of a level below L is split when it holds more than leaf_max particles.  The tree is
+        then 2:1 balanced over the full octree, empty cells included (a reading: the paper's kd-tree
+        needs no balance): a cell of level l whose closed box touches the box of a split cell of
+        level l + 1 is split as well, until nothing changes, so two leaves that touch differ by at
+        most one level.  A cell that is not split, and every cell below it, is terminal; the top-most
+        terminal cells are the adaptive leaves."""
+        R = [set() for _ in range(self.L + 1)]
+        for l in range(self.L):
+            for c in self.cells[l]:
+                if len(self._mem[l][c]) > leaf_max:
+                    R[l].add(c)
+        changed = True
+        while changed:
+            changed = False
+            for l in range(self.L - 1, -1, -1):
+                if not R[l + 1]:
+                    continue
+                fine = np.array(sorted(R[l + 1]), np.int64)
+                for B in self.cells[l]:
+                    if B in R[l]:
+                        continue
+                    # B spans [2 B, 2 B + 2] in units of the finer level, a cell c spans [c, c + 1]
+                    lo = 2 * np.asarray(B, np.int64)
+                    if np.any(np.all((fine + 1 >= lo) & (fine <= lo + 2), axis=1)):
+                        R[l].add(B)
+                        changed = True
+        return R
+
+    def walk_lists(self, X, theta=None, ndirect=0, leaf_direct=False, leaf_max=0):
+        """Interaction lists of a dual tree walk over pairs of cells of one level (Sec. III), from the
+        root paired with itself, so that every ordered pair of particles is counted once.
+
+        Acceptance for M2L, of a pair of distinct cells that hold at least ndirect particles together
+        (and, with leaf_direct, are not both terminal: the paper's direct interaction of leaf pairs):
+          * theta None: the cells are farther apart than ws (Chebyshev distance of their coordinates
+            > ws), the well-separation rule;
+          * theta: the paper's multipole acceptance criterion (eq:mac), theta |z_A - z_B| > r_A + r_B
+            with z the cell centres and r the enclosing radii, for cells that are not adjacent
+            (Chebyshev distance >= 2: Thole-damped pairs, closer than a leaf edge, stay direct).
+        A pair that is not accepted goes to the direct part when both cells are terminal, else it is
+        split into the pairs of the two cells' children.  Terminal cells: the leaf level L; with
+        leaf_max > 0 also every cell that the adaptive rule (refined_cells) does not split, and the
+        cells below it.  Below ndirect particles the children hold fewer still, so all of a pair's
+        descendants are direct.
+        Returns (m2l, near): m2l[l] the (B, A) pairs accepted at level l; near the (l, B, A) pairs of
+        cells whose particles are summed directly."""
+        renc = self.enclosing_radii(X) if theta is not None else None
+        R = self.refined_cells(leaf_max) if leaf_max > 0 else None
+
+        def terminal(l, c):
+            return l == self.L or (R is not None and c not in R[l])
+
         kids = [dict() for _ in range(self.L + 1)]
         for l in range(1, self.L + 1):
             for c in self.cells[l]:
@@ -367,22 +417,33 @@ class Octree:
         stack = [(0, (0, 0, 0), (0, 0, 0))]
         while stack:
             l, B, A = stack.pop()
-            if (A != B and self.cheb(A, B) >= 2 and count[l][B] + count[l][A] >= ndirect
-                    and not (leaf_direct and l == self.L)):
-                dist = float(self._length((np.asarray(B, np.float64) - np.asarray(A, np.float64)) * self.width(l))[0])
-                if theta * dist > renc[l][B] + renc[l][A]:
-                    m2l[l].append((B, A))
-                    continue
-            if l == self.L:
-                near.append((B, A))
-                continue
-            for b in kids[l][B]:
-                for a in kids[l][A]:
-                    stack.append((l + 1, b, a))
+            tB, tA = terminal(l, B), terminal(l, A)
+            accept = False
+            if (A != B and len(self._mem[l][B]) + len(self._mem[l][A]) >= ndirect
+                    and not (leaf_direct and tB and tA)):
+                if theta is None:
+                    accept = self.cheb(A, B) > self.ws
+                elif self.cheb(A, B) >= 2:
+                    dist = float(self._length((np.asarray(B, np.float64) - np.asarray(A, np.float64)) * self.width(l))[0])
+                    accept = theta * dist > renc[l][B] + renc[l][A]
+            if accept:
+                m2l[l].append((B, A))
+            elif tB and tA:
+                near.append((l, B, A))
+            else:
+                for b in kids[l][B]:
+                    for a in kids[l][A]:
+                        stack.append((l + 1, b, a))
         for lst in m2l:
             lst.sort()
         near.sort()
         return m2l, near
+
+    def mac_lists(self, X, theta, ndirect=0, leaf_direct=False):
+        """The lists of the paper's multipole acceptance criterion on this uniform-depth octree
+        (walk_lists with theta): (m2l, near) with near the (B, A) leaf pairs summed directly."""
+        m2l, near = self.walk_lists(X, theta, ndirect, leaf_direct)
+        return m2l, sorted((B, A) for _, B, A in near)
 
 
 # ----------------------------------------------------------------------------------------------
@@ -390,7 +451,7 @@ class Octree:
 # ----------------------------------------------------------------------------------------------
 
 def fmm_fields(X, q, mu, alpha, thole_a, p, leaf_width, ws=1, want_grad=True, order_slack=-1,
-               pair_dl=0.0, excl=None, theta=None, ndirect=0, leaf_direct=False):
+               pair_dl=0.0, excl=None, theta=None, ndirect=0, leaf_direct=False, leaf_max=0):
     """FMM fields of charges q and point dipoles mu at every particle.
 
     pair_dl > 0 builds the multipoles of the dipoles from their +/- q^mu pairs (Sec. II.C, p2m_pair)
@@ -398,8 +459,13 @@ def fmm_fields(X, q, mu, alpha, thole_a, p, leaf_width, ws=1, want_grad=True, or
     excl: excluded pairs (direct.exclusion_matrix); the exact terms of each excluded pair are taken
     off the result, wherever the pair was counted (near field, or M2L to within its truncation).
     theta: the interaction lists of the paper's dual tree walk with its acceptance criterion
-    (Octree.mac_lists, with ndirect and leaf_direct) instead of the well-separation lists; the M2L
+    (Octree.walk_lists, with ndirect and leaf_direct) instead of the well-separation lists; the M2L
     then runs at order p.
+    leaf_max > 0: the adaptive octree (Octree.refined_cells): the walk stops at pairs of terminal
+    cells, whose particles are summed directly, with the well-separation rule of ws (theta None) or
+    the acceptance criterion; every M2L at order p.  The expansions of the cells below an adaptive
+    leaf (P2M at the leaf level, M2M, L2L and L2P there) are the exact translations of the leaf's
+    own, so they serve the interactions with finer neighbours at the finer levels.
 
     Returns a dict with
       phi  total potential (undamped),
@@ -435,9 +501,11 @@ def fmm_fields(X, q, mu, alpha, thole_a, p, leaf_width, ws=1, want_grad=True, or
     # transfer
     nm = m2l_matrix(p)
     F = [dict() for _ in range(L + 1)]
-    mac = tree.mac_lists(X, theta, ndirect, leaf_direct) if theta is not None else None
+    walk = None
+    if theta is not None or leaf_max > 0:
+        walk = tree.walk_lists(X, theta, ndirect, leaf_direct, leaf_max)
     for l in range(1, L + 1):
-        pairs = mac[0][l] if mac is not None else tree.m2l_pairs(l)
+        pairs = walk[0][l] if walk is not None else tree.m2l_pairs(l)
         for s in range(0, len(pairs), 256):
             chunk = pairs[s:s + 256]
             R = np.array([tree.centre(l, B) - tree.centre(l, A) for B, A in chunk])
@@ -466,8 +534,8 @@ def fmm_fields(X, q, mu, alpha, thole_a, p, leaf_width, ws=1, want_grad=True, or
 
     # near field, direct with point dipoles
     E_u = E_far.copy(); E_d = E_far.copy(); G_d = G_far.copy()
-    for B, A in (mac[1] if mac is not None else tree.near_pairs()):
-        ib = tree.leaves[B]; ia = tree.leaves[A]
+    for l, B, A in (walk[1] if walk is not None else [(L, B, A) for B, A in tree.near_pairs()]):
+        ib = tree.members(l, B); ia = tree.members(l, A)
         for i in ib:
             src = [j for j in ia if j != i]
             if not src:
