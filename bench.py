@@ -118,6 +118,9 @@ def parse():
                     help="with --theta: cell pairs holding fewer particles together are summed directly")
     ap.add_argument("--leaf-direct", type=int, default=1, choices=[0, 1],
                     help="with --theta: leaf pairs are always summed directly")
+    ap.add_argument("--leaf-max", type=int, default=0,
+                    help="the adaptive octree: cells above the finest level split only when they hold more than "
+                         "this many particles (0: every leaf at the finest level); every M2L at order p")
     ap.add_argument("--oracle-sample", type=int, default=0,
                     help="targets of the sampled oracle check (0: about 2e9 / n, between 64 and 4096)")
     ap.add_argument("--no-split", action="store_true",
@@ -146,7 +149,7 @@ def main():
     for k in ("p", "ws", "leaf", "tol", "slack", "pc", "pc_iters", "relax"):
         if getattr(args, k) is not None:
             wl[k] = getattr(args, k)
-    if args.theta > 0.0:
+    if args.theta > 0.0 or args.leaf_max > 0:
         wl["slack"] = -1
     ps = inputs.make(wl["gen"])
     n = ps.n
@@ -178,7 +181,7 @@ def main():
                        m2l_order_slack=wl["slack"], precond_cutoff=wl["pc"], precond_iters=wl["pc_iters"],
                        scf_relax=wl["relax"], dipole_pair_dl=args.pair_dl, precision=prec, timing=timing,
                        dipole_tree=int(args.dipole_tree), mac_theta=args.theta, mac_ndirect=args.ndirect,
-                       mac_leaf_direct=args.leaf_direct)
+                       mac_leaf_direct=args.leaf_direct, adaptive_leaf_max=args.leaf_max)
         if pairs is not None:
             s.set_exclusions(n, pairs)
         return s
@@ -297,8 +300,8 @@ def main():
                 "avg_launch_ms": round(ms / nl, 4), "work_per_launch": work, "pairs": stats["n_p2p"],
                 "flops_per_pair": P2P_SCF_FLOPS_PER_PAIR}
 
-    if dominant == "m2l" and args.theta > 0.0:
-        # the M2L of the acceptance-criterion lists runs on the float64 matrix cores on both paths
+    if dominant == "m2l" and (args.theta > 0.0 or args.leaf_max > 0):
+        # the M2L of the dual-walk lists runs on the float64 matrix cores on both paths
         mr = m2l_roof(kst, PEAK["fp64_mfma"])
         roofline = {"bound": "mfma", "kernel": "m2l_mac", "achieved": mr["achieved"], "peak": PEAK["fp64_mfma"],
                     "unit": "TFLOP/s", "frac": mr["frac"], "traffic": None,
@@ -370,6 +373,7 @@ def main():
                    "dipole_solve_sites": int(r0["res"].stats["n_sites"]),
                    "mac_theta": args.theta, "mac_ndirect": args.ndirect if args.theta > 0 else None,
                    "mac_leaf_direct": args.leaf_direct if args.theta > 0 else None,
+                   "adaptive_leaf_max": args.leaf_max,
                    "m2l_pairs": int(r0["res"].stats["n_m2l"]), "near_pairs": int(r0["res"].stats["n_p2p"]),
                    "levels": r0["res"].stats["levels"],
                    "step": "solve (tree, charge field, dipole CG, energy, forces) + backward",

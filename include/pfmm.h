@@ -143,6 +143,21 @@ typedef struct pfmm_config {
                           direct interaction of small node pairs, about 64); 0 = no such rule      */
   int mac_leaf_direct; /* with mac_theta: 1 = pairs of leaves are always summed directly (the paper's
                           rule for two leaves), 0 = leaf pairs are accepted by the criterion too    */
+  int adaptive_leaf_max; /* 0: every leaf at the finest level (the default).  > 0: the adaptive
+                          octree, the octree form of the paper's adaptive tree whose recursion stops
+                          at N_bucket particles (Sec. III): a cell above the finest level (edge
+                          leaf_width) is split only when it holds more than this many particles, and
+                          the tree is 2:1 balanced over the full octree, empty cells included (a
+                          cell touching a split cell one level finer is split too, so touching
+                          leaves differ by at most one level).  The lists come from a dual tree walk
+                          over cell pairs of one level that sums two cells directly once both are
+                          terminal (a leaf or below one), with the well-separation rule of ws
+                          (mac_theta = 0; mac_ndirect and mac_leaf_direct unused) or the acceptance
+                          criterion.  The expansions of cells below a leaf are exact translations of
+                          the leaf's own and serve its interactions with finer neighbours.  Every
+                          M2L is at order p (m2l_order_slack must be -1, order_p at most 9) in
+                          float64; the Thole damping radius must not exceed ws leaf edges (leaf
+                          edges with mac_theta).                                                   */
 } pfmm_config;
 
 typedef struct pfmm_result {
@@ -189,7 +204,7 @@ typedef struct pfmm_handle pfmm_handle;
    scf_max_iter = 200, graph_iters = 4, thole_a = 2.0, coulomb_k = 332.06371,
    flags = WANT_FORCES | WANT_POTENTIALS | SAVE_FOR_BACKWARD, m2l_order_slack = -1,
    precond_cutoff = 0, precond_iters = 4, scf_relax = 0, dipole_pair_dl = 0, dipole_tree = 0,
-   mac_theta = 0, mac_ndirect = 64, mac_leaf_direct = 1. */
+   mac_theta = 0, mac_ndirect = 64, mac_leaf_direct = 1, adaptive_leaf_max = 0. */
 void pfmm_config_default(pfmm_config* cfg);
 
 /* Create a handle for a configuration.  Validates cfg, builds the constant operator tables of

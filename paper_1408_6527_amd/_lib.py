@@ -56,6 +56,7 @@ class Config(ctypes.Structure):
         ("mac_theta", ctypes.c_double),
         ("mac_ndirect", ctypes.c_int),
         ("mac_leaf_direct", ctypes.c_int),
+        ("adaptive_leaf_max", ctypes.c_int),
     ]
 
 

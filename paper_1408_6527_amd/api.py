@@ -32,7 +32,8 @@ def config(**kw) -> _lib.Config:
     Keywords: order_p, ws, leaf_width, precision ("fp64" | "mixed"), scf_tol, scf_max_iter,
     graph_iters, thole_a, coulomb_k, m2l_order_slack, precond_cutoff, precond_iters, scf_relax,
     dipole_pair_dl, dipole_tree (0 | 1), mac_theta (0, or the acceptance parameter in [0.3, 1)),
-    mac_ndirect, mac_leaf_direct (0 | 1),
+    mac_ndirect, mac_leaf_direct (0 | 1), adaptive_leaf_max (0, or the particles above which a cell
+    of the adaptive octree is split),
     forces (bool), potentials (bool), save_for_backward (bool), warm_start (bool), timing (bool).
     """
     c = _lib.Config()

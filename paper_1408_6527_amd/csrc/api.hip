@@ -7,7 +7,7 @@
 //             dipoles per iteration                                             (solver.hip)
 //   stage 3   field of the converged dipoles, energy, forces, un-permutation
 // An FMM pass is P2M -> M2M (up) -> M2L -> L2L (down) -> L2P, plus P2P over colleague leaves; with
-// mac_theta the M2L and P2P run from the lists of the acceptance-criterion walk (mac.hip).
+// mac_theta or adaptive_leaf_max the M2L and P2P run from the lists of the dual tree walk (mac.hip).
 #include <algorithm>
 #include <array>
 #include <chrono>
@@ -252,13 +252,15 @@ struct pfmm_handle {
   int64_t n_m2l = 0, n_p2p = 0, m2l_flops = 0;
   int64_t m2l_flops_cap[11] = {};  // useful M2L flops per evaluation with every order capped at c
   int n_evals = 0;
-  // acceptance-criterion lists (mac_theta > 0): operator rows of the offsets in
-  // [-(2 Rp + 1), 2 Rp + 1]^3, enclosing radii, split partners, the frontier pairs of the walk and
-  // their prefix sums, the near pairs and their rows sorted by target
+  // lists of the dual tree walk (mac_theta > 0 or adaptive_leaf_max > 0): operator rows of the offsets
+  // in [-(2 Rp + 1), 2 Rp + 1]^3, enclosing radii, split partners, the frontier pairs of the walk and
+  // their prefix sums, the near pairs and their rows sorted by target; on the adaptive octree the
+  // split flags of the cells and the level-L cells below each cell
   bool mac = false;
+  int leaf_max = 0;
   MacView mv;
   DevBuf t_mdvec, m_renc, m_split, m_bad, m_acc, m_kid, m_accs, m_kids, m_stmp, m_stmp2, m_nt, m_ns, m_sort_tmp,
-      m_cnt, m_nkout, m_nvout, m_nptr;
+      m_cnt, m_nkout, m_nvout, m_nptr, m_nearc, m_nears, m_nonleaf, m_lfirst, m_lcount;
   DevBuf m_fr[2];
 };
 
@@ -322,10 +324,13 @@ void validate_config(const pfmm_config* c) {
   if (c->mac_ndirect < 0) throw Error(PFMM_ERR_INVALID_ARG, "mac_ndirect must be >= 0");
   if (c->mac_leaf_direct != 0 && c->mac_leaf_direct != 1)
     throw Error(PFMM_ERR_INVALID_ARG, "mac_leaf_direct must be 0 or 1");
-  if (c->mac_theta > 0.0 && c->order_p > MAX_P_MAC)
-    throw Error(PFMM_ERR_INVALID_ARG, "mac_theta supports order_p up to " + std::to_string(MAX_P_MAC));
-  if (c->mac_theta > 0.0 && c->m2l_order_slack >= 0)
-    throw Error(PFMM_ERR_INVALID_ARG, "mac_theta runs every M2L at order p: m2l_order_slack must be -1");
+  if (c->adaptive_leaf_max < 0) throw Error(PFMM_ERR_INVALID_ARG, "adaptive_leaf_max must be >= 0");
+  const bool walk = c->mac_theta > 0.0 || c->adaptive_leaf_max > 0;
+  if (walk && c->order_p > MAX_P_MAC)
+    throw Error(PFMM_ERR_INVALID_ARG, "mac_theta and adaptive_leaf_max support order_p up to " + std::to_string(MAX_P_MAC));
+  if (walk && c->m2l_order_slack >= 0)
+    throw Error(PFMM_ERR_INVALID_ARG,
+                "mac_theta and adaptive_leaf_max run every M2L at order p: m2l_order_slack must be -1");
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -366,9 +371,9 @@ void build_tree(pfmm_handle* h, int n, const double* pos, const double* q, const
     extent = std::max(extent, hi[a] - lo[a]);
   }
   const double alpha_max = hb.bb[6];
-  // leaves whose pairs are always summed directly: within ws, or the adjacent ones of the
-  // acceptance-criterion walk
-  const int reach = h->mac ? 1 : c.ws;
+  // leaves whose pairs are always summed directly: within ws, or below the separation that the dual
+  // tree walk accepts (adjacent with the criterion, within ws with the ws rule)
+  const int reach = h->mac ? h->mv.minsep - 1 : c.ws;
   const double s_max = c.thole_a * std::cbrt(alpha_max);  // a (alpha_max^2)^(1/6)
   double w = c.leaf_width;
   if (w == 0.0) {
@@ -382,8 +387,8 @@ void build_tree(pfmm_handle* h, int n, const double* pos, const double* q, const
   if (s_max > reach * w)
     throw Error(PFMM_ERR_INVALID_ARG,
                 "Thole damping radius " + std::to_string(s_max) + " exceeds the near-field range " +
-                    (h->mac ? std::string("leaf_width = ") : std::string("ws * leaf_width = ")) +
-                    std::to_string(reach * w) + "; increase leaf_width" + (h->mac ? "" : " or ws"));
+                    (reach == 1 ? std::string("leaf_width = ") : std::string("ws * leaf_width = ")) +
+                    std::to_string(reach * w) + "; increase leaf_width" + (h->mv.use_theta && h->mac ? "" : " or ws"));
   int L = 0;
   while (w * std::ldexp(1.0, L) < extent * (1.0 + std::ldexp(1.0, -20))) {
     ++L;
@@ -524,16 +529,37 @@ void set_m2l_split(pfmm_handle* h) {
   }
 }
 
-// The acceptance-criterion walk (mac.hip) for the tree in h->tv: the split partners of every cell of
-// levels < L (h->mv.split, read by the M2L), each leaf's near row (h->tv.nptr / nidx) and the pair
-// statistics.  One synchronisation per level reads the sizes of the next frontier.
+// The dual tree walk (mac.hip) for the tree in h->tv, with the acceptance criterion or, on the
+// adaptive octree, the ws rule: the split flags of the adaptive cells, the split partners of every
+// cell of levels < L (h->mv.split, read by the M2L), each leaf's near row (h->tv.nptr / nidx: source
+// cells of any level) and the pair statistics.  One synchronisation per level reads the sizes of the
+// next frontier and of the level's near entries.
 void build_mac_lists(pfmm_handle* h, hipStream_t s) {
   TreeView& t = h->tv;
   MacView& mv = h->mv;
   const int L = t.L, ncell = t.ncell;
-  double* renc = dev<double>(h->m_renc, ncell);
-  for (int l = 0; l <= L; ++l) launch_mac_radii(t, h->pa.P, l, renc, s);
-  mv.renc = renc;
+  mv.renc = nullptr;
+  if (mv.use_theta) {
+    double* renc = dev<double>(h->m_renc, ncell);
+    for (int l = 0; l <= L; ++l) launch_mac_radii(t, h->pa.P, l, renc, s);
+    mv.renc = renc;
+  }
+  mv.nonleaf = mv.lfirst = mv.lcount = nullptr;
+  if (h->leaf_max > 0) {
+    // the adaptive octree: over-full cells split, then the 2:1 balance from the finest level up (a
+    // cell's flag is final once the level below it is done)
+    int* nonleaf = dev<int>(h->m_nonleaf, ncell);
+    int* lfirst = dev<int>(h->m_lfirst, ncell);
+    int* lcount = dev<int>(h->m_lcount, ncell);
+    for (int l = 0; l <= L; ++l) {
+      launch_adapt_init(t, l, h->leaf_max, nonleaf, s);
+      launch_leaf_range(t, l, lfirst, lcount, s);
+    }
+    for (int l = L - 1; l >= 0; --l) launch_adapt_balance(t, l, nonleaf, s);
+    mv.nonleaf = nonleaf;
+    mv.lfirst = lfirst;
+    mv.lcount = lcount;
+  }
   const int side = 2 * mv.Rp + 1, nn = side * side * side;
   int* split = dev<int>(h->m_split, (int64_t)std::max(t.off[L], 1) * nn);
   launch_fill_int(split, (int64_t)std::max(t.off[L], 1) * nn, -1, s);
@@ -543,48 +569,83 @@ void build_mac_lists(pfmm_handle* h, hipStream_t s) {
   int cur = 0;
   int2* fr = dev<int2>(h->m_fr[cur], 1);
   launch_fill_int(reinterpret_cast<int*>(fr), 2, 0, s);  // (root, root)
-  int64_t nfr = 1, nm = 0;
-  int nnear = 0;
-  int* near_t = nullptr;
-  int* near_s = nullptr;
+  int64_t nfr = 1, nm = 0, nnear = 0;
+  // near entries of all levels, appended level by level: the buffers start at a guess and grow
+  // keeping their contents (from the scratch array during an allocation-free call)
+  {
+    const int64_t guess = std::max<int64_t>(1024, 32LL * (t.off[L + 1] - t.off[L]));
+    dev<int>(h->m_nt, guess);
+    dev<int>(h->m_ns, guess);
+  }
+  auto near_room = [&](int64_t want) {
+    const size_t b = (size_t)want * sizeof(int);
+    if (b <= h->m_nt.bytes && b <= h->m_ns.bytes) return;
+    DevBuf nt2, ns2;
+    int* a = dev<int>(nt2, 2 * want);
+    int* c = dev<int>(ns2, 2 * want);
+    if (nnear > 0) {
+      PFMM_HIP(hipMemcpyAsync(a, h->m_nt.ptr, (size_t)nnear * sizeof(int), hipMemcpyDeviceToDevice, s));
+      PFMM_HIP(hipMemcpyAsync(c, h->m_ns.ptr, (size_t)nnear * sizeof(int), hipMemcpyDeviceToDevice, s));
+    }
+    PFMM_HIP(hipStreamSynchronize(s));  // the old buffers may be released below
+    if (g_arena) {
+      h->m_nt.borrow(a, nt2.bytes);
+      h->m_ns.borrow(c, ns2.bytes);
+      return;
+    }
+    for (auto [dst, src] : {std::pair<DevBuf*, DevBuf*>{&h->m_nt, &nt2}, {&h->m_ns, &ns2}}) {
+      std::swap(dst->own, src->own);
+      std::swap(dst->own_bytes, src->own_bytes);
+      dst->ptr = dst->own;
+      dst->bytes = dst->own_bytes;
+      src->ptr = src->own;
+      src->bytes = src->own_bytes;
+    }
+  };
   for (int l = 0; l <= L; ++l) {
     // the child pairs of a split pair are at most 64; the prefix sums are 32-bit
     if (l < L && nfr * 64 > INT_MAX)
-      throw Error(PFMM_ERR_INVALID_ARG, "acceptance-criterion lists too large (" + std::to_string(nfr) +
+      throw Error(PFMM_ERR_INVALID_ARG, "dual-walk lists too large (" + std::to_string(nfr) +
                                             " cell pairs at level " + std::to_string(l) +
-                                            "); raise leaf_width or mac_theta");
+                                            "); raise leaf_width, mac_theta or adaptive_leaf_max");
     const int nf = (int)nfr;
     int* acc = dev<int>(h->m_acc, nf);
     int* kid = dev<int>(h->m_kid, nf);
+    int* nearc = dev<int>(h->m_nearc, nf);
     int* accs = dev<int>(h->m_accs, nf);
     int* kids = dev<int>(h->m_kids, nf);
-    launch_mac_classify(t, mv, l, fr, nf, acc, kid, s);
+    int* nears = dev<int>(h->m_nears, nf);
+    launch_mac_classify(t, mv, l, fr, nf, acc, kid, nearc, s);
     const size_t tb = scan_temp_bytes(nf);
     void* tmp = raw(h->m_stmp, tb);
     launch_inclusive_scan(tmp, tb, acc, accs, nf, s);
     launch_inclusive_scan(tmp, tb, kid, kids, nf, s);
-    int tot[2];
+    launch_inclusive_scan(tmp, tb, nearc, nears, nf, s);
+    int tot[3];
     void* pin = h->pinned.get(sizeof(tot));
     PFMM_HIP(hipMemcpyAsync(pin, accs + (nf - 1), sizeof(int), hipMemcpyDeviceToHost, s));
     PFMM_HIP(hipMemcpyAsync((char*)pin + sizeof(int), kids + (nf - 1), sizeof(int), hipMemcpyDeviceToHost, s));
+    PFMM_HIP(hipMemcpyAsync((char*)pin + 2 * sizeof(int), nears + (nf - 1), sizeof(int), hipMemcpyDeviceToHost, s));
     PFMM_HIP(hipStreamSynchronize(s));
     std::memcpy(tot, pin, sizeof(tot));
     nm += tot[0];
-    int2* next = nullptr;
-    if (l == L) {
-      nnear = tot[1];
-      near_t = dev<int>(h->m_nt, nnear);
-      near_s = dev<int>(h->m_ns, nnear);
-    } else {
-      next = dev<int2>(h->m_fr[cur ^ 1], tot[1]);
-    }
-    launch_mac_emit(t, mv, l, fr, nf, accs, kids, next, split, near_t, near_s, bad, s);
+    if (l == L && tot[1] != 0) throw Error(PFMM_ERR_HIP, "internal: the walk split a pair of leaves");
+    if (nnear + tot[2] > INT_MAX) throw Error(PFMM_ERR_INVALID_ARG, "dual-walk near list too large");
+    near_room(std::max<int64_t>(nnear + tot[2], 1));
+    int2* next = l < L ? dev<int2>(h->m_fr[cur ^ 1], tot[1]) : nullptr;
+    launch_mac_emit(t, mv, l, fr, nf, kids, nears, next, split, h->m_nt.as<int>() + nnear,
+                    h->m_ns.as<int>() + nnear, bad, s);
+    nnear += tot[2];
     if (l < L) {
       fr = next;
       nfr = tot[1];
       cur ^= 1;
+      if (nfr == 0) break;
     }
   }
+  int* near_t = h->m_nt.as<int>();
+  int* near_s = h->m_ns.as<int>();
+  const int nnear_i = (int)nnear;
   int badh = 0;
   sync_read(h, bad, &badh, sizeof(int), s);
   if (badh) throw Error(PFMM_ERR_INVALID_ARG, "internal: a split cell pair lies beyond the partner table");
@@ -593,15 +654,15 @@ void build_mac_lists(pfmm_handle* h, hipStream_t s) {
   int bits = 1;
   while ((1LL << bits) <= (int64_t)ncell) ++bits;
   const int nleaf = t.off[L + 1] - t.off[L];
-  int* nkey = dev<int>(h->m_nkout, nnear);
-  int* nsrc = dev<int>(h->m_nvout, nnear);
-  const size_t sortb = mac_sort_temp_bytes(nnear, bits);
-  launch_mac_sort(raw(h->m_sort_tmp, sortb), sortb, near_t, nkey, near_s, nsrc, nnear, bits, s);
+  int* nkey = dev<int>(h->m_nkout, nnear_i);
+  int* nsrc = dev<int>(h->m_nvout, nnear_i);
+  const size_t sortb = mac_sort_temp_bytes(nnear_i, bits);
+  launch_mac_sort(raw(h->m_sort_tmp, sortb), sortb, near_t, nkey, near_s, nsrc, nnear_i, bits, s);
   int* nptr = dev<int>(h->m_nptr, (int64_t)nleaf + 1);
   launch_fill_int(nptr, (int64_t)nleaf + 1, 0, s);
   int* cnt = dev<int>(h->m_cnt, nleaf);
   launch_fill_int(cnt, nleaf, 0, s);
-  launch_mac_count(nkey, nnear, t.off[L], cnt, s);
+  launch_mac_count(nkey, nnear_i, t.off[L], cnt, s);
   const size_t scanb = scan_temp_bytes(nleaf);
   launch_inclusive_scan(raw(h->m_stmp2, scanb), scanb, cnt, nptr + 1, nleaf, s);
   t.nptr = nptr;
@@ -609,7 +670,7 @@ void build_mac_lists(pfmm_handle* h, hipStream_t s) {
 
   unsigned long long* pairs = dev<unsigned long long>(h->w_stats, 1);
   launch_fill_int(reinterpret_cast<int*>(pairs), 2, 0, s);
-  launch_mac_near_pairs(t, nkey, nsrc, nnear, pairs, s);
+  launch_mac_near_pairs(t, nkey, nsrc, nnear_i, pairs, s);
   unsigned long long np = 0;
   sync_read(h, pairs, &np, sizeof(np), s);
   h->n_m2l = nm;
@@ -1158,6 +1219,7 @@ void pfmm_config_default(pfmm_config* c) {
   c->mac_theta = 0.0;
   c->mac_ndirect = 64;
   c->mac_leaf_direct = 1;
+  c->adaptive_leaf_max = 0;
 }
 
 pfmm_status pfmm_create(const pfmm_config* cfg, pfmm_handle** out) {
@@ -1195,17 +1257,30 @@ pfmm_status pfmm_create(const pfmm_config* cfg, pfmm_handle** out) {
     op.hidx = h->t_hidx.as<unsigned short>();
     op.dorder = h->t_dorder.as<unsigned char>();
     op.nblocks = T.nblocks;
-    if (cfg->mac_theta > 0.0) {
-      // a split pair whose children can be accepted failed the criterion (or was adjacent): its
-      // offset D has |D| <= (r_A + r_B) / (theta w) <= sqrt(3) / theta, as every particle of a cell
-      // lies within sqrt(3) w / 2 of its centre; the child offsets 2 D + (o_B - o_A) then lie within
-      // 2 Rp + 1, the radius of the operator table
+    if (cfg->mac_theta > 0.0 || cfg->adaptive_leaf_max > 0) {
       h->mac = true;
+      h->leaf_max = cfg->adaptive_leaf_max;
       MacView& mv = h->mv;
-      mv.theta = cfg->mac_theta;
-      mv.ndirect = cfg->mac_ndirect;
-      mv.leaf_direct = cfg->mac_leaf_direct;
-      mv.Rp = std::max(1, (int)std::floor(std::sqrt(3.0) / cfg->mac_theta * (1.0 + 1e-9)));
+      if (cfg->mac_theta > 0.0) {
+        // a split pair whose children can be accepted failed the criterion (or was adjacent): its
+        // offset D has |D| <= (r_A + r_B) / (theta w) <= sqrt(3) / theta, as every particle of a cell
+        // lies within sqrt(3) w / 2 of its centre; the child offsets 2 D + (o_B - o_A) then lie within
+        // 2 Rp + 1, the radius of the operator table
+        mv.use_theta = 1;
+        mv.minsep = 2;
+        mv.theta = cfg->mac_theta;
+        mv.ndirect = cfg->mac_ndirect;
+        mv.leaf_direct = cfg->mac_leaf_direct;
+        mv.Rp = std::max(1, (int)std::floor(std::sqrt(3.0) / cfg->mac_theta * (1.0 + 1e-9)));
+      } else {
+        // the ws rule on the adaptive octree: split pairs lie within ws, accepted ones beyond
+        mv.use_theta = 0;
+        mv.minsep = cfg->ws + 1;
+        mv.theta = 0.0;
+        mv.ndirect = 0;
+        mv.leaf_direct = 0;
+        mv.Rp = cfg->ws;
+      }
       upload(h->t_mdvec, mac_operator_rows(T, 2 * mv.Rp + 1));
       mv.dvec = h->t_mdvec.as<double>();
     }

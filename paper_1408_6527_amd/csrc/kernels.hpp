@@ -153,40 +153,60 @@ void launch_exclusions(const Particles& pa, const int* perm, const int* inv, con
 void launch_inverse_perm(const int* perm, int n, int* inv, hipStream_t s);
 
 // ---------------------------------------------------------------- mac.hip
-// The acceptance-criterion walk: the criterion's parameters, the cells' enclosing radii, and for every
-// cell of levels < L the partners of its split pairs (the pairs whose children the walk examined):
-// split[B (2 Rp + 1)^3 + slot(A - B)] = A, -1 elsewhere, the offsets of split pairs that can have
-// accepted children lying in [-Rp, Rp]^3.  The M2L kernel runs over these like the colleagues of the
-// ws lists and applies the criterion to the children (mac.hpp); dvec holds D_k(d) at unit cell width
-// for every offset in [-(2 Rp + 1), 2 Rp + 1]^3 at the row pitch of the M2L tables.
+// The lists of the dual tree walk: the acceptance rule's parameters, the cells' enclosing radii, and
+// for every cell of levels < L the partners of its split pairs (the pairs whose children the walk
+// examined): split[B (2 Rp + 1)^3 + slot(A - B)] = A, -1 elsewhere, the offsets of split pairs that
+// can have accepted children lying in [-Rp, Rp]^3.  The M2L kernel runs over these like the
+// colleagues of the ws lists and applies the rule to the children (mac.hpp); dvec holds D_k(d) at
+// unit cell width for every offset in [-(2 Rp + 1), 2 Rp + 1]^3 at the row pitch of the M2L tables.
+// Acceptance of two distinct cells of one level at Chebyshev distance >= minsep holding at least
+// ndirect particles together (with leaf_direct, not both terminal): with use_theta the criterion
+// theta |z_B - z_A| > r_B + r_A (minsep 2), otherwise nothing more (the ws rule, minsep ws + 1).
+// Adaptive octree (nonleaf != NULL): nonleaf[c] = 1 for the cells that are split (the others, and
+// all cells of level L, are terminal), and lfirst[c] / lcount[c] the range of the level-L cells
+// below c; a pair of terminal cells that is not accepted is summed directly at any level.  Without
+// it, only the cells of level L are terminal.
 struct MacView {
   double theta = 0.0;
+  int use_theta = 1, minsep = 2;
   int ndirect = 0, leaf_direct = 0, Rp = 0;
   const double* renc = nullptr;
   const int* split = nullptr;
   const double* dvec = nullptr;
+  const int* nonleaf = nullptr;
+  const int* lfirst = nullptr;
+  const int* lcount = nullptr;
 };
 // enclosing radius of every cell of a level: the largest distance from its centre to its particles
 void launch_mac_radii(const TreeView& t, const double4* P, int level, double* renc, hipStream_t s);
 // one level of the walk over the frontier pairs fr (target, source) of level l:
-// classify: acc[i] = 1 if the pair is accepted for M2L (never below ndirect particles together, nor
-// at the leaf level with leaf_direct); kid[i] = its child pairs (l < L) or 1 if it goes to the near
-// list (l = L), 0 otherwise;
-// emit (from the inclusive prefix sums of acc and kid): child pairs to next and the split table's
-// entries (l < L), or near pairs to near_tgt / near_src (l = L); *bad |= 1 for a split pair whose
-// children could be accepted outside [-Rp, Rp]^3 (which the bound on the radii rules out)
+// classify: acc[i] = 1 if the pair is accepted for M2L; otherwise, when both cells are terminal,
+// nearc[i] = the near-list entries it makes (one per level-L cell below the target, each paired with
+// the source cell), else kid[i] = its child pairs; the other two are 0;
+// emit (from the inclusive prefix sums of kid and nearc): child pairs to next and the split
+// table's entries, near entries to near_tgt / near_src (level-L target, source cell of level l);
+// *bad |= 1 for a split pair whose children could be accepted outside [-Rp, Rp]^3 (which the bound
+// on the radii rules out)
 void launch_mac_classify(const TreeView& t, const MacView& mv, int level, const int2* fr, int nfr, int* acc, int* kid,
-                         hipStream_t s);
-void launch_mac_emit(const TreeView& t, const MacView& mv, int level, const int2* fr, int nfr, const int* acc_scan,
-                     const int* kid_scan, int2* next, int* split, int* near_tgt, int* near_src, int* bad,
+                         int* nearc, hipStream_t s);
+void launch_mac_emit(const TreeView& t, const MacView& mv, int level, const int2* fr, int nfr, const int* kid_scan,
+                     const int* near_scan, int2* next, int* split, int* near_tgt, int* near_src, int* bad,
                      hipStream_t s);
+// Adaptive octree: nonleaf[c] = 1 for the cells of level < L holding more than leaf_max particles
+// (one launch per level), then, from level L - 1 up to 0, every cell of level l touching a split
+// cell of level l + 1 is split (2:1 balance over the full octree); lfirst / lcount: the level-L cells
+// below each cell of a level
+void launch_adapt_init(const TreeView& t, int level, int leaf_max, int* nonleaf, hipStream_t s);
+void launch_adapt_balance(const TreeView& t, int level, int* nonleaf, hipStream_t s);
+void launch_leaf_range(const TreeView& t, int level, int* lfirst, int* lcount, hipStream_t s);
 // stable sort of (key, value) int pairs by key over the low end_bit bits
 size_t mac_sort_temp_bytes(int n, int end_bit);
 void launch_mac_sort(void* tmp, size_t tmp_bytes, const int* kin, int* kout, const int* vin, int* vout, int n,
                      int end_bit, hipStream_t s);
 // counts per key (keys - key0 in [0, nkey)), added to cnt
 void launch_mac_count(const int* keys, int n, int key0, int* cnt, hipStream_t s);
-// ordered near-field particle pairs of the near list (i != j), added to *pairs
+// ordered near-field particle pairs of the near list (i != j; the target cell may lie inside the
+// source cell), added to *pairs
 void launch_mac_near_pairs(const TreeView& t, const int* near_tgt, const int* near_src, int n,
                            unsigned long long* pairs, hipStream_t s);
 

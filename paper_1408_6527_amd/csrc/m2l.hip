@@ -172,10 +172,11 @@ __device__ __forceinline__ void m2l_slot(int q, const kt* Dv, const kt* Bp, cons
 template <int P, bool F32>
 constexpr int m2l_waves_per_eu() { return 2; }
 
-// MAC: the lists of the acceptance-criterion walk.  The split partners of each parent (mv.split, at
-// offsets e in [-Rp, Rp]^3) take the place of its colleagues, the operator rows come from mv.dvec,
-// and every (target, source) column of a slot is tested with the criterion (mac.hpp); the columns
-// of pairs that are not accepted multiply zero source coefficients.  Every M2L at order P or the cap.
+// MAC: the lists of the dual tree walk (the acceptance criterion, or the ws rule on the adaptive
+// octree).  The split partners of each parent (mv.split, at offsets e in [-Rp, Rp]^3) take the place
+// of its colleagues, the operator rows come from mv.dvec, and every (target, source) column of a slot
+// is tested with the walk's acceptance rule (mac.hpp); the columns of pairs that are not accepted
+// multiply zero source coefficients.  Every M2L at order P or the cap.
 template <int P, bool F32, bool MAC>
 __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(m2l_waves_per_eu<P, F32>()))) void k_m2l(TreeView t, OpTables op, MacView mv, int lp_lo, int lp_hi, int nsplit,
                                              const double* __restrict__ M, const float* __restrict__ M32,
@@ -254,6 +255,7 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(m2l_waves_p
   // ws lists: colleagues within ws; MAC: split partners within Rp.  Offsets d = u - 2 e of a slot
   // then lie within R = 2 ws + 1 (or 2 Rp + 1), the radius of the operator table.
   const int ws = MAC ? mv.Rp : t.ws, side = 2 * ws + 1, nn = MAC ? side * side * side : t.nnear;
+  const int near_r = MAC ? mv.minsep - 1 : ws;  // offsets within this Chebyshev distance never interact
   const int* colls = MAC ? mv.split : t.coll;
   const int R = 2 * ws + 1, cube = 2 * R + 1;
   const kt* dtab;
@@ -369,7 +371,7 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(m2l_waves_p
             if (src < 0) continue;
             const int d0 = ((o >> 2) & 1) - ((rr >> 2) & 1) - 2 * e0, d1 = ((o >> 1) & 1) - ((rr >> 1) & 1) - 2 * e1,
                       d2 = (o & 1) - (rr & 1) - 2 * e2;
-            if (mac_accept(t, mv.renc, mv.theta, mv.ndirect, wt, tg, src, d0, d1, d2)) bits |= 1u << rr;
+            if (mac_accept(t, mv, wt, tg, src, d0, d1, d2)) bits |= 1u << rr;
           }
         }
         sMask[o][c] = (unsigned char)bits;
@@ -380,7 +382,7 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(m2l_waves_p
     for (int e = threadIdx.x; e < NU * DP; e += TPB) {
       const int v = e / DP, k = e - v * DP;
       const int d0 = v / 9 - 1 - 2 * e0, d1 = (v / 3) % 3 - 1 - 2 * e1, d2 = v % 3 - 1 - 2 * e2;
-      if (max(abs(d0), max(abs(d1), abs(d2))) > (MAC ? 1 : ws)) {
+      if (max(abs(d0), max(abs(d1), abs(d2))) > near_r) {
         // D_k(d) for |k| <= q(d), zero above: the M2L truncated at order q(d)
         const int slot = ((d0 + R) * cube + (d1 + R)) * cube + (d2 + R);
         const int q = MAC ? min(P, qc) : min((int)op.dorder[slot], qc);
@@ -406,7 +408,7 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(m2l_waves_p
       auto octant_slot = [&](acc_t(&acc)[NCB][NLOC], int o, bool act) {
         const int u0 = ((o >> 2) & 1) - ((r >> 2) & 1), u1 = ((o >> 1) & 1) - ((r >> 1) & 1), u2 = (o & 1) - (r & 1);
         const int d0 = u0 - 2 * e0, d1 = u1 - 2 * e1, d2 = u2 - 2 * e2;
-        if (act && max(abs(d0), max(abs(d1), abs(d2))) > (MAC ? 1 : ws)) {  // wave-uniform
+        if (act && max(abs(d0), max(abs(d1), abs(d2))) > near_r) {  // wave-uniform
           bool bm[NCB];
           bool run = true;
           if constexpr (MAC) {
@@ -503,7 +505,7 @@ void m2l_dispatch(const TreeView& t, const OpTables& op, int nsplit, const doubl
         hipLaunchKernelGGL((k_m2l<P, false, true>), dim3(nt * nsplit), dim3(TPB), 0, s, t, op, *mac, 1, hi, nsplit,
                            M, M32, F, split_stride, done, qcap);
     } else {
-      throw Error(PFMM_ERR_INVALID_ARG, "mac_theta supports order_p up to 9");
+      throw Error(PFMM_ERR_INVALID_ARG, "the dual-walk lists (mac_theta, adaptive_leaf_max) support order_p up to 9");
     }
     return;
   }
@@ -568,8 +570,9 @@ void launch_m2l(const TreeView& t, const OpTables& op, int nsplit, const double*
   const int side = mac ? 2 * mac->Rp + 1 : 0;
   if (nsplit < 1 || nsplit > (mac ? side * side * side : t.nnear))
     throw Error(PFMM_ERR_INVALID_ARG, "internal: M2L split out of range");
-  if (mac && (!mac->split || !mac->dvec || !mac->renc || mac->Rp < 1))
-    throw Error(PFMM_ERR_INVALID_ARG, "internal: acceptance-criterion M2L inputs missing");
+  if (mac && (!mac->split || !mac->dvec || (mac->use_theta && !mac->renc) || mac->Rp < 1 || mac->minsep < 2 ||
+              (mac->nonleaf && (!mac->lfirst || !mac->lcount))))
+    throw Error(PFMM_ERR_INVALID_ARG, "internal: dual-walk M2L inputs missing");
   if (!mac && fp32 && (!op.dvec32 || !M32)) throw Error(PFMM_ERR_INVALID_ARG, "internal: float32 M2L inputs missing");
   switch (op.p) {
 #define PFMM_M2L_CASE(PP)                                                                               \

@@ -1,6 +1,7 @@
 """pfmm_field_noalloc through the C interface: the allocation-free variant of pfmm_field (for callers
 that cannot allocate) gives bitwise the results of pfmm_field on the same inputs, on two calls in a
-row (the second smaller), takes no device memory, and refuses an evaluation larger than its scratch."""
+row (the second smaller), takes no device memory, and refuses an evaluation larger than its scratch;
+with the well-separation lists and with the adaptive octree's walk."""
 import ctypes
 
 import numpy as np
@@ -27,7 +28,8 @@ def _noalloc(lib):
     return f
 
 
-def test_field_noalloc_matches_field_and_allocates_nothing():
+@pytest.mark.parametrize("lists", ["ws", "adaptive"])
+def test_field_noalloc_matches_field_and_allocates_nothing(lists):
     import torch
     from paper_1408_6527_amd import api
     from paper_1408_6527_amd._lib import lib
@@ -36,11 +38,16 @@ def test_field_noalloc_matches_field_and_allocates_nothing():
     dev = torch.device("cuda", 0)
     T = lambda x: torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device=dev)
     kw = dict(order_p=6, ws=2, leaf_width=4.0, thole_a=2.0)
+    if lists == "adaptive":
+        # the dual walk's lists, whose near rows grow level by level inside the scratch
+        kw.update(adaptive_leaf_max=12)
     ref_solver = api.Solver(**kw)
     na_solver = api.Solver(**kw)  # a fresh handle: only its tables are allocated
     stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
-    for n, seed in ((40_000, 1), (7_000, 2)):
-        print(f"[case] noalloc field n={n}", flush=True)
+    # (the walk's frontiers, split-partner table and near rows take more workspace per particle)
+    sizes = ((40_000, 1), (7_000, 2)) if lists == "ws" else ((10_000, 1), (2_500, 2))
+    for n, seed in sizes:
+        print(f"[case] noalloc field {lists} n={n}", flush=True)
         X, q, a, mu = _cloud(n, 0.05, seed)
         pos, qq, al, mm = T(X), T(q), T(a), T(mu)
         ref = ref_solver.field(pos, qq, mm, al)
