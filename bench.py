@@ -31,12 +31,14 @@ sys.path.insert(0, ROOT)
 # the stopping rule is still checked at the full orders).  The 1M-particle preset is the fastest
 # setting measured whose float64 force error on the sampled oracle check stays below 1e-5.
 WORKLOADS = {
+    # mixed_target: the settings of the mixed path at its own stated error (relative force error
+    # <= 1e-4 instead of the float64 path's 1e-5), timed beside the shared settings
     "scaling_1m": dict(gen="scaling_1m", p=10, ws=2, leaf=6.0, tol=1e-6, slack=2, pc=5.0, pc_iters=4,
-                       relax=0.01),
+                       relax=0.01, mixed_target=dict(p=8, leaf=5.5)),
     "scaling_250k": dict(gen="scaling_250k", p=10, ws=2, leaf=6.0, tol=1e-6, slack=2, pc=5.0, pc_iters=4,
-                         relax=0.01),
+                         relax=0.01, mixed_target=dict(p=8, leaf=5.5)),
     "scaling_4m": dict(gen="scaling_4m", p=10, ws=2, leaf=6.0, tol=1e-6, slack=3, pc=5.0, pc_iters=4,
-                       relax=0.01),
+                       relax=0.01, mixed_target=dict(p=8, leaf=5.5)),
     "globular_50k": dict(gen="globular_50k", p=6, ws=2, leaf=4.0, tol=1e-6, slack=-1, pc=4.0, pc_iters=4,
                          relax=0.0),
     "uniform_cube_1k": dict(gen="uniform_cube_1k", p=4, ws=1, leaf=5.0, tol=1e-8, slack=-1, pc=0.0, pc_iters=4,
@@ -127,6 +129,8 @@ def parse():
                     help="skip the extra float64 solve at tolerance 1e-10 that splits the force error into the "
                          "FMM evaluation error and the part the solver tolerance adds")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed-target", action="store_true",
+                    help="skip the mixed path at its own error target (the workload's mixed_target settings)")
     ap.add_argument("--precision", default="both", choices=["fp64", "mixed", "both"])
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB before the benchmark, so that a "
@@ -146,9 +150,11 @@ def main():
     from paper_1408_6527_amd import api, inputs
 
     wl = dict(WORKLOADS[args.workload])
+    mixed_target = wl.pop("mixed_target", None)
     for k in ("p", "ws", "leaf", "tol", "slack", "pc", "pc_iters", "relax"):
         if getattr(args, k) is not None:
             wl[k] = getattr(args, k)
+            mixed_target = None  # settings given by hand: no second set
     if args.theta > 0.0 or args.leaf_max > 0:
         wl["slack"] = -1
     ps = inputs.make(wl["gen"])
@@ -176,10 +182,11 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    def make(prec, timing=False, tol=None):
-        s = api.Solver(order_p=wl["p"], ws=wl["ws"], leaf_width=wl["leaf"], scf_tol=tol or wl["tol"],
-                       m2l_order_slack=wl["slack"], precond_cutoff=wl["pc"], precond_iters=wl["pc_iters"],
-                       scf_relax=wl["relax"], dipole_pair_dl=args.pair_dl, precision=prec, timing=timing,
+    def make(prec, timing=False, tol=None, over=None):
+        w = dict(wl, **(over or {}))
+        s = api.Solver(order_p=w["p"], ws=w["ws"], leaf_width=w["leaf"], scf_tol=tol or w["tol"],
+                       m2l_order_slack=w["slack"], precond_cutoff=w["pc"], precond_iters=w["pc_iters"],
+                       scf_relax=w["relax"], dipole_pair_dl=args.pair_dl, precision=prec, timing=timing,
                        dipole_tree=int(args.dipole_tree), mac_theta=args.theta, mac_ndirect=args.ndirect,
                        mac_leaf_direct=args.leaf_direct, adaptive_leaf_max=args.leaf_max)
         if pairs is not None:
@@ -191,8 +198,8 @@ def main():
         s.backward(1.0)
         return r
 
-    def timed(prec):
-        s = make(prec)
+    def timed(prec, over=None):
+        s = make(prec, over=over)
         for _ in range(args.warmup):
             step(s)
         torch.cuda.synchronize()
@@ -209,6 +216,12 @@ def main():
         s, r, dt = timed(prec)
         results[prec] = dict(solver=s, res=r, dt=dt)
         del s
+    if args.no_mixed_target or args.precision != "both" or variant:
+        mixed_target = None
+    if mixed_target:
+        s, r, dt = timed("mixed", over=mixed_target)
+        results["mixed_target"] = dict(solver=s, res=r, dt=dt)
+        del s
 
     prim = precs[0]
     from oracle import native as NT
@@ -221,7 +234,7 @@ def main():
     idx = np.sort(rng.choice(n, S, replace=False))
     errs = {}
     t_full = None
-    for prec in precs:
+    for prec in precs + (["mixed_target"] if mixed_target else []):
         r = results[prec]["res"]
         e = dict(scf_residual=float(r.residual), iters=int(r.iters), scf_restarts=int(r.stats["scf_restarts"]),
                  m2l_order_cap_min=int(r.stats["m2l_order_cap_min"]))
@@ -386,6 +399,23 @@ def main():
         out["mixed"] = {"value": round(n / results["mixed"]["dt"], 2),
                         "ms_per_step": round(results["mixed"]["dt"] * 1e3, 3),
                         "speedup_vs_fp64": round(results["fp64"]["dt"] / results["mixed"]["dt"], 3)}
+    if mixed_target:
+        # the mixed path at its own stated error: the same step (solve + backward, same tolerance,
+        # preconditioner and relaxation) at the workload's mixed_target order and leaf edge
+        rm = results["mixed_target"]
+        w = dict(wl, **mixed_target)
+        stt = make("mixed", timing=True, over=mixed_target)
+        kt = stt.solve(pos, q, al, qE=qE).stats
+        del stt
+        out["mixed_at_target"] = {
+            "target": "relative force error <= 1e-4 (the mixed path's; float64 path <= 1e-5)",
+            "config": {"order_p": w["p"], "leaf_width": w["leaf"], "m2l_order_slack": w["slack"],
+                       "levels": rm["res"].stats["levels"], "m2l_pairs": int(rm["res"].stats["n_m2l"]),
+                       "near_pairs": int(rm["res"].stats["n_p2p"])},
+            "value": round(n / rm["dt"], 2), "ms_per_step": round(rm["dt"] * 1e3, 3),
+            "speedup_vs_fp64": round(results["fp64"]["dt"] / rm["dt"], 3),
+            "errors": errs.pop("mixed_target"),
+            "kernel_ms_per_step": {k: round(v, 3) for k, v in kt["t_kernel_ms"].items()}}
     print(json.dumps(out), flush=True)
 
 

@@ -282,14 +282,18 @@ def test_c4_finite_differences_50k(api):
 
 # ------------------------------------------------------------------ C5: scaling sweep
 
-@pytest.mark.parametrize("precision,gate", [("fp64", 1e-5), ("mixed", 1e-4)])
+@pytest.mark.parametrize("precision,gate", [("fp64", 1e-5), ("mixed", 1e-4), ("mixed_target", 1e-4)])
 def test_c5_250k_vs_full_oracle(api, precision, gate):
     """250,000 particles (half uniform cube, half clumped ball) in the 1M benchmark's settings
     against the exact solution of the direct-sum oracle, forward and backward; and the sampled
-    estimator against that full error."""
+    estimator against that full error.  mixed_target: the mixed path at the settings the benchmark
+    times for its own error target (1e-4)."""
     print_case(f"C5 250k {precision}")
     ps, ref = load_reference("scaling_250k")
-    s = make_solver(api, preset("scaling_250k"), precision)
+    wl = preset("scaling_250k")
+    if precision == "mixed_target":
+        wl.update(wl["mixed_target"])
+    s = make_solver(api, wl, "fp64" if precision == "fp64" else "mixed")
     r = s.solve(T(ps.pos), T(ps.q), T(ps.alpha))
     e = error_report(f"C5 250k {precision}", r, ps, ref)
     assert e["force"] < gate and e["energy"] < gate and e["dipole"] < 2 * gate
@@ -305,8 +309,10 @@ def _big_sampled(api, workload, S, seed, tight=False):
     idx = np.sort(np.random.default_rng(seed).choice(ps.n, S, replace=False))
     out = {}
     runs = [("fp64", {}), ("mixed", {})] + ([("fp64_tight", dict(tol=1e-10))] if tight else [])
+    if "mixed_target" in preset(workload):
+        runs.append(("mixed_target", preset(workload)["mixed_target"]))
     for name, over in runs:
-        prec = "mixed" if name == "mixed" else "fp64"
+        prec = "mixed" if name.startswith("mixed") else "fp64"
         s = make_solver(api, preset(workload, **over), prec)
         r = s.solve(pos, q, al)
         gp, gq, _ = s.backward(1.0, solve_id=r.stats["solve_id"])
@@ -339,7 +345,8 @@ def test_c5_1m_sampled(api):
     assert FULL_OVER_SAMPLED * out["fp64"]["eval"] < 1e-5
     assert FULL_OVER_SAMPLED * out["fp64_tight"]["eval"] < 1e-5
     assert FULL_OVER_SAMPLED * out["mixed"]["eval"] < 1e-4
-    for k in ("fp64", "mixed"):
+    assert FULL_OVER_SAMPLED * out["mixed_target"]["eval"] < 1e-4
+    for k in ("fp64", "mixed", "mixed_target"):
         assert FULL_OVER_SAMPLED * out[k]["grad_x"] < (1e-5 if k == "fp64" else 1e-4)
         assert out[k]["residual"] <= 1e-6
     assert scf_part < 1e-5
@@ -352,3 +359,5 @@ def test_c5_4m_sampled(api):
     _, out = _big_sampled(api, "scaling_4m", 256, 12)
     assert FULL_OVER_SAMPLED * out["fp64"]["eval"] < 1e-5 and FULL_OVER_SAMPLED * out["mixed"]["eval"] < 1e-4
     assert FULL_OVER_SAMPLED * out["fp64"]["grad_x"] < 1e-5 and FULL_OVER_SAMPLED * out["mixed"]["grad_x"] < 1e-4
+    assert FULL_OVER_SAMPLED * out["mixed_target"]["eval"] < 1e-4
+    assert FULL_OVER_SAMPLED * out["mixed_target"]["grad_x"] < 1e-4
