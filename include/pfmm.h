@@ -73,9 +73,11 @@ enum pfmm_flags {
 };
 
 typedef struct pfmm_config {
-  int order_p;         /* expansion order p, 1..10 (Sec. II.B truncation |n| + |m| <= p).  Orders
-                          above 10 are refused: the M2L keeps a tile's local expansions in
-                          registers, which holds up to C(13, 3) = 286 coefficients              */
+  int order_p;         /* expansion order p, 1..12 (Sec. II.B truncation |n| + |m| <= p).  Up to
+                          10 the M2L runs on the matrix cores (a tile's local expansions stay in
+                          registers and its staged operands fill the LDS at C(13, 3) = 286
+                          coefficients); orders 11 and 12 run a float64 vector M2L, on both
+                          precision paths, several times slower per interaction                  */
   int ws;              /* well-separation parameter, 1 or 2: near field = leaves within Chebyshev
                           distance ws; M2L between children of near parents that are farther     */
   double leaf_width;   /* leaf cell edge in Angstrom; 0 = choose from the mean density            */

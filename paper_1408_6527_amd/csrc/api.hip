@@ -250,7 +250,7 @@ struct pfmm_handle {
   int n_cu = 0;  // compute units of the device (M2L workgroup rounds)
   int64_t split_stride = 0;
   int64_t n_m2l = 0, n_p2p = 0, m2l_flops = 0;
-  int64_t m2l_flops_cap[11] = {};  // useful M2L flops per evaluation with every order capped at c
+  int64_t m2l_flops_cap[MAX_P + 1] = {};  // useful M2L flops per evaluation with every order capped at c
   int n_evals = 0;
   // lists of the dual tree walk (mac_theta > 0 or adaptive_leaf_max > 0): operator rows of the offsets
   // in [-(2 Rp + 1), 2 Rp + 1]^3, enclosing radii, split partners, the frontier pairs of the walk and
@@ -297,7 +297,8 @@ void sync_read(pfmm_handle* h, const void* dsrc, void* hdst, size_t bytes, hipSt
 
 void validate_config(const pfmm_config* c) {
   if (!c) throw Error(PFMM_ERR_INVALID_ARG, "config is NULL");
-  if (c->order_p < 1 || c->order_p > MAX_P) throw Error(PFMM_ERR_INVALID_ARG, "order_p must be in 1..10");
+  if (c->order_p < 1 || c->order_p > MAX_P)
+    throw Error(PFMM_ERR_INVALID_ARG, "order_p must be in 1.." + std::to_string(MAX_P));
   if (c->ws < 1 || c->ws > 2) throw Error(PFMM_ERR_INVALID_ARG, "ws must be 1 or 2");
   if (!(c->leaf_width >= 0.0) || !std::isfinite(c->leaf_width))
     throw Error(PFMM_ERR_INVALID_ARG, "leaf_width must be >= 0");
@@ -480,10 +481,11 @@ void build_tree(pfmm_handle* h, int n, const double* pos, const double* q, const
 // (also with every order capped at c).
 void build_tree_stats(pfmm_handle* h, hipStream_t s) {
   const TreeView& t = h->tv;
-  unsigned long long* stats = dev<unsigned long long>(h->w_stats, 14);
-  PFMM_HIP(hipMemsetAsync(stats, 0, 14 * sizeof(unsigned long long), s));
+  constexpr int NST = 3 + MAX_P + 1;
+  unsigned long long* stats = dev<unsigned long long>(h->w_stats, NST);
+  PFMM_HIP(hipMemsetAsync(stats, 0, NST * sizeof(unsigned long long), s));
   launch_tree_stats(t, h->op.m2l_code, h->op.dorder, h->op.noff, h->op.p, stats, s);
-  unsigned long long st[14];
+  unsigned long long st[NST];
   {
     void* pin = h->pinned.get(sizeof(st));
     PFMM_HIP(hipMemcpyAsync(pin, stats, sizeof(st), hipMemcpyDeviceToHost, s));
@@ -493,7 +495,7 @@ void build_tree_stats(pfmm_handle* h, hipStream_t s) {
   h->n_m2l = (int64_t)st[0];
   h->n_p2p = (int64_t)st[1];
   h->m2l_flops = (int64_t)st[2];
-  for (int c = 0; c <= 10; ++c) h->m2l_flops_cap[c] = c <= h->op.p ? (int64_t)st[3 + c] : 0;
+  for (int c = 0; c <= MAX_P; ++c) h->m2l_flops_cap[c] = c <= h->op.p ? (int64_t)st[3 + c] : 0;
 }
 
 void set_m2l_split(pfmm_handle* h) {
@@ -511,8 +513,12 @@ void set_m2l_split(pfmm_handle* h) {
   const int side = 2 * h->mv.Rp + 1;
   const int nn = mac ? side * side * side : t.nnear;
   const int lp_hi = L - 1 - (mac && h->mv.leaf_direct ? 1 : 0);
-  h->m2l_tiles = L >= 2 ? m2l_tiles(t, 1, lp_hi, mac ? 1 : m2l_tile_ncb(c.order_p, c.precision == PFMM_MIXED)) : 0;
   h->nsplit = 1;
+  if (c.order_p > MAX_P_MFMA) {  // the vector M2L: one workgroup per target cell, no splits
+    h->m2l_tiles = 0;
+    return;
+  }
+  h->m2l_tiles = L >= 2 ? m2l_tiles(t, 1, lp_hi, mac ? 1 : m2l_tile_ncb(c.order_p, c.precision == PFMM_MIXED)) : 0;
   if (h->m2l_tiles > 0) {
     const int64_t T = h->m2l_tiles, C = std::max(1, h->n_cu);
     const int hi = std::max(1, std::min(32, nn / 4));
@@ -677,7 +683,7 @@ void build_mac_lists(pfmm_handle* h, hipStream_t s) {
   h->n_p2p = (int64_t)np;
   auto flops = [](int q) { return 2 * (int64_t)mi_count(q) * (q + 4) * (q + 5) * (q + 6) / 120; };
   h->m2l_flops = nm * flops(h->op.p);
-  for (int c = 0; c <= 10; ++c) h->m2l_flops_cap[c] = c <= h->op.p ? nm * flops(c) : 0;
+  for (int c = 0; c <= MAX_P; ++c) h->m2l_flops_cap[c] = c <= h->op.p ? nm * flops(c) : 0;
 }
 
 // One FMM evaluation: sources 1 = charges, 2 = dipoles (mu4), 3 = both.

@@ -31,12 +31,12 @@ constexpr int P2M_CHUNK = 64;
 // per coefficient.  PAIR: each dipole enters as its pair of Sec. II.C, the charges +/- |mu| / (2 dl)
 // at rho +/- (dl / w) mu/|mu|, staged as two more point charges after the particle's own charge (a
 // zero dipole stages two zero charges); otherwise through the point-dipole term above.
-template <bool PAIR>
+template <bool PAIR, int PM>
 __global__ __launch_bounds__(P2M_TPB) void k_p2m(TreeView t, OpTables op, Particles pa,
                                                  const double4* __restrict__ mu4, int sources, double pair_dl,
                                                  double* __restrict__ M, const int* done) {
   if (done && *done) return;
-  __shared__ double pw[P2M_CHUNK][3][MAX_P + 1];
+  __shared__ double pw[P2M_CHUNK][3][PM + 1];
   __shared__ double sq[P2M_CHUNK], sm[P2M_CHUNK][3];
   const int g = t.off[t.L] + blockIdx.x;
   const int first = t.first[g], cnt = t.count[g];
@@ -44,7 +44,7 @@ __global__ __launch_bounds__(P2M_TPB) void k_p2m(TreeView t, OpTables op, Partic
   cell_centre(t, g, t.L, c, w);
   const double iw = 1.0 / w;
   const int p = op.p, nc = op.nc;
-  constexpr int KPT = (286 + P2M_TPB - 1) / P2M_TPB;  // coefficients per thread at p = 10
+  constexpr int KPT = (mi_count(PM) + P2M_TPB - 1) / P2M_TPB;  // coefficients per thread at order PM
   double acc[KPT];
   int ex[KPT][3];
   for (int r = 0; r < KPT; ++r) {
@@ -124,7 +124,6 @@ __global__ __launch_bounds__(P2M_TPB) void k_p2m(TreeView t, OpTables op, Partic
 }
 
 constexpr int SH_TPB = 256;
-constexpr int MAX_STRIDE = 288;  // row stride of an expansion at p = 10
 
 
 // (h/4)^e / e! and (-h/4)^e / e! for e = 0..p: per-axis factors of the shift coefficients x^k / k!
@@ -144,12 +143,14 @@ __device__ inline void shift_powers(double* plus, double* minus, int p, double h
 // edges).  The shift coefficient factorises over the axes, and children that differ only in their
 // z bit (then y, then x) share the x and y factors, so the sum runs as three passes over LDS rows:
 // z (8 rows -> 4), y (4 -> 2), x (2 -> 1), each term one multiply-add.
+template <int PM>
 __global__ __launch_bounds__(SH_TPB) void k_m2m(TreeView t, OpTables op, int lp,
                                                 double* __restrict__ M, const int* done) {
   if (done && *done) return;
+  constexpr int MAX_STRIDE = sched_stride(PM);  // row stride of an expansion at order PM
   __shared__ double sA[8][MAX_STRIDE];
   __shared__ double sB[4][MAX_STRIDE];
-  __shared__ double hp[2][MAX_P + 1];
+  __shared__ double hp[2][PM + 1];
   __shared__ int ch[8];
   const int g = t.off[lp] + blockIdx.x;
   const int nc = op.nc, p = op.p;
@@ -201,13 +202,15 @@ __global__ __launch_bounds__(SH_TPB) void k_m2m(TreeView t, OpTables op, int lp,
 // xl_a = +1/4 for octant bit 1 and -1/4 for bit 0 (the parent row is complete because levels run
 // top-down).  As in M2M the sum factorises: z (1 row -> 2), y (2 -> 4), x (4 -> 8 children).
 // The truncation |k| <= p - |n| is kept exactly: each pass only reaches indices of degree <= p.
+template <int PM>
 __global__ __launch_bounds__(SH_TPB) void k_l2l(TreeView t, OpTables op, int lc, double* F,
                                                 int nsplit, int64_t split_stride, const int* done) {
   if (done && *done) return;
+  constexpr int MAX_STRIDE = sched_stride(PM);  // row stride of an expansion at order PM
   __shared__ double sP[MAX_STRIDE];
   __shared__ double sU1[2][MAX_STRIDE];
   __shared__ double sU2[4][MAX_STRIDE];
-  __shared__ double qp[2][MAX_P + 1];  // [bit]: bit 1 -> +1/4, bit 0 -> -1/4
+  __shared__ double qp[2][PM + 1];  // [bit]: bit 1 -> +1/4, bit 0 -> -1/4
   __shared__ int ch[8];
   const int g = t.off[lc - 1] + blockIdx.x;
   const int nc = op.nc, p = op.p;
@@ -257,7 +260,6 @@ __global__ __launch_bounds__(SH_TPB) void k_l2l(TreeView t, OpTables op, int lc,
 }
 
 constexpr int L2P_TPB = 64;
-constexpr int MAX_NC = 286;  // multi-indices of degree <= 10
 
 // One wavefront per leaf.  A leaf holds few particles at protein density, so each particle is
 // served by G = 64 / T lanes (T = the leaf occupancy rounded up to a power of two), each lane taking
@@ -267,14 +269,15 @@ constexpr int MAX_NC = 286;  // multi-indices of degree <= 10
 // is read through the scalar cache.
 // MODE 0 (dipole-solve evaluations): E only, so the coefficients of degree p, which feed only the
 // potential, are skipped; MODE 1: potential, field and field gradient.
-template <int MODE>
+template <int MODE, int PM>
 __global__ __launch_bounds__(L2P_TPB) void k_l2p(TreeView t, OpTables op, Particles pa,
                                                  const double* __restrict__ F, FieldOut out,
                                                  const int* done) {
   constexpr int mode = MODE;
   if (done && *done) return;
+  constexpr int MAX_NC = mi_count(PM);  // multi-indices of degree <= PM
   __shared__ double sF[MAX_NC];
-  __shared__ double pw[3][MAX_P + 1][L2P_TPB];
+  __shared__ double pw[3][PM + 1][L2P_TPB];
   // the per-coefficient table, packed, and 1/k!: read from LDS (a broadcast per slice) rather
   // than from global memory in the inner loop
   __shared__ int4 sT[MAX_NC];    // nx | ny << 8 | nz << 16 | deg << 24, e_x | e_y << 16, e_z | ee_xx << 16, ee_yy | ee_zz << 16
@@ -362,16 +365,18 @@ __global__ __launch_bounds__(L2P_TPB) void k_l2p(TreeView t, OpTables op, Partic
 
 }  // namespace
 
+// The kernels' LDS and registers are sized for an order class: orders up to MAX_P_MFMA, the
+// benchmark's, keep the smaller footprint; the orders above take the larger one.
+constexpr int PM_LO = MAX_P_MFMA, PM_HI = MAX_P;
+
 void launch_p2m(const TreeView& t, const OpTables& op, const Particles& pa, const double4* mu4,
                 int sources, double pair_dl, double* M, const int* done, hipStream_t s) {
   const int nleaf = t.off[t.L + 1] - t.off[t.L];
   if (nleaf <= 0) return;
-  if (pair_dl > 0.0 && (sources & 2))
-    hipLaunchKernelGGL(k_p2m<true>, dim3(nleaf), dim3(P2M_TPB), 0, s, t, op, pa, mu4, sources, pair_dl, M,
-                       done);
-  else
-    hipLaunchKernelGGL(k_p2m<false>, dim3(nleaf), dim3(P2M_TPB), 0, s, t, op, pa, mu4, sources, pair_dl, M,
-                       done);
+  if (op.p > PM_HI) throw Error(PFMM_ERR_INVALID_ARG, "order_p out of range");
+  const bool pair = pair_dl > 0.0 && (sources & 2), lo = op.p <= PM_LO;
+  auto k = pair ? (lo ? k_p2m<true, PM_LO> : k_p2m<true, PM_HI>) : (lo ? k_p2m<false, PM_LO> : k_p2m<false, PM_HI>);
+  hipLaunchKernelGGL(k, dim3(nleaf), dim3(P2M_TPB), 0, s, t, op, pa, mu4, sources, pair_dl, M, done);
   PFMM_LAUNCH_CHECK();
 }
 
@@ -379,7 +384,9 @@ void launch_m2m(const TreeView& t, const OpTables& op, int parent_level, double*
                 hipStream_t s) {
   const int nc = t.off[parent_level + 1] - t.off[parent_level];
   if (nc <= 0) return;
-  hipLaunchKernelGGL(k_m2m, dim3(nc), dim3(SH_TPB), 0, s, t, op, parent_level, M, done);
+  if (op.p > PM_HI) throw Error(PFMM_ERR_INVALID_ARG, "order_p out of range");
+  hipLaunchKernelGGL(op.p <= PM_LO ? k_m2m<PM_LO> : k_m2m<PM_HI>, dim3(nc), dim3(SH_TPB), 0, s, t, op, parent_level,
+                     M, done);
   PFMM_LAUNCH_CHECK();
 }
 
@@ -388,8 +395,9 @@ void launch_l2l(const TreeView& t, const OpTables& op, int child_level, double* 
   if (child_level < 2) return;
   const int np = t.off[child_level] - t.off[child_level - 1];
   if (np <= 0 || (child_level < 3 && nsplit <= 1)) return;
-  hipLaunchKernelGGL(k_l2l, dim3(np), dim3(SH_TPB), 0, s, t, op, child_level, F, nsplit, split_stride,
-                     done);
+  if (op.p > PM_HI) throw Error(PFMM_ERR_INVALID_ARG, "order_p out of range");
+  hipLaunchKernelGGL(op.p <= PM_LO ? k_l2l<PM_LO> : k_l2l<PM_HI>, dim3(np), dim3(SH_TPB), 0, s, t, op, child_level,
+                     F, nsplit, split_stride, done);
   PFMM_LAUNCH_CHECK();
 }
 
@@ -397,11 +405,10 @@ void launch_l2p(const TreeView& t, const OpTables& op, const Particles& pa, cons
                 FieldOut out, const int* done, hipStream_t s) {
   const int nleaf = t.off[t.L + 1] - t.off[t.L];
   if (nleaf <= 0) return;
-  if (op.nc > MAX_NC) throw Error(PFMM_ERR_INVALID_ARG, "order_p out of range");
-  if (mode == 1)
-    hipLaunchKernelGGL(k_l2p<1>, dim3(nleaf), dim3(L2P_TPB), 0, s, t, op, pa, F, out, done);
-  else
-    hipLaunchKernelGGL(k_l2p<0>, dim3(nleaf), dim3(L2P_TPB), 0, s, t, op, pa, F, out, done);
+  if (op.p > PM_HI || op.nc > mi_count(PM_HI)) throw Error(PFMM_ERR_INVALID_ARG, "order_p out of range");
+  const bool lo = op.p <= PM_LO;
+  auto k = mode == 1 ? (lo ? k_l2p<1, PM_LO> : k_l2p<1, PM_HI>) : (lo ? k_l2p<0, PM_LO> : k_l2p<0, PM_HI>);
+  hipLaunchKernelGGL(k, dim3(nleaf), dim3(L2P_TPB), 0, s, t, op, pa, F, out, done);
   PFMM_LAUNCH_CHECK();
 }
 

@@ -11,8 +11,10 @@
 namespace pfmm {
 
 constexpr int MAX_LEVELS = 21;  // 63-bit Morton keys
-constexpr int MAX_P = 10;
-constexpr int MAX_P_MAC = 9;  // highest order of the acceptance-criterion M2L
+constexpr int MAX_P = 12;       // highest expansion order
+constexpr int MAX_P_MFMA = 10;  // highest order of the matrix-core M2L (its tile's LDS and registers);
+                                // orders above run the vector M2L (m2l.hip, k_m2l_vector)
+constexpr int MAX_P_MAC = 9;    // highest order of the acceptance-criterion M2L
 
 // Device view of the octree.  Cells of all levels live in one array, level by level; inside a
 // level they are in Morton order, so each cell's particles are a contiguous range of the sorted

@@ -529,6 +529,84 @@ void m2l_dispatch(const TreeView& t, const OpTables& op, int nsplit, const doubl
   }
 }
 
+// Orders above the matrix-core kernel's (MAX_P_MFMA < p <= MAX_P): the same contraction on the
+// vector units in float64, one workgroup per target cell B of levels 2..L.  For each source A, a
+// child of a colleague of B's parent farther than ws from B, the workgroup stages the source row and
+// the operator row D(d), d = B - A, truncated at the offset's order q(d) (or the cap), in LDS, and
+// each thread accumulates its rows n of
+//   F~_n(B) = sum_{|m| <= q - |n|} D_{n+m}(d) M~_m(A)
+// in the sources' fixed order; F~(B) is written once (no offset splits).  Float64 on both precision
+// paths.
+constexpr int VTPB = 256;
+
+template <int PM>
+__global__ __launch_bounds__(VTPB) void k_m2l_vector(TreeView t, OpTables op, const double* __restrict__ M,
+                                                     double* __restrict__ F, const int* done, const int* qcap) {
+  if (done && *done) return;
+  constexpr int NCM = mi_count(PM), DPM = sched_dpitch(PM);
+  constexpr int RPT = (NCM + VTPB - 1) / VTPB;  // rows per thread
+  __shared__ double sM[NCM];
+  __shared__ double sD[DPM];
+  __shared__ int sE[NCM];  // exponents of m packed nx | ny << 8 | nz << 16
+  const int B = t.off[2] + blockIdx.x;
+  const int nc = op.nc, p = op.p;
+  const int qc = qcap ? min(*qcap, p) : p;
+  const int ws = t.ws, R = 2 * ws + 1, cube = 2 * R + 1;
+  for (int k = threadIdx.x; k < nc; k += VTPB) sE[k] = op.mi[3 * k] | (op.mi[3 * k + 1] << 8) | (op.mi[3 * k + 2] << 16);
+  int cb[3];
+  {
+    const uint64_t k = t.key[B];
+    cb[0] = compact3(k >> 2); cb[1] = compact3(k >> 1); cb[2] = compact3(k);
+  }
+  int rn[RPT], rdeg[RPT];
+  double acc[RPT];
+#pragma unroll
+  for (int r = 0; r < RPT; ++r) {
+    rn[r] = threadIdx.x + r * VTPB;
+    rdeg[r] = rn[r] < nc ? op.mi[3 * rn[r]] + op.mi[3 * rn[r] + 1] + op.mi[3 * rn[r] + 2] : PM + 1;
+    acc[r] = 0.0;
+  }
+  const int P_ = t.parent[B];
+  for (int k = 0; k < t.nnear; ++k) {
+    const int S = t.coll[(int64_t)P_ * t.nnear + k];
+    if (S < 0) continue;
+    for (int c = 0; c < 8; ++c) {
+      const int A = t.child8[8 * S + c];
+      if (A < 0) continue;
+      const uint64_t ka = t.key[A];
+      const int d0 = cb[0] - compact3(ka >> 2), d1 = cb[1] - compact3(ka >> 1), d2 = cb[2] - compact3(ka);
+      if (max(abs(d0), max(abs(d1), abs(d2))) <= ws) continue;  // uniform over the workgroup
+      const int slot = ((d0 + R) * cube + (d1 + R)) * cube + (d2 + R);
+      const int q = min((int)op.dorder[slot], qc);
+      const int nq = mi_count(q);
+      __syncthreads();  // the previous source's rows are no longer read
+      for (int j = threadIdx.x; j < nq; j += VTPB) {
+        sM[j] = M[(int64_t)A * op.stride + j];
+        sD[j] = op.dvec[(int64_t)slot * sched_dpitch(p) + j];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < RPT; ++r) {
+        const int dn = rdeg[r];
+        if (dn > q) continue;
+        const int n = rn[r];
+        const int nx = op.mi[3 * n], ny = op.mi[3 * n + 1], nz = op.mi[3 * n + 2];
+        const int cnt = mi_count(q - dn);
+        double a = 0.0;
+        for (int m = 0; m < cnt; ++m) {
+          const int e = sE[m];
+          a = fma(sD[mi_index(nx + (e & 0xff), ny + ((e >> 8) & 0xff), nz + (e >> 16))], sM[m], a);
+        }
+        acc[r] += a;
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < RPT; ++r)
+    if (rn[r] < op.stride) F[(int64_t)B * op.stride + rn[r]] = rn[r] < nc ? acc[r] : 0.0;
+  for (int k = NCM + threadIdx.x; k < op.stride; k += VTPB) F[(int64_t)B * op.stride + k] = 0.0;
+}
+
 }  // namespace
 
 __global__ __launch_bounds__(256) void k_to_float(const double* __restrict__ in, float* __restrict__ out,
@@ -552,7 +630,7 @@ int m2l_tile_ncb(int p, bool fp32) {
     PFMM_NCB_CASE(1) PFMM_NCB_CASE(2) PFMM_NCB_CASE(3) PFMM_NCB_CASE(4) PFMM_NCB_CASE(5)
     PFMM_NCB_CASE(6) PFMM_NCB_CASE(7) PFMM_NCB_CASE(8) PFMM_NCB_CASE(9) PFMM_NCB_CASE(10)
 #undef PFMM_NCB_CASE
-    default: throw Error(PFMM_ERR_INVALID_ARG, "order_p out of range");
+    default: return 1;  // the vector M2L of the higher orders
   }
 }
 
@@ -573,6 +651,14 @@ void launch_m2l(const TreeView& t, const OpTables& op, int nsplit, const double*
   if (mac && (!mac->split || !mac->dvec || (mac->use_theta && !mac->renc) || mac->Rp < 1 || mac->minsep < 2 ||
               (mac->nonleaf && (!mac->lfirst || !mac->lcount))))
     throw Error(PFMM_ERR_INVALID_ARG, "internal: dual-walk M2L inputs missing");
+  if (op.p > MAX_P_MFMA) {
+    if (mac || nsplit != 1 || op.p > MAX_P) throw Error(PFMM_ERR_INVALID_ARG, "internal: vector M2L configuration");
+    const int nt = t.ncell - t.off[2];  // target cells of levels 2..L
+    if (nt > 0)
+      hipLaunchKernelGGL(k_m2l_vector<MAX_P>, dim3(nt), dim3(VTPB), 0, s, t, op, M, F, done, qcap);
+    PFMM_LAUNCH_CHECK();
+    return;
+  }
   if (!mac && fp32 && (!op.dvec32 || !M32)) throw Error(PFMM_ERR_INVALID_ARG, "internal: float32 M2L inputs missing");
   switch (op.p) {
 #define PFMM_M2L_CASE(PP)                                                                               \

@@ -204,7 +204,7 @@ __global__ __launch_bounds__(TPB) void k_tree_stats(TreeView t, const int* __res
                                                     unsigned long long* stats) {
   const int first2 = t.L >= 2 ? t.off[2] : t.ncell;
   unsigned long long m2l = 0, p2p = 0, flops = 0;
-  unsigned long long fcap[11] = {};  // p <= 10
+  unsigned long long fcap[MAX_P + 1] = {};
   for (int g = blockIdx.x * TPB + threadIdx.x; g < t.ncell; g += gridDim.x * TPB) {
     if (g >= first2) {
       const int oct = (int)(t.key[g] & 7);
@@ -217,7 +217,7 @@ __global__ __launch_bounds__(TPB) void k_tree_stats(TreeView t, const int* __res
           const unsigned long long q = dorder[code & 0xfff];
           flops += m2l_pair_flops(q);
 #pragma unroll
-          for (int c = 0; c <= 10; ++c)
+          for (int c = 0; c <= MAX_P; ++c)
             if (c <= p) fcap[c] += m2l_pair_flops(q < (unsigned long long)c ? q : (unsigned long long)c);
         }
       }
@@ -235,7 +235,7 @@ __global__ __launch_bounds__(TPB) void k_tree_stats(TreeView t, const int* __res
   if (p2p) atomicAdd(&stats[1], p2p);
   if (flops) atomicAdd(&stats[2], flops);
 #pragma unroll
-  for (int c = 0; c <= 10; ++c)
+  for (int c = 0; c <= MAX_P; ++c)
     if (c <= p && fcap[c]) atomicAdd(&stats[3 + c], fcap[c]);
 }
 
@@ -336,7 +336,7 @@ void launch_colleagues(const uint64_t* ckey, int off_l, int ncell_l, int l, int 
 
 void launch_tree_stats(const TreeView& t, const int* m2l_code, const unsigned char* dorder, int noff,
                        int p, unsigned long long* stats, hipStream_t s) {
-  if (p < 0 || p > 10) throw Error(PFMM_ERR_INVALID_ARG, "internal: order out of range in tree stats");
+  if (p < 0 || p > MAX_P) throw Error(PFMM_ERR_INVALID_ARG, "internal: order out of range in tree stats");
   hipLaunchKernelGGL(k_tree_stats, dim3(grid_for(t.ncell)), dim3(TPB), 0, s, t, m2l_code, dorder, noff, p,
                      stats);
   PFMM_LAUNCH_CHECK();

@@ -179,6 +179,24 @@ def test_solve_pair_dipoles_matches_oracle_fmm(api, dl):
     assert abs(e_pair - e_point) < 0.01 * e_point
 
 
+@pytest.mark.parametrize("p,ws,slack", [(11, 2, -1), (12, 1, 2)])
+def test_field_high_orders_match_oracle_fmm(api, p, ws, slack):
+    """Orders 11 and 12, above the matrix-core M2L's: the vector M2L (float64 on both paths) and the
+    expansion kernels of the larger order class against the oracle's FMM, with fixed and per-offset
+    truncation orders."""
+    print_case(f"field fmm high order p={p} ws={ws} slack={slack}")
+    X, q, a, mu = cube(300, 11.0, 2)
+    ref = FM.fmm_fields(X, q, mu, a, 0.0, p, 1.5, ws, order_slack=slack)
+    assert ref["tree"].L >= 3
+    for precision in ("fp64", "mixed"):
+        s = api.Solver(order_p=p, ws=ws, leaf_width=1.5, thole_a=0.0, m2l_order_slack=slack, precision=precision)
+        phi, E, Ed, G = s.field(T(X), T(q), T(mu), T(a))
+        errs = [relmax(N(phi), ref["phi"]), relmax(N(E), ref["E_u"]), relmax(N(Ed), ref["E_d"]),
+                relmax(N(G), ref["G_d"])]
+        print(f"high order p={p} ws={ws} slack={slack} {precision}: field errors {max(errs):.1e}", flush=True)
+        assert max(errs) < (1e-11 if precision == "fp64" else 1e-5)
+
+
 @pytest.mark.parametrize("p", [9, 10])
 def test_mixed_field_deep_tree_matches_fp64(api, p):
     """The float32 M2L (levels below 4 of a deep tree, two 16-parent tiles per workgroup, float32
@@ -772,7 +790,7 @@ def test_errors(api):
     with pytest.raises(api.PFMMError, match="NO_STATE"):
         api.Solver(order_p=4, ws=1).backward(1.0, n=5)
     with pytest.raises(api.PFMMError):
-        api.Solver(order_p=11)
+        api.Solver(order_p=13)
 
 
 def test_one_hip_runtime_is_mapped(api):

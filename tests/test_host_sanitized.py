@@ -1,5 +1,5 @@
 """The host side of the operator tables (csrc/tables.cpp) and the M2L schedule (csrc/schedule.hpp),
-built with g++ under AddressSanitizer and UndefinedBehaviorSanitizer, for every order p = 1..10, both
+built with g++ under AddressSanitizer and UndefinedBehaviorSanitizer, for every order p = 1..12, both
 separations and several order slacks, with every index the kernels read from the tables checked
 against the range of what it indexes:
 
@@ -34,7 +34,7 @@ using namespace pfmm;
 static int fails = 0;
 #define CHECK(c) do { if (!(c)) { std::printf("FAIL p=%d ws=%d slack=%d: %s (line %d)\n", p, ws, slack, #c, __LINE__); if (++fails > 20) std::exit(1); } } while (0)
 int main() {
-  for (int p = 1; p <= 10; ++p)
+  for (int p = 1; p <= 12; ++p)
     for (int ws = 1; ws <= 2; ++ws)
       for (int slack = -1; slack <= 3; ++slack) {
         HostTables t;
