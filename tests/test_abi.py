@@ -49,7 +49,7 @@ def test_status_strings_and_defaults(lib):
     assert c.dipole_pair_dl == 0.0
 
 
-@pytest.mark.parametrize("field,value", [("order_p", 0), ("order_p", 11), ("ws", 3), ("precision", 5),
+@pytest.mark.parametrize("field,value", [("order_p", 0), ("order_p", 13), ("ws", 3), ("precision", 5),
                                          ("scf_tol", 0.0), ("scf_max_iter", 0), ("thole_a", -1.0),
                                          ("leaf_width", -2.0), ("m2l_order_slack", -2),
                                          ("precond_cutoff", -1.0), ("scf_relax", -0.1), ("scf_relax", 1.0),
