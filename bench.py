@@ -122,7 +122,7 @@ def parse():
                     help="with --theta: leaf pairs are always summed directly")
     ap.add_argument("--leaf-max", type=int, default=0,
                     help="the adaptive octree: cells above the finest level split only when they hold more than "
-                         "this many particles (0: every leaf at the finest level); every M2L at order p")
+                         "this many particles (0: every leaf at the finest level)")
     ap.add_argument("--oracle-sample", type=int, default=0,
                     help="targets of the sampled oracle check (0: about 2e9 / n, between 64 and 4096)")
     ap.add_argument("--no-split", action="store_true",
@@ -155,7 +155,7 @@ def main():
         if getattr(args, k) is not None:
             wl[k] = getattr(args, k)
             mixed_target = None  # settings given by hand: no second set
-    if args.theta > 0.0 or args.leaf_max > 0:
+    if args.theta > 0.0:
         wl["slack"] = -1
     ps = inputs.make(wl["gen"])
     n = ps.n

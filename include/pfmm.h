@@ -156,10 +156,10 @@ typedef struct pfmm_config {
                           terminal (a leaf or below one), with the well-separation rule of ws
                           (mac_theta = 0; mac_ndirect and mac_leaf_direct unused) or the acceptance
                           criterion.  The expansions of cells below a leaf are exact translations of
-                          the leaf's own and serve its interactions with finer neighbours.  Every
-                          M2L is at order p (m2l_order_slack must be -1, order_p at most 9) in
-                          float64; the Thole damping radius must not exceed ws leaf edges (leaf
-                          edges with mac_theta).                                                   */
+                          the leaf's own and serve its interactions with finer neighbours.  The
+                          M2L runs in float64 (order_p at most 9) at the ws lists' per-offset orders
+                          (m2l_order_slack), or at order p with mac_theta; the Thole damping radius
+                          must not exceed ws leaf edges (leaf edges with mac_theta).               */
 } pfmm_config;
 
 typedef struct pfmm_result {

@@ -260,7 +260,7 @@ struct pfmm_handle {
   int leaf_max = 0;
   MacView mv;
   DevBuf t_mdvec, m_renc, m_split, m_bad, m_acc, m_kid, m_accs, m_kids, m_stmp, m_stmp2, m_nt, m_ns, m_sort_tmp,
-      m_cnt, m_nkout, m_nvout, m_nptr, m_nearc, m_nears, m_nonleaf, m_lfirst, m_lcount;
+      m_cnt, m_nkout, m_nvout, m_nptr, m_nearc, m_nears, m_nonleaf, m_lfirst, m_lcount, m_flops;
   DevBuf m_fr[2];
 };
 
@@ -329,9 +329,8 @@ void validate_config(const pfmm_config* c) {
   const bool walk = c->mac_theta > 0.0 || c->adaptive_leaf_max > 0;
   if (walk && c->order_p > MAX_P_MAC)
     throw Error(PFMM_ERR_INVALID_ARG, "mac_theta and adaptive_leaf_max support order_p up to " + std::to_string(MAX_P_MAC));
-  if (walk && c->m2l_order_slack >= 0)
-    throw Error(PFMM_ERR_INVALID_ARG,
-                "mac_theta and adaptive_leaf_max run every M2L at order p: m2l_order_slack must be -1");
+  if (c->mac_theta > 0.0 && c->m2l_order_slack >= 0)
+    throw Error(PFMM_ERR_INVALID_ARG, "mac_theta runs every M2L at order p: m2l_order_slack must be -1");
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -572,6 +571,9 @@ void build_mac_lists(pfmm_handle* h, hipStream_t s) {
   mv.split = split;
   int* bad = dev<int>(h->m_bad, 1);
   launch_fill_int(bad, 1, 0, s);
+  // the accepted pairs' useful flops (at their orders, and capped at each c <= p)
+  unsigned long long* fst = dev<unsigned long long>(h->m_flops, MAX_P + 2);
+  launch_fill_int(reinterpret_cast<int*>(fst), 2 * (MAX_P + 2), 0, s);
   int cur = 0;
   int2* fr = dev<int2>(h->m_fr[cur], 1);
   launch_fill_int(reinterpret_cast<int*>(fr), 2, 0, s);  // (root, root)
@@ -622,6 +624,7 @@ void build_mac_lists(pfmm_handle* h, hipStream_t s) {
     int* kids = dev<int>(h->m_kids, nf);
     int* nears = dev<int>(h->m_nears, nf);
     launch_mac_classify(t, mv, l, fr, nf, acc, kid, nearc, s);
+    launch_mac_flops(t, mv, fr, nf, acc, h->op.dorder, h->op.p, fst, s);
     const size_t tb = scan_temp_bytes(nf);
     void* tmp = raw(h->m_stmp, tb);
     launch_inclusive_scan(tmp, tb, acc, accs, nf, s);
@@ -677,13 +680,13 @@ void build_mac_lists(pfmm_handle* h, hipStream_t s) {
   unsigned long long* pairs = dev<unsigned long long>(h->w_stats, 1);
   launch_fill_int(reinterpret_cast<int*>(pairs), 2, 0, s);
   launch_mac_near_pairs(t, nkey, nsrc, nnear_i, pairs, s);
-  unsigned long long np = 0;
+  unsigned long long np = 0, fl[MAX_P + 2];
   sync_read(h, pairs, &np, sizeof(np), s);
+  sync_read(h, fst, fl, sizeof(fl), s);
   h->n_m2l = nm;
   h->n_p2p = (int64_t)np;
-  auto flops = [](int q) { return 2 * (int64_t)mi_count(q) * (q + 4) * (q + 5) * (q + 6) / 120; };
-  h->m2l_flops = nm * flops(h->op.p);
-  for (int c = 0; c <= MAX_P; ++c) h->m2l_flops_cap[c] = c <= h->op.p ? nm * flops(c) : 0;
+  h->m2l_flops = (int64_t)fl[0];
+  for (int c = 0; c <= MAX_P; ++c) h->m2l_flops_cap[c] = c <= h->op.p ? (int64_t)fl[1 + c] : 0;
 }
 
 // One FMM evaluation: sources 1 = charges, 2 = dipoles (mu4), 3 = both.

@@ -194,6 +194,11 @@ void launch_mac_classify(const TreeView& t, const MacView& mv, int level, const 
 void launch_mac_emit(const TreeView& t, const MacView& mv, int level, const int2* fr, int nfr, const int* kid_scan,
                      const int* near_scan, int2* next, int* split, int* near_tgt, int* near_src, int* bad,
                      hipStream_t s);
+// useful M2L flops of the accepted pairs of a frontier (acc from classify), 2 C(q + 6, 6) per pair at
+// its order q (p with the criterion, the per-offset order dorder of the ws rule): added to st[0], and
+// with every order capped at c <= p to st[1 + c] (MAX_P + 2 entries)
+void launch_mac_flops(const TreeView& t, const MacView& mv, const int2* fr, int nfr, const int* acc,
+                      const unsigned char* dorder, int p, unsigned long long* st, hipStream_t s);
 // Adaptive octree: nonleaf[c] = 1 for the cells of level < L holding more than leaf_max particles
 // (one launch per level), then, from level L - 1 up to 0, every cell of level l touching a split
 // cell of level l + 1 is split (2:1 balance over the full octree); lfirst / lcount: the level-L cells

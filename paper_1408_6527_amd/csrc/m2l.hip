@@ -385,7 +385,8 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(m2l_waves_p
       if (max(abs(d0), max(abs(d1), abs(d2))) > near_r) {
         // D_k(d) for |k| <= q(d), zero above: the M2L truncated at order q(d)
         const int slot = ((d0 + R) * cube + (d1 + R)) * cube + (d2 + R);
-        const int q = MAC ? min(P, qc) : min((int)op.dorder[slot], qc);
+        // (the ws rule of the adaptive octree keeps the ws lists' per-offset orders)
+        const int q = MAC && mv.use_theta ? min(P, qc) : min((int)op.dorder[slot], qc);
         sD[e] = k < mi_count(q) ? dtab[(int64_t)slot * DP + k] : (kt)0;
         if (k == 0) sQ[v] = q;
       }

@@ -87,6 +87,44 @@ __global__ __launch_bounds__(256) void k_mac_classify(TreeView t, MacView mv, in
   }
 }
 
+// useful flops of the accepted pairs of a frontier, 2 C(q + 6, 6) per pair at its order q (p with
+// the criterion; the ws lists' per-offset order with the ws rule): st[0] at the pairs' orders,
+// st[1 + c] with every order capped at c <= p
+__global__ __launch_bounds__(256) void k_mac_flops(TreeView t, MacView mv, const int2* __restrict__ fr, int nfr,
+                                                   const int* __restrict__ acc, const unsigned char* __restrict__ dorder,
+                                                   int p, unsigned long long* st) {
+  __shared__ unsigned long long red[256];
+  auto fl = [](unsigned long long q) {
+    return 2 * ((q + 1) * (q + 2) * (q + 3) * (q + 4) * (q + 5) * (q + 6) / 720);
+  };
+  unsigned long long f[MAX_P + 2] = {};
+  const int R = 2 * mv.Rp + 1, cube = 2 * R + 1;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nfr; i += gridDim.x * blockDim.x) {
+    if (!acc[i]) continue;
+    int q = p;
+    if (!mv.use_theta) {
+      int cb[3], ca[3];
+      mac_coords(t.key[fr[i].x], cb);
+      mac_coords(t.key[fr[i].y], ca);
+      q = min(p, (int)dorder[((cb[0] - ca[0] + R) * cube + (cb[1] - ca[1] + R)) * cube + (cb[2] - ca[2] + R)]);
+    }
+    f[0] += fl(q);
+#pragma unroll
+    for (int c = 0; c <= MAX_P; ++c)
+      if (c <= p) f[1 + c] += fl(min(q, c));
+  }
+  for (int k = 0; k < MAX_P + 2; ++k) {
+    red[threadIdx.x] = f[k];
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+      if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0 && red[0]) atomicAdd(&st[k], red[0]);
+    __syncthreads();
+  }
+}
+
 __global__ __launch_bounds__(256) void k_mac_emit(TreeView t, MacView mv, int level, const int2* __restrict__ fr,
                                                   int nfr, const int* __restrict__ kid_scan,
                                                   const int* __restrict__ near_scan,
@@ -229,6 +267,14 @@ void launch_mac_classify(const TreeView& t, const MacView& mv, int level, const 
                          int* nearc, hipStream_t s) {
   if (nfr <= 0) return;
   hipLaunchKernelGGL(k_mac_classify, dim3(grid_of(nfr)), dim3(256), 0, s, t, mv, level, fr, nfr, acc, kid, nearc);
+  PFMM_LAUNCH_CHECK();
+}
+
+void launch_mac_flops(const TreeView& t, const MacView& mv, const int2* fr, int nfr, const int* acc,
+                      const unsigned char* dorder, int p, unsigned long long* st, hipStream_t s) {
+  if (nfr <= 0) return;
+  hipLaunchKernelGGL(k_mac_flops, dim3(std::min(grid_of(nfr), 1024)), dim3(256), 0, s, t, mv, fr, nfr, acc, dorder,
+                     p, st);
   PFMM_LAUNCH_CHECK();
 }
 

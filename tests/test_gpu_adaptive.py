@@ -183,11 +183,31 @@ def test_adaptive_solve_matches_oracle_fmm(api, precision):
     assert fe < 1.5 * fu
 
 
+@pytest.mark.parametrize("ws,p,slack", [(2, 6, 1), (1, 8, 0)])
+def test_adaptive_offset_orders_match_oracle(api, ws, p, slack):
+    """The ws lists' per-offset truncation orders (m2l_order_slack) on the adaptive octree: the same
+    orders as the oracle's offset_order for every accepted pair, so the fields agree to rounding."""
+    print(f"[case] adaptive offset orders ws={ws} p={p} slack={slack}", flush=True)
+    X, q, a, mu = _clumped(220, 330, 4)
+    s = api.Solver(order_p=p, ws=ws, leaf_width=LW, thole_a=THOLE, adaptive_leaf_max=10, m2l_order_slack=slack)
+    phi, E, Ed, G = s.field(T(X), T(q), T(mu), T(a))
+    ref = FM.fmm_fields(X, q, mu, a, THOLE, p, LW, ws, order_slack=slack, leaf_max=10)
+    plain = FM.fmm_fields(X, q, mu, a, THOLE, p, LW, ws, leaf_max=10)
+    assert relmax(ref["E_d"], plain["E_d"]) > 1e-9  # the truncation really differs
+    errs = [relmax(N(phi), ref["phi"]), relmax(N(E), ref["E_u"]), relmax(N(Ed), ref["E_d"]),
+            relmax(N(G), ref["G_d"])]
+    print(f"adaptive offset orders ws={ws} p={p} slack={slack}: field errors {max(errs):.1e}", flush=True)
+    assert max(errs) < 1e-11
+    sm = api.Solver(order_p=p, ws=ws, leaf_width=LW, thole_a=THOLE, adaptive_leaf_max=10, m2l_order_slack=slack,
+                    precision="mixed")
+    assert relmax(N(sm.field(T(X), T(q), T(mu), T(a))[2]), ref["E_d"]) < 1e-5
+
+
 def test_config_rules(api):
     with pytest.raises(api.PFMMError, match="INVALID_ARG"):
         api.Solver(order_p=10, adaptive_leaf_max=8)
     with pytest.raises(api.PFMMError, match="INVALID_ARG"):
-        api.Solver(order_p=6, adaptive_leaf_max=8, m2l_order_slack=1)
+        api.Solver(order_p=6, adaptive_leaf_max=8, mac_theta=0.5, m2l_order_slack=1)
     with pytest.raises(api.PFMMError, match="INVALID_ARG"):
         api.Solver(order_p=6, adaptive_leaf_max=-1)
 
@@ -195,8 +215,8 @@ def test_config_rules(api):
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_hexamer_shell_160k_adaptive_vs_full_oracle(api, precision):
     """Six 20k blobs at 0.1 per A^3 in a shell of 40k solvent sites at 0.03 per A^3 (p = 8, ws = 2,
-    5 A finest leaves): the adaptive octree (cells split above 32 particles) against the exact
-    solution of the direct-sum oracle, beside the uniform tree at the same settings."""
+    5 A finest leaves, order slack 2): the adaptive octree (cells split above 32 particles) against
+    the exact solution of the direct-sum oracle, beside the uniform tree at the same settings."""
     print(f"[case] adaptive hexamer shell 160k {precision}", flush=True)
     import os
     import torch
@@ -206,7 +226,7 @@ def test_hexamer_shell_160k_adaptive_vs_full_oracle(api, precision):
     out = {}
     for lmax in (0, 32):
         s = api.Solver(order_p=8, ws=2, leaf_width=5.0, scf_tol=1e-6, precond_cutoff=4.0, precision=precision,
-                       adaptive_leaf_max=lmax)
+                       m2l_order_slack=2, adaptive_leaf_max=lmax)
         s.solve(T(ps.pos), T(ps.q), T(ps.alpha))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
