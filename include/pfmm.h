@@ -136,9 +136,9 @@ typedef struct pfmm_config {
                           the largest distance from a cell's centre to one of its particles;
                           otherwise the pairs of their children are examined, down to the leaves,
                           whose pairs that are not accepted are summed directly.  Every M2L is at
-                          order p (m2l_order_slack must be -1; order_p at most 9) and runs in float64
-                          on both precision paths; ws no longer shapes the lists.  The Thole damping radius must not
-                          exceed the leaf edge.  Below 0.3 the offsets of accepted pairs outgrow the
+                          order p (m2l_order_slack must be -1; order_p at most 9), with the float32
+                          tiles of the mixed path as for the ws lists; ws no longer shapes the lists.
+                          The Thole damping radius must not exceed the leaf edge.  Below 0.3 the offsets of accepted pairs outgrow the
                           operator table (PFMM_ERR_INVALID_ARG).                                   */
   int mac_ndirect;     /* with mac_theta: a pair of cells holding fewer than this many particles
                           together is summed directly, whatever the criterion says (the paper's
@@ -157,9 +157,10 @@ typedef struct pfmm_config {
                           (mac_theta = 0; mac_ndirect and mac_leaf_direct unused) or the acceptance
                           criterion.  The expansions of cells below a leaf are exact translations of
                           the leaf's own and serve its interactions with finer neighbours.  The
-                          M2L runs in float64 (order_p at most 9) at the ws lists' per-offset orders
-                          (m2l_order_slack), or at order p with mac_theta; the Thole damping radius
-                          must not exceed ws leaf edges (leaf edges with mac_theta).               */
+                          M2L (order_p at most 9, float32 tiles on the mixed path) runs at the ws
+                          lists' per-offset orders (m2l_order_slack), or at order p with mac_theta;
+                          the Thole damping radius must not exceed ws leaf edges (leaf edges with
+                          mac_theta).                                                              */
 } pfmm_config;
 
 typedef struct pfmm_result {

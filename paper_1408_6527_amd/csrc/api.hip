@@ -259,7 +259,7 @@ struct pfmm_handle {
   bool mac = false;
   int leaf_max = 0;
   MacView mv;
-  DevBuf t_mdvec, m_renc, m_split, m_bad, m_acc, m_kid, m_accs, m_kids, m_stmp, m_stmp2, m_nt, m_ns, m_sort_tmp,
+  DevBuf t_mdvec, t_mdvec32, m_renc, m_split, m_bad, m_acc, m_kid, m_accs, m_kids, m_stmp, m_stmp2, m_nt, m_ns, m_sort_tmp,
       m_cnt, m_nkout, m_nvout, m_nptr, m_nearc, m_nears, m_nonleaf, m_lfirst, m_lcount, m_flops;
   DevBuf m_fr[2];
 };
@@ -471,7 +471,7 @@ void build_tree(pfmm_handle* h, int n, const double* pos, const double* q, const
   h->split_stride = rows * h->op.stride;
   double* M = dev<double>(h->w_M, rows * h->op.stride);
   dev<double>(h->w_F, rows * h->op.stride * h->nsplit);
-  if (c.precision == PFMM_MIXED && !h->mac) dev<float>(h->w_M32, rows * h->op.stride);
+  if (c.precision == PFMM_MIXED) dev<float>(h->w_M32, rows * h->op.stride);
   launch_fill_double(M + (int64_t)ncell * h->op.stride, h->op.stride, 0.0, s);
   h->n_evals = 0;
 }
@@ -719,15 +719,14 @@ void fmm_pass(pfmm_handle* h, int sources, int mode, FieldOut out, int* err, con
         for (int sp = 0; sp < h->nsplit; ++sp)
           launch_fill_double(F + sp * h->split_stride + (int64_t)t.off[t.L] * op.stride,
                              (int64_t)(t.ncell - t.off[t.L]) * op.stride, 0.0, s);
-      launch_m2l(t, op, h->nsplit, M, nullptr, F, h->split_stride, false, 0, done, qcap, s, &h->mv);
-    } else {
-      float* M32 = nullptr;
-      if (fp32) {
-        M32 = h->w_M32.as<float>();
-        launch_to_float(M, M32, ((int64_t)t.ncell + 1) * op.stride, done, s);
-      }
-      launch_m2l(t, op, h->nsplit, M, M32, F, h->split_stride, fp32, 3, done, qcap, s);
     }
+    float* M32 = nullptr;
+    if (fp32 && op.p <= MAX_P_MFMA) {
+      M32 = h->w_M32.as<float>();
+      launch_to_float(M, M32, ((int64_t)t.ncell + 1) * op.stride, done, s);
+    }
+    launch_m2l(t, op, h->nsplit, M, M32, F, h->split_stride, fp32 && op.p <= MAX_P_MFMA, 3, done, qcap, s,
+               h->mac ? &h->mv : nullptr);
     kt.end(KC_M2L, e);
     e = kt.begin();
     for (int lc = 2; lc <= t.L; ++lc) launch_l2l(t, op, lc, F, h->nsplit, h->split_stride, done, s);
@@ -1290,8 +1289,13 @@ pfmm_status pfmm_create(const pfmm_config* cfg, pfmm_handle** out) {
         mv.leaf_direct = 0;
         mv.Rp = cfg->ws;
       }
-      upload(h->t_mdvec, mac_operator_rows(T, 2 * mv.Rp + 1));
+      const std::vector<double> rows = mac_operator_rows(T, 2 * mv.Rp + 1);
+      upload(h->t_mdvec, rows);
       mv.dvec = h->t_mdvec.as<double>();
+      if (cfg->precision == PFMM_MIXED) {
+        upload(h->t_mdvec32, std::vector<float>(rows.begin(), rows.end()));
+        mv.dvec32 = h->t_mdvec32.as<float>();
+      }
     }
     PFMM_HIP(hipGetDevice(&h->device));
     // host staging for the small read-backs, so that later calls need not allocate it

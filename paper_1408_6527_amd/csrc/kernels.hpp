@@ -131,9 +131,9 @@ int m2l_tile_ncb(int p, bool fp32);
 // qcap (device, may be NULL): every offset's order is capped at *qcap.  M32: float32 copy of M,
 // read by the float32 launches of the mixed path (launch_to_float).
 struct MacView;
-// mac (may be NULL): the acceptance-criterion lists instead of the ws lists: the split partners of
-// each parent take the place of its colleagues and every child pair is tested with the criterion;
-// float64 on both paths, every M2L at order p (or the cap).
+// mac (may be NULL): the dual walk's lists instead of the ws lists: the split partners of each
+// parent take the place of its colleagues and every child pair is tested with the walk's rule; the
+// float32 tiles of the mixed path read mac->dvec32.
 void launch_m2l(const TreeView& t, const OpTables& op, int nsplit, const double* M, const float* M32,
                 double* F, int64_t split_stride, bool fp32, int fp64_max_level, const int* done,
                 const int* qcap, hipStream_t s, const MacView* mac = nullptr);
@@ -175,6 +175,7 @@ struct MacView {
   const double* renc = nullptr;
   const int* split = nullptr;
   const double* dvec = nullptr;
+  const float* dvec32 = nullptr;  // float copy of dvec (mixed path)
   const int* nonleaf = nullptr;
   const int* lfirst = nullptr;
   const int* lcount = nullptr;

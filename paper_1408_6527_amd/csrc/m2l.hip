@@ -23,7 +23,7 @@
 // (the two halves' shares of row block 0 are added through LDS first): no atomics, deterministic.
 //
 // FP64 path: v_mfma_f64_16x16x4f64.  Mixed path: v_mfma_f32_16x16x4f32 with float32 operands and
-// float32 accumulation, except for targets at levels <= fp64_max_level.
+// float32 accumulation, except for targets at levels <= fp64_max_level (both list kinds).
 #include <algorithm>
 #include <type_traits>
 #include <utility>
@@ -183,7 +183,6 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(m2l_waves_p
                                              double* __restrict__ F,
                                              int64_t split_stride, const int* done, const int* qcap) {
   if (done && *done) return;
-  static_assert(!(MAC && F32), "the acceptance-criterion M2L runs in float64");
   const int qc = qcap ? *qcap : P;  // order cap of a relaxed evaluation
   using kt = typename std::conditional<F32, float, double>::type;
   using kt2 = typename std::conditional<F32, float2, double2>::type;
@@ -259,7 +258,7 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(m2l_waves_p
   const int* colls = MAC ? mv.split : t.coll;
   const int R = 2 * ws + 1, cube = 2 * R + 1;
   const kt* dtab;
-  if constexpr (F32) dtab = op.dvec32; else dtab = MAC ? mv.dvec : op.dvec;
+  if constexpr (F32) dtab = MAC ? mv.dvec32 : op.dvec32; else dtab = MAC ? mv.dvec : op.dvec;
   const double wt = ldexp(t.w, t.L - (lp + 1));  // cell edge of the targets (MAC)
 
   constexpr const SchedHalves& HS = SchedHalvesOf<P>::value;
@@ -497,14 +496,25 @@ void m2l_dispatch(const TreeView& t, const OpTables& op, int nsplit, const doubl
                   double* F, int64_t split_stride, bool fp32, int fp64_max_level, const int* done,
                   const int* qcap, hipStream_t s, const MacView* mac) {
   if (mac) {
-    // parents of levels [1, L - 1] (L - 2 when leaf pairs are direct), float64 on both paths.  At
-    // order 10 the accumulators of a tile leave no registers for the criterion's masks.
+    // parents of levels [1, L - 1] (L - 2 when leaf pairs are direct); on the mixed path float32
+    // tiles below fp64_max_level, as for the ws lists.  At order 10 the accumulators of a tile leave
+    // no registers for the rule's masks.
     if constexpr (P <= MAX_P_MAC) {
-      const int hi = t.L - 1 - (mac->leaf_direct ? 1 : 0);
-      const int nt = m2l_tiles(t, 1, hi, 1);
-      if (nt > 0)
-        hipLaunchKernelGGL((k_m2l<P, false, true>), dim3(nt * nsplit), dim3(TPB), 0, s, t, op, *mac, 1, hi, nsplit,
-                           M, M32, F, split_stride, done, qcap);
+      const int lo = 1, hi = t.L - 1 - (mac->leaf_direct ? 1 : 0);
+      const int hi64 = fp32 ? std::min(hi, fp64_max_level - 1) : hi;
+      if (hi64 >= lo) {
+        const int nt = m2l_tiles(t, lo, hi64, 1);
+        if (nt > 0)
+          hipLaunchKernelGGL((k_m2l<P, false, true>), dim3(nt * nsplit), dim3(TPB), 0, s, t, op, *mac, lo, hi64,
+                             nsplit, M, M32, F, split_stride, done, qcap);
+      }
+      const int lo32 = std::max(lo, hi64 + 1);
+      if (fp32 && hi >= lo32) {
+        const int nt = m2l_tiles(t, lo32, hi, 1);
+        if (nt > 0)
+          hipLaunchKernelGGL((k_m2l<P, true, true>), dim3(nt * nsplit), dim3(TPB), 0, s, t, op, *mac, lo32, hi,
+                             nsplit, M, M32, F, split_stride, done, qcap);
+      }
     } else {
       throw Error(PFMM_ERR_INVALID_ARG, "the dual-walk lists (mac_theta, adaptive_leaf_max) support order_p up to 9");
     }
@@ -660,7 +670,8 @@ void launch_m2l(const TreeView& t, const OpTables& op, int nsplit, const double*
     PFMM_LAUNCH_CHECK();
     return;
   }
-  if (!mac && fp32 && (!op.dvec32 || !M32)) throw Error(PFMM_ERR_INVALID_ARG, "internal: float32 M2L inputs missing");
+  if (fp32 && (!(mac ? mac->dvec32 : op.dvec32) || !M32))
+    throw Error(PFMM_ERR_INVALID_ARG, "internal: float32 M2L inputs missing");
   switch (op.p) {
 #define PFMM_M2L_CASE(PP)                                                                               \
   case PP:                                                                                              \

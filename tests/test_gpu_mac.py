@@ -114,6 +114,12 @@ def test_mac_fields_and_lists_match_oracle(api, n, side, lw, thole, theta, p, nd
           f"(oracle {npairs}), field errors {max(errs):.1e}", flush=True)
     assert max(errs) < 1e-11
     assert r.stats["n_m2l"] == nm and r.stats["n_p2p"] == npairs
+    # the mixed path: float32 M2L tiles below level 4 and float32 P2P on the same lists
+    sm = api.Solver(scf_tol=1e-10, precision="mixed", **kw)
+    Edm = N(sm.field(T(X), T(q), T(mu), T(a))[2])
+    em = float(np.linalg.norm(Edm - ref["E_d"]) / np.linalg.norm(ref["E_d"]))
+    print(f"mac fields theta={theta} mixed: E_d error {em:.1e}", flush=True)
+    assert em < 1e-5
 
 
 @pytest.mark.parametrize("theta", [None, 0.5])
