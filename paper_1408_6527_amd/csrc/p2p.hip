@@ -193,6 +193,39 @@ __global__ __launch_bounds__(TPB) void k_p2p(TreeView t, Particles pa, const dou
         // DAMP: the chunk may hold pairs inside a damping cone; otherwise v = 1 for every pair
         auto chunk = [&](auto dampc) {
           constexpr bool DAMP = decltype(dampc)::value;
+          if constexpr (MODE == 3) {
+            // The cutoff keeps about a tenth of the staged sources: mark the lane's sources inside it
+            // (at most 64: m <= 64), then evaluate those alone, in the same order; the others would
+            // add exact zeros.
+            unsigned long long in = 0ULL;
+  #pragma unroll 4
+            for (int jj = slice, b = 0; jj < m; jj += G, ++b) {
+              const T rx = xi - sx[jj], ry = yi - sy[jj], rz = zi - sz[jj];
+              const T r2 = rx * rx + ry * ry + rz * rz;
+              if (r2 > T(0) && r2 < rc2) in |= 1ULL << b;
+            }
+            while (in) {
+              const int jj = slice + __builtin_ctzll(in) * G;
+              in &= in - 1ULL;
+              const T rx = xi - sx[jj], ry = yi - sy[jj], rz = zi - sz[jj];
+              const T r2 = rx * rx + ry * ry + rz * rz;
+              const T rinv = rsqrt_t(r2), rinv2 = rinv * rinv, rinv3 = rinv * rinv2;
+              const T mx = smx[jj], my = smy[jj], mz = smz[jj];
+              const T rmu = rx * mx + ry * my + rz * mz;
+              T v = T(1), v4 = T(1);
+              if constexpr (DAMP) {
+                const T ii = iti * sit[jj];
+                v = ii > T(0) ? fmin(r2 * rinv * ii, T(1)) : T(1);
+                v4 = v * v * v * v;
+              }
+              const T fe = DAMP ? v * v * v * (T(4) - T(3) * v) : T(1);
+              const T c3 = T(3) * v4 * rmu * rinv2;
+              edx += (c3 * rx - fe * mx) * rinv3;
+              edy += (c3 * ry - fe * my) * rinv3;
+              edz += (c3 * rz - fe * mz) * rinv3;
+            }
+            return;
+          }
   #pragma unroll 4
           for (int jj = slice; jj < m; jj += G) {
             const T rx = xi - sx[jj], ry = yi - sy[jj], rz = zi - sz[jj];
