@@ -203,6 +203,43 @@ def test_adaptive_offset_orders_match_oracle(api, ws, p, slack):
     assert relmax(N(sm.field(T(X), T(q), T(mu), T(a))[2]), ref["E_d"]) < 1e-5
 
 
+def test_adaptive_edge_cases(api):
+    """Sizes 0, 1 and 2; every particle in one cell; leaf_max = 1 (the deepest tree the balance
+    allows); two clusters far apart with nothing between them: the library against the oracle."""
+    print("[case] adaptive edge cases", flush=True)
+    import torch
+    s = api.Solver(order_p=4, ws=1, leaf_width=LW, adaptive_leaf_max=8)
+    z = torch.zeros((0, 3), dtype=torch.float64, device="cuda")
+    r = s.solve(z, torch.zeros(0, dtype=torch.float64, device="cuda"), torch.zeros(0, dtype=torch.float64, device="cuda"))
+    assert r.U == 0.0 and r.mu.shape == (0, 3)
+    r = s.solve(T([[1.0, 2.0, 3.0]]), T([0.7]), T([1.2]))
+    assert r.U == 0.0 and np.all(N(r.mu) == 0) and np.all(N(r.forces) == 0)
+    X2 = np.array([[0.0, 0.0, 0.0], [0.0, 0.0, 3.1]])
+    r = api.Solver(order_p=4, ws=1, scf_tol=1e-14, thole_a=0.0, adaptive_leaf_max=1).solve(
+        T(X2), T([0.7, -0.4]), T([1.3, 0.9]))
+    ref = D.solve(X2, np.array([0.7, -0.4]), np.array([1.3, 0.9]), thole_a=0.0)
+    assert relmax(N(r.mu), ref["mu"]) < 1e-13
+    rng = np.random.default_rng(11)
+    # every particle in one finest cell
+    Xc = rng.uniform(0.0, 2.0, (40, 3))
+    qc, ac, mc = rng.normal(0, 0.5, 40), rng.uniform(0.1, 0.3, 40), rng.normal(0, 0.2, (40, 3))
+    fc = api.Solver(order_p=4, ws=1, leaf_width=LW, thole_a=0.0, adaptive_leaf_max=4).field(T(Xc), T(qc), T(mc), T(ac))
+    pq, Eq, _ = D.charge_fields(Xc, qc)
+    pm, Eu, _, _ = D.dipole_fields(Xc, mc, ac, 0.0)
+    assert relmax(N(fc[1]), Eq + Eu) < 1e-12
+    # leaf_max = 1, and two clusters 150 A apart
+    X, q, a, mu = _clumped(150, 150, 12)
+    Xf = np.vstack([X[:150], X[150:] + np.array([150.0, 0.0, 0.0])])
+    for Xs, lmax in ((X, 1), (Xf, 10)):
+        f = api.Solver(order_p=4, ws=1, leaf_width=LW, thole_a=THOLE, adaptive_leaf_max=lmax).field(
+            T(Xs), T(q), T(mu), T(a))
+        ref = FM.fmm_fields(Xs, q, mu, a, THOLE, 4, LW, 1, leaf_max=lmax)
+        err = max(relmax(N(f[0]), ref["phi"]), relmax(N(f[1]), ref["E_u"]), relmax(N(f[2]), ref["E_d"]),
+                  relmax(N(f[3]), ref["G_d"]))
+        print(f"adaptive edge leaf_max={lmax} levels {ref['tree'].L}: field errors {err:.1e}", flush=True)
+        assert err < 1e-11
+
+
 def test_config_rules(api):
     with pytest.raises(api.PFMMError, match="INVALID_ARG"):
         api.Solver(order_p=10, adaptive_leaf_max=8)

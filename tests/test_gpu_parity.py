@@ -359,6 +359,20 @@ def test_solve_error_falls_with_order(api):
     assert errs[-1] < 1e-3
 
 
+def test_solve_high_orders_against_dense_oracle(api):
+    """Solves at orders 8, 10 and 12 (the last on the vector M2L) against the dense oracle: the force
+    error keeps falling with the order."""
+    print_case("solve error at high orders")
+    X, q, a, _ = cube(500, 16.0, 6)
+    ref = D.solve(X, q, a, thole_a=2.0)
+    errs = []
+    for p in (8, 10, 12):
+        r = api.Solver(order_p=p, ws=2, leaf_width=1.5, scf_tol=1e-11).solve(T(X), T(q), T(a))
+        errs.append(relnorm(N(r.forces), ref["F"]))
+    print("force error at p = 8, 10, 12 (ws=2):", errs, flush=True)
+    assert errs[2] < errs[1] < errs[0] and errs[2] < errs[0] / 3
+
+
 def test_backward_gradients_match_oracle(api):
     print_case("backward one leaf")
     X, q, a, _ = cube(120, 7.5, 7)
