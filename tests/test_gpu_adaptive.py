@@ -240,6 +240,34 @@ def test_adaptive_edge_cases(api):
         assert err < 1e-11
 
 
+def test_adaptive_with_exclusions_and_site_tree(api):
+    """The adaptive lists with excluded pairs (1-2 and 1-3 pairs of a chain through the particle
+    order and two far pairs) against the oracle's FMM with the same exclusions; and the dipole solve
+    on a tree of the polarisable sites (a third of the particles), also adaptive, against the single
+    adaptive tree."""
+    print("[case] adaptive exclusions and site tree", flush=True)
+    X, q, a, mu = _clumped(220, 330, 6)
+    n = len(X)
+    excl = [(i, i + 1) for i in range(n - 1)] + [(i, i + 2) for i in range(n - 2)] + [(3, 500), (10, 540)]
+    s = api.Solver(order_p=5, ws=1, leaf_width=LW, thole_a=THOLE, adaptive_leaf_max=8)
+    s.set_exclusions(n, excl)
+    f = s.field(T(X), T(q), T(mu), T(a))
+    ref = FM.fmm_fields(X, q, mu, a, THOLE, 5, LW, 1, excl=excl, leaf_max=8)
+    err = max(relmax(N(f[0]), ref["phi"]), relmax(N(f[1]), ref["E_u"]), relmax(N(f[2]), ref["E_d"]),
+              relmax(N(f[3]), ref["G_d"]))
+    print(f"adaptive exclusions: field errors {err:.1e}", flush=True)
+    assert err < 1e-11
+    a3 = a.copy()
+    a3[np.random.default_rng(7).permutation(n) >= n // 3] = 0.0
+    kw = dict(order_p=6, ws=2, leaf_width=LW, scf_tol=1e-9, adaptive_leaf_max=10)
+    r1 = api.Solver(**kw).solve(T(X), T(q), T(a3))
+    r2 = api.Solver(dipole_tree=1, **kw).solve(T(X), T(q), T(a3))
+    d = float(np.linalg.norm(N(r2.forces) - N(r1.forces)) / np.linalg.norm(N(r1.forces)))
+    print(f"adaptive site tree: {r2.stats['n_sites']} sites, force difference from the single tree {d:.2e}",
+          flush=True)
+    assert r2.stats["n_sites"] == int(np.sum(a3 > 0)) and d < 1e-3
+
+
 def test_config_rules(api):
     with pytest.raises(api.PFMMError, match="INVALID_ARG"):
         api.Solver(order_p=10, adaptive_leaf_max=8)
