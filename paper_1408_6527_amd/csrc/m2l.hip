@@ -277,6 +277,10 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(m2l_waves_p
   // the multipoles (half the registers and bytes of the float64 rows).
   double2 pre[F32 ? 1 : PF];
   float4 pre4[F32 ? PF4 : 1];
+  // The schedules of orders <= min(P, cap) read the coefficients below count(that order), rounded up
+  // to whole step pairs (8): a capped launch loads only those pieces of each source row (the rest
+  // of the staged row is never read).
+  const int nread = (mi_count(min(P, qc)) + 7) / 8 * 8;
   auto prefetch = [&](int r) {
     if constexpr (F32) {
 #pragma unroll
@@ -286,7 +290,7 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(m2l_waves_p
         if (e < ROWS * QUART) {
           const int row = e / QUART, h = e - row * QUART;
           const int src = sSrc[r][row];
-          if (src >= 0) v = reinterpret_cast<const float4*>(M32 + (int64_t)src * STRIDE)[h];
+          if (src >= 0 && 4 * h < nread) v = reinterpret_cast<const float4*>(M32 + (int64_t)src * STRIDE)[h];
         }
         pre4[i] = v;
       }
@@ -298,7 +302,7 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(m2l_waves_p
         if (e < ROWS * HALF) {
           const int row = e / HALF, h = e - row * HALF;
           const int src = sSrc[r][row];
-          if (src >= 0) v = reinterpret_cast<const double2*>(M + (int64_t)src * STRIDE)[h];
+          if (src >= 0 && 2 * h < nread) v = reinterpret_cast<const double2*>(M + (int64_t)src * STRIDE)[h];
         }
         pre[i] = v;
       }
