@@ -202,7 +202,7 @@ struct pfmm_handle {
   OpTables op;
   int device = 0;
   // constant tables
-  DevBuf t_mi, t_p2m, t_ifact, t_l2p, t_code, t_dvec, t_dvec32, t_hidx, t_dorder;
+  DevBuf t_mi, t_p2m, t_ifact, t_l2p, t_code, t_dvec, t_dvec32, t_hidx, t_dorder, t_slotq;
   // tree workspace
   DevBuf w_partial, w_flags, w_bbox, w_keys_in, w_keys, w_vals_in, w_perm, w_sort_tmp, w_scan_tmp,
       w_lvl_flags, w_cid, w_counts, w_ckey, w_cfirst, w_ccount, w_cparent, w_child8, w_coll, w_stats;
@@ -1248,6 +1248,7 @@ pfmm_status pfmm_create(const pfmm_config* cfg, pfmm_handle** out) {
     upload(h->t_dvec, T.dvec);
     upload(h->t_hidx, T.hidx);
     upload(h->t_dorder, T.dorder);
+    upload(h->t_slotq, T.slotq);
     if (cfg->precision == PFMM_MIXED) {
       std::vector<float> d32(T.dvec.begin(), T.dvec.end());
       upload(h->t_dvec32, d32);
@@ -1264,6 +1265,7 @@ pfmm_status pfmm_create(const pfmm_config* cfg, pfmm_handle** out) {
     op.dvec32 = cfg->precision == PFMM_MIXED ? h->t_dvec32.as<float>() : nullptr;
     op.hidx = h->t_hidx.as<unsigned short>();
     op.dorder = h->t_dorder.as<unsigned char>();
+    op.slotq = h->t_slotq.as<unsigned char>();
     op.nblocks = T.nblocks;
     if (cfg->mac_theta > 0.0 || cfg->adaptive_leaf_max > 0) {
       h->mac = true;

@@ -103,6 +103,7 @@ struct OpTables {
   // (one index into such a row per MFMA block and lane, schedule.hpp)
   const double* dvec = nullptr; const float* dvec32 = nullptr; const unsigned short* hidx = nullptr;
   const unsigned char* dorder = nullptr;  // truncation order per offset slot
+  const unsigned char* slotq = nullptr;   // highest order per (colleague offset, source octant)
   int nblocks = 0;
 };
 // sources: 1 = charges (P.w), 2 = dipoles (mu4), 3 = both

@@ -277,11 +277,16 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(m2l_waves_p
   // the multipoles (half the registers and bytes of the float64 rows).
   double2 pre[F32 ? 1 : PF];
   float4 pre4[F32 ? PF4 : 1];
-  // The schedules of orders <= min(P, cap) read the coefficients below count(that order), rounded up
-  // to whole step pairs (8): a capped launch loads only those pieces of each source row (the rest
-  // of the staged row is never read).
-  const int nread = (mi_count(min(P, qc)) + 7) / 8 * 8;
+  // The schedule of order q reads the coefficients below count(q), rounded up to whole step pairs
+  // (8), so a slot loads only those pieces of each source row, for the highest order among its
+  // target octants (op.slotq, with the ws lists' per-offset orders) and at most the cap; the rest
+  // of the staged row is never read.
+  // (the float32 tiles, two column blocks, have no registers to spare for the per-slot bound: they
+  // take the cap's alone)
+  __shared__ int sNread[8];  // coefficients to load per source octant of the current offset
+  const int nread_cap = (mi_count(min(P, qc)) + 7) / 8 * 8;
   auto prefetch = [&](int r) {
+    const int nread = F32 ? nread_cap : sNread[r];
     if constexpr (F32) {
 #pragma unroll
       for (int i = 0; i < PF4; ++i) {
@@ -352,6 +357,10 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(m2l_waves_p
         if (S >= 0) src = t.child8[8 * S + r];
       }
       sSrc[r][c] = src;
+    }
+    if (!F32 && threadIdx.x < 8) {
+      const int qs = MAC && mv.use_theta ? min(P, qc) : min((int)op.slotq[ci * 8 + threadIdx.x], qc);
+      sNread[threadIdx.x] = (mi_count(qs) + 7) / 8 * 8;
     }
     __syncthreads();
     unsigned live = 0;  // source octants with at least one source (same value in every thread)

@@ -188,6 +188,26 @@ void HostTables::build(int p_, int ws_, int order_slack) {
         std::copy(Dn.begin(), Dn.end(), dvec.begin() + (size_t)slot * dpitch);
         dorder[slot] = (unsigned char)offset_order(d, p, ws, order_slack);
       }
+  {
+    const int side = 2 * ws + 1, nn = side * side * side;
+    slotq.assign((size_t)nn * 8, 0);
+    for (int ci = 0; ci < nn; ++ci) {
+      const int e[3] = {ci / (side * side) - ws, (ci / side) % side - ws, ci % side - ws};
+      for (int c = 0; c < 8; ++c) {
+        int qm = 0;
+        for (int o = 0; o < 8; ++o) {
+          int d[3], cheb = 0;
+          for (int a = 0; a < 3; ++a) {
+            d[a] = ((o >> (2 - a)) & 1) - ((c >> (2 - a)) & 1) - 2 * e[a];
+            cheb = std::max(cheb, std::abs(d[a]));
+          }
+          if (cheb <= ws) continue;
+          qm = std::max(qm, (int)dorder[((d[0] + R) * cube + (d[1] + R)) * cube + (d[2] + R)]);
+        }
+        slotq[(size_t)ci * 8 + c] = (unsigned char)qm;
+      }
+    }
+  }
   std::vector<int> degv(nc);
   for (int k = 0; k < nc; ++k) degv[k] = ix.deg(k);
   const int nrb = sched_nrb(p);

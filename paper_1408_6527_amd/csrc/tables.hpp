@@ -35,6 +35,9 @@ struct HostTables {
 
   // truncation order of the M2L per offset slot (0 for the near slots), see offset_order()
   std::vector<unsigned char> dorder;
+  // per colleague offset e (index ((e + ws) (2 ws + 1) + ...)) and source octant c: the highest order
+  // over the eight target octants o of the offsets d = o - c - 2 e that interact (0 if none)
+  std::vector<unsigned char> slotq;
 
   void build(int p, int ws, int order_slack);
 };
