@@ -40,6 +40,7 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 constexpr int TPB = 512;  // 8 waves: 4 octant pairs x 2 row halves
+constexpr int M2L_XCD_TILES = 2;  // tiles per XCD chunk (k_m2l)
 constexpr int NU = 27;    // u = oB - c in [-1, 1]^3
 
 // The blocks of the order-P schedule (schedule.hpp) that a truncation at order Q <= P needs (rows
@@ -178,7 +179,7 @@ constexpr int m2l_waves_per_eu() { return 2; }
 // is tested with the walk's acceptance rule (mac.hpp); the columns of pairs that are not accepted
 // multiply zero source coefficients.  Every M2L at order P or the cap.
 template <int P, bool F32, bool MAC>
-__global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(m2l_waves_per_eu<P, F32>()))) void k_m2l(TreeView t, OpTables op, MacView mv, int lp_lo, int lp_hi, int nsplit,
+__global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(m2l_waves_per_eu<P, F32>()))) void k_m2l(TreeView t, OpTables op, MacView mv, int lp_lo, int lp_hi, int nsplit, int nwork,
                                              const double* __restrict__ M, const float* __restrict__ M32,
                                              double* __restrict__ F,
                                              int64_t split_stride, const int* done, const int* qcap) {
@@ -223,10 +224,16 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(m2l_waves_p
   const int pair = half == 0 ? simd : (simd ^ 1);
   constexpr int PAIRS[4][2] = {{0, 3}, {5, 6}, {1, 2}, {4, 7}};
   const int oc[2] = {PAIRS[pair][0], PAIRS[pair][1]};
-  const int split = blockIdx.x % nsplit;
+  // XCD-aware order: the dispatcher hands workgroup b to XCD b % 8, so chunks of M2L_XCD_TILES
+  // consecutive tiles (Morton-adjacent parents, which share most of their source rows) go to one XCD
+  // in turn and meet in its L2; the chunks still run in tile order across the chip
+  const int chunk = M2L_XCD_TILES * nsplit;
+  const int wg = (((int)(blockIdx.x >> 3) / chunk) * 8 + (int)(blockIdx.x & 7)) * chunk + (int)(blockIdx.x >> 3) % chunk;
+  if (wg >= nwork) return;  // padding of the last chunks: whole workgroup, before any barrier
+  const int split = wg % nsplit;
   // finest level first: the coarse levels' tiles, fewer and lighter (their colleagues often fall
   // outside the occupied region), fill the end of the launch
-  int tile = blockIdx.x / nsplit, lp = lp_hi;
+  int tile = wg / nsplit, lp = lp_hi;
   for (; lp >= lp_lo; --lp) {
     const int nt = (t.off[lp + 1] - t.off[lp] + ROWS - 1) / ROWS;
     if (tile < nt) break;
@@ -504,6 +511,12 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(m2l_waves_p
   }
 }
 
+// workgroups of a launch of nt tiles: whole chunks of M2L_XCD_TILES tiles on each of the 8 XCDs
+int m2l_grid(int nt, int nsplit) {
+  const int per = 8 * M2L_XCD_TILES * nsplit;
+  return (nt * nsplit + per - 1) / per * per;
+}
+
 template <int P>
 void m2l_dispatch(const TreeView& t, const OpTables& op, int nsplit, const double* M, const float* M32,
                   double* F, int64_t split_stride, bool fp32, int fp64_max_level, const int* done,
@@ -518,15 +531,13 @@ void m2l_dispatch(const TreeView& t, const OpTables& op, int nsplit, const doubl
       if (hi64 >= lo) {
         const int nt = m2l_tiles(t, lo, hi64, 1);
         if (nt > 0)
-          hipLaunchKernelGGL((k_m2l<P, false, true>), dim3(nt * nsplit), dim3(TPB), 0, s, t, op, *mac, lo, hi64,
-                             nsplit, M, M32, F, split_stride, done, qcap);
+          hipLaunchKernelGGL((k_m2l<P, false, true>), dim3(m2l_grid(nt, nsplit)), dim3(TPB), 0, s, t, op, *mac, lo, hi64, nsplit, nt * nsplit, M, M32, F, split_stride, done, qcap);
       }
       const int lo32 = std::max(lo, hi64 + 1);
       if (fp32 && hi >= lo32) {
         const int nt = m2l_tiles(t, lo32, hi, 1);
         if (nt > 0)
-          hipLaunchKernelGGL((k_m2l<P, true, true>), dim3(nt * nsplit), dim3(TPB), 0, s, t, op, *mac, lo32, hi,
-                             nsplit, M, M32, F, split_stride, done, qcap);
+          hipLaunchKernelGGL((k_m2l<P, true, true>), dim3(m2l_grid(nt, nsplit)), dim3(TPB), 0, s, t, op, *mac, lo32, hi, nsplit, nt * nsplit, M, M32, F, split_stride, done, qcap);
       }
     } else {
       throw Error(PFMM_ERR_INVALID_ARG, "the dual-walk lists (mac_theta, adaptive_leaf_max) support order_p up to 9");
@@ -539,16 +550,14 @@ void m2l_dispatch(const TreeView& t, const OpTables& op, int nsplit, const doubl
   if (hi64 >= lo) {
     const int nt = m2l_tiles(t, lo, hi64, m2l_ncb<P, false>());
     if (nt > 0)
-      hipLaunchKernelGGL((k_m2l<P, false, false>), dim3(nt * nsplit), dim3(TPB), 0, s, t, op, MacView(), lo, hi64,
-                         nsplit, M, M32, F, split_stride, done, qcap);
+      hipLaunchKernelGGL((k_m2l<P, false, false>), dim3(m2l_grid(nt, nsplit)), dim3(TPB), 0, s, t, op, MacView(), lo, hi64, nsplit, nt * nsplit, M, M32, F, split_stride, done, qcap);
   }
   if (fp32) {
     const int lo32 = std::max(lo, hi64 + 1);
     if (hi >= lo32) {
       const int nt = m2l_tiles(t, lo32, hi, m2l_ncb<P, true>());
       if (nt > 0)
-        hipLaunchKernelGGL((k_m2l<P, true, false>), dim3(nt * nsplit), dim3(TPB), 0, s, t, op, MacView(), lo32, hi,
-                           nsplit, M, M32, F, split_stride, done, qcap);
+        hipLaunchKernelGGL((k_m2l<P, true, false>), dim3(m2l_grid(nt, nsplit)), dim3(TPB), 0, s, t, op, MacView(), lo32, hi, nsplit, nt * nsplit, M, M32, F, split_stride, done, qcap);
     }
   }
 }
