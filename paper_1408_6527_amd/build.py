@@ -48,9 +48,10 @@ def _scratch_users(remarks: str):
     return out
 
 
-# The M2L schedule is one fully unrolled, compile-time table-driven loop per truncation order; its
+# The M2L schedule and the fixed-order L2P are fully unrolled, compile-time table-driven loops; their
 # unrolled size exceeds the default limit for pragma-directed unrolling at the higher orders.
-EXTRA = {"m2l.hip": ["-mllvm", "-pragma-unroll-threshold=60000"]}
+EXTRA = {"m2l.hip": ["-mllvm", "-pragma-unroll-threshold=60000"],
+         "expansions.hip": ["-mllvm", "-pragma-unroll-threshold=200000"]}
 
 
 def _compile(src: str) -> str:

@@ -8,6 +8,8 @@
 //        d_a E_b = -(1/w^3) sum rho^n/n! F~_{n+e_a+e_b}
 // with M~_n = M_n / w^|n| and F~_n = F_n w^(|n|+1) for the cell edge w of the level.
 // All four are memory-bound; they run in float64 on both precision paths.
+#include <utility>
+
 #include "kernels.hpp"
 #include "morton.hpp"
 #include "schedule.hpp"
@@ -261,6 +263,7 @@ __global__ __launch_bounds__(SH_TPB) void k_l2l(TreeView t, OpTables op, int lc,
 
 constexpr int L2P_TPB = 64;
 
+// Orders above MAX_P_MFMA (k_l2p_fixed below serves the others).
 // One wavefront per leaf.  A leaf holds few particles at protein density, so each particle is
 // served by G = 64 / T lanes (T = the leaf occupancy rounded up to a power of two), each lane taking
 // every G-th coefficient; the partial sums are combined by a fixed butterfly of cross-lane
@@ -363,6 +366,118 @@ __global__ __launch_bounds__(L2P_TPB) void k_l2p(TreeView t, OpTables op, Partic
   }
 }
 
+// L2P at a compile-time order (orders up to MAX_P_MFMA).  The coefficient loop unrolls into
+// straight-line code whose exponents and F~ indices are constants, so neither the per-coefficient
+// table nor the powers need LDS.  The coefficients are visited x-major (n_x, then n_y, then n_z
+// ascending), so each rho^n / n! follows from the previous one by one factor rho_a / n_a, and only
+// three running products stay live.  Half a wavefront serves one leaf, 32 particles at a time; a
+// workgroup serves 8 consecutive leaves, whose F~ rows it stages in LDS (18 KB at p = 10).  The sums,
+// and MODE, are those of k_l2p.
+constexpr int L2PF_TPB = 256, L2PF_LANES = 32, L2PF_LEAVES = L2PF_TPB / L2PF_LANES;
+constexpr int L2PF_MIN_WAVES = 4;  // waves per SIMD the register budget must allow
+
+// the multi-indices of degree <= D in x-major order
+template <int D>
+struct MiXMajor {
+  int x[mi_count(D)], y[mi_count(D)], z[mi_count(D)];
+  constexpr MiXMajor() : x(), y(), z() {
+    int k = 0;
+    for (int nx = 0; nx <= D; ++nx)
+      for (int ny = 0; ny <= D - nx; ++ny)
+        for (int nz = 0; nz <= D - nx - ny; ++nz) {
+          x[k] = nx;
+          y[k] = ny;
+          z[k] = nz;
+          ++k;
+        }
+  }
+};
+
+template <int MODE, int P>
+__global__ __launch_bounds__(L2PF_TPB, L2PF_MIN_WAVES) void k_l2p_fixed(TreeView t, int stride, Particles pa,
+                                                                        const double* __restrict__ F,
+                                                                        FieldOut out, const int* done) {
+  if (done && *done) return;
+  constexpr int NC = mi_count(P);
+  constexpr int D = MODE == 1 ? P : P - 1;  // MODE 0 skips the degree-P coefficients
+  __shared__ double sF[L2PF_LEAVES][NC];
+  const int g0 = t.off[t.L] + blockIdx.x * L2PF_LEAVES;
+  const int nl = min(L2PF_LEAVES, t.off[t.L + 1] - g0);
+  for (int e = threadIdx.x; e < nl * NC; e += L2PF_TPB) {
+    const int l = e / NC, k = e - l * NC;
+    sF[l][k] = F[(int64_t)(g0 + l) * stride + k];
+  }
+  __syncthreads();
+  const int l = threadIdx.x / L2PF_LANES, slot = threadIdx.x % L2PF_LANES;
+  if (l >= nl) return;
+  const int g = g0 + l;
+  const int first = t.first[g], cnt = t.count[g];
+  double c[3], w;
+  cell_centre(t, g, t.L, c, w);
+  const double iw = 1.0 / w;
+  const double* Fl = sF[l];
+  constexpr MiXMajor<D> mx{};
+#pragma unroll 1
+  for (int li = slot; li < cnt; li += L2PF_LANES) {
+    const int i = first + li;
+    const double4 Pi = pa.P[i];
+    const double rx = (Pi.x - c[0]) * iw, ry = (Pi.y - c[1]) * iw, rz = (Pi.z - c[2]) * iw;
+    double phi = 0.0, ex = 0.0, ey = 0.0, ez = 0.0;
+    double gxx = 0.0, gyy = 0.0, gzz = 0.0, gxy = 0.0, gxz = 0.0, gyz = 0.0;
+    double a = 1.0, b = 1.0, m = 1.0;  // rho_x^nx/nx!, times rho_y^ny/ny!, times rho_z^nz/nz!
+#pragma unroll
+    for (int k = 0; k < mi_count(D); ++k) {
+      const int x = mx.x[k], y = mx.y[k], z = mx.z[k];
+      // a compiler-only fence at the start of each run of n_z: the LDS reads of one run are not
+      // merged with, or hoisted into, another's, which would keep them live across the body
+      if (z == 0) __asm__ volatile("" ::: "memory");
+      if (z > 0) {
+        m = m * (rz * (1.0 / z));
+      } else if (y > 0) {
+        b = b * (ry * (1.0 / y));
+        m = b;
+      } else if (x > 0) {
+        a = a * (rx * (1.0 / x));
+        b = a;
+        m = a;
+      }
+      if (MODE == 1) phi += m * Fl[mi_index(x, y, z)];
+      if (x + y + z <= P - 1) {
+        ex -= m * Fl[mi_index(x + 1, y, z)];
+        ey -= m * Fl[mi_index(x, y + 1, z)];
+        ez -= m * Fl[mi_index(x, y, z + 1)];
+        if (MODE == 1 && x + y + z <= P - 2) {
+          gxx -= m * Fl[mi_index(x + 2, y, z)];
+          gyy -= m * Fl[mi_index(x, y + 2, z)];
+          gzz -= m * Fl[mi_index(x, y, z + 2)];
+          gxy -= m * Fl[mi_index(x + 1, y + 1, z)];
+          gxz -= m * Fl[mi_index(x + 1, y, z + 1)];
+          gyz -= m * Fl[mi_index(x, y + 1, z + 1)];
+        }
+      }
+    }
+    const double iw2 = iw * iw, iw3 = iw2 * iw;
+    ex *= iw2; ey *= iw2; ez *= iw2;
+    out.Ed[3 * i] = ex; out.Ed[3 * i + 1] = ey; out.Ed[3 * i + 2] = ez;
+    if (MODE == 1) {
+      out.phi[i] = phi * iw;
+      out.Eu[3 * i] = ex; out.Eu[3 * i + 1] = ey; out.Eu[3 * i + 2] = ez;
+      double* G6 = out.G + 6 * (int64_t)i;
+      G6[0] = gxx * iw3; G6[1] = gyy * iw3; G6[2] = gzz * iw3;
+      G6[3] = gxy * iw3; G6[4] = gxz * iw3; G6[5] = gyz * iw3;
+    }
+  }
+}
+
+typedef void (*L2PFixedKernel)(TreeView, int, Particles, const double*, FieldOut, const int*);
+
+template <int MODE, int... Ps>
+L2PFixedKernel l2p_fixed_kernel(int p, std::integer_sequence<int, Ps...>) {
+  L2PFixedKernel k = nullptr;
+  ((p == Ps + 1 ? (void)(k = &k_l2p_fixed<MODE, Ps + 1>) : (void)0), ...);
+  return k;
+}
+
 }  // namespace
 
 // The kernels' LDS and registers are sized for an order class: orders up to MAX_P_MFMA, the
@@ -405,10 +520,17 @@ void launch_l2p(const TreeView& t, const OpTables& op, const Particles& pa, cons
                 FieldOut out, const int* done, hipStream_t s) {
   const int nleaf = t.off[t.L + 1] - t.off[t.L];
   if (nleaf <= 0) return;
-  if (op.p > PM_HI || op.nc > mi_count(PM_HI)) throw Error(PFMM_ERR_INVALID_ARG, "order_p out of range");
-  const bool lo = op.p <= PM_LO;
-  auto k = mode == 1 ? (lo ? k_l2p<1, PM_LO> : k_l2p<1, PM_HI>) : (lo ? k_l2p<0, PM_LO> : k_l2p<0, PM_HI>);
-  hipLaunchKernelGGL(k, dim3(nleaf), dim3(L2P_TPB), 0, s, t, op, pa, F, out, done);
+  if (op.p < 1 || op.p > PM_HI || op.nc != mi_count(op.p)) throw Error(PFMM_ERR_INVALID_ARG, "order_p out of range");
+  if (op.p <= PM_LO) {
+    const L2PFixedKernel k = mode == 1 ? l2p_fixed_kernel<1>(op.p, std::make_integer_sequence<int, PM_LO>{})
+                                       : l2p_fixed_kernel<0>(op.p, std::make_integer_sequence<int, PM_LO>{});
+    if (!k) throw Error(PFMM_ERR_INVALID_ARG, "order_p out of range");
+    hipLaunchKernelGGL(k, dim3((nleaf + L2PF_LEAVES - 1) / L2PF_LEAVES), dim3(L2PF_TPB), 0, s, t, op.stride, pa, F,
+                       out, done);
+  } else {
+    auto k = mode == 1 ? k_l2p<1, PM_HI> : k_l2p<0, PM_HI>;
+    hipLaunchKernelGGL(k, dim3(nleaf), dim3(L2P_TPB), 0, s, t, op, pa, F, out, done);
+  }
   PFMM_LAUNCH_CHECK();
 }
 
