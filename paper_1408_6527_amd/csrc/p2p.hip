@@ -230,7 +230,9 @@ __global__ __launch_bounds__(TPB) void k_p2p(TreeView t, Particles pa, const dou
           for (int jj = slice; jj < m; jj += G) {
             const T rx = xi - sx[jj], ry = yi - sy[jj], rz = zi - sz[jj];
             const T r2 = rx * rx + ry * ry + rz * rz;
-            const bool valid = r2 > T(0) && (MODE != 3 || r2 < rc2);
+            // Undamped chunks hold sources of non-adjacent leaves only, a leaf edge or more away:
+            // no self pair and no coincident pair can occur there, so the test is left out.
+            const bool valid = !DAMP || (r2 > T(0) && (MODE != 3 || r2 < rc2));
             if (MODE == 1 && !valid && sidx[jj] != i) bad = 1;
             const T rinv = valid ? rsqrt_t(valid ? r2 : T(1)) : T(0);
             const T rinv2 = rinv * rinv;
