@@ -80,7 +80,8 @@ def test_field_one_leaf_equals_direct_sums(api):
     assert relmax(N(G), Gq + Gd) < 1e-12
 
 
-@pytest.mark.parametrize("p,ws,lw", [(4, 1, 1.8), (6, 2, 1.8), (8, 2, 1.8), (3, 1, 1.2)])
+@pytest.mark.parametrize("p,ws,lw", [(4, 1, 1.8), (6, 2, 1.8), (8, 2, 1.8), (3, 1, 1.2), (1, 1, 1.8), (2, 2, 1.8),
+                                     (7, 2, 1.8)])
 def test_field_fmm_matches_oracle_fmm(api, p, ws, lw):
     print_case(f"field fmm p={p} ws={ws}")
     X, q, a, mu = cube(600, 13.0, 2)
@@ -93,6 +94,25 @@ def test_field_fmm_matches_oracle_fmm(api, p, ws, lw):
     assert relmax(N(E), ref["E_u"]) < 1e-11
     assert relmax(N(Ed), ref["E_d"]) < 1e-11
     assert relmax(N(G), ref["G_d"]) < 1e-11
+
+
+@pytest.mark.parametrize("p,ws", [(2, 2), (7, 2)])
+def test_solve_satisfies_oracle_fmm_equations(api, p, ws):
+    """The dipoles of a tight solve satisfy the polarisation equations mu = alpha E_d(mu) (Sec. II.A)
+    with the fields of the oracle's FMM at the same order and tree: the solve's own field
+    evaluations (the dipole-field-only pass of its iterations) agree with that operator."""
+    print_case(f"solve vs oracle fmm equations p={p} ws={ws}")
+    X, q, a, _ = cube(600, 13.0, 6)
+    lw = 1.8
+    thole = 2.0 if lw * ws > 2.6 else 0.0
+    r = api.Solver(order_p=p, ws=ws, leaf_width=lw, thole_a=thole, scf_tol=1e-11).solve(T(X), T(q), T(a))
+    mu = N(r.mu)
+    ref = FM.fmm_fields(X, q, mu, a, thole, p, lw, ws, want_grad=False)
+    assert ref["tree"].L >= 3
+    b = a[:, None] * FM.fmm_fields(X, q, None, a, thole, p, lw, ws, want_grad=False)["E_d"]
+    res = mu - a[:, None] * ref["E_d"]
+    assert np.linalg.norm(res) < 1e-9 * np.linalg.norm(b)
+    assert np.linalg.norm(mu - b) > 1e-3 * np.linalg.norm(b)  # the dipole coupling is not negligible
 
 
 @pytest.mark.parametrize("p,ws,lw,slack", [(6, 2, 1.8, 0), (8, 2, 1.8, 1), (4, 1, 1.8, 0), (10, 2, 1.8, 2)])
