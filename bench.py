@@ -34,11 +34,11 @@ WORKLOADS = {
     # mixed_target: the settings of the mixed path at its own stated error (relative force error
     # <= 1e-4 instead of the float64 path's 1e-5), timed beside the shared settings
     "scaling_1m": dict(gen="scaling_1m", p=10, ws=2, leaf=6.0, tol=1e-6, slack=2, pc=5.5, pc_iters=3,
-                       relax=0.03, mixed_target=dict(p=8, leaf=5.5, relax=0.01, pc=5.0)),
+                       relax=0.03, mixed_target=dict(p=8, leaf=5.5, slack=1, relax=0.01, pc=5.0)),
     "scaling_250k": dict(gen="scaling_250k", p=10, ws=2, leaf=6.0, tol=1e-6, slack=2, pc=5.5, pc_iters=3,
-                         relax=0.03, mixed_target=dict(p=8, leaf=5.5, relax=0.01, pc=5.0)),
+                         relax=0.03, mixed_target=dict(p=8, leaf=5.5, slack=1, relax=0.01, pc=5.0)),
     "scaling_4m": dict(gen="scaling_4m", p=10, ws=2, leaf=6.0, tol=1e-6, slack=3, pc=5.5, pc_iters=3,
-                       relax=0.03, mixed_target=dict(p=8, leaf=5.5, relax=0.01, pc=5.0)),
+                       relax=0.03, mixed_target=dict(p=8, leaf=5.5, slack=1, relax=0.01, pc=5.0)),
     "globular_50k": dict(gen="globular_50k", p=6, ws=2, leaf=4.0, tol=1e-6, slack=-1, pc=4.0, pc_iters=4,
                          relax=0.0),
     "uniform_cube_1k": dict(gen="uniform_cube_1k", p=4, ws=1, leaf=5.0, tol=1e-8, slack=-1, pc=0.0, pc_iters=4,
