@@ -44,7 +44,9 @@ __device__ inline double rsqrt_t(double x) {
   const double e = fma(-x * y, y, 1.0);
   return fma(y * e, fma(e, 0.375, 0.5), y);
 }
-__device__ inline float rsqrt_t(float x) { return rsqrtf(x); }
+// float32: the hardware estimate alone (the library function's result for every normal x; it adds a
+// rescaling of denormal arguments, which an r^2 here never is).
+__device__ inline float rsqrt_t(float x) { return __builtin_amdgcn_rsqf(x); }
 
 template <typename T, int MODE, int SRC, bool LIST>
 __global__ __launch_bounds__(TPB) void k_p2p(TreeView t, Particles pa, const double4* __restrict__ mu4,
