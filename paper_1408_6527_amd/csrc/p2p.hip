@@ -207,13 +207,25 @@ __global__ __launch_bounds__(TPB) void k_p2p(TreeView t, Particles pa, const dou
             // The cutoff keeps about a tenth of the staged sources: mark the lane's sources inside it
             // (at most 64: m <= 64), then evaluate those alone, in the same order; the others would
             // add exact zeros.
-            unsigned long long in = 0ULL;
-  #pragma unroll 4
-            for (int jj = slice, b = 0; jj < m; jj += G, ++b) {
+            // Bit b of the mask is the lane's source jj = slice + b G.  The first nfull of them are
+            // below m on every slice (a loop with a wave-uniform trip count), one more on some.
+            const int Gu = __builtin_amdgcn_readfirstlane(G), mu = __builtin_amdgcn_readfirstlane(m);
+            const int nfull = mu >= Gu ? (mu - Gu) / Gu + 1 : 0;
+            auto inside = [&](int jj) {
               const T rx = xi - sx[jj], ry = yi - sy[jj], rz = zi - sz[jj];
               const T r2 = rx * rx + ry * ry + rz * rz;
-              if (r2 > T(0) && r2 < rc2) in |= 1ULL << b;
+              return r2 > T(0) && r2 < rc2;
+            };
+            unsigned lo = 0u, hi = 0u;
+            const int n0 = min(nfull, 32);
+  #pragma unroll 4
+            for (int b = 0; b < n0; ++b) lo |= inside(slice + b * Gu) ? 1u << b : 0u;
+  #pragma unroll 4
+            for (int b = n0; b < nfull; ++b) hi |= inside(slice + b * Gu) ? 1u << (b - 32) : 0u;
+            if (nfull < 64 && slice + nfull * Gu < mu && inside(slice + nfull * Gu)) {
+              if (nfull < 32) lo |= 1u << nfull; else hi |= 1u << (nfull - 32);
             }
+            unsigned long long in = ((unsigned long long)hi << 32) | lo;
             while (in) {
               const int jj = slice + __builtin_ctzll(in) * G;
               in &= in - 1ULL;
