@@ -96,7 +96,7 @@ def test_field_fmm_matches_oracle_fmm(api, p, ws, lw):
     assert relmax(N(G), ref["G_d"]) < 1e-11
 
 
-@pytest.mark.parametrize("p,ws", [(2, 2), (7, 2)])
+@pytest.mark.parametrize("p,ws", [(1, 2), (2, 2), (3, 2), (7, 2)])
 def test_solve_satisfies_oracle_fmm_equations(api, p, ws):
     """The dipoles of a tight solve satisfy the polarisation equations mu = alpha E_d(mu) (Sec. II.A)
     with the fields of the oracle's FMM at the same order and tree: the solve's own field
